@@ -1,0 +1,283 @@
+"""FP64 CPU oracle of the relocalization hot path (arXiv 2511.01219).
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It shares no code
+with the HIP library (``paper_2511_01219_amd``) and never imports it.
+
+The arithmetic lives in ``reloc_oracle.cpp`` (plain C++17, FP64, IEEE, no
+fast-math), loaded through ctypes; this module only marshals numpy arrays and
+strings the C functions together in the paper's order:
+scan preprocessing (eq. 11-16, 25-26) -> panoramic ray cast (eq. 13-14) ->
+SMAD by direct summation (eq. 17-20) -> SMAD order and batches -> TAM over
+orientations (eq. 22-31) -> early termination -> ranking (eq. 8-9).
+
+Parity status of each part (what pins it) is listed in ``tests/test_oracle_*``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "reloc_oracle.cpp")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# status codes shared (as numbers, by definition) with the C-ABI
+E_INVALID, E_BEAMGRID, E_EMPTY = -1, -4, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared",
+                               "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_SO)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _declare(L):
+    vp, i32, i64, f64, f32, u64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                   ctypes.c_double, ctypes.c_float, ctypes.c_uint64)
+    L.orc_edt_brute.argtypes = [i32, i32, vp, i32, vp]
+    L.orc_edt.argtypes = [i32, i32, vp, i32, vp]
+    L.orc_dirs.argtypes = [i32, vp]
+    L.orc_dirs.restype = None
+    L.orc_raycast.argtypes = [i32, i32, vp, i32, i32, i32, f64, f32, i32, vp, i32,
+                              vp, vp, i32]
+    L.orc_prep.argtypes = [i32, vp, f64, f64, i32, vp, vp, f32, f32, i32, i32, i32,
+                           f64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_smad.argtypes = [i32, i32, vp, i32, vp, f64, i32, i32, vp, vp, vp, i32]
+    L.orc_tam.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
+                          f64, f64, f64, f64, i32, vp, vp, vp, i32]
+    L.orc_stages.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
+                             f64, f64, f64, f64, i32, vp, vp, i32, f64, vp, vp, vp,
+                             vp, vp, i32]
+    L.orc_sample.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, i32,
+                             f64, f64, u64, i32, vp, vp]
+    L.orc_num_threads.argtypes = []
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+def edt(occ: np.ndarray, thr: int = 65, brute: bool = False) -> np.ndarray:
+    """Exact squared EDT in cells (int64, -1 everywhere for an empty map)."""
+    occ = np.ascontiguousarray(occ, dtype=np.int8)
+    H, W = occ.shape
+    k = np.empty((H, W), dtype=np.int64)
+    f = lib().orc_edt_brute if brute else lib().orc_edt
+    f(W, H, _p(occ), thr, _p(k))
+    return k
+
+
+def dirs(Ng: int) -> np.ndarray:
+    U = np.empty((Ng, 2), dtype=np.int32)
+    lib().orc_dirs(Ng, _p(U))
+    return U
+
+
+def raycast(occ: np.ndarray, hyp_xy: np.ndarray, Ns: int, Ng: int, res: float,
+            range_max: float, thr: int = 65, brute: bool = False,
+            threads: int = 0):
+    """Hit cell (int32, -1 none) and range (float32, 0 none) for every
+    hypothesis and panoramic direction j < Ns."""
+    occ = np.ascontiguousarray(occ, dtype=np.int8)
+    H, W = occ.shape
+    hyp = np.ascontiguousarray(hyp_xy, dtype=np.int32).reshape(-1, 2)
+    n = hyp.shape[0]
+    hit = np.empty((n, Ns), dtype=np.int32)
+    rng = np.empty((n, Ns), dtype=np.float32)
+    st = lib().orc_raycast(W, H, _p(occ), thr, Ng, Ns, res, np.float32(range_max),
+                           n, _p(hyp), int(brute), _p(hit), _p(rng), threads)
+    if st != 0:
+        raise ValueError("orc_raycast failed: %d" % st)
+    return hit, rng
+
+
+def prep(ranges: np.ndarray, angle_min: float, angle_increment: float,
+         res: float, fov: Optional[Sequence] = None, range_min: float = 0.02,
+         range_max: float = 30.0, n_skip_beam: int = 1, n_skip_enum: int = 1,
+         n_theta: int = 0, alpha_mid_pm=(900, 700), alpha_low_pm=(700, 500)) -> Dict:
+    ranges = np.ascontiguousarray(ranges, dtype=np.float32)
+    n = len(ranges)
+    nd = (n + n_skip_beam - 1) // n_skip_beam
+    if fov:
+        lo = np.array([float(a) for a, _ in fov], dtype=np.float64)
+        hi = np.array([float(b) for _, b in fov], dtype=np.float64)
+    else:
+        lo = hi = None
+    info = np.zeros(16, dtype=np.int64)
+    dinfo = np.zeros(4, dtype=np.float64)
+    bj = np.zeros(nd, dtype=np.int32)
+    bs = np.zeros(nd, dtype=np.int32)
+    bz = np.zeros(nd, dtype=np.float64)
+    bq = np.zeros(nd, dtype=np.int32)
+    am = np.array(alpha_mid_pm, dtype=np.int32)
+    al = np.array(alpha_low_pm, dtype=np.int32)
+    st = lib().orc_prep(n, _p(ranges), angle_min, angle_increment,
+                        len(fov) if fov else 0, _p(lo), _p(hi),
+                        np.float32(range_min), np.float32(range_max),
+                        n_skip_beam, n_skip_enum, n_theta, res, _p(am), _p(al),
+                        _p(info), _p(dinfo), _p(bj), _p(bs), _p(bz), _p(bq))
+    out = dict(status=int(st), Ns=int(info[1]), Ntheta=int(info[2]), Ng=int(info[3]),
+               N_fov=int(info[4]), N_valid=int(info[5]), k_full=int(info[6]),
+               k_mid=int(info[7]), k_low=int(info[8]), panoramic=bool(info[9]),
+               n_runs=int(info[10]), j0=int(info[11]), n_down=int(info[12]),
+               n_shifts=int(info[13]), zbar=float(dinfo[0]), lam=float(dinfo[1]),
+               beam_j=bj, beam_state=bs, beam_z=bz, beam_zq=bq,
+               n_skip_enum=n_skip_enum, range_max=float(np.float32(range_max)))
+    valid = bs == 2
+    out["fov_j"] = np.ascontiguousarray(bj[bs >= 1])
+    out["valid_j"] = np.ascontiguousarray(bj[valid])
+    out["valid_zq"] = np.ascontiguousarray(bq[valid])
+    return out
+
+
+def smad(zhat: np.ndarray, pr: Dict, all_shifts: bool = False, threads: int = 0):
+    """SMAD per hypothesis (FP64) and argmin shift m (eq. 16-20)."""
+    zhat = np.ascontiguousarray(zhat, dtype=np.float32)
+    n, Ns = zhat.shape
+    assert Ns == pr["Ns"]
+    s = np.empty(n, dtype=np.float64)
+    a = np.empty(n, dtype=np.int32)
+    allv = np.empty((n, pr["n_shifts"]), dtype=np.float64) if all_shifts else None
+    lib().orc_smad(n, Ns, _p(zhat), len(pr["fov_j"]), _p(pr["fov_j"]), pr["zbar"],
+                   pr["n_skip_enum"], int(pr["panoramic"]), _p(s), _p(a), _p(allv),
+                   threads)
+    return (s, a, allv) if all_shifts else (s, a)
+
+
+def tam(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_k: np.ndarray,
+        z_hit: float = 1.0, sigma_hit: float = 0.2, z_rand: float = 0.0,
+        d_max: float = 2.0, threads: int = 0) -> np.ndarray:
+    """[nq, 8] = T, P, s_d, c, Lbar, top-k_full / k_mid / k_low means, for
+    each query (cell xy, heading k)."""
+    kmap = np.ascontiguousarray(kmap, dtype=np.int64)
+    H, W = kmap.shape
+    q_xy = np.ascontiguousarray(q_xy, dtype=np.int32).reshape(-1, 2)
+    q_k = np.ascontiguousarray(q_k, dtype=np.int32)
+    out = np.empty((len(q_k), 8), dtype=np.float64)
+    lib().orc_tam(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
+                  _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
+                  pr["k_low"], z_hit, sigma_hit, z_rand, d_max, len(q_k), _p(q_xy),
+                  _p(q_k), _p(out), threads)
+    return out
+
+
+def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2,
+           z_rand=0.0, d_max=2.0, all_T=False, threads: int = 0) -> Dict:
+    kmap = np.ascontiguousarray(kmap, dtype=np.int64)
+    H, W = kmap.shape
+    hyp = np.ascontiguousarray(hyp_xy, dtype=np.int32).reshape(-1, 2)
+    n = hyp.shape[0]
+    smad_v = np.ascontiguousarray(smad_v, dtype=np.float64)
+    order = np.empty(n, dtype=np.int32)
+    tstar = np.zeros(n, dtype=np.float64)
+    kstar = np.full(n, -1, dtype=np.int32)
+    info = np.zeros(4, dtype=np.int64)
+    allT = np.zeros((n, pr["Ntheta"]), dtype=np.float64) if all_T else None
+    lib().orc_stages(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
+                     _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
+                     pr["k_low"], z_hit, sigma_hit, z_rand, d_max, n, _p(hyp),
+                     _p(smad_v), batch_k,
+                     float("nan") if tau is None else float(tau),
+                     _p(order), _p(tstar), _p(kstar), _p(info), _p(allT), threads)
+    ne = int(info[2])
+    out = dict(order=order, stages=int(info[0]), early_stopped=bool(info[1]),
+               n_eval=ne, tstar=tstar[:ne], kstar=kstar[:ne])
+    if all_T:
+        out["all_T"] = allT[:ne]
+    return out
+
+
+def sample(occ: np.ndarray, kmap: np.ndarray, res: float, origin=(0.0, 0.0),
+           min_spacing: float = 0.3, robot_radius: float = 0.21, p0=None,
+           seed: int = 0, n_target: int = 100, thr: int = 65) -> np.ndarray:
+    """Hypothesis cells [n, 2] (x, y) in acceptance order."""
+    occ = np.ascontiguousarray(occ, dtype=np.int8)
+    kmap = np.ascontiguousarray(kmap, dtype=np.int64)
+    H, W = occ.shape
+    out = np.empty((n_target, 2), dtype=np.int32)
+    n = np.zeros(1, dtype=np.int32)
+    st = lib().orc_sample(W, H, _p(occ), thr, _p(kmap), res, origin[0], origin[1],
+                          min_spacing, robot_radius, 0 if p0 is None else 1,
+                          0.0 if p0 is None else p0[0], 0.0 if p0 is None else p0[1],
+                          ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), n_target,
+                          _p(out), _p(n))
+    if st != 0:
+        raise ValueError("orc_sample failed: %d" % st)
+    return out[:int(n[0])].copy()
+
+
+def heading(k: int, Ntheta: int) -> float:
+    """Heading of orientation index k, wrapped to [-pi, pi)."""
+    th = (2.0 * math.pi * k) / Ntheta
+    if th >= math.pi:
+        th -= 2.0 * math.pi
+    return th
+
+
+def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
+               ranges: np.ndarray, angle_min: float, angle_increment: float,
+               range_min: float, range_max: float, fov=None, n_theta: int = 0,
+               batch_k: int = 64, tau: Optional[float] = 0.95, k_out: int = 10,
+               z_hit: float = 1.0, sigma_hit: float = 0.2, z_rand: float = 0.0,
+               d_max: float = 2.0, n_skip_beam: int = 1, n_skip_enum: int = 1,
+               alpha_mid_pm=(900, 700), alpha_low_pm=(700, 500), thr: int = 65,
+               kmap: Optional[np.ndarray] = None, threads: int = 0,
+               keep: bool = False) -> Dict:
+    """The whole hot path, step by step, in the paper's order."""
+    if kmap is None:
+        kmap = edt(occ, thr)
+    pr = prep(ranges, angle_min, angle_increment, res, fov, range_min, range_max,
+              n_skip_beam, n_skip_enum, n_theta, alpha_mid_pm, alpha_low_pm)
+    if pr["status"] != 0:
+        raise ValueError("scan rejected: %d" % pr["status"])
+    hit, zhat = raycast(occ, hyp_xy, pr["Ns"], pr["Ng"], res, range_max, thr,
+                        threads=threads)
+    sm, am = smad(zhat, pr, threads=threads)
+    st = stages(kmap, res, pr, hyp_xy, sm, batch_k, tau, z_hit, sigma_hit, z_rand,
+                d_max, threads=threads)
+    ne = st["n_eval"]
+    ranks = np.arange(ne)
+    rank_order = np.lexsort((ranks, -st["tstar"]))     # T desc, rank asc
+    hyp = np.asarray(hyp_xy).reshape(-1, 2)
+    poses = []
+    for r in rank_order[:k_out]:
+        h = int(st["order"][r])
+        k = int(st["kstar"][r])
+        poses.append(dict(x=origin[0] + (hyp[h, 0] + 0.5) * res,
+                          y=origin[1] + (hyp[h, 1] + 0.5) * res,
+                          theta=heading(k, pr["Ntheta"]), tam=float(st["tstar"][r]),
+                          smad=float(sm[h]), hyp=h, k=k, rank=int(r),
+                          stage=int(r) // batch_k))
+    out = dict(poses=poses, prep=pr, stages=st["stages"],
+               early_stopped=st["early_stopped"], n_eval=ne,
+               smad_evals=len(sm) * pr["n_shifts"], tam_evals=ne * pr["Ntheta"])
+    if keep:
+        out.update(hit=hit, zhat=zhat, smad=sm, argm=am, order=st["order"],
+                   tstar=st["tstar"], kstar=st["kstar"], kmap=kmap)
+    return out

@@ -1,0 +1,183 @@
+"""Oracle pins: hypothesis sampler invariants and the staged inference.
+
+Sampler (feasibility of TraversabilityCheck, reachability R(p0), spacing of
+VoxelDownsample; Algorithm 1's constraints): every accepted cell is feasible
+and reachable, pairwise spacing holds, the set is deterministic, any smaller
+target is a prefix, and when the sampler runs out the set is maximal.
+
+Staged inference (Sec. III pipeline, eq. 8-9, 22, early termination): with
+K = N_p and tau = none the best pose equals a brute-force argmax of T over
+every hypothesis and every orientation; with tau = none the result does not
+depend on K; a noiseless scan from an on-grid pose in an asymmetric room is
+relocalized to that pose; early termination stops at the first batch whose
+best exceeds tau.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from synth import make_config, make_micro
+
+RES = 0.05
+
+
+def _feasible(occ, kmap, rr=0.21):
+    q = rr / RES
+    Kr = math.ceil(q * q - 1e-9)
+    return (occ >= 0) & (occ < 65) & (kmap >= Kr)
+
+
+@pytest.mark.parametrize("seed,n", [(0, 50), (1, 400), (2, 10000)])
+def test_sampler_invariants(seed, n):
+    occ = make_micro(seed, 90, 70, n_boxes=10, p_unknown=0.02)
+    kmap = oracle.edt(occ)
+    pts = oracle.sample(occ, kmap, RES, n_target=n, seed=seed, min_spacing=0.3)
+    F = _feasible(occ, kmap)
+    lab, nl = ndimage.label(F)
+    sizes = np.bincount(lab.ravel()); sizes[0] = 0
+    big = int(np.argmax(sizes))
+    assert len(pts) == min(n, len(pts)) and len(pts) > 0
+    assert F[pts[:, 1], pts[:, 0]].all()
+    assert (lab[pts[:, 1], pts[:, 0]] == big).all()
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, 10 ** 9)
+    assert d2.min() >= 36
+    again = oracle.sample(occ, kmap, RES, n_target=n, seed=seed, min_spacing=0.3)
+    assert (again == pts).all()
+    if len(pts) < n:
+        # maximal: every reachable cell is within the spacing of a sample
+        ys, xs = np.nonzero(lab == big)
+        c = np.stack([xs, ys], 1)
+        dd = ((c[:, None, :] - pts[None, :, :]) ** 2).sum(-1).min(1)
+        assert (dd < 36).all()
+
+
+def test_sampler_prefix_and_seed():
+    occ = make_micro(5, 80, 80, n_boxes=8)
+    kmap = oracle.edt(occ)
+    a = oracle.sample(occ, kmap, RES, n_target=60, seed=9)
+    b = oracle.sample(occ, kmap, RES, n_target=25, seed=9)
+    c = oracle.sample(occ, kmap, RES, n_target=60, seed=10)
+    assert (a[:25] == b).all()
+    assert not (a == c).all()
+
+
+def test_sampler_p0_component():
+    occ = np.zeros((40, 60), np.int8)
+    occ[0, :] = occ[-1, :] = occ[:, 0] = occ[:, -1] = 100
+    occ[:, 30] = 100                                  # two sealed rooms
+    kmap = oracle.edt(occ)
+    left = oracle.sample(occ, kmap, RES, n_target=500, p0=(10 * RES, 10 * RES), seed=1)
+    right = oracle.sample(occ, kmap, RES, n_target=500, p0=(45 * RES, 20 * RES), seed=1)
+    assert (left[:, 0] < 30).all() and (right[:, 0] > 30).all()
+    with pytest.raises(ValueError):
+        oracle.sample(occ, kmap, RES, n_target=5, p0=(30.5 * RES, 20 * RES))
+
+
+def _tiny_world(seed):
+    occ = make_micro(seed, 44, 36, n_boxes=5)
+    kmap = oracle.edt(occ)
+    hyp = oracle.sample(occ, kmap, RES, n_target=40, seed=seed, min_spacing=0.15)
+    return occ, kmap, hyp
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_stages_equal_brute_force_argmax(seed):
+    occ, kmap, hyp = _tiny_world(seed)
+    w_rng = np.random.default_rng(seed)
+    N, inc = 120, math.radians(2.0)
+    z = (w_rng.random(N) * 1.2 + 0.1).astype(np.float32)
+    amin = -math.radians(120.0)
+    pr = oracle.prep(z, amin, inc, RES, range_max=10.0, n_theta=72)
+    _, zhat = oracle.raycast(occ, hyp, pr["Ns"], pr["Ng"], RES, 10.0)
+    sm, _ = oracle.smad(zhat, pr)
+    st = oracle.stages(kmap, RES, pr, hyp, sm, len(hyp), None, all_T=True)
+    assert st["stages"] == 1 and st["n_eval"] == len(hyp)
+    # brute force over every (hypothesis, orientation)
+    q = np.repeat(hyp, 72, axis=0)
+    k = np.tile(np.arange(72), len(hyp))
+    T = oracle.tam(kmap, RES, pr, q, k)[:, 0].reshape(len(hyp), 72)
+    rank_of = np.empty(len(hyp), int)
+    rank_of[st["order"]] = np.arange(len(hyp))
+    best = max(((T[h, kk], -rank_of[h], -kk, h, kk) for h in range(len(hyp))
+                for kk in range(72)))
+    r = int(np.lexsort((np.arange(st["n_eval"]), -st["tstar"]))[0])
+    assert st["order"][r] == best[3] and st["kstar"][r] == best[4]
+    assert st["tstar"][r] == best[0]
+    # all_T is rank-major
+    assert (st["all_T"] == T[st["order"]]).all()
+
+
+def test_tau_none_independent_of_K():
+    occ, kmap, hyp = _tiny_world(4)
+    N, inc = 90, math.radians(3.0)
+    z = (np.random.default_rng(4).random(N) * 1.5 + 0.1).astype(np.float32)
+    pr = oracle.prep(z, -math.radians(135.0), inc, RES, range_max=10.0, n_theta=60)
+    _, zhat = oracle.raycast(occ, hyp, pr["Ns"], pr["Ng"], RES, 10.0)
+    sm, _ = oracle.smad(zhat, pr)
+    ref = None
+    for K in (1, 3, 7, len(hyp)):
+        st = oracle.stages(kmap, RES, pr, hyp, sm, K, None)
+        assert st["n_eval"] == len(hyp) and not st["early_stopped"]
+        got = (st["tstar"].copy(), st["kstar"].copy())
+        if ref is None:
+            ref = got
+        assert (got[0] == ref[0]).all() and (got[1] == ref[1]).all()
+
+
+def test_early_termination_rule():
+    occ, kmap, hyp = _tiny_world(6)
+    N, inc = 90, math.radians(3.0)
+    z = (np.random.default_rng(6).random(N) * 1.5 + 0.1).astype(np.float32)
+    pr = oracle.prep(z, -math.radians(135.0), inc, RES, range_max=10.0, n_theta=60)
+    _, zhat = oracle.raycast(occ, hyp, pr["Ns"], pr["Ng"], RES, 10.0)
+    sm, _ = oracle.smad(zhat, pr)
+    K = 4
+    full = oracle.stages(kmap, RES, pr, hyp, sm, K, None)
+    bests = [full["tstar"][b:b + K].max() for b in range(0, len(hyp), K)]
+    tau = float(np.median(bests))
+    st = oracle.stages(kmap, RES, pr, hyp, sm, K, tau)
+    first = next(i for i, b in enumerate(bests) if b > tau)
+    assert st["early_stopped"] and st["stages"] == first + 1
+    assert st["n_eval"] == min(len(hyp), (first + 1) * K)
+    assert (st["tstar"] == full["tstar"][:st["n_eval"]]).all()
+
+
+def test_noiseless_on_grid_pose_is_found():
+    occ = make_micro(31, 70, 52, n_boxes=9)
+    kmap = oracle.edt(occ)
+    hyp = oracle.sample(occ, kmap, RES, n_target=80, seed=3, min_spacing=0.2)
+    true_h, Ns = 17, 480
+    _, zhat = oracle.raycast(occ, hyp[true_h:true_h + 1], Ns, Ns, RES, 20.0)
+    n_beams, m0 = 360, 123
+    inc = 2 * math.pi / Ns
+    amin = -math.radians(135.0)
+    j0 = int(round(amin / inc)) % Ns
+    idx = (j0 + np.arange(n_beams) + m0) % Ns
+    z = zhat[0][idx]
+    z = np.where(z > 0, z, np.nan).astype(np.float32)
+    res = oracle.relocalize(occ, RES, (0.0, 0.0), hyp, z, amin, inc, 0.02, 20.0,
+                            n_theta=Ns, batch_k=8, tau=None, k_out=3)
+    best = res["poses"][0]
+    assert best["hyp"] == true_h
+    # endpoints sit exactly on the entry face of the hit cell, so half of them
+    # fall in the free neighbour cell; the heading is right within one step
+    assert min((best["k"] - m0) % Ns, (m0 - best["k"]) % Ns) <= 1
+
+
+def test_config1_relocalizes_within_paper_criterion():
+    w = make_config(1)
+    kmap = oracle.edt(w.occ)
+    hyp = oracle.sample(w.occ, kmap, w.resolution, n_target=300, seed=1,
+                        min_spacing=0.3, robot_radius=0.21)
+    assert len(hyp) == 300
+    res = oracle.relocalize(w.occ, w.resolution, w.origin, hyp, w.ranges, w.angle_min,
+                            w.angle_increment, w.range_min, w.range_max, n_theta=360,
+                            batch_k=10, tau=None, k_out=5, kmap=kmap)
+    b = res["poses"][0]
+    d = math.hypot(b["x"] - w.pose[0], b["y"] - w.pose[1])
+    dth = abs((b["theta"] - w.pose[2] + math.pi) % (2 * math.pi) - math.pi)
+    assert d < 0.5 and dth < math.radians(30)      # success criterion, Sec. IV-C
