@@ -1,0 +1,289 @@
+/*
+ * reloc.h - C ABI of the MI355X relocalization library (libreloc.so).
+ *
+ * Passive 2-D global relocalization by batched multi-stage hypothesis
+ * inference (arXiv 2511.01219, Sec. III): for every feasible positional
+ * hypothesis ray-cast a panoramic synthetic scan (eq. 13-14), score every
+ * circular beam shift with SMAD (eq. 16-20), order the hypotheses by SMAD,
+ * re-score them batch by batch over all orientations with TAM against a
+ * distance field (eq. 22-31) and stop as soon as a batch's best TAM exceeds
+ * the threshold tau (Sec. III, pipeline description).
+ *
+ * Conventions
+ *   - SI units (metres, radians). World frame: x right, y up, theta counter-
+ *     clockwise from +x, reported in [-pi, pi) (eq. 1).
+ *   - A map is a row-major int8 grid, row 0 at the minimum y; cell (ix, iy)
+ *     covers [ox + ix*res, ox + (ix+1)*res) x [oy + iy*res, ...). A cell is
+ *     occupied iff value >= occ_threshold, unknown iff value < 0, otherwise
+ *     free. Unknown cells are free for ray casting, not obstacles for the
+ *     distance transform, and infeasible for hypotheses.
+ *   - Every call returns an int32 status: RELOC_OK (0) or a negative
+ *     RELOC_E_* code. On error no output is written (counts are set to 0)
+ *     and reloc_last_error() describes the failure. Nothing throws across
+ *     the ABI.
+ *   - Ownership: the caller owns every buffer it passes; inputs are copied
+ *     before the call returns. Maps, hypothesis sets and requests live in the
+ *     context and are named by integer ids. Pointers documented as "host"
+ *     are host memory.
+ *   - Device memory comes from the allocator given to reloc_ctx_create
+ *     (hipMalloc when NULL). Work is issued on the stream given there (a
+ *     hipStream_t passed as void*; a private default-priority stream when
+ *     NULL). Calls on one context are serialized internally.
+ *   - Results are deterministic: the same inputs give bit-identical outputs,
+ *     whatever else runs on the device.
+ */
+#ifndef RELOC_H
+#define RELOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RELOC_VERSION 1
+
+enum {
+  RELOC_OK = 0,
+  RELOC_E_INVALID = -1,   /* bad argument */
+  RELOC_E_NOMEM = -2,     /* allocation failed or the HBM budget is exceeded */
+  RELOC_E_NOTFOUND = -3,  /* unknown map, hypothesis set or request id */
+  RELOC_E_BEAMGRID = -4,  /* beams not on an equiangular grid dividing 2*pi */
+  RELOC_E_EMPTY = -5,     /* no feasible hypothesis, no valid beam, empty map */
+  RELOC_E_BUSY = -6,      /* object in use (e.g. map with live hypothesis sets) */
+  RELOC_E_PENDING = -7,   /* result not ready yet */
+  RELOC_E_TIMEOUT = -8,   /* deadline passed */
+  RELOC_E_DEVICE = -9     /* HIP runtime / device error */
+};
+
+typedef struct reloc_ctx reloc_ctx;
+
+/* Device allocator hook. alloc returns device memory of at least `bytes`
+ * bytes (NULL on failure); free releases it. Both are called with `user`. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} reloc_allocator;
+
+/* Library version (RELOC_VERSION of the build). */
+int32_t reloc_version(void);
+
+/* Thread-local description of the last error on this thread; valid until
+ * the next call on the same thread. Never NULL. */
+const char* reloc_last_error(void);
+
+/* Create a context on HIP device `device`.
+ *   alloc      : allocator hook, or NULL for hipMalloc/hipFree.
+ *   stream     : hipStream_t (as void*) all work is issued on, or NULL for a
+ *                private stream owned by the context.
+ *   hbm_budget : bytes of device memory the context may hold; 0 means the
+ *                free device memory at creation. Allocations beyond it fail
+ *                with RELOC_E_NOMEM.
+ * Errors: RELOC_E_INVALID (null out), RELOC_E_DEVICE (no such device). */
+int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
+                         size_t hbm_budget, reloc_ctx** out);
+
+/* Waits for outstanding work and frees everything the context holds. */
+void reloc_ctx_destroy(reloc_ctx* ctx);
+
+/* Bytes of device memory the context currently holds. */
+size_t reloc_ctx_bytes(const reloc_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Map residency. The occupancy grid M (Sec. II-A) is bit-packed on the
+ * device in 8x8-cell tiles (one uint64 per tile), and the exact Euclidean
+ * distance transform used by MinDistToObstacle (Sec. III-A) and by TAM's
+ * d_obs (eq. 23) is computed on the device as k[c] = min over occupied o of
+ * (dx^2 + dy^2) in cells (uint32). Both stay resident until unload.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t width, height;    /* cells, 1 .. 32768 each */
+  double resolution;        /* metres per cell, >= 1/32 */
+  double origin_x, origin_y;/* world position of the lower-left map corner */
+  int32_t occ_threshold;    /* occupied iff value >= threshold (65) */
+} reloc_map_desc;
+
+/* occ: host int8[height*width]. Errors: RELOC_E_INVALID (bad sizes),
+ * RELOC_E_EMPTY (no occupied cell), RELOC_E_NOMEM, RELOC_E_DEVICE. */
+int32_t reloc_load_map(reloc_ctx* ctx, const reloc_map_desc* desc, const int8_t* occ,
+                       int32_t* map_id);
+
+/* RELOC_E_BUSY while hypothesis sets of the map exist. */
+int32_t reloc_unload_map(reloc_ctx* ctx, int32_t map_id);
+
+/* Copies the squared-distance transform k (uint32[height*width], row-major,
+ * host) of a resident map. */
+int32_t reloc_read_edt(reloc_ctx* ctx, int32_t map_id, uint32_t* k_out);
+
+/* ------------------------------------------------------------------------
+ * Hypothesis sets (the positions P of eq. 6). The sampler keeps the
+ * constraints of Algorithm 1 with a deterministic integer procedure:
+ *   feasible  : known-free cells with k >= ceil((robot_radius/res)^2 - 1e-9)
+ *               (TraversabilityCheck at cell centres);
+ *   reachable : the 4-connected feasible component of p0's cell (R(p0)),
+ *               or the largest component (ties: smallest cell index) when
+ *               has_p0 == 0;
+ *   order     : ascending (splitmix64(seed + c), c) over reachable cells c
+ *               (linear index), splitmix64 being the published output
+ *               function applied to x + 0x9E3779B97F4A7C15;
+ *   spacing   : accept c iff every accepted c' has dx^2 + dy^2 >=
+ *               ceil((min_spacing/res)^2 - 1e-9) (VoxelDownsample spacing);
+ *               stop after n_target acceptances.
+ * Positions are cell centres, kept in acceptance order, so any prefix of a
+ * set is itself a valid set. Returning fewer than n_target is not an error.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_target;
+  double min_spacing;       /* rho, metres (0.3) */
+  double robot_radius;      /* r_robot, metres (0.21) */
+  int32_t has_p0;
+  double p0_x, p0_y;        /* world position of the reachability seed */
+  uint64_t seed;
+} reloc_sample_params;
+
+int32_t reloc_sample_hypotheses(reloc_ctx* ctx, int32_t map_id,
+                                const reloc_sample_params* params, int32_t* set_id,
+                                int32_t* n_out);
+
+/* A caller-supplied set: cell_xy = host int32[2*n] (ix, iy) pairs of free
+ * in-map cells. */
+int32_t reloc_set_hypotheses(reloc_ctx* ctx, int32_t map_id, const int32_t* cell_xy,
+                             int32_t n, int32_t* set_id);
+
+/* Copies up to cap cells (host int32[2*cap]); *n_out = set size. */
+int32_t reloc_read_hypotheses(reloc_ctx* ctx, int32_t set_id, int32_t* cell_xy,
+                              int32_t cap, int32_t* n_out);
+
+int32_t reloc_free_hypotheses(reloc_ctx* ctx, int32_t set_id);
+
+/* ------------------------------------------------------------------------
+ * Scans and search parameters.
+ * Beam i (before downsampling) has robot-frame angle
+ * angle_min + i * angle_increment. The scan is downsampled by n_skip_beam
+ * (eq. 11); Ns = 2*pi / (angle_increment * n_skip_beam) must be an integer
+ * (eq. 14) and angle_min a multiple of the downsampled step, both within
+ * 1e-6 * Ns, else RELOC_E_BEAMGRID. Ns <= 4096.
+ * FoV intervals (eq. 12) are robot-frame angle intervals [lo, hi]; a beam is
+ * in the FoV iff its angle lies in one of them (all beams when n_fov == 0).
+ * A FoV beam is valid iff its range is finite and range_min <= z <=
+ * range_max; invalid FoV beams take the placeholder 0 in SMAD (Sec. III-B)
+ * and are left out of TAM.
+ * ---------------------------------------------------------------------- */
+typedef struct { double lo, hi; } reloc_interval;
+
+typedef struct {
+  int32_t n_beams;
+  const float* ranges;          /* host float[n_beams]; NaN = no return */
+  double angle_min, angle_increment;
+  int32_t n_fov;
+  const reloc_interval* fov;    /* host, n_fov entries, or NULL */
+  float range_min, range_max;   /* range_max < 64 m */
+} reloc_scan;
+
+typedef struct {
+  int32_t n_theta;        /* TAM orientations N_theta (0: = Ns) */
+  int32_t n_skip_beam;    /* eq. 11 stride (1) */
+  int32_t n_skip_enum;    /* eq. 15 SMAD shift stride (1) */
+  int32_t batch_k;        /* hypotheses per stage (64) */
+  int32_t k_out;          /* ranked poses to return (10) */
+  double tau;             /* early-termination threshold (0.95); NaN: none */
+  int32_t n_hyp;          /* use the first n_hyp of the set (0: all) */
+  double z_hit, sigma_hit, z_rand; /* likelihood field, eq. 23 (1, 0.2, 0) */
+  double d_max;           /* eq. 29 clamp and off-map distance (2.0 m) */
+  int32_t alpha_mid_pm[2];/* alpha_mid at lambda = 0 and 1, per mille (900, 700) */
+  int32_t alpha_low_pm[2];/* alpha_low at lambda = 0 and 1, per mille (700, 500) */
+  double deadline_s;      /* plain path: stop with RELOC_E_TIMEOUT after this (0: none) */
+} reloc_search_params;
+
+/* Fills the defaults listed above. */
+void reloc_search_defaults(reloc_search_params* p);
+
+/* Host-only preprocessing summary of a scan (eq. 11-16, 25-26):
+ * k_mid = floor(N'_Z * (A0*Ns + (A1 - A0)*N_FoV) / (1000*Ns)), likewise
+ * k_low; zbar = FP64 mean of the FoV ranges with placeholders (eq. 16);
+ * panoramic = (10*N_FoV >= 9*Ns), eq. 20's lambda >= 0.9. */
+typedef struct {
+  int32_t Ns, Ntheta, Ng;       /* Ng = lcm(Ns, Ntheta) */
+  int32_t n_down;               /* beams after downsampling */
+  int32_t n_fov, n_valid;       /* N_FoV (= sum |I_k|), N'_Z */
+  int32_t k_full, k_mid, k_low;
+  int32_t panoramic, n_runs, n_shifts, j0;
+  double zbar, lambda;
+} reloc_scan_info;
+
+int32_t reloc_scan_info_get(const reloc_scan* scan, const reloc_search_params* params,
+                            double resolution, reloc_scan_info* out);
+
+/* One ranked pose hypothesis (eq. 8-9). x, y: world cell centre; theta:
+ * heading k * 2*pi / N_theta wrapped to [-pi, pi); tam: T (eq. 31) at
+ * theta*; smad: SMAD(p) (eq. 20) as FP32; hyp: index in the set; k:
+ * orientation index; rank: position in the SMAD order; stage: batch index. */
+typedef struct {
+  double x, y, theta;
+  float tam, smad;
+  int32_t hyp, k, rank, stage;
+} reloc_pose;
+
+typedef struct {
+  int64_t smad_evals;   /* N_p x shifts (1 when panoramic) */
+  int64_t tam_evals;    /* hypotheses evaluated by TAM x N_theta */
+  int64_t rays;         /* N_p x Ns */
+  int64_t tam_lookups;  /* tam_evals x N'_Z */
+  int32_t n_hyp, stages, early_stopped, n_eval;
+  float ms_total, ms_raycast, ms_sort, ms_tam, ms_rank; /* device time */
+} reloc_stats;
+
+/* ------------------------------------------------------------------------
+ * Relocalization.
+ * A request binds a scan to a map and hypothesis set: the scan is
+ * preprocessed on the host (reloc_scan_info) and its tables uploaded once.
+ * reloc_run then executes the whole hot path on the device:
+ *   ray cast + SMAD for every hypothesis -> stable sort by (SMAD, index) ->
+ *   stages of batch_k hypotheses: TAM over N_theta orientations, theta* per
+ *   hypothesis (ties: smallest k), batch best (ties: earlier rank), stop when
+ *   it exceeds tau -> all evaluated poses ranked by (T desc, rank asc).
+ * out: host reloc_pose[cap]; *n_out = min(cap, k_out, evaluated).
+ * stats may be NULL.
+ * ---------------------------------------------------------------------- */
+int32_t reloc_prepare(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
+                      const reloc_scan* scan, const reloc_search_params* params,
+                      int32_t* request_id);
+
+int32_t reloc_run(reloc_ctx* ctx, int32_t request_id, reloc_pose* out, int32_t cap,
+                  int32_t* n_out, reloc_stats* stats);
+
+int32_t reloc_release(reloc_ctx* ctx, int32_t request_id);
+
+/* prepare + run + release in one call. */
+int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
+                         const reloc_scan* scan, const reloc_search_params* params,
+                         reloc_pose* out, int32_t cap, int32_t* n_out, reloc_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * Parity / inspection entry points (same kernels as reloc_run).
+ * ---------------------------------------------------------------------- */
+
+/* Panoramic synthetic scan of every hypothesis of the request (eq. 13):
+ * hit_cell: host int32[n_hyp*Ns] (linear index, -1 none), range: host
+ * float[n_hyp*Ns] (0 none), steps: host int32[n_hyp*Ns] grid-line crossings
+ * the traversal made (an exact corner counts once). Any pointer may be NULL. */
+int32_t reloc_debug_raycast(reloc_ctx* ctx, int32_t request_id, int32_t* hit_cell,
+                            float* range, int32_t* steps);
+
+/* SMAD(p) (FP64) and its argmin shift for every hypothesis, and the SMAD
+ * order (hypothesis index per rank). Any pointer may be NULL. */
+int32_t reloc_debug_smad(reloc_ctx* ctx, int32_t request_id, double* smad,
+                         int32_t* argmin, int32_t* order);
+
+/* TAM of every orientation for n ranks starting at rank r0 of the SMAD order:
+ * T: host float[n*N_theta] (rank-major, may be NULL), tstar / kstar: host
+ * float[n] / int32[n] (may be NULL). */
+int32_t reloc_debug_tam(reloc_ctx* ctx, int32_t request_id, int32_t r0, int32_t n,
+                        float* T, float* tstar, int32_t* kstar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RELOC_H */

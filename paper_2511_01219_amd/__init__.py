@@ -1,0 +1,274 @@
+"""MI355X relocalization library: Python binding of libreloc.so.
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels behind the C ABI of ``include/reloc.h``. PyTorch supplies device
+memory (its caching allocator, through the allocator hook) and the stream
+work is issued on (the current torch stream).
+
+    import paper_2511_01219_amd as reloc
+    ctx = reloc.Context()
+    m = ctx.load_map(occ, resolution=0.05)
+    s, n = ctx.sample_hypotheses(m, n_target=20000, min_spacing=0.3)
+    poses, stats = ctx.relocalize(m, s, ranges, angle_min, angle_increment,
+                                  range_max=25.0, n_theta=720, batch_k=64)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _abi
+from ._abi import (E_BEAMGRID, E_BUSY, E_DEVICE, E_EMPTY, E_INVALID, E_NOMEM, E_NOTFOUND,
+                   E_PENDING, E_TIMEOUT, OK, STATUS_NAMES)
+
+__all__ = ["Context", "RelocError", "scan_info", "search_params", "lib", "version",
+           "OK", "E_INVALID", "E_NOMEM", "E_NOTFOUND", "E_BEAMGRID", "E_EMPTY", "E_BUSY",
+           "E_PENDING", "E_TIMEOUT", "E_DEVICE"]
+
+
+class RelocError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+def lib():
+    return _abi.load()
+
+
+def version() -> int:
+    return int(lib().reloc_version())
+
+
+def _check(code: int, allow=()) -> int:
+    if code != OK and code not in allow:
+        raise RelocError(code, lib().reloc_last_error().decode())
+    return code
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def search_params(**kw) -> _abi.reloc_search_params:
+    """reloc_search_params with the library defaults, overridden by ``kw``
+    (tau=None means no early termination)."""
+    p = _abi.reloc_search_params()
+    lib().reloc_search_defaults(C.byref(p))
+    for k, v in kw.items():
+        if k == "tau" and v is None:
+            v = float("nan")
+        if k in ("alpha_mid_pm", "alpha_low_pm"):
+            getattr(p, k)[0], getattr(p, k)[1] = int(v[0]), int(v[1])
+            continue
+        if not hasattr(p, k):
+            raise TypeError("unknown search parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+class _Scan:
+    """Keeps the host buffers of a reloc_scan alive."""
+
+    def __init__(self, ranges, angle_min, angle_increment, range_min, range_max, fov):
+        self.ranges = np.ascontiguousarray(ranges, dtype=np.float32)
+        self.fov = None
+        n_fov = 0
+        if fov:
+            self.fov = (_abi.reloc_interval * len(fov))(
+                *[_abi.reloc_interval(float(a), float(b)) for a, b in fov])
+            n_fov = len(fov)
+        self.s = _abi.reloc_scan(len(self.ranges), self.ranges.ctypes.data, float(angle_min),
+                                 float(angle_increment), n_fov, self.fov, float(range_min),
+                                 float(range_max))
+
+
+def scan_info(ranges, angle_min, angle_increment, resolution, range_min=0.02,
+              range_max=30.0, fov=None, **search) -> Dict:
+    """Host-side preprocessing summary of a scan (no device needed)."""
+    sc = _Scan(ranges, angle_min, angle_increment, range_min, range_max, fov)
+    p = search_params(**search)
+    out = _abi.reloc_scan_info()
+    _check(lib().reloc_scan_info_get(C.byref(sc.s), C.byref(p), float(resolution),
+                                     C.byref(out)))
+    d = {f: getattr(out, f) for f, _ in out._fields_}
+    d["lambda"] = d.pop("lambda_")
+    return d
+
+
+class Context:
+    """A reloc_ctx on one GPU, with torch's caching allocator and stream."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, use_torch: bool = True,
+                 stream=None):
+        self._lib = lib()
+        self._h = C.c_void_p()
+        self._cb = None
+        alloc_p = None
+        stream_p = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RelocError(E_DEVICE, "no GPU visible to torch")
+            self._torch_dev = device
+            st = stream if stream is not None else torch.cuda.current_stream(device)
+            if st.cuda_stream == 0:
+                # the legacy default stream: give the library a stream of its
+                # own (default priority) so torch's allocator can track it
+                st = torch.cuda.Stream(device=device)
+            self._torch_stream = st
+            stream_p = C.c_void_p(st.cuda_stream)
+
+            def _alloc(nbytes, user, _t=torch, _d=device, _s=st):
+                try:
+                    return int(_t.cuda.caching_allocator_alloc(int(nbytes), _d, _s))
+                except Exception:
+                    return None
+
+            def _free(ptr, user, _t=torch):
+                _t.cuda.caching_allocator_delete(ptr)
+
+            self._cb = (_abi.ALLOC_FN(_alloc), _abi.FREE_FN(_free))
+            self._alloc_struct = _abi.reloc_allocator(self._cb[0], self._cb[1], None)
+            alloc_p = C.byref(self._alloc_struct)
+        _check(self._lib.reloc_ctx_create(int(device), alloc_p, stream_p, int(hbm_budget),
+                                          C.byref(self._h)))
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if self._h:
+            self._lib.reloc_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def bytes(self) -> int:
+        return int(self._lib.reloc_ctx_bytes(self._h))
+
+    # -- maps -----------------------------------------------------------------
+    def load_map(self, occ: np.ndarray, resolution: float = 0.05,
+                 origin: Tuple[float, float] = (0.0, 0.0), occ_threshold: int = 65) -> int:
+        occ = np.ascontiguousarray(occ, dtype=np.int8)
+        H, W = occ.shape
+        d = _abi.reloc_map_desc(W, H, float(resolution), float(origin[0]), float(origin[1]),
+                                int(occ_threshold))
+        mid = C.c_int32()
+        _check(self._lib.reloc_load_map(self._h, C.byref(d), _ptr(occ), C.byref(mid)))
+        self._shapes = getattr(self, "_shapes", {})
+        self._shapes[mid.value] = (H, W)
+        return mid.value
+
+    def unload_map(self, map_id: int):
+        _check(self._lib.reloc_unload_map(self._h, int(map_id)))
+
+    def read_edt(self, map_id: int) -> np.ndarray:
+        H, W = self._shapes[map_id]
+        k = np.empty((H, W), dtype=np.uint32)
+        _check(self._lib.reloc_read_edt(self._h, int(map_id), _ptr(k)))
+        return k
+
+    # -- hypotheses -----------------------------------------------------------
+    def sample_hypotheses(self, map_id: int, n_target: int, min_spacing: float = 0.3,
+                          robot_radius: float = 0.21, p0=None, seed: int = 0):
+        p = _abi.reloc_sample_params(int(n_target), float(min_spacing), float(robot_radius),
+                                     0 if p0 is None else 1,
+                                     0.0 if p0 is None else float(p0[0]),
+                                     0.0 if p0 is None else float(p0[1]),
+                                     int(seed) & 0xFFFFFFFFFFFFFFFF)
+        sid, n = C.c_int32(), C.c_int32()
+        _check(self._lib.reloc_sample_hypotheses(self._h, int(map_id), C.byref(p),
+                                                 C.byref(sid), C.byref(n)))
+        return sid.value, n.value
+
+    def set_hypotheses(self, map_id: int, cell_xy: np.ndarray) -> int:
+        xy = np.ascontiguousarray(cell_xy, dtype=np.int32).reshape(-1, 2)
+        sid = C.c_int32()
+        _check(self._lib.reloc_set_hypotheses(self._h, int(map_id), _ptr(xy), len(xy),
+                                              C.byref(sid)))
+        return sid.value
+
+    def read_hypotheses(self, set_id: int) -> np.ndarray:
+        n = C.c_int32()
+        _check(self._lib.reloc_read_hypotheses(self._h, int(set_id), None, 0, C.byref(n)))
+        out = np.empty((n.value, 2), dtype=np.int32)
+        _check(self._lib.reloc_read_hypotheses(self._h, int(set_id), _ptr(out), n.value,
+                                               C.byref(n)))
+        return out
+
+    def free_hypotheses(self, set_id: int):
+        _check(self._lib.reloc_free_hypotheses(self._h, int(set_id)))
+
+    # -- requests -------------------------------------------------------------
+    def prepare(self, map_id: int, set_id: int, ranges, angle_min: float,
+                angle_increment: float, range_min: float = 0.02, range_max: float = 30.0,
+                fov: Optional[Sequence] = None, **search) -> int:
+        sc = _Scan(ranges, angle_min, angle_increment, range_min, range_max, fov)
+        p = search_params(**search)
+        rid = C.c_int32()
+        _check(self._lib.reloc_prepare(self._h, int(map_id), int(set_id), C.byref(sc.s),
+                                       C.byref(p), C.byref(rid)))
+        return rid.value
+
+    def run(self, request_id: int, cap: int = 64, allow_timeout: bool = False):
+        out = (_abi.reloc_pose * max(1, cap))()
+        n = C.c_int32()
+        st = _abi.reloc_stats()
+        code = _check(self._lib.reloc_run(self._h, int(request_id), out, int(cap), C.byref(n),
+                                          C.byref(st)),
+                      allow=(E_TIMEOUT,) if allow_timeout else ())
+        poses = [{f: getattr(out[i], f) for f, _ in out[i]._fields_} for i in range(n.value)]
+        stats = {f: getattr(st, f) for f, _ in st._fields_}
+        stats["status"] = code
+        return poses, stats
+
+    def release(self, request_id: int):
+        _check(self._lib.reloc_release(self._h, int(request_id)))
+
+    def relocalize(self, map_id: int, set_id: int, ranges, angle_min: float,
+                   angle_increment: float, range_min: float = 0.02, range_max: float = 30.0,
+                   fov: Optional[Sequence] = None, cap: int = 64, **search):
+        """relocalize(scan, fov, beam angles) -> (ranked poses, stats)."""
+        rid = self.prepare(map_id, set_id, ranges, angle_min, angle_increment, range_min,
+                           range_max, fov, **search)
+        try:
+            return self.run(rid, cap)
+        finally:
+            self.release(rid)
+
+    # -- parity / inspection ----------------------------------------------------
+    def debug_raycast(self, request_id: int, n_hyp: int, Ns: int, steps: bool = False):
+        hit = np.empty((n_hyp, Ns), dtype=np.int32)
+        rng = np.empty((n_hyp, Ns), dtype=np.float32)
+        stp = np.empty((n_hyp, Ns), dtype=np.int32) if steps else None
+        _check(self._lib.reloc_debug_raycast(self._h, int(request_id), _ptr(hit), _ptr(rng),
+                                             _ptr(stp)))
+        return (hit, rng, stp) if steps else (hit, rng)
+
+    def debug_smad(self, request_id: int, n_hyp: int):
+        s = np.empty(n_hyp, dtype=np.float64)
+        a = np.empty(n_hyp, dtype=np.int32)
+        o = np.empty(n_hyp, dtype=np.int32)
+        _check(self._lib.reloc_debug_smad(self._h, int(request_id), _ptr(s), _ptr(a), _ptr(o)))
+        return s, a, o
+
+    def debug_tam(self, request_id: int, r0: int, n: int, Ntheta: int, want_T: bool = True):
+        T = np.empty((n, Ntheta), dtype=np.float32) if want_T else None
+        ts = np.empty(n, dtype=np.float32)
+        ks = np.empty(n, dtype=np.int32)
+        _check(self._lib.reloc_debug_tam(self._h, int(request_id), int(r0), int(n), _ptr(T),
+                                         _ptr(ts), _ptr(ks)))
+        return T, ts, ks

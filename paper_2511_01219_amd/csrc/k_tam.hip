@@ -1,0 +1,302 @@
+// TAM over enumerated orientations (eq. 22-31), per-hypothesis argmax,
+// batch reduction with the early-termination test, and final ranking.
+//
+// Work layout: one workgroup (4 wavefronts) per (hypothesis, tile of 16
+// orientations); each wavefront evaluates one (p, theta_k) at a time with the
+// valid beams spread over its 64 lanes.
+//
+// Per beam the endpoint cell is computed exactly in 64-bit integers,
+// e = floor((X * 2^20 + zq * U) / 2^28), and the squared EDT distance k of
+// that cell is gathered. The likelihood l(k) of eq. 23 is monotone
+// non-increasing in k, so the top-k_mid selection of eq. 24-27 is a
+// selection of the k_mid smallest integer keys: key = 2 * min(k, kcap) for
+// in-map endpoints and a host-chosen odd key for off-map ones (d = d_max).
+// kcap is where l(k) has converged to within 1e-10 of its limit. The
+// threshold key comes from a two-level LDS histogram; sums are exact
+// integers (l in Q26 fixed point from a host table, sqrt(k) in Q16, k
+// itself), so the result does not depend on lane order or co-scheduling.
+// The median of eq. 27 is always the top-k_mid mean (top-k means are
+// non-increasing in k and k_low <= k_mid <= k_full).
+#include <cmath>
+
+#include "reloc_internal.h"
+
+namespace reloc {
+
+namespace {
+
+constexpr int TB = 256;
+constexpr int NW = TB / 64;
+constexpr int THETA_PER_BLOCK = 16;
+constexpr uint32_t NOKEY = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t sqrt_q16(uint32_t k) {
+  return __float2uint_rn(__fsqrt_rn((float)k) * 65536.0f);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Smallest bin b of the NB-bin histogram h at which the cumulative count
+// reaches `need` (>= 1), and the count strictly below b. Lane l owns bins
+// [l*P, (l+1)*P).
+template <int P>
+__device__ __forceinline__ void find_bin(const uint32_t* h, int lane, int need, int* bin,
+                                         int* below) {
+  int loc = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) loc += (int)h[lane * P + p];
+  int incl = loc;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  const unsigned long long m = __ballot(incl >= need);
+  const int first = m ? __ffsll((unsigned long long)m) - 1 : 63;
+  int b = 0, bl = 0;
+  if (lane == first) {
+    int acc = incl - loc;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int c = (int)h[lane * P + p];
+      if (acc + c >= need) {
+        b = lane * P + p;
+        bl = acc;
+        break;
+      }
+      acc += c;
+    }
+  }
+  *bin = __shfl(b, first, 64);
+  *below = __shfl(bl, first, 64);
+}
+
+template <int R, int KB>
+__global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
+  constexpr int LB2 = KB / 2;
+  constexpr int NB = 1 << LB2;        // bins per level (level 1: key >> LB2)
+  constexpr int P = NB / 64;
+  extern __shared__ int32_t smem[];
+  int32_t* sbase = smem;              // [nv]
+  int32_t* szq = smem + a.nv;         // [nv]
+  uint32_t* hist_all = (uint32_t*)(smem + 2 * a.nv);   // [NW][NB]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t* hist = hist_all + wv * NB;
+
+  for (int v = tid; v < a.nv; v += TB) {
+    sbase[v] = a.beam_base[v];
+    szq[v] = a.beam_zq[v];
+  }
+  const int r = a.r0 + blockIdx.y;
+  const int hyp = a.order[r];
+  const int64_t X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
+  const int64_t Y20 = (int64_t)(256 * a.hyp_xy[2 * hyp + 1] + 128) * (int64_t)(1 << 20);
+  const int k0 = blockIdx.x * THETA_PER_BLOCK;
+  __syncthreads();
+
+  for (int it = 0; it < THETA_PER_BLOCK / NW; ++it) {
+    const int k = k0 + wv + NW * it;
+    const bool active = k < a.Nt;
+    uint32_t keys[R];
+    uint64_t sumk = 0, sumsq = 0;
+    int noff = 0;
+    if (active) {
+      const int ok = (int)(((int64_t)a.o * k) % a.Ng);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int v = lane + 64 * i;
+        uint32_t key = NOKEY;
+        if (v < a.nv) {
+          int t = sbase[v] + ok;
+          if (t >= a.Ng) t -= a.Ng;
+          const int2 U = a.dirs[t];
+          const int64_t zq = szq[v];
+          const int64_t ex = (X20 + zq * U.x) >> 28;
+          const int64_t ey = (Y20 + zq * U.y) >> 28;
+          if ((uint64_t)ex < (uint64_t)a.W && (uint64_t)ey < (uint64_t)a.H) {
+            const uint32_t kk = a.kmap[(size_t)ey * a.W + (size_t)ex];
+            key = 2u * min(kk, (uint32_t)a.kcap);
+            sumk += kk;
+            sumsq += sqrt_q16(kk);
+          } else {
+            key = (uint32_t)a.key_off;
+            ++noff;
+          }
+        }
+        keys[i] = key;
+      }
+    }
+    // level 1: coarse histogram of key >> LB2
+#pragma unroll
+    for (int p = 0; p < P; ++p) hist[lane * P + p] = 0;
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (keys[i] != NOKEY) atomicAdd(&hist[keys[i] >> LB2], 1u);
+    }
+    __syncthreads();
+    int b1 = 0, below1 = 0;
+    if (active) find_bin<P>(hist, lane, a.kmid, &b1, &below1);
+    __syncthreads();
+    // level 2: fine histogram inside the threshold bin
+#pragma unroll
+    for (int p = 0; p < P; ++p) hist[lane * P + p] = 0;
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (keys[i] != NOKEY && (int)(keys[i] >> LB2) == b1)
+          atomicAdd(&hist[keys[i] & (NB - 1)], 1u);
+    }
+    __syncthreads();
+    if (active) {
+      int b2 = 0, below2 = 0;
+      find_bin<P>(hist, lane, a.kmid - below1, &b2, &below2);
+      const uint32_t tkey = ((uint32_t)b1 << LB2) | (uint32_t)b2;
+      const int below = below1 + below2;
+      int64_t sl = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (keys[i] < tkey) sl += a.lut[keys[i]];
+      sl = wave_sum(sl);
+      sumk = wave_sum(sumk);
+      sumsq = wave_sum(sumsq);
+      noff = wave_sum(noff);
+      if (lane == 0) {
+        sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
+        const double Lbar = (double)sl / (67108864.0 * (double)a.kmid);
+        const double Pl = exp(Lbar);
+        const double nv = (double)a.nv;
+        const double sum_d = a.res * ((double)sumsq / 65536.0) + (double)noff * a.d_max;
+        const double sum_d2 = a.res * a.res * (double)sumk + (double)noff * a.d_max * a.d_max;
+        const double dbar = sum_d / nv;
+        double var = sum_d2 / nv - dbar * dbar;
+        if (var < 0.0) var = 0.0;
+        const double dmin = 0.5 * a.res;
+        const double dt = fmin(fmax(dbar, dmin), a.d_max);
+        const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
+        const double c = exp(-0.5 * var);
+        const float T = (float)cbrt(Pl * sd * c);
+        if (a.T_out) a.T_out[(size_t)blockIdx.y * a.Nt + k] = T;
+        const uint64_t packed =
+            ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+        atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int R, int KB>
+hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)2 * a.nv * sizeof(int32_t) +
+                     (size_t)NW * (1 << (KB / 2)) * sizeof(uint32_t);
+  dim3 grid((a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK, a.nb);
+  hipLaunchKernelGGL((tam_kernel<R, KB>), grid, dim3(TB), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_tam_kb(const TamArgs& a, hipStream_t s) {
+  const int R = (a.nv + 63) / 64;
+  if (R <= 4) return launch_tam_t<4, KB>(a, s);
+  if (R <= 8) return launch_tam_t<8, KB>(a, s);
+  if (R <= 16) return launch_tam_t<16, KB>(a, s);
+  if (R <= 32) return launch_tam_t<32, KB>(a, s);
+  if (R <= 64) return launch_tam_t<64, KB>(a, s);
+  return hipErrorInvalidValue;
+}
+
+__global__ void stage_reduce_kernel(StageArgs a) {
+  __shared__ unsigned long long red[TB / 64];
+  unsigned long long best = 0;
+  for (int i = threadIdx.x; i < a.nb; i += TB) {
+    const int r = a.r0 + i;
+    const uint64_t tb = a.best[r] >> 32;
+    const unsigned long long key = (tb << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)r);
+    if (key > best) best = key;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off, 64);
+    if (o > best) best = o;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < TB / 64; ++q)
+      if (red[q] > best) best = red[q];
+    a.stage_out[0] = best;
+    const float T = __uint_as_float((uint32_t)(best >> 32));
+    a.flag_out[0] = ((double)T > a.tau) ? 1 : 0;
+  }
+}
+
+__global__ void fill_u64_kernel(uint64_t* p, uint64_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void rank_keys_kernel(const uint64_t* best, int n, uint64_t* keys) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t tb = (uint32_t)(best[r] >> 32);
+  keys[r] = ((uint64_t)(0xFFFFFFFFu - tb) << 32) | (uint64_t)(uint32_t)r;
+}
+
+__global__ void rank_gather_kernel(const uint64_t* sorted, const uint64_t* best,
+                                   const int32_t* order, const double* smad, int n,
+                                   PoseRow* rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = (int)(uint32_t)(sorted[i] & 0xFFFFFFFFu);
+  const uint64_t b = best[r];
+  PoseRow row;
+  row.rank = r;
+  row.k = (int32_t)(0xFFFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu));
+  row.hyp = order[r];
+  row.tbits = (uint32_t)(b >> 32);
+  row.smad = smad[row.hyp];
+  rows[i] = row;
+}
+
+}  // namespace
+
+hipError_t launch_tam(const TamArgs& a, hipStream_t s) {
+  if (a.nb <= 0) return hipSuccess;
+  if (a.keybits <= 12) return launch_tam_kb<12>(a, s);
+  if (a.keybits <= 16) return launch_tam_kb<16>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(stage_reduce_kernel, dim3(1), dim3(TB), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_keys(const uint64_t* best, int n, uint64_t* keys, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, s, best, n, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_gather(const uint64_t* sorted, const uint64_t* best,
+                              const int32_t* order, const double* smad, int n, PoseRow* rows,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, sorted, best,
+                     order, smad, n, rows);
+  return hipGetLastError();
+}
+
+}  // namespace reloc

@@ -1,0 +1,98 @@
+// Internal declarations shared by the host runtime and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace reloc {
+
+// ---- map residency -------------------------------------------------------
+// Bit-packed occupancy: one uint64 per 8x8-cell tile, tiles row-major
+// (tpr tiles per row); bit ((y & 7) << 3) | (x & 7) of tile (x >> 3, y >> 3).
+hipError_t launch_bitpack(const int8_t* occ, int W, int H, int thr, uint64_t* bits,
+                          int tpr, int tph, hipStream_t s);
+// Exact squared EDT in cells; g is int32 scratch of W*H.
+hipError_t launch_edt(const int8_t* occ, int W, int H, int thr, int32_t* g, uint32_t* k,
+                      hipStream_t s);
+
+// ---- ray cast + SMAD (fused) --------------------------------------------
+struct RayArgs {
+  const uint64_t* bits;
+  int W, H, tpr;
+  const int32_t* hyp_xy;     // [n_hyp][2]
+  int n_hyp;
+  const int2* dirs;          // [Ns] ray directions (Q20 integer vectors)
+  const float2* kap;         // [Ns] metres per Q8 unit along x / y
+  int Ns;
+  float rmax;                // fl32(range_max)
+  int rcells;                // Chebyshev cut-off (result neutral)
+  const int2* runs;          // [n_runs] (start index u, length L) of FoV runs
+  int n_runs;
+  int nfov;                  // N_FoV
+  double zbar;               // measured mean (eq. 16)
+  int n_shifts, n_enum;
+  double* smad;              // [n_hyp]
+  int32_t* argm;             // [n_hyp]
+  uint64_t* keys;            // [n_hyp] sort key = bits of SMAD
+  int32_t* vals;             // [n_hyp] hypothesis index
+  int32_t* dbg_hit;          // optional [n_hyp][Ns]
+  float* dbg_rng;            // optional [n_hyp][Ns]
+  int32_t* dbg_steps;        // optional [n_hyp][Ns] DDA iterations per ray
+};
+hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
+
+// ---- sorting (hipCUB radix sort) -----------------------------------------
+hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
+                              uint64_t* kout, const int32_t* vin, int32_t* vout, int n,
+                              hipStream_t s);
+hipError_t sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
+                         int n, hipStream_t s);
+
+// ---- TAM -----------------------------------------------------------------
+struct TamArgs {
+  const uint32_t* kmap;
+  int W, H;
+  const int32_t* hyp_xy;
+  const int32_t* order;      // hypothesis index per SMAD rank
+  int r0, nb;                // ranks [r0, r0 + nb)
+  const int32_t* beam_base;  // [nv] (b * j_v) mod Ng
+  const int32_t* beam_zq;    // [nv] range in Q8 cells
+  int nv;
+  const int2* dirs;          // [Ng] direction table
+  int Ng, o, Nt;             // o = Ng / Nt
+  const int32_t* lut;        // [n_keys] likelihood per selection key, Q26
+  int kcap, key_off, keybits;
+  int kmid;
+  double res, d_max;
+  float* T_out;              // optional [nb][Nt]
+  uint64_t* best;            // [>= r0 + nb] packed (T bits, ~k) per rank
+};
+hipError_t launch_tam(const TamArgs& a, hipStream_t s);
+
+struct StageArgs {
+  const uint64_t* best;      // per rank
+  int r0, nb;
+  double tau;                // NaN: never stop
+  uint64_t* stage_out;       // [1] packed (T bits, ~rank)
+  int32_t* flag_out;         // [1] 1 = stop
+};
+hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s);
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+
+// rank keys: ((~T bits) << 32 | rank) for ranks [0, n)
+hipError_t launch_rank_keys(const uint64_t* best, int n, uint64_t* keys, hipStream_t s);
+
+struct PoseRow {
+  int32_t rank, k, hyp;
+  uint32_t tbits;
+  double smad;
+};
+// rows[i] for i < n from the sorted rank keys
+hipError_t launch_rank_gather(const uint64_t* sorted, const uint64_t* best,
+                              const int32_t* order, const double* smad, int n, PoseRow* rows,
+                              hipStream_t s);
+
+}  // namespace reloc

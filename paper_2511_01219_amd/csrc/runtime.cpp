@@ -1,0 +1,1089 @@
+// Host runtime of libreloc: context, device memory accounting, map registry,
+// hypothesis sampler, scan preprocessing and the staged relocalization driver.
+// Every arithmetic step of the hot path runs in the HIP kernels; this file
+// prepares their tables and sequences them on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "reloc.h"
+#include "reloc_internal.h"
+
+using namespace reloc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RELOC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+constexpr int kMaxNs = 4096;
+constexpr int kMaxDim = 32768;
+constexpr int kMaxNg = 1 << 20;
+
+// ---- direction table -------------------------------------------------------
+// U[t] for the turn fraction t / Ng reduced to lowest terms p / q:
+// round-half-even(2^20 * (cos a, sin a)), a = (2 pi p) / q in FP64 (libm).
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+std::vector<int2> direction_table(int Ng) {
+  std::vector<int2> U(Ng);
+  for (int t = 0; t < Ng; ++t) {
+    const int64_t g = gcd64(t, Ng);
+    const double a = (2.0 * M_PI * (double)(t / g)) / (double)(Ng / g);
+    U[t].x = (int)std::llrint(std::ldexp(std::cos(a), 20));
+    U[t].y = (int)std::llrint(std::ldexp(std::sin(a), 20));
+  }
+  return U;
+}
+
+// Metres travelled per Q8 unit of progress along axis a for direction (ua, ub).
+float axis_scale(int ua, int ub, double res) {
+  const double n = std::sqrt((double)ua * (double)ua + (double)ub * (double)ub);
+  return (float)(((res / 256.0) * n) / std::fabs((double)ua));
+}
+
+// splitmix64 output function (Steele, Lea & Flood 2014).
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// ---- scan preprocessing (eq. 11-16, 25-26) ---------------------------------
+struct Prep {
+  reloc_scan_info info{};
+  std::vector<int2> runs;         // (panoramic start, length) per FoV run
+  std::vector<int32_t> vj, vzq;   // valid beams: panoramic index, range in Q8 cells
+};
+
+int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double res, Prep* out) {
+  if (!sc || !p) return fail(RELOC_E_INVALID, "null scan or params");
+  if (sc->n_beams <= 0 || !sc->ranges) return fail(RELOC_E_INVALID, "scan has no beams");
+  if (p->n_skip_beam <= 0 || p->n_skip_enum <= 0)
+    return fail(RELOC_E_INVALID, "n_skip_beam and n_skip_enum must be >= 1");
+  if (!(sc->angle_increment > 0) || !std::isfinite(sc->angle_min))
+    return fail(RELOC_E_INVALID, "angle_increment must be > 0");
+  if (!(sc->range_max > 0) || !(sc->range_max < 64.f) || !(sc->range_min >= 0))
+    return fail(RELOC_E_INVALID, "need 0 < range_max < 64 m and range_min >= 0");
+  if (sc->n_fov < 0 || (sc->n_fov > 0 && !sc->fov))
+    return fail(RELOC_E_INVALID, "bad FoV interval list");
+  const double step = sc->angle_increment * (double)p->n_skip_beam;
+  const double turns = (2.0 * M_PI) / step;
+  const int64_t Ns = std::llround(turns);
+  if (Ns < 1 || std::fabs(turns - (double)Ns) > 1e-6 * (double)Ns)
+    return fail(RELOC_E_BEAMGRID, "2*pi / beam step = %.9f is not an integer", turns);
+  if (Ns > kMaxNs) return fail(RELOC_E_INVALID, "Ns = %lld exceeds %d", (long long)Ns, kMaxNs);
+  const double j0r = sc->angle_min / step;
+  const int64_t j0 = std::llround(j0r);
+  if (std::fabs(j0r - (double)j0) > 1e-6 * (double)Ns)
+    return fail(RELOC_E_BEAMGRID, "angle_min is not on the beam grid");
+  const int nd = (sc->n_beams + p->n_skip_beam - 1) / p->n_skip_beam;
+  if (nd > Ns) return fail(RELOC_E_BEAMGRID, "more beams than grid directions");
+  const int64_t Nt = p->n_theta > 0 ? p->n_theta : Ns;
+  const int64_t Ng = Ns / gcd64(Ns, Nt) * Nt;
+  if (Ng > kMaxNg) return fail(RELOC_E_INVALID, "lcm(Ns, n_theta) = %lld too large", (long long)Ng);
+
+  Prep P;
+  int64_t nfov = 0, nvalid = 0;
+  double sum = 0.0;
+  bool prev_in = false;
+  for (int i = 0; i < nd; ++i) {
+    const int src = i * p->n_skip_beam;
+    const double phi = sc->angle_min + (double)src * sc->angle_increment;
+    bool in = sc->n_fov == 0;
+    for (int f = 0; f < sc->n_fov && !in; ++f) in = sc->fov[f].lo <= phi && phi <= sc->fov[f].hi;
+    const int jj = (int)(((j0 + i) % Ns + Ns) % Ns);
+    if (in) {
+      const float z = sc->ranges[src];
+      const bool ok = std::isfinite(z) && z >= sc->range_min && z <= sc->range_max;
+      ++nfov;
+      if (ok) {
+        sum += (double)z;
+        ++nvalid;
+        P.vj.push_back(jj);
+        P.vzq.push_back((int32_t)std::llrint(((double)z * 256.0) / res));
+      } else {
+        sum += 0.0;
+      }
+      if (!prev_in) P.runs.push_back(make_int2(jj, 0));
+      P.runs.back().y += 1;
+    }
+    prev_in = in;
+  }
+  if (nfov == 0) return fail(RELOC_E_EMPTY, "no beam inside the FoV");
+  if (nvalid == 0) return fail(RELOC_E_EMPTY, "no valid beam");
+  const int64_t a0 = p->alpha_mid_pm[0], a1 = p->alpha_mid_pm[1];
+  const int64_t c0 = p->alpha_low_pm[0], c1 = p->alpha_low_pm[1];
+  if (a0 < 1 || a0 > 1000 || a1 < 1 || a1 > 1000 || c0 < 1 || c0 > 1000 || c1 < 1 || c1 > 1000)
+    return fail(RELOC_E_INVALID, "alpha per-mille values must be in [1, 1000]");
+  const int64_t kmid = (nvalid * (a0 * Ns + (a1 - a0) * nfov)) / (1000 * Ns);
+  const int64_t klow = (nvalid * (c0 * Ns + (c1 - c0) * nfov)) / (1000 * Ns);
+  if (kmid < 1 || klow < 1) return fail(RELOC_E_EMPTY, "too few valid beams for TAM");
+  reloc_scan_info& I = P.info;
+  I.Ns = (int)Ns;
+  I.Ntheta = (int)Nt;
+  I.Ng = (int)Ng;
+  I.n_down = nd;
+  I.n_fov = (int)nfov;
+  I.n_valid = (int)nvalid;
+  I.k_full = (int)nvalid;
+  I.k_mid = (int)kmid;
+  I.k_low = (int)klow;
+  I.panoramic = (10 * nfov >= 9 * Ns) ? 1 : 0;
+  I.n_runs = (int)P.runs.size();
+  I.n_shifts = I.panoramic ? 1 : (int)((Ns + p->n_skip_enum - 1) / p->n_skip_enum);
+  I.j0 = (int)(((j0 % Ns) + Ns) % Ns);
+  I.zbar = sum / (double)nfov;
+  I.lambda = (double)nfov / (double)Ns;
+  *out = std::move(P);
+  return RELOC_OK;
+}
+
+// ---- likelihood table for TAM (eq. 23) --------------------------------------
+struct Lut {
+  std::vector<int32_t> q;   // Q26 likelihood per selection key
+  int kcap = 1, key_off = 2, keybits = 12;
+};
+
+int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
+  const double zh = p->z_hit, sg = p->sigma_hit, zr = p->z_rand, dm = p->d_max;
+  if (!(zh >= 0 && zh <= 1e6) || !(sg > 0) || !(zr >= 0 && zr <= 1e6) || !(dm > res / 2.0))
+    return fail(RELOC_E_INVALID, "need z_hit, z_rand in [0, 1e6], sigma_hit > 0, d_max > res/2");
+  auto ell = [&](double d) { return std::log(zh * std::exp(-(d * d) / (2.0 * sg * sg)) + zr + 1e-6); };
+  // smallest k where l(k) is within 1e-10 of its limit ln(z_rand + 1e-6)
+  double need = 1.0;
+  if (zh > 0) need = std::ceil((2.0 * sg * sg) / (res * res) * std::log(zh / (1e-10 * (zr + 1e-6))));
+  int kcap = (int)std::min(32767.0, std::max(1.0, need));
+  L->kcap = kcap;
+  L->keybits = (2 * kcap + 2 <= 4096) ? 12 : 16;
+  const int nk = 1 << L->keybits;
+  L->q.assign(nk, 0);
+  for (int k = 0; k <= kcap; ++k) {
+    const double v = ell(std::sqrt((double)k) * res);
+    L->q[2 * k] = (int32_t)std::llrint(v * 67108864.0);
+    if (2 * k + 1 < nk) L->q[2 * k + 1] = L->q[2 * k];
+  }
+  const double koff = (dm / res) * (dm / res);
+  if (koff >= (double)kcap) {
+    L->key_off = 2 * kcap;
+  } else {
+    const int fk = (int)std::floor(koff);
+    L->key_off = 2 * fk + 1;
+    L->q[L->key_off] = (int32_t)std::llrint(ell(dm) * 67108864.0);
+  }
+  return RELOC_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+struct DevMap {
+  int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
+  double res = 0.05, ox = 0, oy = 0;
+  uint64_t* bits = nullptr;
+  uint32_t* kmap = nullptr;
+  std::vector<int8_t> occ;        // host copy for the sampler
+  std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
+  int n_sets = 0;
+};
+
+struct HypSet {
+  int map_id = -1;
+  int n = 0;
+  int32_t* dev = nullptr;         // [n][2]
+  std::vector<int32_t> host;
+};
+
+struct Request {
+  int map_id = -1, set_id = -1, n_hyp = 0;
+  Prep prep;
+  reloc_search_params prm{};
+  float rmax = 0.f;
+  int rcells = 0;
+  Lut lut;
+  // device tables
+  int2* raydirs = nullptr;
+  float2* kap = nullptr;
+  int2* runs = nullptr;
+  int32_t* base = nullptr;
+  int32_t* zq = nullptr;
+  int2* dirs = nullptr;
+  int32_t* dlut = nullptr;
+  // device work
+  double* smad = nullptr;
+  int32_t* argm = nullptr;
+  uint64_t* keys = nullptr;
+  uint64_t* keys2 = nullptr;
+  int32_t* vals = nullptr;
+  int32_t* order = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  uint64_t* best = nullptr;
+  uint64_t* stage = nullptr;
+  int32_t* flag = nullptr;
+  PoseRow* rows = nullptr;
+  int rows_cap = 0;
+  std::vector<void*> owned;
+};
+
+struct reloc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  reloc_allocator alloc{};
+  bool has_alloc = false;
+  size_t budget = 0, used = 0;
+  std::map<void*, size_t> sizes;
+  std::recursive_mutex mu;
+  std::map<int, DevMap> maps;
+  std::map<int, HypSet> sets;
+  std::map<int, Request> reqs;
+  int next_id = 1;
+  hipEvent_t ev[6] = {};
+  void* pinned = nullptr;         // small pinned staging buffer
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (used + bytes > budget) {
+      fail(RELOC_E_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu", used, bytes,
+           budget);
+      return nullptr;
+    }
+    void* p = nullptr;
+    if (has_alloc) {
+      p = alloc.alloc(bytes, alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (!p) {
+      fail(RELOC_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+      return nullptr;
+    }
+    sizes[p] = bytes;
+    used += bytes;
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = sizes.find(p);
+    if (it == sizes.end()) return;
+    used -= it->second;
+    sizes.erase(it);
+    if (has_alloc)
+      alloc.free(p, alloc.user);
+    else
+      (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int32_t set_device(reloc_ctx* c) {
+  HIP_TRY(hipSetDevice(c->device));
+  return RELOC_OK;
+}
+
+void release_request(reloc_ctx* c, Request& r) {
+  for (void* p : r.owned) c->dfree(p);
+  r.owned.clear();
+}
+
+template <typename T>
+T* req_alloc(reloc_ctx* c, Request& r, size_t count) {
+  void* p = c->dalloc(count * sizeof(T));
+  if (p) r.owned.push_back(p);
+  return (T*)p;
+}
+
+template <typename T>
+int32_t upload(reloc_ctx* c, T* dst, const T* src, size_t count) {
+  if (count == 0) return RELOC_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return RELOC_OK;
+}
+
+int32_t ensure_khost(reloc_ctx* c, DevMap& m) {
+  if (!m.khost.empty()) return RELOC_OK;
+  m.khost.resize((size_t)m.W * m.H);
+  HIP_TRY(hipMemcpyAsync(m.khost.data(), m.kmap, m.khost.size() * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return RELOC_OK;
+}
+
+// Deterministic integer sampler (documented in reloc.h). Component search by
+// breadth-first flood fill; the visiting order is produced chunk by chunk
+// with nth_element; spacing is checked in a bucket grid of side
+// ceil(sqrt(S)) cells, so only the 3 x 3 neighbouring buckets can conflict.
+int32_t sample_cells(const DevMap& m, const reloc_sample_params* p, std::vector<int32_t>* out) {
+  const int W = m.W, H = m.H;
+  const double qr = p->robot_radius / m.res, qs = p->min_spacing / m.res;
+  const int64_t Kr = (int64_t)std::ceil(qr * qr - 1e-9);
+  const int64_t S = (int64_t)std::ceil(qs * qs - 1e-9);
+  const int64_t N = (int64_t)W * H;
+  std::vector<uint8_t> feas(N);
+  for (int64_t c = 0; c < N; ++c) {
+    const int8_t v = m.occ[c];
+    feas[c] = (v >= 0 && (int)v < m.thr && (int64_t)m.khost[c] >= Kr) ? 1 : 0;
+  }
+  std::vector<int32_t> label(N, -1);
+  std::vector<int64_t> queue;
+  auto flood = [&](int64_t s, int id, std::vector<int64_t>* cells) -> int64_t {
+    queue.clear();
+    queue.push_back(s);
+    label[s] = id;
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+      const int64_t c = queue[qi];
+      const int x = (int)(c % W), y = (int)(c / W);
+      if (x > 0 && feas[c - 1] && label[c - 1] < 0) { label[c - 1] = id; queue.push_back(c - 1); }
+      if (x + 1 < W && feas[c + 1] && label[c + 1] < 0) { label[c + 1] = id; queue.push_back(c + 1); }
+      if (y > 0 && feas[c - W] && label[c - W] < 0) { label[c - W] = id; queue.push_back(c - W); }
+      if (y + 1 < H && feas[c + W] && label[c + W] < 0) { label[c + W] = id; queue.push_back(c + W); }
+    }
+    if (cells) *cells = queue;
+    return (int64_t)queue.size();
+  };
+  std::vector<int64_t> region;
+  if (p->has_p0) {
+    const double fx = std::floor((p->p0_x - m.ox) / m.res), fy = std::floor((p->p0_y - m.oy) / m.res);
+    if (!(fx >= 0 && fx < W && fy >= 0 && fy < H))
+      return fail(RELOC_E_EMPTY, "p0 lies outside the map");
+    const int64_t s = (int64_t)fy * W + (int64_t)fx;
+    if (!feas[s]) return fail(RELOC_E_EMPTY, "p0 is not a feasible cell");
+    flood(s, 0, &region);
+  } else {
+    int64_t best_n = 0, best_seed = -1;
+    int id = 0;
+    for (int64_t c = 0; c < N; ++c)
+      if (feas[c] && label[c] < 0) {
+        const int64_t n = flood(c, id++, nullptr);
+        if (n > best_n) { best_n = n; best_seed = c; }
+      }
+    if (best_seed < 0) return fail(RELOC_E_EMPTY, "map has no feasible cell");
+    const int bid = label[best_seed];
+    region.reserve(best_n);
+    for (int64_t c = 0; c < N; ++c)
+      if (label[c] == bid) region.push_back(c);
+  }
+  std::vector<std::pair<uint64_t, int64_t>> cand(region.size());
+  for (size_t i = 0; i < region.size(); ++i)
+    cand[i] = {splitmix64(p->seed + (uint64_t)region[i]), region[i]};
+  const int side = std::max<int>(1, (int)std::ceil(std::sqrt((double)S)));
+  const int bw = (W + side - 1) / side, bh = (H + side - 1) / side;
+  std::vector<std::vector<int32_t>> bucket((size_t)bw * bh);
+  out->clear();
+  size_t lo = 0;
+  const size_t chunk = std::max<size_t>(65536, 8 * (size_t)p->n_target);
+  while (lo < cand.size() && (int)(out->size() / 2) < p->n_target) {
+    const size_t hi = std::min(cand.size(), lo + chunk);
+    if (hi < cand.size())
+      std::nth_element(cand.begin() + lo, cand.begin() + hi, cand.end());
+    std::sort(cand.begin() + lo, cand.begin() + hi);
+    for (size_t i = lo; i < hi && (int)(out->size() / 2) < p->n_target; ++i) {
+      const int64_t c = cand[i].second;
+      const int x = (int)(c % W), y = (int)(c / W);
+      const int bx = x / side, by = y / side;
+      bool ok = true;
+      for (int yy = std::max(0, by - 1); yy <= std::min(bh - 1, by + 1) && ok; ++yy)
+        for (int xx = std::max(0, bx - 1); xx <= std::min(bw - 1, bx + 1) && ok; ++xx)
+          for (int32_t q : bucket[(size_t)yy * bw + xx]) {
+            const int64_t dx = x - (*out)[2 * q], dy = y - (*out)[2 * q + 1];
+            if (dx * dx + dy * dy < S) { ok = false; break; }
+          }
+      if (!ok) continue;
+      bucket[(size_t)by * bw + bx].push_back((int32_t)(out->size() / 2));
+      out->push_back(x);
+      out->push_back(y);
+    }
+    lo = hi;
+  }
+  return RELOC_OK;
+}
+
+int32_t new_set(reloc_ctx* c, int map_id, std::vector<int32_t>&& xy, int32_t* set_id) {
+  HypSet hs;
+  hs.map_id = map_id;
+  hs.n = (int)(xy.size() / 2);
+  hs.host = std::move(xy);
+  hs.dev = (int32_t*)c->dalloc(std::max<size_t>(1, hs.host.size()) * sizeof(int32_t));
+  if (!hs.dev) return RELOC_E_NOMEM;
+  if (int32_t e = upload(c, hs.dev, hs.host.data(), hs.host.size())) {
+    c->dfree(hs.dev);
+    return e;
+  }
+  const int id = c->next_id++;
+  c->maps[map_id].n_sets += 1;
+  c->sets[id] = std::move(hs);
+  *set_id = id;
+  return RELOC_OK;
+}
+
+// Builds the request's device tables and work buffers.
+int32_t build_request(reloc_ctx* c, Request& R) {
+  DevMap& m = c->maps[R.map_id];
+  const reloc_scan_info& I = R.prep.info;
+  const int Ns = I.Ns, Ng = I.Ng, b = Ng / Ns;
+  const std::vector<int2> U = direction_table(Ng);
+  std::vector<int2> rd(Ns);
+  std::vector<float2> kp(Ns);
+  for (int j = 0; j < Ns; ++j) {
+    rd[j] = U[(size_t)j * b];
+    kp[j].x = rd[j].x ? axis_scale(rd[j].x, rd[j].y, m.res) : 0.f;
+    kp[j].y = rd[j].y ? axis_scale(rd[j].y, rd[j].x, m.res) : 0.f;
+  }
+  std::vector<int32_t> base(R.prep.vj.size());
+  for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
+  if (int32_t e = build_lut(&R.prm, m.res, &R.lut)) return e;
+  const int n = R.n_hyp, nv = I.n_valid;
+  R.raydirs = req_alloc<int2>(c, R, Ns);
+  R.kap = req_alloc<float2>(c, R, Ns);
+  R.runs = req_alloc<int2>(c, R, R.prep.runs.size());
+  R.base = req_alloc<int32_t>(c, R, nv);
+  R.zq = req_alloc<int32_t>(c, R, nv);
+  R.dirs = req_alloc<int2>(c, R, Ng);
+  R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
+  R.smad = req_alloc<double>(c, R, n);
+  R.argm = req_alloc<int32_t>(c, R, n);
+  R.keys = req_alloc<uint64_t>(c, R, n);
+  R.keys2 = req_alloc<uint64_t>(c, R, n);
+  R.vals = req_alloc<int32_t>(c, R, n);
+  R.order = req_alloc<int32_t>(c, R, n);
+  R.best = req_alloc<uint64_t>(c, R, n);
+  const int max_stages = (n + R.prm.batch_k - 1) / R.prm.batch_k;
+  R.stage = req_alloc<uint64_t>(c, R, max_stages);
+  R.flag = req_alloc<int32_t>(c, R, max_stages);
+  R.rows_cap = std::max(1, std::min(n, R.prm.k_out));
+  R.rows = req_alloc<PoseRow>(c, R, R.rows_cap);
+  for (void* p : R.owned)
+    if (!p) return RELOC_E_NOMEM;
+  size_t t1 = 0, t2 = 0;
+  HIP_TRY(sort_pairs_u64_i32(nullptr, &t1, R.keys, R.keys2, R.vals, R.order, n, c->stream));
+  HIP_TRY(sort_keys_u64(nullptr, &t2, R.keys, R.keys2, n, c->stream));
+  R.tmp_bytes = std::max<size_t>(16, std::max(t1, t2));
+  R.tmp = req_alloc<uint8_t>(c, R, R.tmp_bytes);
+  if (!R.tmp) return RELOC_E_NOMEM;
+  if (int32_t e = upload(c, R.raydirs, rd.data(), rd.size())) return e;
+  if (int32_t e = upload(c, R.kap, kp.data(), kp.size())) return e;
+  if (int32_t e = upload(c, R.runs, R.prep.runs.data(), R.prep.runs.size())) return e;
+  if (int32_t e = upload(c, R.base, base.data(), base.size())) return e;
+  if (int32_t e = upload(c, R.zq, R.prep.vzq.data(), R.prep.vzq.size())) return e;
+  if (int32_t e = upload(c, R.dirs, U.data(), U.size())) return e;
+  if (int32_t e = upload(c, R.dlut, R.lut.q.data(), R.lut.q.size())) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  return RELOC_OK;
+}
+
+RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, float* dbg_rng) {
+  DevMap& m = c->maps[R.map_id];
+  const reloc_scan_info& I = R.prep.info;
+  RayArgs a;
+  a.bits = m.bits;
+  a.W = m.W;
+  a.H = m.H;
+  a.tpr = m.tpr;
+  a.hyp_xy = c->sets[R.set_id].dev;
+  a.n_hyp = R.n_hyp;
+  a.dirs = R.raydirs;
+  a.kap = R.kap;
+  a.Ns = I.Ns;
+  a.rmax = R.rmax;
+  a.rcells = R.rcells;
+  a.runs = R.runs;
+  a.n_runs = I.n_runs;
+  a.nfov = I.n_fov;
+  a.zbar = I.zbar;
+  a.n_shifts = I.n_shifts;
+  a.n_enum = R.prm.n_skip_enum;
+  a.smad = R.smad;
+  a.argm = R.argm;
+  a.keys = R.keys;
+  a.vals = R.vals;
+  a.dbg_hit = dbg_hit;
+  a.dbg_rng = dbg_rng;
+  a.dbg_steps = nullptr;
+  return a;
+}
+
+TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
+  DevMap& m = c->maps[R.map_id];
+  const reloc_scan_info& I = R.prep.info;
+  TamArgs a;
+  a.kmap = m.kmap;
+  a.W = m.W;
+  a.H = m.H;
+  a.hyp_xy = c->sets[R.set_id].dev;
+  a.order = R.order;
+  a.r0 = r0;
+  a.nb = nb;
+  a.beam_base = R.base;
+  a.beam_zq = R.zq;
+  a.nv = I.n_valid;
+  a.dirs = R.dirs;
+  a.Ng = I.Ng;
+  a.o = I.Ng / I.Ntheta;
+  a.Nt = I.Ntheta;
+  a.lut = R.dlut;
+  a.kcap = R.lut.kcap;
+  a.key_off = R.lut.key_off;
+  a.keybits = R.lut.keybits;
+  a.kmid = I.k_mid;
+  a.res = m.res;
+  a.d_max = R.prm.d_max;
+  a.T_out = T_out;
+  a.best = R.best;
+  return a;
+}
+
+// ray cast + SMAD for all hypotheses, then the stable SMAD order
+int32_t run_smad_order(reloc_ctx* c, Request& R) {
+  HIP_TRY(launch_raycast_smad(ray_args(c, R, nullptr, nullptr), c->stream));
+  size_t tb = R.tmp_bytes;
+  HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, c->stream));
+  return RELOC_OK;
+}
+
+int32_t validate_search(const reloc_search_params* p) {
+  if (!p) return fail(RELOC_E_INVALID, "null search params");
+  if (p->batch_k <= 0) return fail(RELOC_E_INVALID, "batch_k must be >= 1");
+  if (p->k_out <= 0) return fail(RELOC_E_INVALID, "k_out must be >= 1");
+  if (p->n_theta < 0 || p->n_hyp < 0) return fail(RELOC_E_INVALID, "negative n_theta / n_hyp");
+  return RELOC_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int32_t reloc_version(void) { return RELOC_VERSION; }
+
+const char* reloc_last_error(void) { return g_err.c_str(); }
+
+void reloc_search_defaults(reloc_search_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->n_theta = 0;
+  p->n_skip_beam = 1;
+  p->n_skip_enum = 1;
+  p->batch_k = 64;
+  p->k_out = 10;
+  p->tau = 0.95;
+  p->n_hyp = 0;
+  p->z_hit = 1.0;
+  p->sigma_hit = 0.2;
+  p->z_rand = 0.0;
+  p->d_max = 2.0;
+  p->alpha_mid_pm[0] = 900;
+  p->alpha_mid_pm[1] = 700;
+  p->alpha_low_pm[0] = 700;
+  p->alpha_low_pm[1] = 500;
+  p->deadline_s = 0.0;
+}
+
+int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
+                         size_t hbm_budget, reloc_ctx** out) {
+  if (!out) return fail(RELOC_E_INVALID, "null out");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(RELOC_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= n) return fail(RELOC_E_DEVICE, "device %d out of range", device);
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(RELOC_E_INVALID, "allocator needs both alloc and free");
+  std::unique_ptr<reloc_ctx> c(new reloc_ctx());
+  c->device = device;
+  HIP_TRY(hipSetDevice(device));
+  if (alloc) {
+    c->alloc = *alloc;
+    c->has_alloc = true;
+  }
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  size_t fr = 0, tot = 0;
+  HIP_TRY(hipMemGetInfo(&fr, &tot));
+  c->budget = hbm_budget ? hbm_budget : fr;
+  for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+  HIP_TRY(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
+  *out = c.release();
+  return RELOC_OK;
+}
+
+void reloc_ctx_destroy(reloc_ctx* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->reqs) release_request(c, kv.second);
+    for (auto& kv : c->sets) c->dfree(kv.second.dev);
+    for (auto& kv : c->maps) {
+      c->dfree(kv.second.bits);
+      c->dfree(kv.second.kmap);
+    }
+    c->reqs.clear();
+    c->sets.clear();
+    c->maps.clear();
+    for (auto& e : c->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+size_t reloc_ctx_bytes(const reloc_ctx* c) { return c ? c->used : 0; }
+
+int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
+                       int32_t* map_id) {
+  if (!c || !d || !occ || !map_id) return fail(RELOC_E_INVALID, "null argument");
+  *map_id = -1;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (d->width < 1 || d->height < 1 || d->width > kMaxDim || d->height > kMaxDim)
+    return fail(RELOC_E_INVALID, "map size %dx%d outside 1..%d", d->width, d->height, kMaxDim);
+  if (!(d->resolution >= 1.0 / 32.0) || !(d->resolution <= 100.0))
+    return fail(RELOC_E_INVALID, "resolution must be in [1/32, 100] m");
+  if (!std::isfinite(d->origin_x) || !std::isfinite(d->origin_y))
+    return fail(RELOC_E_INVALID, "origin must be finite");
+  const size_t N = (size_t)d->width * d->height;
+  bool any = false;
+  for (size_t i = 0; i < N && !any; ++i) any = (int)occ[i] >= d->occ_threshold;
+  if (!any) return fail(RELOC_E_EMPTY, "map has no occupied cell");
+  if (int32_t e = set_device(c)) return e;
+  DevMap m;
+  m.W = d->width;
+  m.H = d->height;
+  m.thr = d->occ_threshold;
+  m.res = d->resolution;
+  m.ox = d->origin_x;
+  m.oy = d->origin_y;
+  m.tpr = (m.W + 7) / 8;
+  m.tph = (m.H + 7) / 8;
+  m.occ.assign(occ, occ + N);
+  int8_t* docc = (int8_t*)c->dalloc(N);
+  int32_t* g = (int32_t*)c->dalloc(N * sizeof(int32_t));
+  m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
+  m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
+  auto cleanup = [&]() {
+    c->dfree(docc);
+    c->dfree(g);
+  };
+  if (!docc || !g || !m.bits || !m.kmap) {
+    cleanup();
+    c->dfree(m.bits);
+    c->dfree(m.kmap);
+    return RELOC_E_NOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(docc, occ, N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_bitpack(docc, m.W, m.H, m.thr, m.bits, m.tpr, m.tph, c->stream);
+  if (e == hipSuccess) e = launch_edt(docc, m.W, m.H, m.thr, g, m.kmap, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) {
+    c->dfree(m.bits);
+    c->dfree(m.kmap);
+    return fail(RELOC_E_DEVICE, "map upload failed: %s", hipGetErrorString(e));
+  }
+  const int id = c->next_id++;
+  c->maps[id] = std::move(m);
+  *map_id = id;
+  return RELOC_OK;
+}
+
+int32_t reloc_unload_map(reloc_ctx* c, int32_t map_id) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->maps.find(map_id);
+  if (it == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  if (it->second.n_sets > 0) return fail(RELOC_E_BUSY, "map %d has live hypothesis sets", map_id);
+  (void)hipStreamSynchronize(c->stream);
+  c->dfree(it->second.bits);
+  c->dfree(it->second.kmap);
+  c->maps.erase(it);
+  return RELOC_OK;
+}
+
+int32_t reloc_read_edt(reloc_ctx* c, int32_t map_id, uint32_t* k_out) {
+  if (!c || !k_out) return fail(RELOC_E_INVALID, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->maps.find(map_id);
+  if (it == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  if (int32_t e = set_device(c)) return e;
+  DevMap& m = it->second;
+  HIP_TRY(hipMemcpyAsync(k_out, m.kmap, (size_t)m.W * m.H * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return RELOC_OK;
+}
+
+int32_t reloc_sample_hypotheses(reloc_ctx* c, int32_t map_id, const reloc_sample_params* p,
+                                int32_t* set_id, int32_t* n_out) {
+  if (!c || !p || !set_id || !n_out) return fail(RELOC_E_INVALID, "null argument");
+  *n_out = 0;
+  *set_id = -1;
+  if (p->n_target < 1) return fail(RELOC_E_INVALID, "n_target must be >= 1");
+  if (!(p->min_spacing >= 0) || !(p->robot_radius >= 0))
+    return fail(RELOC_E_INVALID, "min_spacing and robot_radius must be >= 0");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->maps.find(map_id);
+  if (it == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  if (int32_t e = set_device(c)) return e;
+  DevMap& m = it->second;
+  if (int32_t e = ensure_khost(c, m)) return e;
+  std::vector<int32_t> xy;
+  if (int32_t e = sample_cells(m, p, &xy)) return e;
+  if (xy.empty()) return fail(RELOC_E_EMPTY, "no feasible hypothesis");
+  const int n = (int)(xy.size() / 2);
+  if (int32_t e = new_set(c, map_id, std::move(xy), set_id)) return e;
+  *n_out = n;
+  return RELOC_OK;
+}
+
+int32_t reloc_set_hypotheses(reloc_ctx* c, int32_t map_id, const int32_t* cell_xy, int32_t n,
+                             int32_t* set_id) {
+  if (!c || !cell_xy || !set_id) return fail(RELOC_E_INVALID, "null argument");
+  *set_id = -1;
+  if (n < 1) return fail(RELOC_E_INVALID, "empty hypothesis set");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->maps.find(map_id);
+  if (it == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  const DevMap& m = it->second;
+  for (int i = 0; i < n; ++i) {
+    const int x = cell_xy[2 * i], y = cell_xy[2 * i + 1];
+    if (x < 0 || x >= m.W || y < 0 || y >= m.H)
+      return fail(RELOC_E_INVALID, "hypothesis %d (%d, %d) outside the map", i, x, y);
+    const int8_t v = m.occ[(size_t)y * m.W + x];
+    if (v < 0 || (int)v >= m.thr)
+      return fail(RELOC_E_INVALID, "hypothesis %d (%d, %d) is not a free cell", i, x, y);
+  }
+  if (int32_t e = set_device(c)) return e;
+  return new_set(c, map_id, std::vector<int32_t>(cell_xy, cell_xy + 2 * (size_t)n), set_id);
+}
+
+int32_t reloc_read_hypotheses(reloc_ctx* c, int32_t set_id, int32_t* cell_xy, int32_t cap,
+                              int32_t* n_out) {
+  if (!c || !n_out) return fail(RELOC_E_INVALID, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->sets.find(set_id);
+  if (it == c->sets.end()) {
+    *n_out = 0;
+    return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
+  }
+  const HypSet& s = it->second;
+  if (cell_xy && cap > 0)
+    std::memcpy(cell_xy, s.host.data(), (size_t)std::min(cap, s.n) * 2 * sizeof(int32_t));
+  *n_out = s.n;
+  return RELOC_OK;
+}
+
+int32_t reloc_free_hypotheses(reloc_ctx* c, int32_t set_id) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->sets.find(set_id);
+  if (it == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
+  for (auto& kv : c->reqs)
+    if (kv.second.set_id == set_id) return fail(RELOC_E_BUSY, "set %d used by a request", set_id);
+  (void)hipStreamSynchronize(c->stream);
+  c->dfree(it->second.dev);
+  c->maps[it->second.map_id].n_sets -= 1;
+  c->sets.erase(it);
+  return RELOC_OK;
+}
+
+int32_t reloc_scan_info_get(const reloc_scan* scan, const reloc_search_params* params,
+                            double resolution, reloc_scan_info* out) {
+  if (!out) return fail(RELOC_E_INVALID, "null out");
+  std::memset(out, 0, sizeof *out);
+  if (!(resolution >= 1.0 / 32.0)) return fail(RELOC_E_INVALID, "resolution must be >= 1/32 m");
+  if (int32_t e = validate_search(params)) return e;
+  Prep P;
+  if (int32_t e = preprocess(scan, params, resolution, &P)) return e;
+  *out = P.info;
+  return RELOC_OK;
+}
+
+int32_t reloc_prepare(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                      const reloc_search_params* params, int32_t* request_id) {
+  if (!c || !request_id) return fail(RELOC_E_INVALID, "null argument");
+  *request_id = -1;
+  if (int32_t e = validate_search(params)) return e;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto mi = c->maps.find(map_id);
+  if (mi == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  auto si = c->sets.find(set_id);
+  if (si == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
+  if (si->second.map_id != map_id)
+    return fail(RELOC_E_INVALID, "set %d belongs to another map", set_id);
+  if (int32_t e = set_device(c)) return e;
+  Request R;
+  R.map_id = map_id;
+  R.set_id = set_id;
+  R.prm = *params;
+  R.n_hyp = params->n_hyp > 0 ? std::min(params->n_hyp, si->second.n) : si->second.n;
+  if (int32_t e = preprocess(scan, params, mi->second.res, &R.prep)) return e;
+  R.rmax = scan->range_max;
+  R.rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
+  if (int32_t e = build_request(c, R)) {
+    release_request(c, R);
+    return e;
+  }
+  const int id = c->next_id++;
+  c->reqs[id] = std::move(R);
+  *request_id = id;
+  return RELOC_OK;
+}
+
+int32_t reloc_release(reloc_ctx* c, int32_t request_id) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  (void)hipStreamSynchronize(c->stream);
+  release_request(c, it->second);
+  c->reqs.erase(it);
+  return RELOC_OK;
+}
+
+int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap,
+                  int32_t* n_out, reloc_stats* st) {
+  if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
+  *n_out = 0;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  if (int32_t e = set_device(c)) return e;
+  Request& R = it->second;
+  const reloc_scan_info& I = R.prep.info;
+  const DevMap& m = c->maps[R.map_id];
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = c->stream;
+  HIP_TRY(hipEventRecord(c->ev[0], s));
+  HIP_TRY(launch_raycast_smad(ray_args(c, R, nullptr, nullptr), s));
+  HIP_TRY(hipEventRecord(c->ev[1], s));
+  size_t tb = R.tmp_bytes;
+  HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, s));
+  HIP_TRY(launch_fill_u64(R.best, 0, (size_t)R.n_hyp, s));
+  HIP_TRY(hipEventRecord(c->ev[2], s));
+  const int K = R.prm.batch_k;
+  int stages = 0, stopped = 0, n_eval = 0;
+  int32_t status = RELOC_OK;
+  int32_t* hflag = (int32_t*)c->pinned;
+  for (int r0 = 0; r0 < R.n_hyp; r0 += K) {
+    const int nb = std::min(K, R.n_hyp - r0);
+    HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
+    StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stages, R.flag + stages};
+    HIP_TRY(launch_stage_reduce(sa, s));
+    HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ++stages;
+    n_eval = r0 + nb;
+    if (*hflag) {
+      stopped = 1;
+      break;
+    }
+    if (R.prm.deadline_s > 0) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      if (el > R.prm.deadline_s && n_eval < R.n_hyp) {
+        status = fail(RELOC_E_TIMEOUT, "deadline of %.3f s passed after %d stages", R.prm.deadline_s, stages);
+        break;
+      }
+    }
+  }
+  HIP_TRY(hipEventRecord(c->ev[3], s));
+  HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
+  tb = R.tmp_bytes;
+  HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
+  const int nrow = std::min(std::min(R.rows_cap, n_eval), std::max(0, cap));
+  HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, nrow, R.rows, s));
+  std::vector<PoseRow> rows(nrow);
+  if (nrow > 0)
+    HIP_TRY(hipMemcpyAsync(rows.data(), R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(c->ev[4], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const HypSet& hs = c->sets[R.set_id];
+  for (int i = 0; i < nrow; ++i) {
+    const PoseRow& w = rows[i];
+    reloc_pose& p = out[i];
+    const int ix = hs.host[2 * w.hyp], iy = hs.host[2 * w.hyp + 1];
+    p.x = m.ox + ((double)ix + 0.5) * m.res;
+    p.y = m.oy + ((double)iy + 0.5) * m.res;
+    double th = (2.0 * M_PI * (double)w.k) / (double)I.Ntheta;
+    if (th >= M_PI) th -= 2.0 * M_PI;
+    p.theta = th;
+    uint32_t tb32 = w.tbits;
+    std::memcpy(&p.tam, &tb32, sizeof(float));
+    p.smad = (float)w.smad;
+    p.hyp = w.hyp;
+    p.k = w.k;
+    p.rank = w.rank;
+    p.stage = w.rank / K;
+  }
+  *n_out = nrow;
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->n_hyp = R.n_hyp;
+    st->smad_evals = (int64_t)R.n_hyp * I.n_shifts;
+    st->tam_evals = (int64_t)n_eval * I.Ntheta;
+    st->rays = (int64_t)R.n_hyp * I.Ns;
+    st->tam_lookups = st->tam_evals * I.n_valid;
+    st->stages = stages;
+    st->early_stopped = stopped;
+    st->n_eval = n_eval;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[4]);
+    st->ms_total = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    st->ms_raycast = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+    st->ms_sort = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
+    st->ms_tam = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[3], c->ev[4]);
+    st->ms_rank = ms;
+  }
+  return status;
+}
+
+int32_t reloc_relocalize(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                         const reloc_search_params* params, reloc_pose* out, int32_t cap,
+                         int32_t* n_out, reloc_stats* st) {
+  if (n_out) *n_out = 0;
+  int32_t rid = -1;
+  if (int32_t e = reloc_prepare(c, map_id, set_id, scan, params, &rid)) return e;
+  const int32_t e = reloc_run(c, rid, out, cap, n_out, st);
+  const std::string msg = g_err;
+  reloc_release(c, rid);
+  g_err = msg;
+  return e;
+}
+
+int32_t reloc_debug_raycast(reloc_ctx* c, int32_t request_id, int32_t* hit_cell, float* range,
+                            int32_t* steps) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  if (int32_t e = set_device(c)) return e;
+  Request& R = it->second;
+  const size_t n = (size_t)R.n_hyp * R.prep.info.Ns;
+  int32_t* dh = (int32_t*)c->dalloc(n * sizeof(int32_t));
+  float* dr = (float*)c->dalloc(n * sizeof(float));
+  int32_t* ds = steps ? (int32_t*)c->dalloc(n * sizeof(int32_t)) : nullptr;
+  if (!dh || !dr || (steps && !ds)) {
+    c->dfree(dh);
+    c->dfree(dr);
+    c->dfree(ds);
+    return RELOC_E_NOMEM;
+  }
+  RayArgs ra = ray_args(c, R, dh, dr);
+  ra.dbg_steps = ds;
+  hipError_t e = launch_raycast_smad(ra, c->stream);
+  if (e == hipSuccess && hit_cell)
+    e = hipMemcpyAsync(hit_cell, dh, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && range)
+    e = hipMemcpyAsync(range, dr, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && steps)
+    e = hipMemcpyAsync(steps, ds, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->dfree(dh);
+  c->dfree(dr);
+  c->dfree(ds);
+  if (e != hipSuccess) return fail(RELOC_E_DEVICE, "debug ray cast failed: %s", hipGetErrorString(e));
+  return RELOC_OK;
+}
+
+int32_t reloc_debug_smad(reloc_ctx* c, int32_t request_id, double* smad, int32_t* argmin,
+                         int32_t* order) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  if (int32_t e = set_device(c)) return e;
+  Request& R = it->second;
+  if (int32_t e = run_smad_order(c, R)) return e;
+  const size_t n = (size_t)R.n_hyp;
+  if (smad) HIP_TRY(hipMemcpyAsync(smad, R.smad, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (argmin) HIP_TRY(hipMemcpyAsync(argmin, R.argm, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  if (order) HIP_TRY(hipMemcpyAsync(order, R.order, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return RELOC_OK;
+}
+
+int32_t reloc_debug_tam(reloc_ctx* c, int32_t request_id, int32_t r0, int32_t n, float* T,
+                        float* tstar, int32_t* kstar) {
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  Request& R = it->second;
+  if (r0 < 0 || n < 1 || r0 + n > R.n_hyp) return fail(RELOC_E_INVALID, "rank range out of bounds");
+  if (int32_t e = set_device(c)) return e;
+  if (int32_t e = run_smad_order(c, R)) return e;
+  const int Nt = R.prep.info.Ntheta;
+  float* dT = nullptr;
+  if (T) {
+    dT = (float*)c->dalloc((size_t)n * Nt * sizeof(float));
+    if (!dT) return RELOC_E_NOMEM;
+  }
+  std::vector<uint64_t> best(n);
+  hipError_t e = launch_fill_u64(R.best + r0, 0, (size_t)n, c->stream);
+  // TAM launches cover at most batch_k ranks each, like the staged path
+  for (int q = 0; q < n && e == hipSuccess; q += R.prm.batch_k) {
+    const int nb = std::min(R.prm.batch_k, n - q);
+    e = launch_tam(tam_args(c, R, r0 + q, nb, dT ? dT + (size_t)q * Nt : nullptr), c->stream);
+  }
+  if (e == hipSuccess && T)
+    e = hipMemcpyAsync(T, dT, (size_t)n * Nt * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(best.data(), R.best + r0, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->dfree(dT);
+  if (e != hipSuccess) return fail(RELOC_E_DEVICE, "debug TAM failed: %s", hipGetErrorString(e));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t tb32 = (uint32_t)(best[i] >> 32);
+    if (tstar) std::memcpy(&tstar[i], &tb32, sizeof(float));
+    if (kstar) kstar[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(best[i] & 0xFFFFFFFFu));
+  }
+  return RELOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+"""Boundary checks that need no GPU: the C-ABI library loads, exports every
+function declared in include/reloc.h, its host-side scan preprocessing agrees
+with the oracle's, and device entry points fail cleanly without a device."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_01219_amd as reloc
+from paper_2511_01219_amd import _abi
+from synth import make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "reloc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(reloc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_three_calls():
+    names = _declared_functions()
+    for n in ("reloc_load_map", "reloc_sample_hypotheses", "reloc_relocalize"):
+        assert n in names
+
+
+def test_library_exports_every_declared_function():
+    lib = reloc.lib()
+    for n in _declared_functions():
+        assert hasattr(lib, n), n
+    assert set(_declared_functions()) == set(_abi.PROTOS), "binding and header differ"
+
+
+def test_struct_layouts_match_c(tmp_path):
+    # sizes and field offsets as the C compiler lays out include/reloc.h
+    import ctypes
+    import subprocess
+    structs = ["reloc_allocator", "reloc_map_desc", "reloc_sample_params",
+               "reloc_interval", "reloc_scan", "reloc_search_params", "reloc_scan_info",
+               "reloc_pose", "reloc_stats"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "reloc.h"',
+             'int main(void) {']
+    for st in structs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for f, _ in getattr(_abi, st)._fields_:
+            cf = "lambda" if f == "lambda_" else f
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, f, st, cf))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    got = dict(zip(out[::2], map(int, out[1::2])))
+    for st in structs:
+        cls = getattr(_abi, st)
+        assert ctypes.sizeof(cls) == got[st], st
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == got["%s.%s" % (st, f)], (st, f)
+
+
+def test_version_and_error_text():
+    assert reloc.version() == 1
+    assert isinstance(reloc.lib().reloc_last_error(), bytes)
+
+
+def test_ctx_create_without_device_is_an_error():
+    with pytest.raises(reloc.RelocError) as ei:
+        reloc.Context(use_torch=False)
+    assert ei.value.code == reloc.E_DEVICE
+
+
+def _both(ranges, amin, inc, res=0.05, fov=None, rmin=0.02, rmax=20.0, **kw):
+    a = reloc.scan_info(ranges, amin, inc, res, rmin, rmax, fov=fov, **kw)
+    b = oracle.prep(ranges, amin, inc, res, fov=fov, range_min=rmin, range_max=rmax,
+                    n_skip_beam=kw.get("n_skip_beam", 1), n_skip_enum=kw.get("n_skip_enum", 1),
+                    n_theta=kw.get("n_theta", 0),
+                    alpha_mid_pm=kw.get("alpha_mid_pm", (900, 700)),
+                    alpha_low_pm=kw.get("alpha_low_pm", (700, 500)))
+    return a, b
+
+
+@pytest.mark.parametrize("cid", [1, 2, 5])
+def test_scan_info_matches_oracle_on_workloads(cid):
+    w = make_config(cid, n_target=10)
+    nt = {1: 360, 2: 720, 5: 1440}[cid]
+    a, b = _both(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                 rmin=w.range_min, rmax=w.range_max, n_theta=nt)
+    assert b["status"] == 0
+    for ka, kb in (("Ns", "Ns"), ("Ntheta", "Ntheta"), ("Ng", "Ng"), ("n_fov", "N_fov"),
+                   ("n_valid", "N_valid"), ("k_mid", "k_mid"), ("k_low", "k_low"),
+                   ("k_full", "k_full"), ("n_shifts", "n_shifts"), ("j0", "j0"),
+                   ("n_runs", "n_runs"), ("n_down", "n_down")):
+        assert a[ka] == b[kb], ka
+    assert a["zbar"] == b["zbar"]
+    assert bool(a["panoramic"]) == b["panoramic"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_scan_info_matches_oracle_random(seed):
+    rng = np.random.default_rng(seed)
+    fov_deg = [90.0, 180.0, 240.0, 270.0, 360.0, 220.0][seed]
+    n = [120, 360, 320, 720, 1440, 440][seed]
+    inc = math.radians(fov_deg) / n
+    amin = -math.pi if fov_deg == 360 else -math.radians(fov_deg) / 2
+    z = (rng.random(n) * 15).astype(np.float32)
+    z[rng.random(n) < 0.1] = np.nan
+    z[rng.random(n) < 0.05] = 50.0
+    fov = None
+    if seed % 2:
+        fov = [(amin, amin + 0.3 * math.radians(fov_deg)),
+               (amin + 0.45 * math.radians(fov_deg), amin + math.radians(fov_deg))]
+    kw = dict(n_theta=[0, 360, 720, 360, 1440, 0][seed], n_skip_beam=1 + seed % 3,
+              n_skip_enum=1 + (seed % 2), alpha_mid_pm=(900, 650), alpha_low_pm=(720, 480))
+    try:
+        a, b = _both(z, amin, inc, fov=fov, **kw)
+    except reloc.RelocError as e:
+        b = oracle.prep(z, amin, inc, 0.05, fov=fov, range_max=20.0,
+                        n_skip_beam=kw["n_skip_beam"], n_skip_enum=kw["n_skip_enum"],
+                        n_theta=kw["n_theta"], alpha_mid_pm=kw["alpha_mid_pm"],
+                        alpha_low_pm=kw["alpha_low_pm"])
+        assert e.code == b["status"]
+        return
+    assert (a["Ns"], a["n_valid"], a["k_mid"], a["k_low"], a["n_fov"], a["n_runs"]) == \
+        (b["Ns"], b["N_valid"], b["k_mid"], b["k_low"], b["N_fov"], b["n_runs"])
+    assert a["zbar"] == b["zbar"]
+
+
+def test_scan_info_errors_match_oracle_codes():
+    z = np.full(100, 2.0, np.float32)
+    with pytest.raises(reloc.RelocError) as ei:
+        reloc.scan_info(z, 0.0, math.radians(0.7), 0.05)
+    assert ei.value.code == reloc.E_BEAMGRID == oracle.E_BEAMGRID
+    with pytest.raises(reloc.RelocError) as ei:
+        reloc.scan_info(np.full(100, np.nan, np.float32), 0.0, math.radians(1.0), 0.05)
+    assert ei.value.code == reloc.E_EMPTY == oracle.E_EMPTY
+    with pytest.raises(reloc.RelocError) as ei:
+        reloc.scan_info(z, 0.0, math.radians(1.0), 0.05, range_max=80.0)
+    assert ei.value.code == reloc.E_INVALID
+    with pytest.raises(reloc.RelocError) as ei:
+        reloc.scan_info(z, 0.0, 2 * math.pi / 8192, 0.05)
+    assert ei.value.code == reloc.E_INVALID        # Ns above the 4096 limit
+
+
+def test_search_param_defaults():
+    p = reloc.search_params()
+    assert (p.batch_k, p.k_out, p.tau, p.z_hit, p.sigma_hit, p.z_rand, p.d_max) == \
+        (64, 10, 0.95, 1.0, 0.2, 0.0, 2.0)
+    assert tuple(p.alpha_mid_pm) == (900, 700) and tuple(p.alpha_low_pm) == (700, 500)
+    q = reloc.search_params(tau=None)
+    assert math.isnan(q.tau)

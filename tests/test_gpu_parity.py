@@ -1,0 +1,411 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (integer and index work bit-exact; floating point within the stated
+tolerance):
+  * EDT k, hypothesis sets, ray-cast hit cells and FP32 ranges: bit-exact;
+  * SMAD (FP64) bit-exact, hence the SMAD order identical;
+  * TAM per (p, theta): |T_gpu - T_oracle| <= 1e-4 * T_oracle + 1e-7;
+  * theta* identical unless the oracle's best two orientations are within
+    2e-4 relative (then either is accepted);
+  * stop stage identical unless the deciding batch best is within 1e-4 of
+    tau; best pose identical with the same tie rule.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_01219_amd as reloc
+from synth import make_config, make_micro
+
+pytestmark = pytest.mark.gpu
+
+T_RTOL, T_ATOL = 1e-4, 1e-7
+
+
+def _case(msg):
+    print("[gpu case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = reloc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = make_config(1)
+    k = oracle.edt(w.occ)
+    hyp = oracle.sample(w.occ, k, w.resolution, n_target=300, seed=1, min_spacing=0.3,
+                        robot_radius=0.21)
+    return w, k, hyp
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = make_config(2)
+    k = oracle.edt(w.occ)
+    hyp = oracle.sample(w.occ, k, w.resolution, n_target=20000, seed=2, min_spacing=0.3,
+                        robot_radius=0.21)
+    return w, k, hyp
+
+
+def _scan(w):
+    return dict(ranges=w.ranges, angle_min=w.angle_min, angle_increment=w.angle_increment,
+                range_min=w.range_min, range_max=w.range_max)
+
+
+def _oprep(w, n_theta, **kw):
+    return oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                       range_min=w.range_min, range_max=w.range_max, n_theta=n_theta, **kw)
+
+
+def _tam_close(a, b):
+    return np.abs(a.astype(np.float64) - b) <= T_RTOL * np.abs(b) + T_ATOL
+
+
+# --------------------------------------------------------------------------- a0
+@pytest.mark.parametrize("which", ["micro", "ragged", "c1", "c2"])
+def test_edt_bit_exact(ctx, which, c1, c2):
+    if which == "micro":
+        occ = make_micro(3, 37, 29, n_boxes=5, p_unknown=0.05)
+    elif which == "ragged":
+        occ = make_micro(4, 203, 197, n_boxes=30)
+    elif which == "c1":
+        occ = c1[0].occ
+    else:
+        occ = c2[0].occ
+    _case("edt %s %s" % (which, occ.shape))
+    m = ctx.load_map(occ, 0.05)
+    k = ctx.read_edt(m)
+    ref = c1[1] if which == "c1" else (c2[1] if which == "c2" else oracle.edt(occ))
+    assert (k.astype(np.int64) == ref).all()
+    ctx.unload_map(m)
+
+
+def test_load_map_rejects_empty_and_bad(ctx):
+    _case("load_map errors")
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.load_map(np.zeros((10, 10), np.int8))
+    assert ei.value.code == reloc.E_EMPTY
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.load_map(np.full((10, 10), 100, np.int8), resolution=0.01)
+    assert ei.value.code == reloc.E_INVALID
+
+
+# --------------------------------------------------------------------------- a1
+@pytest.mark.parametrize("which,n,seed", [("c1", 300, 1), ("c1", 5000, 7), ("c2", 20000, 2),
+                                          ("micro", 40, 3)])
+def test_sampler_bit_exact(ctx, which, n, seed, c1, c2):
+    if which == "micro":
+        occ = make_micro(8, 70, 55, n_boxes=9, p_unknown=0.03)
+        k = oracle.edt(occ)
+    else:
+        occ, k = (c1[0].occ, c1[1]) if which == "c1" else (c2[0].occ, c2[1])
+    _case("sampler %s n=%d seed=%d" % (which, n, seed))
+    m = ctx.load_map(occ, 0.05)
+    sid, got_n = ctx.sample_hypotheses(m, n, 0.3, 0.21, seed=seed)
+    got = ctx.read_hypotheses(sid)
+    ref = oracle.sample(occ, k, 0.05, n_target=n, seed=seed, min_spacing=0.3,
+                        robot_radius=0.21)
+    assert got_n == len(ref)
+    assert (got == ref).all()
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+def test_sampler_p0_and_busy(ctx):
+    occ = np.zeros((40, 60), np.int8)
+    occ[0, :] = occ[-1, :] = occ[:, 0] = occ[:, -1] = 100
+    occ[:, 30] = 100
+    k = oracle.edt(occ)
+    _case("sampler p0")
+    m = ctx.load_map(occ, 0.05)
+    sid, n = ctx.sample_hypotheses(m, 500, 0.3, 0.21, p0=(45 * 0.05, 20 * 0.05), seed=1)
+    ref = oracle.sample(occ, k, 0.05, n_target=500, p0=(45 * 0.05, 20 * 0.05), seed=1)
+    assert (ctx.read_hypotheses(sid) == ref).all()
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.unload_map(m)
+    assert ei.value.code == reloc.E_BUSY
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.sample_hypotheses(m, 5, 0.3, 0.21, p0=(30.5 * 0.05, 20 * 0.05))
+    assert ei.value.code == reloc.E_EMPTY
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+# ----------------------------------------------------------------------- a3 a4 a5
+def _raycast_case(ctx, occ, hyp, ranges, amin, inc, rmax, n_theta=0, fov=None, **kw):
+    m = ctx.load_map(occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, ranges, amin, inc, 0.02, rmax, fov=fov, n_theta=n_theta, **kw)
+    pr = oracle.prep(ranges, amin, inc, 0.05, fov=fov, range_min=0.02, range_max=rmax,
+                     n_theta=n_theta, n_skip_beam=kw.get("n_skip_beam", 1),
+                     n_skip_enum=kw.get("n_skip_enum", 1))
+    return m, sid, rid, pr
+
+
+def _cleanup(ctx, m, sid, rid):
+    ctx.release(rid)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+@pytest.mark.parametrize("Ns,fov_deg,seed", [(480, 270, 0), (360, 360, 1), (64, 180, 2),
+                                             (1440, 360, 3), (8, 360, 4), (4096, 360, 5),
+                                             (960, 90, 6)])
+def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed):
+    occ = make_micro(50 + seed, 61, 47, n_boxes=8, p_unknown=0.04)
+    occ[0, 10:20] = 0                        # holes: rays leave the map
+    occ[20:25, -1] = 0
+    ys, xs = np.nonzero(occ == 0)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(xs), 50, replace=False)
+    hyp = np.stack([xs[pick], ys[pick]], 1).astype(np.int32)
+    inc = 2 * math.pi / Ns
+    n = int(round(Ns * fov_deg / 360.0))
+    amin = -math.pi if fov_deg == 360 else -inc * (n // 2)
+    z = (rng.random(n) * 2.5 + 0.05).astype(np.float32)
+    z[rng.random(n) < 0.1] = np.nan
+    _case("raycast micro Ns=%d fov=%d seed=%d" % (Ns, fov_deg, seed))
+    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, amin, inc, 3.0)
+    hit, rg = ctx.debug_raycast(rid, len(hyp), Ns)
+    oh, orr = oracle.raycast(occ, hyp, Ns, pr["Ng"], 0.05, 3.0)
+    assert (hit == oh).all()
+    assert (rg.view(np.uint32) == orr.view(np.uint32)).all()
+    s, a, o = ctx.debug_smad(rid, len(hyp))
+    os_, oa = oracle.smad(orr, pr)
+    assert (s.view(np.uint64) == os_.view(np.uint64)).all()
+    assert (a == oa).all()
+    assert (o == np.lexsort((np.arange(len(hyp)), os_))).all()
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_raycast_smad_c1_full(ctx, c1):
+    w, k, hyp = c1
+    _case("raycast+smad c1 300 hyps")
+    m, sid, rid, pr = _raycast_case(ctx, w.occ, hyp, w.ranges, w.angle_min, w.angle_increment,
+                                    w.range_max, n_theta=360)
+    hit, rg = ctx.debug_raycast(rid, len(hyp), pr["Ns"])
+    oh, orr = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, w.range_max)
+    assert (hit == oh).all() and (rg.view(np.uint32) == orr.view(np.uint32)).all()
+    s, a, o = ctx.debug_smad(rid, len(hyp))
+    os_, oa = oracle.smad(orr, pr)
+    assert (s.view(np.uint64) == os_.view(np.uint64)).all() and (a == oa).all()
+    assert (o == np.lexsort((np.arange(len(hyp)), os_))).all()
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_raycast_smad_fov_runs_and_skips(ctx, c1):
+    w, k, hyp = c1
+    fov = [(w.angle_min, -0.4), (0.1, 1.2), (1.5, 2.3)]
+    _case("raycast+smad c1 three FoV runs, n_skip_beam=2, n_skip_enum=3")
+    m, sid, rid, pr = _raycast_case(ctx, w.occ, hyp[:120], w.ranges, w.angle_min,
+                                    w.angle_increment, w.range_max, n_theta=180, fov=fov,
+                                    n_skip_beam=2, n_skip_enum=3)
+    assert pr["n_runs"] == 3
+    _, orr = oracle.raycast(w.occ, hyp[:120], pr["Ns"], pr["Ng"], 0.05, w.range_max)
+    s, a, o = ctx.debug_smad(rid, 120)
+    os_, oa = oracle.smad(orr, pr)
+    assert (s.view(np.uint64) == os_.view(np.uint64)).all() and (a == oa).all()
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_raycast_smad_c2_full_size(ctx, c2):
+    """Full-size plain-large workload, same launch as the benchmark: every
+    SMAD and the order bit-exact; hits/ranges on a hypothesis sample."""
+    w, k, hyp = c2
+    _case("raycast+smad c2 20000 hyps")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=720, batch_k=64)
+    pr = _oprep(w, 720)
+    s, a, o = ctx.debug_smad(rid, len(hyp))
+    _, orr = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, w.range_max, threads=16)
+    os_, oa = oracle.smad(orr, pr, threads=16)
+    assert (s.view(np.uint64) == os_.view(np.uint64)).all() and (a == oa).all()
+    assert (o == np.lexsort((np.arange(len(hyp)), os_))).all()
+    hit, rg = ctx.debug_raycast(rid, len(hyp), pr["Ns"])
+    samp = np.random.default_rng(0).choice(len(hyp), 400, replace=False)
+    oh, orr2 = oracle.raycast(w.occ, hyp[samp], pr["Ns"], pr["Ng"], 0.05, w.range_max)
+    assert (hit[samp] == oh).all()
+    assert (rg[samp].view(np.uint32) == orr2.view(np.uint32)).all()
+    _cleanup(ctx, m, sid, rid)
+
+
+# ----------------------------------------------------------------------------- a6
+def _check_tam(T, ts, ks, ref_T):
+    ok = _tam_close(T, ref_T)
+    assert ok.all(), "max rel err %.3g" % np.max(np.abs(T - ref_T) / np.maximum(ref_T, 1e-7))
+    ts_ref = ref_T.max(1)
+    assert _tam_close(ts, ts_ref).all()
+    kref = ref_T.argmax(1)
+    srt = np.sort(ref_T, 1)
+    ambiguous = (srt[:, -1] - srt[:, -2]) <= 2e-4 * srt[:, -1]
+    assert ((ks == kref) | ambiguous).all()
+    return ambiguous.sum()
+
+
+def test_tam_c1_all_orientations(ctx, c1):
+    w, k, hyp = c1
+    _case("tam c1 first 40 ranks x 360")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=360, batch_k=10)
+    pr = _oprep(w, 360)
+    s, a, order = ctx.debug_smad(rid, len(hyp))
+    T, ts, ks = ctx.debug_tam(rid, 0, 40, 360)
+    q = np.repeat(hyp[order[:40]], 360, axis=0)
+    kk = np.tile(np.arange(360), 40)
+    ref = oracle.tam(k, 0.05, pr, q, kk)[:, 0].reshape(40, 360)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
+@pytest.mark.parametrize("params", [dict(z_hit=0.8, sigma_hit=0.35, z_rand=0.05, d_max=3.0),
+                                    dict(z_hit=1.0, sigma_hit=0.6, z_rand=0.0, d_max=1.0),
+                                    dict(alpha_mid_pm=(950, 500), alpha_low_pm=(800, 300))])
+def test_tam_parameter_variants(ctx, c1, params):
+    w, k, hyp = c1
+    _case("tam c1 params %s" % params)
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=120, batch_k=7, **params)
+    okw = {kk: v for kk, v in params.items() if kk.startswith("alpha")}
+    pr = _oprep(w, 120, **okw)
+    _, _, order = ctx.debug_smad(rid, len(hyp))
+    T, ts, ks = ctx.debug_tam(rid, 5, 23, 120)
+    q = np.repeat(hyp[order[5:28]], 120, axis=0)
+    kk = np.tile(np.arange(120), 23)
+    tk = {kk_: v for kk_, v in params.items() if not kk_.startswith("alpha")}
+    ref = oracle.tam(k, 0.05, pr, q, kk, **tk)[:, 0].reshape(23, 120)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_tam_c2_first_stage_full_size(ctx, c2):
+    w, k, hyp = c2
+    _case("tam c2 first stage 64 x 720")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=720, batch_k=64)
+    pr = _oprep(w, 720)
+    _, _, order = ctx.debug_smad(rid, len(hyp))
+    T, ts, ks = ctx.debug_tam(rid, 0, 64, 720)
+    q = np.repeat(hyp[order[:64]], 720, axis=0)
+    kk = np.tile(np.arange(720), 64)
+    ref = oracle.tam(k, 0.05, pr, q, kk, threads=16)[:, 0].reshape(64, 720)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_tam_off_map_endpoints(ctx):
+    # a small map where most endpoints fall outside: d = d_max path
+    occ = make_micro(9, 30, 24, n_boxes=2)
+    ys, xs = np.nonzero(occ == 0)
+    hyp = np.stack([xs[:30], ys[:30]], 1).astype(np.int32)
+    z = np.full(180, 2.5, np.float32)
+    inc = 2 * math.pi / 180
+    _case("tam off-map endpoints")
+    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, -math.pi, inc, 10.0, n_theta=90)
+    k = oracle.edt(occ)
+    _, _, order = ctx.debug_smad(rid, len(hyp))
+    T, ts, ks = ctx.debug_tam(rid, 0, 30, 90)
+    q = np.repeat(hyp[order[:30]], 90, axis=0)
+    kk = np.tile(np.arange(90), 30)
+    ref = oracle.tam(k, 0.05, pr, q, kk)[:, 0].reshape(30, 90)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
+# ----------------------------------------------------------------------- a7 a8
+def _compare_runs(poses, st, ref, tau, K):
+    assert st["n_hyp"] == len(ref["order"])
+    amb_stop = False
+    if ref["early_stopped"] != bool(st["early_stopped"]) or ref["stages"] != st["stages"]:
+        # only acceptable when the deciding batch best sits within 1e-4 of tau
+        s = min(ref["stages"], st["stages"]) - 1
+        tb = ref["tstar"][s * K:(s + 1) * K].max()
+        amb_stop = tau is not None and abs(tb - tau) <= 1e-4
+        assert amb_stop, (ref["stages"], st["stages"])
+    if amb_stop:
+        return
+    assert st["n_eval"] == ref["n_eval"]
+    b = poses[0]
+    ro = ref["rank_order"]
+    best = ro[0]
+    tied = [r for r in ro[:5] if ref["tstar"][r] >= ref["tstar"][best] * (1 - 2e-4)]
+    assert b["rank"] in tied
+    if b["rank"] == best:
+        kref = ref["kstar"][best]
+        assert b["k"] == kref or abs(ref["all_T"][best][b["k"]] - ref["tstar"][best]) <= \
+            2e-4 * ref["tstar"][best]
+    assert abs(b["tam"] - ref["tstar"][b["rank"]]) <= T_RTOL * ref["tstar"][b["rank"]] + T_ATOL
+
+
+def _oracle_run(w, k, hyp, n_theta, K, tau):
+    pr = _oprep(w, n_theta)
+    _, zhat = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, w.range_max, threads=16)
+    sm, _ = oracle.smad(zhat, pr, threads=16)
+    st = oracle.stages(k, 0.05, pr, hyp, sm, K, tau, all_T=True, threads=16)
+    st["rank_order"] = np.lexsort((np.arange(st["n_eval"]), -st["tstar"]))
+    return st
+
+
+@pytest.mark.parametrize("tau,K", [(None, 10), (0.95, 10), (None, 300), (0.5, 7)])
+def test_relocalize_c1_end_to_end(ctx, c1, tau, K):
+    w, k, hyp = c1
+    _case("relocalize c1 tau=%s K=%d" % (tau, K))
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=K, tau=tau, k_out=10)
+    ref = _oracle_run(w, k, hyp, 360, K, tau)
+    _compare_runs(poses, st, ref, tau, K)
+    if tau is None:
+        assert st["n_eval"] == len(hyp) and not st["early_stopped"]
+    assert st["smad_evals"] == len(hyp) * 480
+    assert st["tam_evals"] == st["n_eval"] * 360
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+def test_relocalize_edge_cases(ctx, c1):
+    w, k, hyp = c1
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    _case("relocalize n_hyp=1")
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=10, tau=None, n_hyp=1)
+    assert st["n_eval"] == 1 and poses[0]["hyp"] == 0 and st["stages"] == 1
+    _case("relocalize K > N_p")
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=1000, tau=None, n_hyp=37)
+    assert st["stages"] == 1 and st["n_eval"] == 37
+    _case("relocalize tau=0 stops after the first stage")
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=16, tau=0.0)
+    assert st["stages"] == 1 and st["early_stopped"] == 1 and st["n_eval"] == 16
+    _case("relocalize k_out > evaluated")
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=16, tau=0.0, k_out=50)
+    assert len(poses) == 16
+    _case("relocalize no valid beam")
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.relocalize(m, sid, np.full(360, np.nan, np.float32), w.angle_min,
+                       w.angle_increment, 0.02, 12.0)
+    assert ei.value.code == reloc.E_EMPTY
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+def test_deterministic_repeat(ctx, c1):
+    w, k, hyp = c1
+    _case("determinism c1 twice")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    a, sa = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=10, tau=None)
+    b, sb = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=10, tau=None)
+    assert a == b
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
