@@ -122,6 +122,13 @@ def load():
     """Loads the in-tree libreloc.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime (loaded by file name libamdhip64.so);
+        # loading it first makes libreloc bind to that same runtime through
+        # the shared soname instead of pulling in a second copy
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libreloc.so is not built; run "
                               "`python -m paper_2511_01219_amd.build` first")

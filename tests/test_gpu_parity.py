@@ -409,3 +409,16 @@ def test_deterministic_repeat(ctx, c1):
     assert a == b
     ctx.free_hypotheses(sid)
     ctx.unload_map(m)
+
+
+def test_library_first_then_torch_in_fresh_process():
+    """Regression: loading libreloc before torch must not start a second HIP
+    runtime in the process."""
+    import subprocess
+    _case("fresh process: library loaded before torch")
+    code = ("import paper_2511_01219_amd as r; r.lib(); import torch; "
+            "c = r.Context(0); print('ok', c.bytes); c.close()")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300, cwd=__import__("os").path.dirname(
+                             __import__("os").path.dirname(__import__("os").path.abspath(__file__))))
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr[-2000:]
