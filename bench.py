@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--tau", default="0.95")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (counter scale)")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the ray-cast kernel")
     args = ap.parse_args()
@@ -94,6 +96,14 @@ def main():
     import paper_2511_01219_amd as reloc
     from synth import make_config
 
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calibrate_copy)
+        del src, dst
     tau = None if args.tau.lower() in ("none", "nan") else float(args.tau)
     n_theta, batch_k = 720, 64
     log("generating the plain-large workload")

@@ -51,7 +51,7 @@ class reloc_search_params(C.Structure):
                 ("tau", C.c_double), ("n_hyp", C.c_int32), ("z_hit", C.c_double),
                 ("sigma_hit", C.c_double), ("z_rand", C.c_double), ("d_max", C.c_double),
                 ("alpha_mid_pm", C.c_int32 * 2), ("alpha_low_pm", C.c_int32 * 2),
-                ("deadline_s", C.c_double)]
+                ("deadline_s", C.c_double), ("variant", C.c_int32)]
 
 
 class reloc_scan_info(C.Structure):

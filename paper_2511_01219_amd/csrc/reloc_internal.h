@@ -20,6 +20,9 @@ hipError_t launch_edt(const int8_t* occ, int W, int H, int thr, int32_t* g, uint
 // ---- ray cast + SMAD (fused) --------------------------------------------
 struct RayArgs {
   const uint64_t* bits;
+  const uint8_t* skip;       // 8x8 byte tiles: 0 occupied, 1 + free-space radius
+  uint32_t skip_bytes;
+  int variant;               // 0: bit tiles, 1: distance skipping
   int W, H, tpr;
   const int32_t* hyp_xy;     // [n_hyp][2]
   int n_hyp;
@@ -42,6 +45,9 @@ struct RayArgs {
   int32_t* dbg_steps;        // optional [n_hyp][Ns] DDA iterations per ray
 };
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
+// free-space skip bytes (8x8 tiles) from the squared EDT
+hipError_t launch_skipmap(const uint32_t* k, int W, int H, int tpr, int tph, uint8_t* out,
+                          hipStream_t s);
 
 // ---- sorting (hipCUB radix sort) -----------------------------------------
 hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,

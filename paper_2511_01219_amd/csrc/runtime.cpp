@@ -216,6 +216,7 @@ struct DevMap {
   int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
   double res = 0.05, ox = 0, oy = 0;
   uint64_t* bits = nullptr;
+  uint8_t* skip = nullptr;
   uint32_t* kmap = nullptr;
   std::vector<int8_t> occ;        // host copy for the sampler
   std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
@@ -514,6 +515,9 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, float* dbg_rng) {
   const reloc_scan_info& I = R.prep.info;
   RayArgs a;
   a.bits = m.bits;
+  a.skip = m.skip;
+  a.skip_bytes = (uint32_t)((size_t)m.tpr * m.tph * 64);
+  a.variant = R.prm.variant == 1 ? 0 : 1;
   a.W = m.W;
   a.H = m.H;
   a.tpr = m.tpr;
@@ -583,6 +587,7 @@ int32_t validate_search(const reloc_search_params* p) {
   if (p->batch_k <= 0) return fail(RELOC_E_INVALID, "batch_k must be >= 1");
   if (p->k_out <= 0) return fail(RELOC_E_INVALID, "k_out must be >= 1");
   if (p->n_theta < 0 || p->n_hyp < 0) return fail(RELOC_E_INVALID, "negative n_theta / n_hyp");
+  if (p->variant < 0 || p->variant > 2) return fail(RELOC_E_INVALID, "variant must be 0, 1 or 2");
   return RELOC_OK;
 }
 
@@ -614,6 +619,7 @@ void reloc_search_defaults(reloc_search_params* p) {
   p->alpha_low_pm[0] = 700;
   p->alpha_low_pm[1] = 500;
   p->deadline_s = 0.0;
+  p->variant = 0;
 }
 
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
@@ -658,6 +664,7 @@ void reloc_ctx_destroy(reloc_ctx* c) {
     for (auto& kv : c->sets) c->dfree(kv.second.dev);
     for (auto& kv : c->maps) {
       c->dfree(kv.second.bits);
+      c->dfree(kv.second.skip);
       c->dfree(kv.second.kmap);
     }
     c->reqs.clear();
@@ -702,24 +709,28 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   int8_t* docc = (int8_t*)c->dalloc(N);
   int32_t* g = (int32_t*)c->dalloc(N * sizeof(int32_t));
   m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
+  m.skip = (uint8_t*)c->dalloc((size_t)m.tpr * m.tph * 64);
   m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
   auto cleanup = [&]() {
     c->dfree(docc);
     c->dfree(g);
   };
-  if (!docc || !g || !m.bits || !m.kmap) {
+  if (!docc || !g || !m.bits || !m.skip || !m.kmap) {
     cleanup();
     c->dfree(m.bits);
+    c->dfree(m.skip);
     c->dfree(m.kmap);
     return RELOC_E_NOMEM;
   }
   hipError_t e = hipMemcpyAsync(docc, occ, N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_bitpack(docc, m.W, m.H, m.thr, m.bits, m.tpr, m.tph, c->stream);
   if (e == hipSuccess) e = launch_edt(docc, m.W, m.H, m.thr, g, m.kmap, c->stream);
+  if (e == hipSuccess) e = launch_skipmap(m.kmap, m.W, m.H, m.tpr, m.tph, m.skip, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {
     c->dfree(m.bits);
+    c->dfree(m.skip);
     c->dfree(m.kmap);
     return fail(RELOC_E_DEVICE, "map upload failed: %s", hipGetErrorString(e));
   }
@@ -737,6 +748,7 @@ int32_t reloc_unload_map(reloc_ctx* c, int32_t map_id) {
   if (it->second.n_sets > 0) return fail(RELOC_E_BUSY, "map %d has live hypothesis sets", map_id);
   (void)hipStreamSynchronize(c->stream);
   c->dfree(it->second.bits);
+  c->dfree(it->second.skip);
   c->dfree(it->second.kmap);
   c->maps.erase(it);
   return RELOC_OK;

@@ -156,10 +156,11 @@ def _cleanup(ctx, m, sid, rid):
     ctx.unload_map(m)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("Ns,fov_deg,seed", [(480, 270, 0), (360, 360, 1), (64, 180, 2),
                                              (1440, 360, 3), (8, 360, 4), (4096, 360, 5),
                                              (960, 90, 6)])
-def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed):
+def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed, variant):
     occ = make_micro(50 + seed, 61, 47, n_boxes=8, p_unknown=0.04)
     occ[0, 10:20] = 0                        # holes: rays leave the map
     occ[20:25, -1] = 0
@@ -172,8 +173,8 @@ def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed):
     amin = -math.pi if fov_deg == 360 else -inc * (n // 2)
     z = (rng.random(n) * 2.5 + 0.05).astype(np.float32)
     z[rng.random(n) < 0.1] = np.nan
-    _case("raycast micro Ns=%d fov=%d seed=%d" % (Ns, fov_deg, seed))
-    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, amin, inc, 3.0)
+    _case("raycast micro Ns=%d fov=%d seed=%d variant=%d" % (Ns, fov_deg, seed, variant))
+    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, amin, inc, 3.0, variant=variant)
     hit, rg = ctx.debug_raycast(rid, len(hyp), Ns)
     oh, orr = oracle.raycast(occ, hyp, Ns, pr["Ng"], 0.05, 3.0)
     assert (hit == oh).all()
@@ -186,11 +187,12 @@ def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed):
     _cleanup(ctx, m, sid, rid)
 
 
-def test_raycast_smad_c1_full(ctx, c1):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_raycast_smad_c1_full(ctx, c1, variant):
     w, k, hyp = c1
-    _case("raycast+smad c1 300 hyps")
+    _case("raycast+smad c1 300 hyps variant=%d" % variant)
     m, sid, rid, pr = _raycast_case(ctx, w.occ, hyp, w.ranges, w.angle_min, w.angle_increment,
-                                    w.range_max, n_theta=360)
+                                    w.range_max, n_theta=360, variant=variant)
     hit, rg = ctx.debug_raycast(rid, len(hyp), pr["Ns"])
     oh, orr = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, w.range_max)
     assert (hit == oh).all() and (rg.view(np.uint32) == orr.view(np.uint32)).all()
@@ -216,14 +218,16 @@ def test_raycast_smad_fov_runs_and_skips(ctx, c1):
     _cleanup(ctx, m, sid, rid)
 
 
-def test_raycast_smad_c2_full_size(ctx, c2):
-    """Full-size plain-large workload, same launch as the benchmark: every
-    SMAD and the order bit-exact; hits/ranges on a hypothesis sample."""
+@pytest.mark.parametrize("variant", [0, 1])
+def test_raycast_smad_c2_full_size(ctx, c2, variant):
+    """Full-size plain-large workload, same launch as the benchmark (variant
+    0 = the tuned default): every SMAD and the order bit-exact; hits/ranges
+    on a hypothesis sample."""
     w, k, hyp = c2
-    _case("raycast+smad c2 20000 hyps")
+    _case("raycast+smad c2 20000 hyps variant=%d" % variant)
     m = ctx.load_map(w.occ, 0.05)
     sid = ctx.set_hypotheses(m, hyp)
-    rid = ctx.prepare(m, sid, **_scan(w), n_theta=720, batch_k=64)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=720, batch_k=64, variant=variant)
     pr = _oprep(w, 720)
     s, a, o = ctx.debug_smad(rid, len(hyp))
     _, orr = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, w.range_max, threads=16)
