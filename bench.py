@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tau", default="0.95")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
@@ -115,7 +117,8 @@ def main():
                                        seed=s["seed"])
     hyp = ctx.read_hypotheses(sid)
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
-                      w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10)
+                      w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
+                      variant=args.variant)
     log("map %dx%d, %d hypotheses, warmup %d" % (w.occ.shape[1], w.occ.shape[0], n_hyp,
                                                args.warmup))
     for _ in range(args.warmup):

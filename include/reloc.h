@@ -195,8 +195,10 @@ typedef struct {
   int32_t alpha_mid_pm[2];/* alpha_mid at lambda = 0 and 1, per mille (900, 700) */
   int32_t alpha_low_pm[2];/* alpha_low at lambda = 0 and 1, per mille (700, 500) */
   double deadline_s;      /* plain path: stop with RELOC_E_TIMEOUT after this (0: none) */
-  int32_t variant;        /* ray-cast kernel: 0 auto, 1 bit tiles, 2 distance skipping;
-                             every variant gives bit-identical results */
+  int32_t variant;        /* ray-cast kernel: 0 default; 1 bit tiles; 2, 3, 4, 5
+                             distance skipping with wavefront ray refill once 1, 8,
+                             16, 32 lanes are idle. Every variant gives
+                             bit-identical results. */
 } reloc_search_params;
 
 /* Fills the defaults listed above. */

@@ -114,107 +114,226 @@ __device__ float cast_ray_bits(const uint64_t* __restrict__ bits, int W, int H, 
 }
 
 // ----------------------------------------------------------------- variant: skip
+// Row-major skip bytes read through a buffer resource with 32-bit offsets.
 struct SkipMap {
   __amdgpu_buffer_rsrc_t rsrc;
-  int tpr;
-  __device__ __forceinline__ uint32_t at(int x, int y) const {
-    const uint32_t off = (tile_off(x, y, tpr) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
-    return __builtin_amdgcn_raw_buffer_load_b8(rsrc, off, 0, 0);
+  __device__ __forceinline__ uint32_t at(int off) const {
+    return __builtin_amdgcn_raw_buffer_load_b8(rsrc, (uint32_t)off, 0, 0);
   }
 };
 
-__device__ float cast_ray_skip(const SkipMap& sm, int W, int H, int ix0, int iy0, int ux, int uy,
-                               float kx, float ky, float rmax, int rcells, int* hit,
-                               int* steps) {
-  const int ax = ux < 0 ? -ux : ux, ay = uy < 0 ? -uy : uy;
-  const int sx = ux > 0 ? 1 : (ux < 0 ? -1 : 0);
-  const int sy = uy > 0 ? 1 : (uy < 0 ? -1 : 0);
-  const int dA = ay << 8, dB = ax << 8;
-  const bool xmaj = ax >= ay;
-  const int amaj = xmaj ? ax : ay, bmin = xmaj ? ay : ax;
-  const int64_t den = (int64_t)amaj << 8;
-  const float rden = 1.0f / (float)den;
-  // crossings of the major axis per cell of path length, rounded down a hair
-  const float f = (float)amaj / sqrtf((float)ax * (float)ax + (float)ay * (float)ay) * 0.99999f;
-  int D = (ay - ax) << 7;
-  int cx = ix0, cy = iy0, nx = 0, ny = 0, it = 0;
-  uint32_t v = sm.at(cx, cy);
-  int h = -1;
-  float z = 0.f;
+// Per-lane traversal state of one ray in its major/minor frame: the major
+// axis is the one with the larger |U| component (a = |U_major|,
+// b = |U_minor|). With na major and nb minor crossings done,
+// Dm = (128 + 256 na) b - (128 + 256 nb) a is negative when the next major
+// crossing comes first, positive when the minor one does, zero at an exact
+// corner (Dm is D of the x/y form for x-major rays and -D for y-major ones).
+struct SkipRay {
+  int a, b;            // |U_major|, |U_minor|
+  int om, on;          // cell-offset change of a major / minor crossing
+  int Dm, na, nb, off, it;
+  int la, lb;          // last in-range major / minor crossing count
+  float f, r;          // major crossings per cell of path (rounded down), b / a
+  float kmaj, kmin;    // metres per Q8 unit along the major / minor axis
+  uint32_t v;          // skip byte of the current cell
+  bool xmaj;
+};
+
+__device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix0, int iy0,
+                                          int W, int H, int rcells, const SkipMap& sm) {
+  const int ux = di.x, uy = di.y;
+  const int ax = abs(ux), ay = abs(uy);
+  r.xmaj = ax >= ay;
+  r.a = r.xmaj ? ax : ay;
+  r.b = r.xmaj ? ay : ax;
+  const int ox = ux < 0 ? -1 : 1, oy = uy < 0 ? -W : W;
+  r.om = r.xmaj ? ox : oy;
+  r.on = r.xmaj ? oy : ox;
+  const int lx = min(rcells, ux > 0 ? W - 1 - ix0 : (ux < 0 ? ix0 : rcells));
+  const int ly = min(rcells, uy > 0 ? H - 1 - iy0 : (uy < 0 ? iy0 : rcells));
+  r.la = r.xmaj ? lx : ly;
+  r.lb = r.xmaj ? ly : lx;
+  r.f = df.x;
+  r.r = df.y;
+  r.kmaj = r.xmaj ? df.z : df.w;
+  r.kmin = r.xmaj ? df.w : df.z;
+  r.Dm = (r.b - r.a) << 7;
+  r.na = r.nb = r.it = 0;
+  r.off = iy0 * W + ix0;
+  r.v = sm.at(r.off);
+}
+
+// One iteration: an optional free-space jump, then one exact crossing with
+// an occupancy test of the entered cell(s). Returns true when the ray ends;
+// *z / *hit then hold its range (0 / -1 for none). Counts beyond la / lb
+// mean the ray left the map or passed the cut-off: a miss.
+//
+// Jump: J major crossings are safe (all touched cells free). The state just
+// after the (na + J)-th major crossing has the unique minor count with
+// 256 (b - a) <= Dm < 256 b. A float estimate of that count is within one of
+// it; Dm is evaluated in wrapping 32-bit arithmetic (exact, the true value is
+// within one step of the window) and one correction lands in the window.
+__device__ __forceinline__ bool skip_iter(SkipRay& r, const SkipMap& sm, int off0, float* z,
+                                          int* hit) {
+  ++r.it;
+  const int s = (int)r.v - 1;
+  const int J = s >= 2 ? (int)((float)s * r.f) : 0;
+  if (J > 0) {
+    const int na = r.na + J;
+    int nb = (int)floorf(((float)na - 0.5f) * r.r - 0.5f) + 1;
+    int Dm = (int)((uint32_t)(128 + 256 * na) * (uint32_t)r.b -
+                   (uint32_t)(128 + 256 * nb) * (uint32_t)r.a);
+    const int dB = r.a << 8;
+    if (Dm >= (r.b << 8)) { ++nb; Dm -= dB; }
+    if (Dm < ((r.b - r.a) << 8)) { --nb; Dm += dB; }
+    r.na = na;
+    r.nb = nb;
+    r.Dm = Dm;
+    r.off = off0 + na * r.om + nb * r.on;
+    if (na > r.la || nb > r.lb) {
+      *z = 0.f;
+      *hit = -1;
+      return true;
+    }
+  }
+  if (r.Dm != 0) {
+    const bool maj = r.Dm < 0;
+    r.na += maj ? 1 : 0;
+    r.nb += maj ? 0 : 1;
+    r.Dm += maj ? (r.b << 8) : -(r.a << 8);
+    r.off += maj ? r.om : r.on;
+    const bool out = r.na > r.la || r.nb > r.lb;
+    r.v = out ? 1u : sm.at(r.off);
+    const bool occ = r.v == 0;
+    if (out || occ) {
+      const int n = maj ? r.na : r.nb;
+      *z = occ ? __fmul_rn((float)(128 + 256 * (n - 1)), maj ? r.kmaj : r.kmin) : 0.f;
+      *hit = occ ? r.off : -1;
+      return true;
+    }
+    return false;
+  }
+  // exact corner: both neighbours and the diagonal share the entry parameter
+  const bool ina = r.na + 1 <= r.la, inb = r.nb + 1 <= r.lb;
+  int best = -1;
+  if (ina && sm.at(r.off + r.om) == 0) best = r.off + r.om;
+  if (inb && sm.at(r.off + r.on) == 0) best = (best < 0 || r.off + r.on < best) ? r.off + r.on : best;
+  const bool ind = ina && inb;
+  const int dg = r.off + r.om + r.on;
+  const uint32_t vd = ind ? sm.at(dg) : 1u;
+  if (ind && vd == 0) best = (best < 0 || dg < best) ? dg : best;
+  r.off = dg;
+  ++r.na;
+  ++r.nb;
+  r.Dm += (r.b - r.a) << 8;
+  r.v = vd;
+  if (best >= 0 || !ind) {
+    // the entry offset is measured along x at a corner
+    const int n = r.xmaj ? r.na : r.nb;
+    *z = best >= 0 ? __fmul_rn((float)(128 + 256 * (n - 1)), r.xmaj ? r.kmaj : r.kmin) : 0.f;
+    *hit = best;
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ SkipMap make_skipmap(const RayArgs& a) {
+  SkipMap sm;
+  sm.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.skip, (short)0, (int)a.skip_bytes,
+                                              0x00020000);
+  return sm;
+}
+
+// Skip-variant ray cast. The rays of all hypotheses form one index space
+// (ray q = hypothesis q / Ns, direction q % Ns); each single-wavefront
+// workgroup owns a contiguous chunk of it. A lane whose ray ends writes the
+// range and goes idle; once at least REFILL lanes are idle they take the
+// next consecutive rays of the chunk together (positions by mbcnt, the chunk
+// counter is wavefront-uniform), so lanes stay busy and neighbouring lanes
+// work on neighbouring directions. The hardware balances the many chunks.
+template <int REFILL>
+__global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
+  const int lane = threadIdx.x;
+  const int Ns = a.Ns, W = a.W, H = a.H, rcells = a.rcells;
+  const int64_t total = (int64_t)a.n_hyp * Ns;
+  const int64_t q0 = (int64_t)blockIdx.x * a.chunk;
+  const int pool = (int)min((int64_t)a.chunk, total - q0);
+  const float inv_ns = 1.0f / (float)Ns;
+  const SkipMap sm = make_skipmap(a);
+  int next = 64;
+  int q = lane, off0 = 0;
+  bool busy = q < pool;
+  bool dry = pool <= 64;
+  SkipRay r;
+  auto start = [&](int qq) {
+    const int64_t g = q0 + qq;
+    int h = (int)((float)g * inv_ns);
+    int64_t jj = g - (int64_t)h * Ns;
+    h += jj < 0 ? -1 : (jj >= Ns ? 1 : 0);
+    jj = g - (int64_t)h * Ns;
+    const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
+    off0 = iy0 * W + ix0;
+    skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, sm);
+  };
+  if (busy) start(q);
   for (;;) {
-    ++it;
-    // free-space jump: J major crossings, all touched cells guaranteed free
-    const int s = (int)v - 1;
-    if (s >= 2) {
-      const int J = (int)((float)s * f);
-      if (J > 0) {
-        const int na = (xmaj ? nx : ny) + J;
-        const int64_t N = (int64_t)(128 + 256 * (na - 1)) * bmin - (int64_t)128 * amaj;
-        int nb = 0;
-        if (N >= 0) {
-          int q = (int)((float)N * rden);
-          const int64_t r = N - (int64_t)q * den;
-          q += (r < 0) ? -1 : (r >= den ? 1 : 0);
-          nb = q + 1;
+    if (busy) {
+      float z;
+      int hit;
+      if (skip_iter(r, sm, off0, &z, &hit)) {
+        if (z > a.rmax) {
+          z = 0.f;
+          hit = -1;
         }
-        nx = xmaj ? na : nb;
-        ny = xmaj ? nb : na;
-        cx = ix0 + sx * nx;
-        cy = iy0 + sy * ny;
-        D = (int)((int64_t)(128 + 256 * nx) * ay - (int64_t)(128 + 256 * ny) * ax);
-        if ((unsigned)cx >= (unsigned)W || (unsigned)cy >= (unsigned)H) break;
-        if (max(nx, ny) > rcells) break;
+        const size_t o = (size_t)(q0 + q);
+        a.zbuf[o] = z;
+        if (a.dbg_hit) a.dbg_hit[o] = hit;
+        if (a.dbg_steps) a.dbg_steps[o] = r.it;
+        busy = false;
       }
     }
-    // one exact crossing, then test the entered cell
-    if (D != 0) {
-      const bool stx = D < 0;
-      cx += stx ? sx : 0;
-      cy += stx ? 0 : sy;
-      nx += stx ? 1 : 0;
-      ny += stx ? 0 : 1;
-      D += stx ? dA : -dB;
-      if ((unsigned)cx >= (unsigned)W || (unsigned)cy >= (unsigned)H) break;
-      v = sm.at(cx, cy);
-      if (v == 0) {
-        const int n = stx ? nx : ny;
-        z = __fmul_rn((float)(128 + 256 * (n - 1)), stx ? kx : ky);
-        h = cy * W + cx;
-        break;
-      }
-    } else {
-      const int x1 = cx + sx, y1 = cy + sy;
-      const bool inx = (unsigned)x1 < (unsigned)W, iny = (unsigned)y1 < (unsigned)H;
-      int best = -1;
-      if (inx && sm.at(x1, cy) == 0) best = cy * W + x1;
-      if (iny && sm.at(cx, y1) == 0) {
-        const int li = y1 * W + cx;
-        if (best < 0 || li < best) best = li;
-      }
-      const bool ind = inx && iny;
-      const uint32_t vd = ind ? sm.at(x1, y1) : 1u;
-      if (ind && vd == 0) {
-        const int li = y1 * W + x1;
-        if (best < 0 || li < best) best = li;
-      }
-      cx = x1; cy = y1; ++nx; ++ny; D += dA - dB;
-      if (best >= 0) {
-        z = __fmul_rn((float)(128 + 256 * (nx - 1)), kx);
-        h = best;
-        break;
-      }
-      if (!ind) break;
-      v = vd;
+    const unsigned long long idle = __ballot(!busy);
+    if (dry) {
+      if (idle == ~0ull) break;
+      continue;
     }
-    if (max(nx, ny) > rcells) break;
+    const int cnt = __popcll(idle);
+    if (cnt >= REFILL) {
+      const int base = next;
+      next += cnt;
+      dry = next >= pool;
+      if (!busy) {
+        q = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+        if (q < pool) {
+          start(q);
+          busy = true;
+        }
+      }
+    }
   }
-  if (z > rmax) {
-    z = 0.f;
-    h = -1;
+}
+
+// Bit-tile ray cast: one workgroup per hypothesis, rays from a shared counter.
+__global__ __launch_bounds__(RT) void raycast_bits_kernel(RayArgs a) {
+  __shared__ int next_ray;
+  const int h = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int Ns = a.Ns;
+  const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
+  if (tid == 0) next_ray = RT;
+  __syncthreads();
+  for (int j = tid; j < Ns; j = atomicAdd(&next_ray, 1)) {
+    const int2 U = a.dirs[j];
+    const float2 kk = a.kap[j];
+    int hit, steps;
+    const float z = cast_ray_bits(a.bits, a.W, a.H, a.tpr, ix0, iy0, U.x, U.y, kk.x, kk.y,
+                                  a.rmax, a.rcells, &hit, &steps);
+    const size_t o = (size_t)h * Ns + j;
+    a.zbuf[o] = z;
+    if (a.dbg_hit) a.dbg_hit[o] = hit;
+    if (a.dbg_steps) a.dbg_steps[o] = steps;
   }
-  *hit = h;
-  *steps = it;
-  return z;
 }
 
 // ------------------------------------------------------------ SMAD epilogue
@@ -292,38 +411,12 @@ __device__ void smad_epilogue(const RayArgs& a, double* S, int h) {
   }
 }
 
-template <int VARIANT>
-__global__ __launch_bounds__(RT) void raycast_smad_kernel(RayArgs a) {
-  extern __shared__ double S[];   // [Ns + 1]: S[j + 1] = range j, then prefix sums
-  __shared__ int next_ray;
+// SMAD of one hypothesis per workgroup from its ranges in zbuf.
+__global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
+  extern __shared__ double S[];   // [Ns + 1]
   const int h = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int Ns = a.Ns;
-  const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
-  if (tid == 0) next_ray = RT;
-  __syncthreads();
-  SkipMap sm;
-  if (VARIANT == 1) {
-    sm.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.skip, (short)0, (int)a.skip_bytes,
-                                                0x00020000);
-    sm.tpr = a.tpr;
-  }
-  for (int j = tid; j < Ns; j = atomicAdd(&next_ray, 1)) {
-    const int2 U = a.dirs[j];
-    const float2 kk = a.kap[j];
-    int hit, steps;
-    float z;
-    if (VARIANT == 1)
-      z = cast_ray_skip(sm, a.W, a.H, ix0, iy0, U.x, U.y, kk.x, kk.y, a.rmax, a.rcells, &hit,
-                        &steps);
-    else
-      z = cast_ray_bits(a.bits, a.W, a.H, a.tpr, ix0, iy0, U.x, U.y, kk.x, kk.y, a.rmax,
-                        a.rcells, &hit, &steps);
-    S[j + 1] = (double)z;
-    if (a.dbg_hit) a.dbg_hit[(size_t)h * Ns + j] = hit;
-    if (a.dbg_rng) a.dbg_rng[(size_t)h * Ns + j] = z;
-    if (a.dbg_steps) a.dbg_steps[(size_t)h * Ns + j] = steps;
-  }
+  const float* z = a.zbuf + (size_t)h * a.Ns;
+  for (int j = threadIdx.x; j < a.Ns; j += RT) S[j + 1] = (double)z[j];
   __syncthreads();
   smad_epilogue(a, S, h);
 }
@@ -332,42 +425,46 @@ __global__ __launch_bounds__(RT) void raycast_smad_kernel(RayArgs a) {
 
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
+  const dim3 b(RT);
+  if (a.skip && a.variant >= 1) {
+    const int64_t total = (int64_t)a.n_hyp * a.Ns;
+    const dim3 g((unsigned)((total + a.chunk - 1) / a.chunk)), w(64);
+    switch (a.variant) {
+      case 1: hipLaunchKernelGGL(raycast_skip_kernel<1>, g, w, 0, s, a); break;
+      case 2: hipLaunchKernelGGL(raycast_skip_kernel<8>, g, w, 0, s, a); break;
+      case 3: hipLaunchKernelGGL(raycast_skip_kernel<16>, g, w, 0, s, a); break;
+      default: hipLaunchKernelGGL(raycast_skip_kernel<32>, g, w, 0, s, a); break;
+    }
+  } else {
+    hipLaunchKernelGGL(raycast_bits_kernel, dim3(a.n_hyp), b, 0, s, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const size_t lds = (size_t)(a.Ns + 1) * sizeof(double);
-  if (a.variant == 1 && a.skip)
-    hipLaunchKernelGGL(raycast_smad_kernel<1>, dim3(a.n_hyp), dim3(RT), lds, s, a);
-  else
-    hipLaunchKernelGGL(raycast_smad_kernel<0>, dim3(a.n_hyp), dim3(RT), lds, s, a);
+  hipLaunchKernelGGL(smad_kernel, dim3(a.n_hyp), b, lds, s, a);
   return hipGetLastError();
 }
 
 // Skip byte per cell from the squared EDT: 0 occupied, else 1 + s with
-// s = floor(sqrt(k) - 1.4145) clamped to [0, 254]. Tiles of 8x8 bytes.
+// s = floor(sqrt(k) - 1.4145) clamped to [0, 254]; row-major.
 namespace {
-__global__ void skipmap_kernel(const uint32_t* __restrict__ k, int W, int H, int tpr, int tph,
+__global__ void skipmap_kernel(const uint32_t* __restrict__ k, uint32_t n,
                                uint8_t* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t n = (uint32_t)tpr * (uint32_t)tph * 64u;
   if (i >= n) return;
-  const uint32_t tile = i >> 6;
-  const int x = (int)(tile % (uint32_t)tpr) * 8 + (int)(i & 7);
-  const int y = (int)(tile / (uint32_t)tpr) * 8 + (int)((i >> 3) & 7);
+  const uint32_t kk = k[i];
   uint8_t v = 0;
-  if (x < W && y < H) {
-    const uint32_t kk = k[(size_t)y * W + x];
-    if (kk != 0) {
-      const float s = floorf(__fsqrt_rn((float)kk) - 1.4145f);
-      v = (uint8_t)(1 + (int)fminf(254.f, fmaxf(0.f, s)));
-    }
+  if (kk != 0) {
+    const float s = floorf(__fsqrt_rn((float)kk) - 1.4145f);
+    v = (uint8_t)(1 + (int)fminf(254.f, fmaxf(0.f, s)));
   }
   out[i] = v;
 }
 }  // namespace
 
-hipError_t launch_skipmap(const uint32_t* k, int W, int H, int tpr, int tph, uint8_t* out,
-                          hipStream_t s) {
-  const uint32_t n = (uint32_t)tpr * (uint32_t)tph * 64u;
-  hipLaunchKernelGGL(skipmap_kernel, dim3((n + 255) / 256), dim3(256), 0, s, k, W, H, tpr, tph,
-                     out);
+hipError_t launch_skipmap(const uint32_t* k, int W, int H, uint8_t* out, hipStream_t s) {
+  const uint32_t n = (uint32_t)W * (uint32_t)H;
+  hipLaunchKernelGGL(skipmap_kernel, dim3((n + 255) / 256), dim3(256), 0, s, k, n, out);
   return hipGetLastError();
 }
 

@@ -20,9 +20,12 @@ hipError_t launch_edt(const int8_t* occ, int W, int H, int thr, int32_t* g, uint
 // ---- ray cast + SMAD (fused) --------------------------------------------
 struct RayArgs {
   const uint64_t* bits;
-  const uint8_t* skip;       // 8x8 byte tiles: 0 occupied, 1 + free-space radius
+  const uint8_t* skip;       // row-major bytes: 0 occupied, 1 + free-space radius
   uint32_t skip_bytes;
-  int variant;               // 0: bit tiles, 1: distance skipping
+  const int4* dir_i;         // [Ns] (Ux, Uy, lo, hi) per direction (skip variant)
+  const float4* dir_f;       // [Ns] (f, r, kappa_x, kappa_y) per direction
+  int variant;               // 0: bit tiles; 1-4: distance skipping with wavefront
+                             // ray refill once 1 / 8 / 16 / 32 lanes are idle
   int W, H, tpr;
   const int32_t* hyp_xy;     // [n_hyp][2]
   int n_hyp;
@@ -40,14 +43,14 @@ struct RayArgs {
   int32_t* argm;             // [n_hyp]
   uint64_t* keys;            // [n_hyp] sort key = bits of SMAD
   int32_t* vals;             // [n_hyp] hypothesis index
+  float* zbuf;                // [n_hyp][Ns] synthetic ranges (ray cast -> SMAD)
+  int chunk;                 // skip variant: rays owned by one wavefront
   int32_t* dbg_hit;          // optional [n_hyp][Ns]
-  float* dbg_rng;            // optional [n_hyp][Ns]
-  int32_t* dbg_steps;        // optional [n_hyp][Ns] DDA iterations per ray
+  int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray
 };
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
 // free-space skip bytes (8x8 tiles) from the squared EDT
-hipError_t launch_skipmap(const uint32_t* k, int W, int H, int tpr, int tph, uint8_t* out,
-                          hipStream_t s);
+hipError_t launch_skipmap(const uint32_t* k, int W, int H, uint8_t* out, hipStream_t s);
 
 // ---- sorting (hipCUB radix sort) -----------------------------------------
 hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,

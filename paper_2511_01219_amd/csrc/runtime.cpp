@@ -240,6 +240,9 @@ struct Request {
   // device tables
   int2* raydirs = nullptr;
   float2* kap = nullptr;
+  int4* dir_i = nullptr;
+  float4* dir_f = nullptr;
+  float* zbuf = nullptr;
   int2* runs = nullptr;
   int32_t* base = nullptr;
   int32_t* zq = nullptr;
@@ -468,17 +471,39 @@ int32_t build_request(reloc_ctx* c, Request& R) {
     kp[j].x = rd[j].x ? axis_scale(rd[j].x, rd[j].y, m.res) : 0.f;
     kp[j].y = rd[j].y ? axis_scale(rd[j].y, rd[j].x, m.res) : 0.f;
   }
+  // per-direction constants of the skip traversal
+  std::vector<int4> di(Ns);
+  std::vector<float4> df(Ns);
+  for (int j = 0; j < Ns; ++j) {
+    const int ax = std::abs(rd[j].x), ay = std::abs(rd[j].y);
+    const bool xmaj = ax >= ay;
+    const int amaj = xmaj ? ax : ay, bmin = xmaj ? ay : ax;
+    di[j].x = rd[j].x;
+    di[j].y = rd[j].y;
+    // D window just after a major crossing: x major 256(ay-ax) <= D < 256 ay,
+    // y major -256 ax < D <= 256(ay-ax)
+    di[j].z = xmaj ? (ay - ax) * 256 : -(ax * 256) + 1;
+    di[j].w = xmaj ? ay * 256 - 1 : (ay - ax) * 256;
+    const double nrm = std::sqrt((double)ax * ax + (double)ay * ay);
+    df[j].x = (float)((double)amaj / nrm * 0.99999);   // rounds down a hair
+    df[j].y = (float)((double)bmin / (double)amaj);
+    df[j].z = kp[j].x;
+    df[j].w = kp[j].y;
+  }
   std::vector<int32_t> base(R.prep.vj.size());
   for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
   if (int32_t e = build_lut(&R.prm, m.res, &R.lut)) return e;
   const int n = R.n_hyp, nv = I.n_valid;
   R.raydirs = req_alloc<int2>(c, R, Ns);
   R.kap = req_alloc<float2>(c, R, Ns);
+  R.dir_i = req_alloc<int4>(c, R, Ns);
+  R.dir_f = req_alloc<float4>(c, R, Ns);
   R.runs = req_alloc<int2>(c, R, R.prep.runs.size());
   R.base = req_alloc<int32_t>(c, R, nv);
   R.zq = req_alloc<int32_t>(c, R, nv);
   R.dirs = req_alloc<int2>(c, R, Ng);
   R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
+  R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
   R.smad = req_alloc<double>(c, R, n);
   R.argm = req_alloc<int32_t>(c, R, n);
   R.keys = req_alloc<uint64_t>(c, R, n);
@@ -501,6 +526,8 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   if (!R.tmp) return RELOC_E_NOMEM;
   if (int32_t e = upload(c, R.raydirs, rd.data(), rd.size())) return e;
   if (int32_t e = upload(c, R.kap, kp.data(), kp.size())) return e;
+  if (int32_t e = upload(c, R.dir_i, di.data(), di.size())) return e;
+  if (int32_t e = upload(c, R.dir_f, df.data(), df.size())) return e;
   if (int32_t e = upload(c, R.runs, R.prep.runs.data(), R.prep.runs.size())) return e;
   if (int32_t e = upload(c, R.base, base.data(), base.size())) return e;
   if (int32_t e = upload(c, R.zq, R.prep.vzq.data(), R.prep.vzq.size())) return e;
@@ -510,14 +537,24 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   return RELOC_OK;
 }
 
-RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, float* dbg_rng) {
+RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps) {
   DevMap& m = c->maps[R.map_id];
   const reloc_scan_info& I = R.prep.info;
   RayArgs a;
   a.bits = m.bits;
   a.skip = m.skip;
-  a.skip_bytes = (uint32_t)((size_t)m.tpr * m.tph * 64);
-  a.variant = R.prm.variant == 1 ? 0 : 1;
+  a.skip_bytes = (uint32_t)((size_t)m.W * m.H);
+  a.dir_i = R.dir_i;
+  a.dir_f = R.dir_f;
+  // public variant: 1 bit tiles; 2, 3, 4, 5 skipping with wavefront refill
+  // at 1, 8, 16, 32 idle lanes; 0 the default
+  static const int kv[6] = {3, 0, 1, 2, 3, 4};
+  a.variant = kv[R.prm.variant];
+  {
+    const int64_t rays = (int64_t)R.n_hyp * I.Ns;
+    a.chunk = (int)std::max<int64_t>(256, std::min<int64_t>(2048, rays / 4096));
+  }
+  a.zbuf = R.zbuf;
   a.W = m.W;
   a.H = m.H;
   a.tpr = m.tpr;
@@ -539,8 +576,7 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, float* dbg_rng) {
   a.keys = R.keys;
   a.vals = R.vals;
   a.dbg_hit = dbg_hit;
-  a.dbg_rng = dbg_rng;
-  a.dbg_steps = nullptr;
+  a.dbg_steps = dbg_steps;
   return a;
 }
 
@@ -587,7 +623,7 @@ int32_t validate_search(const reloc_search_params* p) {
   if (p->batch_k <= 0) return fail(RELOC_E_INVALID, "batch_k must be >= 1");
   if (p->k_out <= 0) return fail(RELOC_E_INVALID, "k_out must be >= 1");
   if (p->n_theta < 0 || p->n_hyp < 0) return fail(RELOC_E_INVALID, "negative n_theta / n_hyp");
-  if (p->variant < 0 || p->variant > 2) return fail(RELOC_E_INVALID, "variant must be 0, 1 or 2");
+  if (p->variant < 0 || p->variant > 5) return fail(RELOC_E_INVALID, "variant must be in 0..5");
   return RELOC_OK;
 }
 
@@ -709,7 +745,7 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   int8_t* docc = (int8_t*)c->dalloc(N);
   int32_t* g = (int32_t*)c->dalloc(N * sizeof(int32_t));
   m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
-  m.skip = (uint8_t*)c->dalloc((size_t)m.tpr * m.tph * 64);
+  m.skip = (uint8_t*)c->dalloc(N);
   m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
   auto cleanup = [&]() {
     c->dfree(docc);
@@ -725,7 +761,7 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   hipError_t e = hipMemcpyAsync(docc, occ, N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_bitpack(docc, m.W, m.H, m.thr, m.bits, m.tpr, m.tph, c->stream);
   if (e == hipSuccess) e = launch_edt(docc, m.W, m.H, m.thr, g, m.kmap, c->stream);
-  if (e == hipSuccess) e = launch_skipmap(m.kmap, m.W, m.H, m.tpr, m.tph, m.skip, c->stream);
+  if (e == hipSuccess) e = launch_skipmap(m.kmap, m.W, m.H, m.skip, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {
@@ -1018,26 +1054,21 @@ int32_t reloc_debug_raycast(reloc_ctx* c, int32_t request_id, int32_t* hit_cell,
   Request& R = it->second;
   const size_t n = (size_t)R.n_hyp * R.prep.info.Ns;
   int32_t* dh = (int32_t*)c->dalloc(n * sizeof(int32_t));
-  float* dr = (float*)c->dalloc(n * sizeof(float));
   int32_t* ds = steps ? (int32_t*)c->dalloc(n * sizeof(int32_t)) : nullptr;
-  if (!dh || !dr || (steps && !ds)) {
+  if (!dh || (steps && !ds)) {
     c->dfree(dh);
-    c->dfree(dr);
     c->dfree(ds);
     return RELOC_E_NOMEM;
   }
-  RayArgs ra = ray_args(c, R, dh, dr);
-  ra.dbg_steps = ds;
-  hipError_t e = launch_raycast_smad(ra, c->stream);
+  hipError_t e = launch_raycast_smad(ray_args(c, R, dh, ds), c->stream);
   if (e == hipSuccess && hit_cell)
     e = hipMemcpyAsync(hit_cell, dh, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && range)
-    e = hipMemcpyAsync(range, dr, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(range, R.zbuf, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && steps)
     e = hipMemcpyAsync(steps, ds, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   c->dfree(dh);
-  c->dfree(dr);
   c->dfree(ds);
   if (e != hipSuccess) return fail(RELOC_E_DEVICE, "debug ray cast failed: %s", hipGetErrorString(e));
   return RELOC_OK;

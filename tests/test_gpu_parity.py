@@ -156,7 +156,7 @@ def _cleanup(ctx, m, sid, rid):
     ctx.unload_map(m)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 4])
 @pytest.mark.parametrize("Ns,fov_deg,seed", [(480, 270, 0), (360, 360, 1), (64, 180, 2),
                                              (1440, 360, 3), (8, 360, 4), (4096, 360, 5),
                                              (960, 90, 6)])
@@ -187,7 +187,7 @@ def test_raycast_and_smad_micro(ctx, Ns, fov_deg, seed, variant):
     _cleanup(ctx, m, sid, rid)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_raycast_smad_c1_full(ctx, c1, variant):
     w, k, hyp = c1
     _case("raycast+smad c1 300 hyps variant=%d" % variant)
