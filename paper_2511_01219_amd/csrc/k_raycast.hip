@@ -1,11 +1,12 @@
-// Fused panoramic ray cast (eq. 13-14) and SMAD scoring (eq. 16-20).
+// Panoramic ray cast (eq. 13-14) and SMAD scoring (eq. 16-20).
 //
-// One workgroup per positional hypothesis. Its threads cast the Ns rays of
-// the panoramic synthetic scan with an exact integer supercover traversal,
-// leave the ranges in LDS, form the cyclic prefix sums of eq. 17 in FP64
-// (every partial sum is an exact multiple of 2^-29 below 2^18 for ranges in
-// [2^-6, 2^6) m, so the summation order cannot change a bit), score every
-// circular shift with eq. 18-19 and reduce to the eq. 20 minimum.
+// The ray cast writes one range per (hypothesis, direction) to a range
+// buffer; the SMAD kernel (one workgroup per positional hypothesis) loads a
+// hypothesis' Ns ranges into LDS, forms the cyclic prefix sums of eq. 17 in
+// FP64 (every partial sum is an exact multiple of 2^-29 below 2^18 for
+// ranges in [2^-6, 2^6) m, so the summation order cannot change a bit),
+// scores every circular shift with eq. 18-19 and reduces to the eq. 20
+// minimum.
 //
 // Traversal. The ray leaves the centre of cell (ix0, iy0), X = 256 ix0 + 128
 // in Q8 units, along the integer direction U. After nx x-crossings and ny
@@ -18,20 +19,19 @@
 // cut-off, or the range exceeds range_max.
 //
 // Two interchangeable variants (identical results):
-//  * bits: one 8x8-cell tile per uint64, one occupancy test per crossing;
-//  * skip: one byte per cell in 8x8 tiles holding 0 for occupied cells and
-//    1 + s for free ones, s = floor(sqrt(k) - 1.4145) cells, k the squared
-//    EDT value. No occupied cell centre lies within sqrt(k) of this cell's
-//    centre, so any ray segment of length s starting inside the cell only
-//    touches free cells (a touched cell's centre is within 0.7072 of the
-//    segment, the segment starts within 0.7072 of this centre). The traversal
-//    then jumps J = floor(s |U_major| / |U|) crossings along the major axis in
-//    one step and recomputes the exact state: the count of minor-axis
-//    crossings at or before the landing parameter (integer division, exact)
-//    and D from the counts. Jumps never skip an occupied cell, so hits,
-//    ranges and tie rules are those of the step-by-step traversal.
-// Rays are handed to lanes dynamically (LDS counter), so a lane that finishes
-// a short ray starts the next one at once instead of idling.
+//  * bits: one 8x8-cell tile per uint64, one occupancy test per crossing,
+//    one workgroup per hypothesis;
+//  * skip: walk words (0 occupied; else a free-space radius byte 1 + s,
+//    s = floor(sqrt(k) - 1.4145) cells with k the squared EDT value, and the
+//    number of free cells that follow along the ray's major direction). No
+//    occupied cell centre lies within sqrt(k) of the cell's centre, so a ray
+//    segment of length s starting inside the cell only touches free cells (a
+//    touched cell's centre is within 0.7072 of the segment, the segment starts
+//    within 0.7072 of this centre). The traversal jumps over such free space
+//    and recomputes the exact crossing state at the landing point, so hits,
+//    ranges and tie rules are those of the step-by-step traversal. The rays
+//    of all hypotheses form one index space split into chunks, one
+//    single-wavefront workgroup per chunk, with lanes refilled as rays end.
 #include <climits>
 #include <cmath>
 
@@ -114,11 +114,12 @@ __device__ float cast_ray_bits(const uint64_t* __restrict__ bits, int W, int H, 
 }
 
 // ----------------------------------------------------------------- variant: skip
-// Row-major skip bytes read through a buffer resource with 32-bit offsets.
-struct SkipMap {
+// Walk words read through a buffer resource with 32-bit byte offsets; a
+// ray reads the plane of its major direction of travel.
+struct WalkMap {
   __amdgpu_buffer_rsrc_t rsrc;
-  __device__ __forceinline__ uint32_t at(int off) const {
-    return __builtin_amdgcn_raw_buffer_load_b8(rsrc, (uint32_t)off, 0, 0);
+  __device__ __forceinline__ uint32_t at(uint32_t pbase, int off) const {
+    return __builtin_amdgcn_raw_buffer_load_b16(rsrc, pbase + 2u * (uint32_t)off, 0, 0);
   }
 };
 
@@ -133,14 +134,17 @@ struct SkipRay {
   int om, on;          // cell-offset change of a major / minor crossing
   int Dm, na, nb, off, it;
   int la, lb;          // last in-range major / minor crossing count
+  uint32_t pbase;      // byte offset of the ray's walk plane
   float f, r;          // major crossings per cell of path (rounded down), b / a
+  float inv;           // 1 / (256 b), +inf for b = 0
   float kmaj, kmin;    // metres per Q8 unit along the major / minor axis
-  uint32_t v;          // skip byte of the current cell
+  uint32_t v;          // walk word of the current cell
   bool xmaj;
 };
 
 __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix0, int iy0,
-                                          int W, int H, int rcells, const SkipMap& sm) {
+                                          int W, int H, int rcells, uint32_t plane_bytes,
+                                          const WalkMap& sm) {
   const int ux = di.x, uy = di.y;
   const int ax = abs(ux), ay = abs(uy);
   r.xmaj = ax >= ay;
@@ -153,6 +157,8 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   const int ly = min(rcells, uy > 0 ? H - 1 - iy0 : (uy < 0 ? iy0 : rcells));
   r.la = r.xmaj ? lx : ly;
   r.lb = r.xmaj ? ly : lx;
+  r.pbase = (uint32_t)di.z * plane_bytes;
+  r.inv = __int_as_float(di.w);
   r.f = df.x;
   r.r = df.y;
   r.kmaj = r.xmaj ? df.z : df.w;
@@ -160,25 +166,50 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.Dm = (r.b - r.a) << 7;
   r.na = r.nb = r.it = 0;
   r.off = iy0 * W + ix0;
-  r.v = sm.at(r.off);
+  r.v = sm.at(r.pbase, r.off);
 }
 
-// One iteration: an optional free-space jump, then one exact crossing with
-// an occupancy test of the entered cell(s). Returns true when the ray ends;
-// *z / *hit then hold its range (0 / -1 for none). Counts beyond la / lb
-// mean the ray left the map or passed the cut-off: a miss.
+// One iteration: at most one exact free-space jump, then one exact crossing
+// with an occupancy test of the entered cell(s). Returns true when the ray
+// ends; *z / *hit then hold its range (0 / -1 for none). Counts beyond
+// la / lb mean the ray left the map or passed the cut-off: a miss.
 //
-// Jump: J major crossings are safe (all touched cells free). The state just
-// after the (na + J)-th major crossing has the unique minor count with
-// 256 (b - a) <= Dm < 256 b. A float estimate of that count is within one of
-// it; Dm is evaluated in wrapping 32-bit arithmetic (exact, the true value is
-// within one step of the window) and one correction lands in the window.
-__device__ __forceinline__ bool skip_iter(SkipRay& r, const SkipMap& sm, int off0, float* z,
+// Two jumps are possible from the current cell, both landing just after a
+// major crossing on the exact crossing sequence; the one reaching further
+// is taken.
+//  * Run jump: while Dm < 0 the next ceil(-Dm / 256 b) crossings are all
+//    major, i.e. cells of the current minor row; the walk word says how
+//    many of those are free (run). A float estimate of the ceiling is at
+//    most one above it and is checked once in exact integers.
+//  * Radius jump: J major crossings are safe when all cells within the
+//    free-space radius are free. The state just after the (na + J)-th major
+//    crossing has the unique minor count with 256 (b - a) <= Dm < 256 b. A
+//    float estimate of that count is within one of it; Dm is evaluated in
+//    wrapping 32-bit arithmetic (exact, the true value is within one step of
+//    the window) and one correction lands in the window.
+__device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off0, float* z,
                                           int* hit) {
   ++r.it;
-  const int s = (int)r.v - 1;
+  const int s = (int)(r.v & 255u) - 1;
   const int J = s >= 2 ? (int)((float)s * r.f) : 0;
-  if (J > 0) {
+  int kr = 0;
+  if (r.Dm < 0) {
+    const float est = fminf((float)(-r.Dm) * r.inv, 256.f);
+    kr = min((int)(r.v >> 8), (int)ceilf(est));
+    if (kr > 0 && r.Dm + (r.b << 8) * (kr - 1) >= 0) --kr;
+  }
+  if (kr >= J) {
+    if (kr > 0) {
+      r.na += kr;
+      r.Dm += (r.b << 8) * kr;
+      r.off += kr * r.om;
+      if (r.na > r.la) {
+        *z = 0.f;
+        *hit = -1;
+        return true;
+      }
+    }
+  } else {
     const int na = r.na + J;
     int nb = (int)floorf(((float)na - 0.5f) * r.r - 0.5f) + 1;
     int Dm = (int)((uint32_t)(128 + 256 * na) * (uint32_t)r.b -
@@ -203,7 +234,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const SkipMap& sm, int off
     r.Dm += maj ? (r.b << 8) : -(r.a << 8);
     r.off += maj ? r.om : r.on;
     const bool out = r.na > r.la || r.nb > r.lb;
-    r.v = out ? 1u : sm.at(r.off);
+    r.v = out ? 1u : sm.at(r.pbase, r.off);
     const bool occ = r.v == 0;
     if (out || occ) {
       const int n = maj ? r.na : r.nb;
@@ -216,11 +247,12 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const SkipMap& sm, int off
   // exact corner: both neighbours and the diagonal share the entry parameter
   const bool ina = r.na + 1 <= r.la, inb = r.nb + 1 <= r.lb;
   int best = -1;
-  if (ina && sm.at(r.off + r.om) == 0) best = r.off + r.om;
-  if (inb && sm.at(r.off + r.on) == 0) best = (best < 0 || r.off + r.on < best) ? r.off + r.on : best;
+  if (ina && sm.at(r.pbase, r.off + r.om) == 0) best = r.off + r.om;
+  if (inb && sm.at(r.pbase, r.off + r.on) == 0)
+    best = (best < 0 || r.off + r.on < best) ? r.off + r.on : best;
   const bool ind = ina && inb;
   const int dg = r.off + r.om + r.on;
-  const uint32_t vd = ind ? sm.at(dg) : 1u;
+  const uint32_t vd = ind ? sm.at(r.pbase, dg) : 1u;
   if (ind && vd == 0) best = (best < 0 || dg < best) ? dg : best;
   r.off = dg;
   ++r.na;
@@ -237,9 +269,9 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const SkipMap& sm, int off
   return false;
 }
 
-__device__ __forceinline__ SkipMap make_skipmap(const RayArgs& a) {
-  SkipMap sm;
-  sm.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.skip, (short)0, (int)a.skip_bytes,
+__device__ __forceinline__ WalkMap make_walkmap(const RayArgs& a) {
+  WalkMap sm;
+  sm.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.walk, (short)0, (int)a.walk_bytes,
                                               0x00020000);
   return sm;
 }
@@ -259,7 +291,8 @@ __global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
   const int64_t q0 = (int64_t)blockIdx.x * a.chunk;
   const int pool = (int)min((int64_t)a.chunk, total - q0);
   const float inv_ns = 1.0f / (float)Ns;
-  const SkipMap sm = make_skipmap(a);
+  const WalkMap sm = make_walkmap(a);
+  const uint32_t plane_bytes = a.walk_bytes >> 2;
   int next = 64;
   int q = lane, off0 = 0;
   bool busy = q < pool;
@@ -273,7 +306,7 @@ __global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
     jj = g - (int64_t)h * Ns;
     const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
     off0 = iy0 * W + ix0;
-    skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, sm);
+    skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, plane_bytes, sm);
   };
   if (busy) start(q);
   for (;;) {
@@ -426,7 +459,7 @@ __global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
   const dim3 b(RT);
-  if (a.skip && a.variant >= 1) {
+  if (a.walk && a.variant >= 1) {
     const int64_t total = (int64_t)a.n_hyp * a.Ns;
     const dim3 g((unsigned)((total + a.chunk - 1) / a.chunk)), w(64);
     switch (a.variant) {
@@ -445,26 +478,65 @@ hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Skip byte per cell from the squared EDT: 0 occupied, else 1 + s with
-// s = floor(sqrt(k) - 1.4145) clamped to [0, 254]; row-major.
+// Walk words from the squared EDT. The radius byte is 1 + s with
+// s = floor(sqrt(k) - 1.4145) clamped to [0, 254]: every cell whose centre
+// lies within s cells of a free cell's centre is free. Runs are counted by
+// one thread per row (x planes) or per column (y planes), walking against
+// the plane's direction.
 namespace {
-__global__ void skipmap_kernel(const uint32_t* __restrict__ k, uint32_t n,
-                               uint8_t* __restrict__ out) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t kk = k[i];
-  uint8_t v = 0;
-  if (kk != 0) {
-    const float s = floorf(__fsqrt_rn((float)kk) - 1.4145f);
-    v = (uint8_t)(1 + (int)fminf(254.f, fmaxf(0.f, s)));
+__device__ __forceinline__ uint32_t radius_byte(uint32_t kk) {
+  if (kk == 0) return 0;
+  const float s = floorf(__fsqrt_rn((float)kk) - 1.4145f);
+  return 1u + (uint32_t)fminf(254.f, fmaxf(0.f, s));
+}
+
+__global__ void walk_rows_kernel(const uint32_t* __restrict__ k, int W, int H,
+                                 uint16_t* __restrict__ out) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= H) return;
+  const size_t N = (size_t)W * H;
+  const size_t row = (size_t)y * W;
+  uint32_t run = 0;   // free cells after x towards +x
+  for (int x = W - 1; x >= 0; --x) {
+    const uint32_t s = radius_byte(k[row + x]);
+    out[row + x] = (uint16_t)(s ? (s | run << 8) : 0u);
+    run = s ? min(run + 1u, 255u) : 0u;
   }
-  out[i] = v;
+  run = 0;            // free cells after x towards -x
+  for (int x = 0; x < W; ++x) {
+    const uint32_t s = radius_byte(k[row + x]);
+    out[N + row + x] = (uint16_t)(s ? (s | run << 8) : 0u);
+    run = s ? min(run + 1u, 255u) : 0u;
+  }
+}
+
+__global__ void walk_cols_kernel(const uint32_t* __restrict__ k, int W, int H,
+                                 uint16_t* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  const size_t N = (size_t)W * H;
+  uint32_t run = 0;   // towards +y
+  for (int y = H - 1; y >= 0; --y) {
+    const size_t c = (size_t)y * W + x;
+    const uint32_t s = radius_byte(k[c]);
+    out[2 * N + c] = (uint16_t)(s ? (s | run << 8) : 0u);
+    run = s ? min(run + 1u, 255u) : 0u;
+  }
+  run = 0;            // towards -y
+  for (int y = 0; y < H; ++y) {
+    const size_t c = (size_t)y * W + x;
+    const uint32_t s = radius_byte(k[c]);
+    out[3 * N + c] = (uint16_t)(s ? (s | run << 8) : 0u);
+    run = s ? min(run + 1u, 255u) : 0u;
+  }
 }
 }  // namespace
 
-hipError_t launch_skipmap(const uint32_t* k, int W, int H, uint8_t* out, hipStream_t s) {
-  const uint32_t n = (uint32_t)W * (uint32_t)H;
-  hipLaunchKernelGGL(skipmap_kernel, dim3((n + 255) / 256), dim3(256), 0, s, k, n, out);
+hipError_t launch_walkmap(const uint32_t* k, int W, int H, uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(walk_rows_kernel, dim3((H + 63) / 64), dim3(64), 0, s, k, W, H, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(walk_cols_kernel, dim3((W + 63) / 64), dim3(64), 0, s, k, W, H, out);
   return hipGetLastError();
 }
 

@@ -20,9 +20,9 @@ hipError_t launch_edt(const int8_t* occ, int W, int H, int thr, int32_t* g, uint
 // ---- ray cast + SMAD (fused) --------------------------------------------
 struct RayArgs {
   const uint64_t* bits;
-  const uint8_t* skip;       // row-major bytes: 0 occupied, 1 + free-space radius
-  uint32_t skip_bytes;
-  const int4* dir_i;         // [Ns] (Ux, Uy, lo, hi) per direction (skip variant)
+  const uint16_t* walk;      // [4][H][W] walk words (see launch_walkmap), or null
+  uint32_t walk_bytes;
+  const int4* dir_i;         // [Ns] (Ux, Uy, walk plane, bits of 1/(256 |U_minor|))
   const float4* dir_f;       // [Ns] (f, r, kappa_x, kappa_y) per direction
   int variant;               // 0: bit tiles; 1-4: distance skipping with wavefront
                              // ray refill once 1 / 8 / 16 / 32 lanes are idle
@@ -49,8 +49,12 @@ struct RayArgs {
   int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray
 };
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
-// free-space skip bytes (8x8 tiles) from the squared EDT
-hipError_t launch_skipmap(const uint32_t* k, int W, int H, uint8_t* out, hipStream_t s);
+// Walk words from the squared EDT: four row-major planes, one per major
+// direction of travel (+x, -x, +y, -y). A word is 0 for an occupied cell,
+// else s | run << 8 with s = 1 + free-space radius byte and run = free
+// cells that follow in the plane's direction inside the map (at most 255).
+constexpr size_t kWalkMaxCells = (size_t)1 << 28;
+hipError_t launch_walkmap(const uint32_t* k, int W, int H, uint16_t* out, hipStream_t s);
 
 // ---- sorting (hipCUB radix sort) -----------------------------------------
 hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,

@@ -216,7 +216,7 @@ struct DevMap {
   int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
   double res = 0.05, ox = 0, oy = 0;
   uint64_t* bits = nullptr;
-  uint8_t* skip = nullptr;
+  uint16_t* walk = nullptr;       // null when the map exceeds kWalkMaxCells
   uint32_t* kmap = nullptr;
   std::vector<int8_t> occ;        // host copy for the sampler
   std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
@@ -480,10 +480,10 @@ int32_t build_request(reloc_ctx* c, Request& R) {
     const int amaj = xmaj ? ax : ay, bmin = xmaj ? ay : ax;
     di[j].x = rd[j].x;
     di[j].y = rd[j].y;
-    // D window just after a major crossing: x major 256(ay-ax) <= D < 256 ay,
-    // y major -256 ax < D <= 256(ay-ax)
-    di[j].z = xmaj ? (ay - ax) * 256 : -(ax * 256) + 1;
-    di[j].w = xmaj ? ay * 256 - 1 : (ay - ax) * 256;
+    // walk plane of the major direction of travel: +x, -x, +y, -y
+    di[j].z = xmaj ? (rd[j].x < 0 ? 1 : 0) : (rd[j].y < 0 ? 3 : 2);
+    const float inv = bmin > 0 ? (float)(1.0 / (256.0 * bmin)) : INFINITY;
+    std::memcpy(&di[j].w, &inv, sizeof(float));
     const double nrm = std::sqrt((double)ax * ax + (double)ay * ay);
     df[j].x = (float)((double)amaj / nrm * 0.99999);   // rounds down a hair
     df[j].y = (float)((double)bmin / (double)amaj);
@@ -542,8 +542,8 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
   const reloc_scan_info& I = R.prep.info;
   RayArgs a;
   a.bits = m.bits;
-  a.skip = m.skip;
-  a.skip_bytes = (uint32_t)((size_t)m.W * m.H);
+  a.walk = m.walk;
+  a.walk_bytes = (uint32_t)(4 * sizeof(uint16_t) * (size_t)m.W * m.H);
   a.dir_i = R.dir_i;
   a.dir_f = R.dir_f;
   // public variant: 1 bit tiles; 2, 3, 4, 5 skipping with wavefront refill
@@ -700,7 +700,7 @@ void reloc_ctx_destroy(reloc_ctx* c) {
     for (auto& kv : c->sets) c->dfree(kv.second.dev);
     for (auto& kv : c->maps) {
       c->dfree(kv.second.bits);
-      c->dfree(kv.second.skip);
+      c->dfree(kv.second.walk);
       c->dfree(kv.second.kmap);
     }
     c->reqs.clear();
@@ -745,28 +745,28 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   int8_t* docc = (int8_t*)c->dalloc(N);
   int32_t* g = (int32_t*)c->dalloc(N * sizeof(int32_t));
   m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
-  m.skip = (uint8_t*)c->dalloc(N);
+  if (N <= kWalkMaxCells) m.walk = (uint16_t*)c->dalloc(4 * N * sizeof(uint16_t));
   m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
   auto cleanup = [&]() {
     c->dfree(docc);
     c->dfree(g);
   };
-  if (!docc || !g || !m.bits || !m.skip || !m.kmap) {
+  if (!docc || !g || !m.bits || (N <= kWalkMaxCells && !m.walk) || !m.kmap) {
     cleanup();
     c->dfree(m.bits);
-    c->dfree(m.skip);
+    c->dfree(m.walk);
     c->dfree(m.kmap);
     return RELOC_E_NOMEM;
   }
   hipError_t e = hipMemcpyAsync(docc, occ, N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_bitpack(docc, m.W, m.H, m.thr, m.bits, m.tpr, m.tph, c->stream);
   if (e == hipSuccess) e = launch_edt(docc, m.W, m.H, m.thr, g, m.kmap, c->stream);
-  if (e == hipSuccess) e = launch_skipmap(m.kmap, m.W, m.H, m.skip, c->stream);
+  if (e == hipSuccess && m.walk) e = launch_walkmap(m.kmap, m.W, m.H, m.walk, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {
     c->dfree(m.bits);
-    c->dfree(m.skip);
+    c->dfree(m.walk);
     c->dfree(m.kmap);
     return fail(RELOC_E_DEVICE, "map upload failed: %s", hipGetErrorString(e));
   }
@@ -784,7 +784,7 @@ int32_t reloc_unload_map(reloc_ctx* c, int32_t map_id) {
   if (it->second.n_sets > 0) return fail(RELOC_E_BUSY, "map %d has live hypothesis sets", map_id);
   (void)hipStreamSynchronize(c->stream);
   c->dfree(it->second.bits);
-  c->dfree(it->second.skip);
+  c->dfree(it->second.walk);
   c->dfree(it->second.kmap);
   c->maps.erase(it);
   return RELOC_OK;
