@@ -30,47 +30,96 @@ if ROOT not in sys.path:
 
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: CUs x SIMDs x lanes x clock
 DDA_OPS_PER_STEP = 10                      # compare, 2 selects, D update, 2 bounds, 3 address, 1 bit test
+RAYCAST_SOURCES = ("paper_2511_01219_amd/csrc/k_raycast.hip",
+                   "paper_2511_01219_amd/csrc/reloc_internal.h")
+TRAFFIC_FILE = "profiles/raycast_skip_kernel_plain-large_traffic.txt"
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def exact_crossings(hit, hyp, Ns, W, H, rcells):
+    """Cell crossings of the plain step-by-step traversal of every ray: for a
+    hit |dx| + |dy| to the hit cell; for a miss the crossings done when the
+    ray first passes the map edge or the cut-off (continuous geometry)."""
+    import numpy as np
+    n = len(hyp)
+    hit = hit.reshape(n, Ns)
+    ix0 = hyp[:, 0:1].astype(np.int64)
+    iy0 = hyp[:, 1:2].astype(np.int64)
+    h = hit.astype(np.int64)
+    hx, hy = h % W, h // W
+    steps = np.where(h >= 0, np.abs(hx - ix0) + np.abs(hy - iy0), 0)
+    ang = 2.0 * np.pi * np.arange(Ns) / Ns
+    ux, uy = np.cos(ang)[None, :], np.sin(ang)[None, :]
+    ux = np.where(np.abs(ux) < 1e-12, 0.0, ux)
+    uy = np.where(np.abs(uy) < 1e-12, 0.0, uy)
+    lx = np.minimum(rcells, np.where(ux > 0, W - 1 - ix0, np.where(ux < 0, ix0, rcells)))
+    ly = np.minimum(rcells, np.where(uy > 0, H - 1 - iy0, np.where(uy < 0, iy0, rcells)))
+    ax, ay = np.abs(ux), np.abs(uy)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = np.where(ax > 0, (0.5 + lx) / ax, np.inf)
+        ty = np.where(ay > 0, (0.5 + ly) / ay, np.inf)
+        te = np.minimum(tx, ty)
+        cx = np.where(ax > 0, np.floor(te * ax - 0.5) + 1, 0)
+        cy = np.where(ay > 0, np.floor(te * ay - 0.5) + 1, 0)
+    miss = cx + cy
+    return int(np.where(h >= 0, steps, miss).sum())
+
+
+def measured_traffic():
+    """HBM bytes per launch of the ray-cast kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    hs = hashlib.sha256()
+    for f in RAYCAST_SOURCES:
+        hs.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256") != hs.hexdigest():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, hyp, n_theta, batch_k, stages_gpu, budget_s):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    ray cast + SMAD for a hypothesis subsample and TAM for the first stages."""
+    """The oracle as it stands on the host cores: whole steps of the same
+    workload (ray cast and direct-sum SMAD of every hypothesis, TAM of the
+    stages the GPU ran), repeated until about budget_s has passed."""
     import numpy as np
     import oracle
     pr = oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
                      range_min=w.range_min, range_max=w.range_max, n_theta=n_theta)
     k = oracle.edt(w.occ)
     threads = oracle.num_threads()
-    # size the sample from a short probe so the whole leg stays near budget_s
-    probe = hyp[:200]
-    t = time.perf_counter()
-    _, z = oracle.raycast(w.occ, probe, pr["Ns"], pr["Ng"], w.resolution, w.range_max)
-    oracle.smad(z, pr)
-    per_hyp = (time.perf_counter() - t) / len(probe)
-    q = np.repeat(hyp[:2], n_theta, axis=0)
-    kk = np.tile(np.arange(n_theta), 2)
-    t = time.perf_counter()
-    oracle.tam(k, w.resolution, pr, q, kk)
-    per_tam_hyp = (time.perf_counter() - t) / 2
-    n_sm = int(min(len(hyp), max(200, 0.6 * budget_s / per_hyp)))
-    n_st = int(min(stages_gpu, max(1, 0.4 * budget_s / (per_tam_hyp * batch_k))))
+    n_tam = min(len(hyp), stages_gpu * batch_k)
+    steps, evals = 0, 0
     t0 = time.perf_counter()
-    _, z = oracle.raycast(w.occ, hyp[:n_sm], pr["Ns"], pr["Ng"], w.resolution, w.range_max)
-    sm, _ = oracle.smad(z, pr)
-    n_tam = min(len(sm), n_st * batch_k)
-    q = np.repeat(hyp[:n_tam], n_theta, axis=0)
-    kk = np.tile(np.arange(n_theta), n_tam)
-    oracle.tam(k, w.resolution, pr, q, kk)
-    dt = time.perf_counter() - t0
-    evals = n_sm * pr["n_shifts"] + n_tam * n_theta
+    while True:
+        _, z = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], w.resolution, w.range_max)
+        sm, _ = oracle.smad(z, pr)
+        order = np.lexsort((np.arange(len(sm)), sm))[:n_tam]
+        q = np.repeat(hyp[order], n_theta, axis=0)
+        kk = np.tile(np.arange(n_theta), n_tam)
+        oracle.tam(k, w.resolution, pr, q, kk)
+        steps += 1
+        evals += len(hyp) * pr["n_shifts"] + n_tam * n_theta
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": "ray cast + direct-sum SMAD of %d of %d hypotheses, TAM of %d "
-                      "hypotheses x %d orientations (%d stages); %.1f s"
-                      % (n_sm, len(hyp), n_tam, n_theta, n_st, dt)}
+            "sample": "%d whole steps: ray cast + direct-sum SMAD of all %d hypotheses, "
+                      "TAM of the first %d in SMAD order x %d orientations; %.1f s"
+                      % (steps, len(hyp), n_tam, n_theta, dt)}
 
 
 def main():
@@ -85,8 +134,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per launch of the ray-cast kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -99,9 +146,12 @@ def main():
     from synth import make_config
 
     if args.calibrate_copy:
+        # one device-to-device copy (a plain copy kernel): reads and writes
+        # exactly this many bytes, the scale of the HBM byte counters
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         log("calibration copy of %d MiB done" % args.calibrate_copy)
@@ -124,7 +174,7 @@ def main():
     for _ in range(args.warmup):
         ctx.run(rid)
     torch.cuda.synchronize()
-    lat, evals, ray_ms, tam_ms, tot_ms = [], 0, [], [], []
+    lat, evals, ray_ms, smad_ms, tam_ms, tot_ms = [], 0, [], [], [], []
     last = None
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -133,6 +183,7 @@ def main():
         lat.append(time.perf_counter() - ts)
         evals += st["smad_evals"] + st["tam_evals"]
         ray_ms.append(st["ms_raycast"])
+        smad_ms.append(st["ms_smad"])
         tam_ms.append(st["ms_tam"])
         tot_ms.append(st["ms_total"])
         last = (poses, st)
@@ -143,23 +194,27 @@ def main():
     log("timed %d steps in %.3f s; stages %d, early stop %d" % (args.steps, elapsed,
                                                               st["stages"], st["early_stopped"]))
 
-    # roofline of the dominant kernel (fused ray cast + SMAD): algorithmic
-    # integer ops = DDA iterations x ops per iteration, counted once outside
-    # the timed region with the same kernel's step output
-    _, _, steps = ctx.debug_raycast(rid, n_hyp, reloc.scan_info(
-        w.ranges, w.angle_min, w.angle_increment, w.resolution, w.range_min, w.range_max,
-        n_theta=n_theta)["Ns"], steps=True)
-    dda_steps = int(steps.astype(np.int64).sum())
+    # roofline of the dominant kernel (the ray cast): algorithmic work = the
+    # cell crossings of the plain step-by-step traversal x DDA_OPS_PER_STEP
+    # integer lane-ops, over the kernel's mean duration from the hipEvents
+    # recorded around it on the library's stream in every timed step
+    Ns = reloc.scan_info(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                         w.range_min, w.range_max, n_theta=n_theta)["Ns"]
+    hit, _, iters = ctx.debug_raycast(rid, n_hyp, Ns, steps=True)
+    rcells = int(math.ceil(w.range_max / w.resolution)) + 2
+    crossings = exact_crossings(hit, hyp[:n_hyp], Ns, w.occ.shape[1], w.occ.shape[0], rcells)
+    iterations = int(iters.astype(np.int64).sum())
     t_ray = float(np.mean(ray_ms)) * 1e-3
-    achieved = dda_steps * DDA_OPS_PER_STEP / t_ray
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-    roofline = {"kernel": "raycast_smad_kernel", "bound": "alu",
+    achieved = crossings * DDA_OPS_PER_STEP / t_ray
+    traffic = measured_traffic()
+    kname = {1: "raycast_bits_kernel", 2: "raycast_skip_kernel<1>", 3: "raycast_skip_kernel<8>",
+             4: "raycast_skip_kernel<16>", 5: "raycast_skip_kernel<32>"}.get(args.variant or 4)
+    roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-                "traffic": traffic, "dda_steps": dda_steps,
-                "avg_ms": t_ray * 1e3}
+                "unit": "TOP/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
+                "traffic": traffic, "dda_crossings": crossings,
+                "loop_iterations": iterations, "avg_ms": t_ray * 1e3,
+                "crossings_per_s": crossings / t_ray}
     out = {
         "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
         "value": evals / elapsed,
@@ -181,6 +236,7 @@ def main():
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
                      "stages": st["stages"], "early_stopped": st["early_stopped"],
                      "device_ms": float(np.mean(tot_ms)), "raycast_ms": float(np.mean(ray_ms)),
+                     "smad_ms": float(np.mean(smad_ms)),
                      "tam_ms": float(np.mean(tam_ms)), "rays": st["rays"],
                      "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"]},
         "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},

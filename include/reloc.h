@@ -236,7 +236,10 @@ typedef struct {
   int64_t rays;         /* N_p x Ns */
   int64_t tam_lookups;  /* tam_evals x N'_Z */
   int32_t n_hyp, stages, early_stopped, n_eval;
-  float ms_total, ms_raycast, ms_sort, ms_tam, ms_rank; /* device time */
+  /* device time (hipEvents on the context's stream): whole run; ray-cast
+   * kernel; SMAD kernel; SMAD order; TAM stages with stage control;
+   * ranking and result copy */
+  float ms_total, ms_raycast, ms_sort, ms_tam, ms_rank, ms_smad;
 } reloc_stats;
 
 /* ------------------------------------------------------------------------

@@ -72,7 +72,8 @@ class reloc_stats(C.Structure):
                 ("tam_lookups", C.c_int64), ("n_hyp", C.c_int32), ("stages", C.c_int32),
                 ("early_stopped", C.c_int32), ("n_eval", C.c_int32),
                 ("ms_total", C.c_float), ("ms_raycast", C.c_float), ("ms_sort", C.c_float),
-                ("ms_tam", C.c_float), ("ms_rank", C.c_float)]
+                ("ms_tam", C.c_float), ("ms_rank", C.c_float),
+                ("ms_smad", C.c_float)]
 
 
 # name -> (restype, argtypes)

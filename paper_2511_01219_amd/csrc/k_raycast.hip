@@ -456,9 +456,8 @@ __global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
 
 }  // namespace
 
-hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
+hipError_t launch_raycast(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
-  const dim3 b(RT);
   if (a.walk && a.variant >= 1) {
     const int64_t total = (int64_t)a.n_hyp * a.Ns;
     const dim3 g((unsigned)((total + a.chunk - 1) / a.chunk)), w(64);
@@ -469,13 +468,21 @@ hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
       default: hipLaunchKernelGGL(raycast_skip_kernel<32>, g, w, 0, s, a); break;
     }
   } else {
-    hipLaunchKernelGGL(raycast_bits_kernel, dim3(a.n_hyp), b, 0, s, a);
+    hipLaunchKernelGGL(raycast_bits_kernel, dim3(a.n_hyp), dim3(RT), 0, s, a);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t lds = (size_t)(a.Ns + 1) * sizeof(double);
-  hipLaunchKernelGGL(smad_kernel, dim3(a.n_hyp), b, lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
+  if (a.n_hyp <= 0) return hipSuccess;
+  const size_t lds = (size_t)(a.Ns + 1) * sizeof(double);
+  hipLaunchKernelGGL(smad_kernel, dim3(a.n_hyp), dim3(RT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
+  const hipError_t e = launch_raycast(a, s);
+  return e != hipSuccess ? e : launch_smad(a, s);
 }
 
 // Walk words from the squared EDT. The radius byte is 1 + s with

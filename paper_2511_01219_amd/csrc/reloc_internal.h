@@ -48,6 +48,8 @@ struct RayArgs {
   int32_t* dbg_hit;          // optional [n_hyp][Ns]
   int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray
 };
+hipError_t launch_raycast(const RayArgs& a, hipStream_t s);   // ranges into zbuf
+hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, argm, keys
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
 // Walk words from the squared EDT: four row-major planes, one per major
 // direction of travel (+x, -x, +y, -y). A word is 0 for an occupied cell,

@@ -944,8 +944,11 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   const DevMap& m = c->maps[R.map_id];
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = c->stream;
+  const RayArgs ra = ray_args(c, R, nullptr, nullptr);
   HIP_TRY(hipEventRecord(c->ev[0], s));
-  HIP_TRY(launch_raycast_smad(ray_args(c, R, nullptr, nullptr), s));
+  HIP_TRY(launch_raycast(ra, s));
+  HIP_TRY(hipEventRecord(c->ev[5], s));
+  HIP_TRY(launch_smad(ra, s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
   size_t tb = R.tmp_bytes;
   HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, s));
@@ -1019,8 +1022,10 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[4]);
     st->ms_total = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[5]);
     st->ms_raycast = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[5], c->ev[1]);
+    st->ms_smad = ms;
     (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
     st->ms_sort = ms;
     (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
