@@ -269,13 +269,87 @@ int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
                          reloc_pose* out, int32_t cap, int32_t* n_out, reloc_stats* stats);
 
 /* ------------------------------------------------------------------------
+ * Batched form: several prepared requests (any maps, scans and parameters)
+ * run together. One ray-cast launch and one SMAD launch cover the
+ * hypotheses of every request, one segmented sort gives every SMAD order,
+ * and the TAM stages of all requests advance together: each step launches
+ * TAM over a rank range of every unfinished request and one stage-control
+ * kernel that reduces each of its stages on the device (Sec. III pipeline,
+ * batch-wise early termination). A range covers 1, 2, 4, ... up to 32
+ * consecutive stages; stages after the first whose best T exceeds tau are
+ * discarded, so every request gets exactly the result of reloc_run.
+ *   request_ids : host int32[n], distinct prepared requests
+ *   out         : host reloc_pose[n * cap]; request i's poses at out + i*cap
+ *   n_out       : host int32[n] poses written per request
+ *   status      : host int32[n]: RELOC_OK, or RELOC_E_TIMEOUT when the
+ *                 request's deadline_s passed (best-so-far poses returned)
+ *   stats       : host reloc_stats[n] or NULL; the ms_* fields time the
+ *                 batch's phases and are the same for every request.
+ * Errors: RELOC_E_INVALID, RELOC_E_NOTFOUND, RELOC_E_NOMEM, RELOC_E_DEVICE.
+ * ---------------------------------------------------------------------- */
+int32_t reloc_run_batch(reloc_ctx* ctx, int32_t n, const int32_t* request_ids,
+                        reloc_pose* out, int32_t cap, int32_t* n_out, int32_t* status,
+                        reloc_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of requests as they arrive.
+ * reloc_submit preprocesses the scan on the calling thread and queues the
+ * request; a scheduler thread owned by the context repeats rounds of
+ *   admission (while fewer than max_inflight requests are on the device,
+ *   at most max_admit per round, and the request's device memory fits the
+ *   context budget minus hbm_reserve; a request that cannot fit even on an
+ *   idle device fails with RELOC_E_NOMEM) -> ray cast, SMAD and order of the
+ *   admitted requests (one launch each, as in reloc_run_batch) -> one TAM
+ *   step of every request in flight -> ranking of the finished ones.
+ * In-flight state (ranges, SMAD, orders, per-rank best) stays on the device;
+ * a request admitted while others run joins them at the next stage
+ * boundary. Each result equals reloc_run's for the same inputs.
+ * submit and poll may be called from any threads concurrently; other calls
+ * on the context wait for the current round. The hypothesis set of a queued
+ * request cannot be freed (RELOC_E_BUSY) until the request finished.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t max_inflight;   /* requests on the device at once (64) */
+  size_t hbm_reserve;     /* bytes of the context budget left free (0) */
+  int32_t max_admit;      /* requests admitted per round (64) */
+} reloc_serve_config;
+
+/* Replaces the scheduler configuration (takes effect at the next round). */
+int32_t reloc_serve_configure(reloc_ctx* ctx, const reloc_serve_config* cfg);
+
+/* Queues a relocalization; *ticket names it for reloc_poll. Errors of the
+ * host preprocessing (RELOC_E_INVALID, RELOC_E_NOTFOUND, RELOC_E_BEAMGRID,
+ * RELOC_E_EMPTY) are returned here. */
+int32_t reloc_submit(reloc_ctx* ctx, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                     const reloc_search_params* params, uint64_t* ticket);
+
+/* Waits up to wait_ms (0: do not wait, < 0: no limit) for the ticket.
+ * RELOC_E_PENDING: not finished (ticket stays valid). Otherwise the ticket
+ * is consumed: its poses (out: host reloc_pose[cap]), *n_out and stats
+ * (may be NULL; ms_total = submit to completion) are written and its status
+ * returned (RELOC_OK, RELOC_E_TIMEOUT with best-so-far poses, or the error
+ * that ended it). RELOC_E_NOTFOUND for an unknown or consumed ticket. */
+int32_t reloc_poll(reloc_ctx* ctx, uint64_t ticket, int32_t wait_ms, reloc_pose* out,
+                   int32_t cap, int32_t* n_out, reloc_stats* stats);
+
+typedef struct {
+  int64_t submitted, completed, failed, ticks;  /* ticks = scheduler rounds */
+  int32_t queued, inflight;
+  double busy_s;                                /* wall time spent in rounds */
+} reloc_serve_stats;
+
+int32_t reloc_serve_stats_get(reloc_ctx* ctx, reloc_serve_stats* out);
+
+/* ------------------------------------------------------------------------
  * Parity / inspection entry points (same kernels as reloc_run).
  * ---------------------------------------------------------------------- */
 
 /* Panoramic synthetic scan of every hypothesis of the request (eq. 13):
  * hit_cell: host int32[n_hyp*Ns] (linear index, -1 none), range: host
- * float[n_hyp*Ns] (0 none), steps: host int32[n_hyp*Ns] grid-line crossings
- * the traversal made (an exact corner counts once). Any pointer may be NULL. */
+ * float[n_hyp*Ns] (0 none), steps: host int32[n_hyp*Ns] traversal loop
+ * iterations of the ray-cast kernel in use (the bit-tile variant makes one per
+ * grid-line crossing, an exact corner counting once; the walk-word variants
+ * one per free-space jump plus crossing). Any pointer may be NULL. */
 int32_t reloc_debug_raycast(reloc_ctx* ctx, int32_t request_id, int32_t* hit_cell,
                             float* range, int32_t* steps);
 

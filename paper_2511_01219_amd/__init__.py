@@ -249,6 +249,62 @@ class Context:
         finally:
             self.release(rid)
 
+    # -- batched form -------------------------------------------------------------
+    def run_batch(self, request_ids: Sequence[int], cap: int = 64):
+        """Runs prepared requests together; returns [(poses, stats)] in order.
+        stats["status"] is OK or E_TIMEOUT per request."""
+        n = len(request_ids)
+        ids = np.ascontiguousarray(request_ids, dtype=np.int32)
+        out = (_abi.reloc_pose * max(1, n * cap))()
+        n_out = np.zeros(max(1, n), dtype=np.int32)
+        status = np.zeros(max(1, n), dtype=np.int32)
+        st = (_abi.reloc_stats * max(1, n))()
+        _check(self._lib.reloc_run_batch(self._h, n, _ptr(ids), out, int(cap), _ptr(n_out),
+                                         _ptr(status), st))
+        res = []
+        for i in range(n):
+            poses = [{f: getattr(out[i * cap + j], f) for f, _ in out[i * cap + j]._fields_}
+                     for j in range(int(n_out[i]))]
+            stats = {f: getattr(st[i], f) for f, _ in st[i]._fields_}
+            stats["status"] = int(status[i])
+            res.append((poses, stats))
+        return res
+
+    # -- serving ----------------------------------------------------------------------
+    def serve_configure(self, max_inflight: int = 64, hbm_reserve: int = 0, max_admit: int = 64):
+        cfg = _abi.reloc_serve_config(int(max_inflight), int(hbm_reserve), int(max_admit))
+        _check(self._lib.reloc_serve_configure(self._h, C.byref(cfg)))
+
+    def submit(self, map_id: int, set_id: int, ranges, angle_min: float,
+               angle_increment: float, range_min: float = 0.02, range_max: float = 30.0,
+               fov: Optional[Sequence] = None, **search) -> int:
+        sc = _Scan(ranges, angle_min, angle_increment, range_min, range_max, fov)
+        p = search_params(**search)
+        t = C.c_uint64()
+        _check(self._lib.reloc_submit(self._h, int(map_id), int(set_id), C.byref(sc.s),
+                                      C.byref(p), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, wait_ms: int = -1, cap: int = 64):
+        """(poses, stats) when finished, None while pending."""
+        out = (_abi.reloc_pose * max(1, cap))()
+        n = C.c_int32()
+        st = _abi.reloc_stats()
+        code = _check(self._lib.reloc_poll(self._h, C.c_uint64(int(ticket)), int(wait_ms), out,
+                                           int(cap), C.byref(n), C.byref(st)),
+                      allow=(E_PENDING, E_TIMEOUT))
+        if code == E_PENDING:
+            return None
+        poses = [{f: getattr(out[i], f) for f, _ in out[i]._fields_} for i in range(n.value)]
+        stats = {f: getattr(st, f) for f, _ in st._fields_}
+        stats["status"] = code
+        return poses, stats
+
+    def serve_stats(self) -> dict:
+        s = _abi.reloc_serve_stats()
+        _check(self._lib.reloc_serve_stats_get(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
     # -- parity / inspection ----------------------------------------------------
     def debug_raycast(self, request_id: int, n_hyp: int, Ns: int, steps: bool = False):
         hit = np.empty((n_hyp, Ns), dtype=np.int32)

@@ -76,6 +76,17 @@ class reloc_stats(C.Structure):
                 ("ms_smad", C.c_float)]
 
 
+class reloc_serve_config(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("hbm_reserve", C.c_size_t),
+                ("max_admit", C.c_int32)]
+
+
+class reloc_serve_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("ticks", C.c_int64), ("queued", C.c_int32), ("inflight", C.c_int32),
+                ("busy_s", C.c_double)]
+
+
 # name -> (restype, argtypes)
 PROTOS = {
     "reloc_version": (C.c_int32, []),
@@ -108,6 +119,15 @@ PROTOS = {
                                      C.POINTER(reloc_search_params), C.POINTER(reloc_pose),
                                      C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(reloc_stats)]),
+    "reloc_run_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(reloc_pose),
+                                    C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.POINTER(reloc_stats)]),
+    "reloc_serve_configure": (C.c_int32, [C.c_void_p, C.POINTER(reloc_serve_config)]),
+    "reloc_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(reloc_scan),
+                                 C.POINTER(reloc_search_params), C.POINTER(C.c_uint64)]),
+    "reloc_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(reloc_pose),
+                               C.c_int32, C.POINTER(C.c_int32), C.POINTER(reloc_stats)]),
+    "reloc_serve_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(reloc_serve_stats)]),
     "reloc_debug_raycast": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "reloc_debug_smad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,

@@ -1,0 +1,753 @@
+// Batched execution of many prepared requests (possibly on different maps
+// and scans) and the serving scheduler behind reloc_submit / reloc_poll.
+//
+// A batch runs in three phases on the context's stream:
+//   front : one ray-cast launch and one SMAD launch over the hypotheses of
+//           every request (per-request descriptors in device memory), then
+//           one segmented stable sort for all SMAD orders;
+//   ticks : each tick is one TAM launch per kernel class over a rank range
+//           of every unfinished request plus one stage-control launch that
+//           reduces every stage of the tick on the device; the host reads
+//           one flag per stage. A request's range covers `spec` consecutive
+//           stages (1, 2, 4, ... up to kMaxSpec); stages after the first one
+//           whose best T exceeds tau are discarded, so the evaluated set and
+//           every result equal those of the one-stage-at-a-time path;
+//   rank  : one segmented sort and one gather for every finished request.
+// The scheduler repeats admission -> front of the admitted requests -> one
+// tick of everything in flight -> rank of the finished ones, so requests
+// that arrive while others run join at the next stage boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "runtime_internal.h"
+
+namespace reloc {
+
+namespace {
+
+constexpr int kMaxSpec = 32;   // stages of one request in one tick, at most
+
+// Contiguous buffers of one front-phase group: SMAD sort keys / values, the
+// SMAD order and the per-rank best of every request of the group.
+struct Arena {
+  reloc_ctx* c = nullptr;
+  std::vector<void*> owned;
+  uint64_t *keys = nullptr, *keys2 = nullptr, *best = nullptr;
+  int32_t *vals = nullptr, *order = nullptr;
+  ~Arena() {
+    for (void* p : owned) c->dfree(p);
+  }
+  template <typename T>
+  T* get(size_t n) {
+    void* p = c->dalloc(std::max<size_t>(1, n) * sizeof(T));
+    if (p) owned.push_back(p);
+    return (T*)p;
+  }
+};
+
+// One request in batched execution.
+struct Flight {
+  int rid = -1;                     // key in c->reqs
+  std::shared_ptr<Arena> arena;
+  int64_t off = 0;                  // first hypothesis of the request in the arena
+  int next_rank = 0, spec = 1, stages = 0, n_eval = 0;
+  bool done = false, stopped = false;
+  int32_t status = RELOC_OK;
+  std::chrono::steady_clock::time_point t_start;
+  int tentry = 0, tstages = 0, tnb = 0;   // the current tick
+  uint64_t ticket = 0;                    // serving only
+};
+
+struct Ticket {
+  uint64_t id = 0;
+  Request R;                        // host part prepared at submit
+  bool done = false;
+  int32_t status = RELOC_E_PENDING;
+  std::vector<reloc_pose> poses;
+  reloc_stats st{};
+  std::chrono::steady_clock::time_point t_submit;
+};
+
+// Byte blob of descriptor tables, copied to the device in one transfer.
+struct Blob {
+  std::vector<uint8_t> b;
+  template <typename T>
+  size_t add(const T* p, size_t n) {
+    const size_t off = (b.size() + 255) & ~(size_t)255;
+    b.resize(off + n * sizeof(T));
+    if (n) std::memcpy(b.data() + off, p, n * sizeof(T));
+    return off;
+  }
+};
+
+}  // namespace
+
+struct ServeState {
+  // staging of descriptor tables: pinned host and device buffers
+  void* hbuf = nullptr;
+  size_t hcap = 0;
+  uint8_t* dbuf = nullptr;
+  size_t dcap = 0;
+  // per-tick stage outputs
+  uint64_t* dstage = nullptr;
+  int32_t* dflag = nullptr;
+  int32_t* hflag = nullptr;
+  size_t stage_cap = 0;
+  // serving
+  std::thread worker;
+  bool running = false;
+  std::mutex qmu;
+  std::condition_variable qcv, dcv;
+  bool stop = false;
+  std::deque<Ticket*> pending;
+  std::map<uint64_t, std::unique_ptr<Ticket>> tickets;
+  uint64_t next_ticket = 1;
+  std::vector<Flight> active;       // touched by the worker only
+  reloc_serve_config cfg{64, 0, 64};
+  reloc_serve_stats stats{};
+  int32_t worker_error = RELOC_OK;
+};
+
+namespace {
+
+ServeState* state(reloc_ctx* c) {
+  if (!c->serve) c->serve = new ServeState();
+  return c->serve;
+}
+
+// Copies the blob to device memory (after the stream has drained, so the
+// pinned buffer is free); *dev receives the device address of offset 0.
+int32_t commit(reloc_ctx* c, ServeState& S, const Blob& bl, uint8_t** dev) {
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t need = std::max<size_t>(bl.b.size(), 256);
+  if (need > S.hcap) {
+    if (S.hbuf) (void)hipHostFree(S.hbuf);
+    S.hbuf = nullptr;
+    S.hcap = 0;
+    const size_t cap = std::max(need, S.hcap * 2);
+    HIP_TRY(hipHostMalloc(&S.hbuf, cap, hipHostMallocDefault));
+    S.hcap = cap;
+  }
+  if (need > S.dcap) {
+    c->dfree(S.dbuf);
+    S.dbuf = nullptr;
+    S.dcap = 0;
+    const size_t cap = std::max(need, (size_t)1 << 16);
+    S.dbuf = (uint8_t*)c->dalloc(cap);
+    if (!S.dbuf) return RELOC_E_NOMEM;
+    S.dcap = cap;
+  }
+  std::memcpy(S.hbuf, bl.b.data(), bl.b.size());
+  HIP_TRY(hipMemcpyAsync(S.dbuf, S.hbuf, bl.b.size(), hipMemcpyHostToDevice, c->stream));
+  *dev = S.dbuf;
+  return RELOC_OK;
+}
+
+int32_t ensure_stage_cap(reloc_ctx* c, ServeState& S, size_t n) {
+  if (n <= S.stage_cap) return RELOC_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dfree(S.dstage);
+  c->dfree(S.dflag);
+  if (S.hflag) (void)hipHostFree(S.hflag);
+  S.dstage = nullptr;
+  S.dflag = nullptr;
+  S.hflag = nullptr;
+  S.stage_cap = 0;
+  const size_t cap = std::max<size_t>(n, 1024);
+  S.dstage = (uint64_t*)c->dalloc(cap * sizeof(uint64_t));
+  S.dflag = (int32_t*)c->dalloc(cap * sizeof(int32_t));
+  if (!S.dstage || !S.dflag) return RELOC_E_NOMEM;
+  HIP_TRY(hipHostMalloc((void**)&S.hflag, cap * sizeof(int32_t), hipHostMallocDefault));
+  S.stage_cap = cap;
+  return RELOC_OK;
+}
+
+struct PhaseTimes {
+  float raycast = 0, smad = 0, sort = 0, tam = 0, rank = 0;
+};
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventSynchronize(b);
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+// Ray cast, SMAD and SMAD order of the requests of F; F's flights get a
+// shared arena and start at stage 0.
+int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* pt) {
+  const int n = (int)F.size();
+  if (n == 0) return RELOC_OK;
+  auto A = std::make_shared<Arena>();
+  A->c = c;
+  std::vector<int64_t> hpre(n + 1, 0), bpre(n + 1, 0);
+  int max_ns = 1;
+  for (int i = 0; i < n; ++i) {
+    const Request& R = c->reqs.at(F[i]->rid);
+    hpre[i + 1] = hpre[i] + R.n_hyp;
+    max_ns = std::max(max_ns, R.prep.info.Ns);
+  }
+  const int64_t N = hpre[n];
+  if (N > INT32_MAX) return fail(RELOC_E_INVALID, "batch holds more than 2^31 hypotheses");
+  A->keys = A->get<uint64_t>(N);
+  A->keys2 = A->get<uint64_t>(N);
+  A->best = A->get<uint64_t>(N);
+  A->vals = A->get<int32_t>(N);
+  A->order = A->get<int32_t>(N);
+  size_t tb = 0;
+  HIP_TRY(seg_sort_pairs_u64_i32(nullptr, &tb, A->keys, A->keys2, A->vals, A->order, N, n,
+                                 nullptr, c->stream));
+  void* tmp = A->get<uint8_t>(tb);
+  if (!A->keys || !A->keys2 || !A->best || !A->vals || !A->order || !tmp) return RELOC_E_NOMEM;
+  std::vector<RayArgs> ra(n);
+  for (int i = 0; i < n; ++i) {
+    Request& R = c->reqs.at(F[i]->rid);
+    RayArgs a = ray_args(c, R, nullptr, nullptr);
+    a.keys = A->keys + hpre[i];
+    a.vals = A->vals + hpre[i];
+    const int64_t rays = (int64_t)R.n_hyp * a.Ns;
+    const int64_t blocks = a.walk ? (rays + a.chunk - 1) / a.chunk : 0;
+    bpre[i + 1] = bpre[i] + blocks;
+    ra[i] = a;
+  }
+  Blob bl;
+  const size_t o_ra = bl.add(ra.data(), n);
+  const size_t o_bp = bl.add(bpre.data(), n + 1);
+  const size_t o_hp = bl.add(hpre.data(), n + 1);
+  uint8_t* d = nullptr;
+  if (int32_t e = commit(c, S, bl, &d)) return e;
+  const RayArgs* d_ra = (const RayArgs*)(d + o_ra);
+  const int64_t* d_bp = (const int64_t*)(d + o_bp);
+  const int64_t* d_hp = (const int64_t*)(d + o_hp);
+  hipStream_t s = c->stream;
+  HIP_TRY(hipEventRecord(c->ev[0], s));
+  for (int i = 0; i < n; ++i)
+    if (!ra[i].walk) HIP_TRY(launch_raycast(ra[i], s));   // maps without walk words
+  HIP_TRY(launch_raycast_batch(d_ra, d_bp, n, bpre[n], s));
+  HIP_TRY(hipEventRecord(c->ev[1], s));
+  HIP_TRY(launch_smad_batch(d_ra, d_hp, n, hpre[n], max_ns, s));
+  HIP_TRY(hipEventRecord(c->ev[2], s));
+  HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp, s));
+  HIP_TRY(launch_fill_u64(A->best, 0, (size_t)N, s));
+  HIP_TRY(hipEventRecord(c->ev[3], s));
+  if (pt) {
+    pt->raycast += elapsed(c->ev[0], c->ev[1]);
+    pt->smad += elapsed(c->ev[1], c->ev[2]);
+    pt->sort += elapsed(c->ev[2], c->ev[3]);
+  }
+  for (int i = 0; i < n; ++i) {
+    Flight& f = *F[i];
+    f.arena = A;
+    f.off = hpre[i];
+    f.next_rank = 0;
+    f.spec = 1;
+    f.stages = 0;
+    f.n_eval = 0;
+    f.done = false;
+  }
+  return RELOC_OK;
+}
+
+// One tick over the unfinished flights of F.
+int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* pt) {
+  std::vector<TamArgs> items[10];
+  std::vector<Flight*> owner[10];
+  std::vector<StageArgs> st;
+  std::vector<Flight*> live;
+  for (Flight* f : F)
+    if (!f->done) live.push_back(f);
+  if (live.empty()) return RELOC_OK;
+  size_t n_entries = 0;
+  for (Flight* f : live) {
+    const Request& R = c->reqs.at(f->rid);
+    const int K = R.prm.batch_k;
+    const int left = (R.n_hyp - f->next_rank + K - 1) / K;
+    n_entries += (size_t)std::min(f->spec, left);
+  }
+  if (int32_t e = ensure_stage_cap(c, S, n_entries)) return e;
+  for (Flight* f : live) {
+    Request& R = c->reqs.at(f->rid);
+    const int K = R.prm.batch_k;
+    const int left = (R.n_hyp - f->next_rank + K - 1) / K;
+    const int ns = std::min(f->spec, left);
+    const int nb = std::min(ns * K, R.n_hyp - f->next_rank);
+    TamArgs a = tam_args(c, R, f->next_rank, nb, nullptr);
+    a.order = f->arena->order + f->off;
+    a.best = f->arena->best + f->off;
+    const int cls = tam_class(a);
+    if (cls < 0) return fail(RELOC_E_INVALID, "TAM configuration outside the kernel classes");
+    items[cls].push_back(a);
+    owner[cls].push_back(f);
+    f->tentry = (int)st.size();
+    f->tstages = ns;
+    f->tnb = nb;
+    for (int b = 0; b < ns; ++b) {
+      const int r0 = f->next_rank + b * K;
+      const size_t e = st.size();
+      st.push_back(StageArgs{a.best, r0, std::min(K, R.n_hyp - r0), R.prm.tau, S.dstage + e,
+                             S.dflag + e});
+    }
+  }
+  Blob bl;
+  size_t o_items[10], o_pre[10];
+  int64_t blocks[10];
+  size_t lds[10];
+  for (int k = 0; k < 10; ++k) {
+    const int m = (int)items[k].size();
+    blocks[k] = 0;
+    lds[k] = 0;
+    if (!m) continue;
+    std::vector<int64_t> pre(m + 1, 0);
+    for (int i = 0; i < m; ++i) {
+      const TamArgs& a = items[k][i];
+      pre[i + 1] = pre[i] + (int64_t)a.nb * ((a.Nt + 15) / 16);
+      lds[k] = std::max(lds[k], tam_lds_bytes(a));
+    }
+    blocks[k] = pre[m];
+    o_items[k] = bl.add(items[k].data(), m);
+    o_pre[k] = bl.add(pre.data(), m + 1);
+  }
+  const size_t o_st = bl.add(st.data(), st.size());
+  uint8_t* d = nullptr;
+  if (int32_t e = commit(c, S, bl, &d)) return e;
+  hipStream_t s = c->stream;
+  HIP_TRY(hipEventRecord(c->ev[3], s));
+  for (int k = 0; k < 10; ++k) {
+    if (!blocks[k]) continue;
+    HIP_TRY(launch_tam_batch(k, (const TamArgs*)(d + o_items[k]), (const int64_t*)(d + o_pre[k]),
+                             (int)items[k].size(), blocks[k], lds[k], s));
+  }
+  HIP_TRY(launch_stage_reduce_batch((const StageArgs*)(d + o_st), (int)st.size(), s));
+  HIP_TRY(hipMemcpyAsync(S.hflag, S.dflag, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(c->ev[4], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (pt) pt->tam += elapsed(c->ev[3], c->ev[4]);
+  const auto now = std::chrono::steady_clock::now();
+  for (Flight* f : live) {
+    const Request& R = c->reqs.at(f->rid);
+    const int K = R.prm.batch_k;
+    int hit = -1;
+    for (int b = 0; b < f->tstages; ++b)
+      if (S.hflag[f->tentry + b]) {
+        hit = b;
+        break;
+      }
+    if (hit >= 0) {
+      f->stages += hit + 1;
+      f->n_eval = std::min(R.n_hyp, f->next_rank + (hit + 1) * K);
+      f->done = true;
+      f->stopped = true;
+      continue;
+    }
+    f->stages += f->tstages;
+    f->next_rank += f->tnb;
+    f->n_eval = f->next_rank;
+    if (f->next_rank >= R.n_hyp) {
+      f->done = true;
+      continue;
+    }
+    f->spec = std::min(kMaxSpec, f->spec * 2);
+    if (R.prm.deadline_s > 0 &&
+        std::chrono::duration<double>(now - f->t_start).count() > R.prm.deadline_s) {
+      f->done = true;
+      f->status = RELOC_E_TIMEOUT;
+    }
+  }
+  return RELOC_OK;
+}
+
+// Ranked poses of finished flights: rows[i] receives min(cap[i], k_out,
+// n_eval) rows of flight F[i].
+int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::vector<int>& cap,
+             std::vector<std::vector<PoseRow>>* rows, PhaseTimes* pt) {
+  const int n = (int)F.size();
+  rows->assign(n, {});
+  if (n == 0) return RELOC_OK;
+  std::vector<int64_t> kpre(n + 1, 0), rpre(n + 1, 0);
+  std::vector<RankArgs> ra(n);
+  for (int i = 0; i < n; ++i) {
+    const Request& R = c->reqs.at(F[i]->rid);
+    const int nr = std::max(0, std::min(std::min(R.rows_cap, F[i]->n_eval), cap[i]));
+    kpre[i + 1] = kpre[i] + F[i]->n_eval;
+    rpre[i + 1] = rpre[i] + nr;
+    ra[i] = RankArgs{F[i]->arena->best + F[i]->off, F[i]->arena->order + F[i]->off, R.smad};
+  }
+  const int64_t NK = kpre[n], NR = rpre[n];
+  Arena T;
+  T.c = c;
+  uint64_t* k1 = T.get<uint64_t>(NK);
+  uint64_t* k2 = T.get<uint64_t>(NK);
+  PoseRow* dr = T.get<PoseRow>(NR);
+  size_t tb = 0;
+  HIP_TRY(seg_sort_keys_u64(nullptr, &tb, k1, k2, NK, n, nullptr, c->stream));
+  void* tmp = T.get<uint8_t>(tb);
+  if (!k1 || !k2 || !dr || !tmp) return RELOC_E_NOMEM;
+  Blob bl;
+  const size_t o_ra = bl.add(ra.data(), n);
+  const size_t o_kp = bl.add(kpre.data(), n + 1);
+  const size_t o_rp = bl.add(rpre.data(), n + 1);
+  uint8_t* d = nullptr;
+  if (int32_t e = commit(c, S, bl, &d)) return e;
+  const RankArgs* d_ra = (const RankArgs*)(d + o_ra);
+  const int64_t* d_kp = (const int64_t*)(d + o_kp);
+  const int64_t* d_rp = (const int64_t*)(d + o_rp);
+  hipStream_t s = c->stream;
+  std::vector<PoseRow> host(NR);
+  HIP_TRY(hipEventRecord(c->ev[4], s));
+  HIP_TRY(launch_rank_keys_batch(d_ra, d_kp, n, NK, k1, s));
+  HIP_TRY(seg_sort_keys_u64(tmp, &tb, k1, k2, NK, n, d_kp, s));
+  HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k2, dr, s));
+  if (NR > 0)
+    HIP_TRY(hipMemcpyAsync(host.data(), dr, NR * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(c->ev[5], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (pt) pt->rank += elapsed(c->ev[4], c->ev[5]);
+  for (int i = 0; i < n; ++i)
+    (*rows)[i].assign(host.begin() + rpre[i], host.begin() + rpre[i + 1]);
+  return RELOC_OK;
+}
+
+void fill_stats(const Request& R, const Flight& f, const PhaseTimes& pt, float total,
+                reloc_stats* st) {
+  const reloc_scan_info& I = R.prep.info;
+  std::memset(st, 0, sizeof *st);
+  st->n_hyp = R.n_hyp;
+  st->smad_evals = (int64_t)R.n_hyp * I.n_shifts;
+  st->tam_evals = (int64_t)f.n_eval * I.Ntheta;
+  st->rays = (int64_t)R.n_hyp * I.Ns;
+  st->tam_lookups = st->tam_evals * I.n_valid;
+  st->stages = f.stages;
+  st->early_stopped = f.stopped ? 1 : 0;
+  st->n_eval = f.n_eval;
+  st->ms_total = total;
+  st->ms_raycast = pt.raycast;
+  st->ms_smad = pt.smad;
+  st->ms_sort = pt.sort;
+  st->ms_tam = pt.tam;
+  st->ms_rank = pt.rank;
+}
+
+// ---- serving worker --------------------------------------------------------
+
+void finish_ticket(ServeState& S, Ticket* t, int32_t status) {
+  std::lock_guard<std::mutex> lk(S.qmu);
+  t->status = status;
+  t->done = true;
+  if (status == RELOC_OK || status == RELOC_E_TIMEOUT)
+    ++S.stats.completed;
+  else
+    ++S.stats.failed;
+}
+
+Ticket* ticket_of(ServeState& S, uint64_t id) {
+  std::lock_guard<std::mutex> lk(S.qmu);
+  auto it = S.tickets.find(id);
+  return it == S.tickets.end() ? nullptr : it->second.get();
+}
+
+// One scheduler round; returns false when there was nothing to do.
+bool serve_round(reloc_ctx* c, ServeState& S) {
+  std::vector<Ticket*> adm;
+  {
+    std::unique_lock<std::mutex> lk(S.qmu);
+    S.stats.queued = (int32_t)S.pending.size();
+    if (S.pending.empty() && S.active.empty()) return false;
+  }
+  std::lock_guard<std::recursive_mutex> cl(c->mu);
+  if (set_device(c) != RELOC_OK) return true;
+  const auto t0 = std::chrono::steady_clock::now();
+  // admission: slots and free HBM
+  {
+    std::unique_lock<std::mutex> lk(S.qmu);
+    size_t planned = 0;
+    while (!S.pending.empty() && (int)(S.active.size() + adm.size()) < S.cfg.max_inflight &&
+           (int)adm.size() < S.cfg.max_admit) {
+      Ticket* t = S.pending.front();
+      const size_t need = request_bytes(t->R) + (size_t)t->R.n_hyp * 40 + (1 << 20);
+      const size_t budget = c->budget > S.cfg.hbm_reserve ? c->budget - S.cfg.hbm_reserve : 0;
+      if (c->used + planned + need > budget) {
+        if (S.active.empty() && adm.empty()) {   // can never fit
+          S.pending.pop_front();
+          lk.unlock();
+          fail(RELOC_E_NOMEM, "request needs %zu bytes, budget %zu", need, budget);
+          finish_ticket(S, t, RELOC_E_NOMEM);
+          lk.lock();
+          continue;
+        }
+        break;
+      }
+      planned += need;
+      S.pending.pop_front();
+      adm.push_back(t);
+    }
+    S.stats.queued = (int32_t)S.pending.size();
+  }
+  std::vector<Flight*> fresh;
+  const size_t base = S.active.size();
+  for (Ticket* t : adm) {
+    Request R = t->R;   // host part; the ticket keeps its copy
+    int32_t e = build_request(c, R);
+    if (e != RELOC_OK) {
+      release_request(c, R);
+      finish_ticket(S, t, e);
+      continue;
+    }
+    const int id = c->next_id++;
+    c->reqs[id] = std::move(R);
+    Flight f;
+    f.rid = id;
+    f.ticket = t->id;
+    f.t_start = t->t_submit;
+    S.active.push_back(f);
+  }
+  for (size_t i = base; i < S.active.size(); ++i) fresh.push_back(&S.active[i]);
+  PhaseTimes pt;
+  int32_t err = front(c, S, fresh, &pt);
+  std::vector<Flight*> all;
+  for (Flight& f : S.active) all.push_back(&f);
+  if (err == RELOC_OK) err = tick(c, S, all, &pt);
+  if (err != RELOC_OK) {
+    for (Flight& f : S.active) {
+      f.done = true;
+      f.status = err;
+    }
+  }
+  std::vector<Flight*> fin;
+  std::vector<int> caps;
+  for (Flight& f : S.active)
+    if (f.done) {
+      fin.push_back(&f);
+      caps.push_back(INT32_MAX);
+    }
+  std::vector<std::vector<PoseRow>> rows;
+  if (!fin.empty() && err == RELOC_OK) err = rank(c, S, fin, caps, &rows, &pt);
+  for (size_t i = 0; i < fin.size(); ++i) {
+    Flight& f = *fin[i];
+    Ticket* t = ticket_of(S, f.ticket);
+    Request& R = c->reqs.at(f.rid);
+    if (t) {
+      int32_t status = err != RELOC_OK ? err : f.status;
+      if (err == RELOC_OK) {
+        t->poses.resize(rows[i].size());
+        rows_to_poses(c, R, rows[i].data(), (int)rows[i].size(), t->poses.data());
+        const float total =
+            std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                     t->t_submit).count();
+        fill_stats(R, f, pt, total, &t->st);
+      }
+      finish_ticket(S, t, status);
+    }
+    release_request(c, R);
+    c->reqs.erase(f.rid);
+    f.arena.reset();
+  }
+  S.active.erase(std::remove_if(S.active.begin(), S.active.end(),
+                                [](const Flight& f) { return f.done; }),
+                 S.active.end());
+  {
+    std::lock_guard<std::mutex> lk(S.qmu);
+    ++S.stats.ticks;
+    S.stats.inflight = (int32_t)S.active.size();
+    S.stats.busy_s +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  S.dcv.notify_all();
+  return true;
+}
+
+void serve_loop(reloc_ctx* c) {
+  ServeState& S = *c->serve;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S.qmu);
+      S.qcv.wait(lk, [&] { return S.stop || !S.pending.empty() || !S.active.empty(); });
+      if (S.stop) break;
+    }
+    serve_round(c, S);
+  }
+}
+
+}  // namespace
+
+bool serve_holds_set(reloc_ctx* c, int32_t set_id) {
+  if (!c->serve) return false;
+  std::lock_guard<std::mutex> lk(c->serve->qmu);
+  for (auto& kv : c->serve->tickets)
+    if (!kv.second->done && kv.second->R.set_id == set_id) return true;
+  return false;
+}
+
+void ctx_stop_serving(reloc_ctx* c) {
+  ServeState* S = c->serve;
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->qmu);
+    S->stop = true;
+  }
+  S->qcv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  std::lock_guard<std::recursive_mutex> cl(c->mu);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (Flight& f : S->active) {
+    auto it = c->reqs.find(f.rid);
+    if (it != c->reqs.end()) {
+      release_request(c, it->second);
+      c->reqs.erase(it);
+    }
+    f.arena.reset();
+  }
+  S->active.clear();
+  c->dfree(S->dbuf);
+  c->dfree(S->dstage);
+  c->dfree(S->dflag);
+  if (S->hbuf) (void)hipHostFree(S->hbuf);
+  if (S->hflag) (void)hipHostFree(S->hflag);
+  S->dcv.notify_all();
+  delete S;
+  c->serve = nullptr;
+}
+
+}  // namespace reloc
+
+using namespace reloc;
+
+extern "C" {
+
+int32_t reloc_run_batch(reloc_ctx* c, int32_t n, const int32_t* request_ids, reloc_pose* out,
+                        int32_t cap, int32_t* n_out, int32_t* status, reloc_stats* stats) {
+  if (!c || n < 0 || (n > 0 && (!request_ids || !n_out || !status)) || (!out && cap > 0))
+    return fail(RELOC_E_INVALID, "null argument");
+  for (int i = 0; i < n; ++i) {
+    n_out[i] = 0;
+    status[i] = RELOC_E_PENDING;
+  }
+  if (n == 0) return RELOC_OK;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  for (int i = 0; i < n; ++i) {
+    if (!c->reqs.count(request_ids[i]))
+      return fail(RELOC_E_NOTFOUND, "unknown request %d", request_ids[i]);
+    for (int j = 0; j < i; ++j)
+      if (request_ids[j] == request_ids[i])
+        return fail(RELOC_E_INVALID, "request %d listed twice", request_ids[i]);
+  }
+  if (int32_t e = set_device(c)) return e;
+  ServeState& S = *state(c);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<Flight> fl(n);
+  std::vector<Flight*> F(n);
+  for (int i = 0; i < n; ++i) {
+    fl[i].rid = request_ids[i];
+    fl[i].t_start = t0;
+    F[i] = &fl[i];
+  }
+  PhaseTimes pt;
+  if (int32_t e = front(c, S, F, &pt)) return e;
+  for (;;) {
+    bool any = false;
+    for (Flight* f : F) any |= !f->done;
+    if (!any) break;
+    if (int32_t e = tick(c, S, F, &pt)) return e;
+  }
+  std::vector<int> caps(n, std::max(0, cap));
+  std::vector<std::vector<PoseRow>> rows;
+  if (int32_t e = rank(c, S, F, caps, &rows, &pt)) return e;
+  const float total =
+      std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < n; ++i) {
+    const Request& R = c->reqs.at(request_ids[i]);
+    rows_to_poses(c, R, rows[i].data(), (int)rows[i].size(), out + (size_t)i * cap);
+    n_out[i] = (int32_t)rows[i].size();
+    status[i] = fl[i].status;
+    if (stats) fill_stats(R, fl[i], pt, total, &stats[i]);
+  }
+  return RELOC_OK;
+}
+
+int32_t reloc_serve_configure(reloc_ctx* c, const reloc_serve_config* cfg) {
+  if (!c || !cfg) return fail(RELOC_E_INVALID, "null argument");
+  if (cfg->max_inflight < 1 || cfg->max_admit < 1)
+    return fail(RELOC_E_INVALID, "max_inflight and max_admit must be >= 1");
+  std::lock_guard<std::recursive_mutex> cl(c->mu);
+  ServeState& S = *state(c);
+  std::lock_guard<std::mutex> lk(S.qmu);
+  S.cfg = *cfg;
+  return RELOC_OK;
+}
+
+int32_t reloc_submit(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                     const reloc_search_params* params, uint64_t* ticket) {
+  if (!c || !ticket) return fail(RELOC_E_INVALID, "null argument");
+  *ticket = 0;
+  auto t = std::make_unique<Ticket>();
+  {
+    std::lock_guard<std::recursive_mutex> cl(c->mu);
+    if (int32_t e = init_request(c, map_id, set_id, scan, params, &t->R)) return e;
+    ServeState& S = *state(c);
+    std::lock_guard<std::mutex> lk(S.qmu);
+    if (!S.running) {
+      S.worker = std::thread(serve_loop, c);
+      S.running = true;
+    }
+    t->id = S.next_ticket++;
+    t->t_submit = std::chrono::steady_clock::now();
+    *ticket = t->id;
+    S.pending.push_back(t.get());
+    S.tickets[t->id] = std::move(t);
+    ++S.stats.submitted;
+    S.stats.queued = (int32_t)S.pending.size();
+  }
+  c->serve->qcv.notify_all();
+  return RELOC_OK;
+}
+
+int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* out, int32_t cap,
+                   int32_t* n_out, reloc_stats* st) {
+  if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
+  *n_out = 0;
+  ServeState* S = nullptr;
+  {
+    std::lock_guard<std::recursive_mutex> cl(c->mu);
+    S = c->serve;
+  }
+  if (!S) return fail(RELOC_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  std::unique_lock<std::mutex> lk(S->qmu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end())
+    return fail(RELOC_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Ticket* t = it->second.get();
+  if (!t->done && wait_ms != 0) {
+    auto pred = [&] { return t->done || S->stop; };
+    if (wait_ms < 0)
+      S->dcv.wait(lk, pred);
+    else
+      S->dcv.wait_for(lk, std::chrono::milliseconds(wait_ms), pred);
+  }
+  if (!t->done) return fail(RELOC_E_PENDING, "ticket %llu not finished", (unsigned long long)ticket);
+  const int32_t status = t->status;
+  const int n = std::min<int>((int)t->poses.size(), std::max(0, cap));
+  for (int i = 0; i < n; ++i) out[i] = t->poses[i];
+  *n_out = n;
+  if (st) *st = t->st;
+  S->tickets.erase(it);
+  if (status != RELOC_OK && status != RELOC_E_TIMEOUT)
+    return fail(status, "request failed with status %d", status);
+  return status;
+}
+
+int32_t reloc_serve_stats_get(reloc_ctx* c, reloc_serve_stats* out) {
+  if (!c || !out) return fail(RELOC_E_INVALID, "null argument");
+  std::memset(out, 0, sizeof *out);
+  ServeState* S = nullptr;
+  {
+    std::lock_guard<std::recursive_mutex> cl(c->mu);
+    S = c->serve;
+  }
+  if (!S) return RELOC_OK;
+  std::lock_guard<std::mutex> lk(S->qmu);
+  *out = S->stats;
+  return RELOC_OK;
+}
+
+}  // extern "C"

@@ -284,11 +284,11 @@ __device__ __forceinline__ WalkMap make_walkmap(const RayArgs& a) {
 // counter is wavefront-uniform), so lanes stay busy and neighbouring lanes
 // work on neighbouring directions. The hardware balances the many chunks.
 template <int REFILL>
-__global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
+__device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   const int lane = threadIdx.x;
   const int Ns = a.Ns, W = a.W, H = a.H, rcells = a.rcells;
   const int64_t total = (int64_t)a.n_hyp * Ns;
-  const int64_t q0 = (int64_t)blockIdx.x * a.chunk;
+  const int64_t q0 = (int64_t)block * a.chunk;
   const int pool = (int)min((int64_t)a.chunk, total - q0);
   const float inv_ns = 1.0f / (float)Ns;
   const WalkMap sm = make_walkmap(a);
@@ -345,6 +345,32 @@ __global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
       }
     }
   }
+}
+
+template <int REFILL>
+__global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
+  raycast_skip_run<REFILL>(a, blockIdx.x);
+}
+
+// Index of the segment holding item t: prefix[r] <= t < prefix[r + 1]
+// (prefix[0] = 0, n segments, t < prefix[n]); wavefront-uniform.
+__device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Ray casts of several requests in one launch: request r owns the blocks
+// [prefix[r], prefix[r + 1]), each one chunk of that request's rays.
+template <int REFILL>
+__global__ __launch_bounds__(64) void raycast_skip_batch_kernel(const RayArgs* __restrict__ reqs,
+                                                                const int64_t* __restrict__ prefix,
+                                                                int n) {
+  const int r = find_segment(prefix, n, blockIdx.x);
+  raycast_skip_run<REFILL>(reqs[r], (int)(blockIdx.x - prefix[r]));
 }
 
 // Bit-tile ray cast: one workgroup per hypothesis, rays from a shared counter.
@@ -445,13 +471,25 @@ __device__ void smad_epilogue(const RayArgs& a, double* S, int h) {
 }
 
 // SMAD of one hypothesis per workgroup from its ranges in zbuf.
-__global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
-  extern __shared__ double S[];   // [Ns + 1]
-  const int h = blockIdx.x;
+__device__ __forceinline__ void smad_run(const RayArgs& a, int h, double* S) {
   const float* z = a.zbuf + (size_t)h * a.Ns;
   for (int j = threadIdx.x; j < a.Ns; j += RT) S[j + 1] = (double)z[j];
   __syncthreads();
   smad_epilogue(a, S, h);
+}
+
+__global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
+  extern __shared__ double S[];   // [Ns + 1]
+  smad_run(a, blockIdx.x, S);
+}
+
+// SMAD of several requests: request r owns blocks [prefix[r], prefix[r + 1]),
+// one per hypothesis.
+__global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restrict__ reqs,
+                                                        const int64_t* __restrict__ prefix, int n) {
+  extern __shared__ double S[];
+  const int r = find_segment(prefix, n, blockIdx.x);
+  smad_run(reqs[r], (int)(blockIdx.x - prefix[r]), S);
 }
 
 }  // namespace
@@ -477,6 +515,22 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
   const size_t lds = (size_t)(a.Ns + 1) * sizeof(double);
   hipLaunchKernelGGL(smad_kernel, dim3(a.n_hyp), dim3(RT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
+                                int64_t blocks, hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(raycast_skip_batch_kernel<16>, dim3((unsigned)blocks), dim3(64), 0, s, reqs,
+                     prefix, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
+                             int max_ns, hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return hipSuccess;
+  const size_t lds = (size_t)(max_ns + 1) * sizeof(double);
+  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(RT), lds, s, reqs, prefix, n);
   return hipGetLastError();
 }
 

@@ -18,4 +18,18 @@ hipError_t sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint
   return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, kin, kout, n, 0, 64, s);
 }
 
+hipError_t seg_sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
+                                  uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t n,
+                                  int nseg, const int64_t* offsets, hipStream_t s) {
+  return hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, *tmp_bytes, kin, kout, vin, vout,
+                                                     (int)n, nseg, offsets, offsets + 1, 0, 64,
+                                                     s);
+}
+
+hipError_t seg_sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
+                             int64_t n, int nseg, const int64_t* offsets, hipStream_t s) {
+  return hipcub::DeviceSegmentedRadixSort::SortKeys(tmp, *tmp_bytes, kin, kout, (int)n, nseg,
+                                                    offsets, offsets + 1, 0, 64, s);
+}
+
 }  // namespace reloc

@@ -74,12 +74,12 @@ __device__ __forceinline__ void find_bin(const uint32_t* h, int lane, int need, 
   *below = __shfl(bl, first, 64);
 }
 
+// One workgroup's work: rank a.r0 + i, orientations [16 kb, 16 kb + 16).
 template <int R, int KB>
-__global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
+__device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
   constexpr int LB2 = KB / 2;
   constexpr int NB = 1 << LB2;        // bins per level (level 1: key >> LB2)
   constexpr int P = NB / 64;
-  extern __shared__ int32_t smem[];
   int32_t* sbase = smem;              // [nv]
   int32_t* szq = smem + a.nv;         // [nv]
   uint32_t* hist_all = (uint32_t*)(smem + 2 * a.nv);   // [NW][NB]
@@ -90,11 +90,11 @@ __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
     sbase[v] = a.beam_base[v];
     szq[v] = a.beam_zq[v];
   }
-  const int r = a.r0 + blockIdx.y;
+  const int r = a.r0 + i;
   const int hyp = a.order[r];
   const int64_t X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
   const int64_t Y20 = (int64_t)(256 * a.hyp_xy[2 * hyp + 1] + 128) * (int64_t)(1 << 20);
-  const int k0 = blockIdx.x * THETA_PER_BLOCK;
+  const int k0 = kb * THETA_PER_BLOCK;
   __syncthreads();
 
   for (int it = 0; it < THETA_PER_BLOCK / NW; ++it) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
         const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
         const double c = exp(-0.5 * var);
         const float T = (float)cbrt(Pl * sd * c);
-        if (a.T_out) a.T_out[(size_t)blockIdx.y * a.Nt + k] = T;
+        if (a.T_out) a.T_out[(size_t)i * a.Nt + k] = T;
         const uint64_t packed =
             ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
         atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
@@ -189,6 +189,35 @@ __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int R, int KB>
+__global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
+  extern __shared__ int32_t smem[];
+  tam_block<R, KB>(a, blockIdx.y, blockIdx.x, smem);
+}
+
+// Index of the segment holding item t: prefix[e] <= t < prefix[e + 1].
+__device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// TAM over several rank ranges (of one or several requests) in one launch:
+// item e owns blocks [prefix[e], prefix[e + 1]) = nb x ceil(Nt / 16).
+template <int R, int KB>
+__global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict__ items,
+                                                       const int64_t* __restrict__ prefix, int n) {
+  extern __shared__ int32_t smem[];
+  const int e = find_segment(prefix, n, blockIdx.x);
+  const TamArgs& a = items[e];
+  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  const int local = (int)(blockIdx.x - prefix[e]);
+  tam_block<R, KB>(a, local / ntb, local % ntb, smem);
 }
 
 template <int R, int KB>
@@ -211,7 +240,7 @@ hipError_t launch_tam_kb(const TamArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-__global__ void stage_reduce_kernel(StageArgs a) {
+__device__ __forceinline__ void stage_reduce_run(const StageArgs& a) {
   __shared__ unsigned long long red[TB / 64];
   unsigned long long best = 0;
   for (int i = threadIdx.x; i < a.nb; i += TB) {
@@ -233,6 +262,13 @@ __global__ void stage_reduce_kernel(StageArgs a) {
     const float T = __uint_as_float((uint32_t)(best >> 32));
     a.flag_out[0] = ((double)T > a.tau) ? 1 : 0;
   }
+}
+
+__global__ void stage_reduce_kernel(StageArgs a) { stage_reduce_run(a); }
+
+// one workgroup per stage entry
+__global__ void stage_reduce_batch_kernel(const StageArgs* __restrict__ items) {
+  stage_reduce_run(items[blockIdx.x]);
 }
 
 __global__ void fill_u64_kernel(uint64_t* p, uint64_t v, size_t n) {
@@ -263,6 +299,58 @@ __global__ void rank_gather_kernel(const uint64_t* sorted, const uint64_t* best,
   rows[i] = row;
 }
 
+// rank keys of several requests: item t of request r = ranks [0, n_eval_r)
+__global__ void rank_keys_batch_kernel(const RankArgs* __restrict__ reqs,
+                                       const int64_t* __restrict__ prefix, int n,
+                                       uint64_t* __restrict__ keys) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= prefix[n]) return;
+  const int r = find_segment(prefix, n, t);
+  const int i = (int)(t - prefix[r]);
+  const uint32_t tb = (uint32_t)(reqs[r].best[i] >> 32);
+  keys[t] = ((uint64_t)(0xFFFFFFFFu - tb) << 32) | (uint64_t)(uint32_t)i;
+}
+
+__global__ void rank_gather_batch_kernel(const RankArgs* __restrict__ reqs,
+                                         const int64_t* __restrict__ row_prefix,
+                                         const int64_t* __restrict__ key_prefix, int n,
+                                         const uint64_t* __restrict__ sorted,
+                                         PoseRow* __restrict__ rows) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= row_prefix[n]) return;
+  const int q = find_segment(row_prefix, n, t);
+  const int64_t i = t - row_prefix[q];
+  const RankArgs& a = reqs[q];
+  const int r = (int)(uint32_t)(sorted[key_prefix[q] + i] & 0xFFFFFFFFu);
+  const uint64_t b = a.best[r];
+  PoseRow row;
+  row.rank = r;
+  row.k = (int32_t)(0xFFFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu));
+  row.hyp = a.order[r];
+  row.tbits = (uint32_t)(b >> 32);
+  row.smad = a.smad[row.hyp];
+  rows[t] = row;
+}
+
+template <int R, int KB>
+hipError_t launch_tam_batch_t(const TamArgs* items, const int64_t* prefix, int n, int64_t blocks,
+                              size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((tam_batch_kernel<R, KB>), dim3((unsigned)blocks), dim3(TB), lds, s, items,
+                     prefix, n);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_tam_batch_kb(int R, const TamArgs* items, const int64_t* prefix, int n,
+                               int64_t blocks, size_t lds, hipStream_t s) {
+  if (R <= 4) return launch_tam_batch_t<4, KB>(items, prefix, n, blocks, lds, s);
+  if (R <= 8) return launch_tam_batch_t<8, KB>(items, prefix, n, blocks, lds, s);
+  if (R <= 16) return launch_tam_batch_t<16, KB>(items, prefix, n, blocks, lds, s);
+  if (R <= 32) return launch_tam_batch_t<32, KB>(items, prefix, n, blocks, lds, s);
+  if (R <= 64) return launch_tam_batch_t<64, KB>(items, prefix, n, blocks, lds, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 hipError_t launch_tam(const TamArgs& a, hipStream_t s) {
@@ -270,6 +358,50 @@ hipError_t launch_tam(const TamArgs& a, hipStream_t s) {
   if (a.keybits <= 12) return launch_tam_kb<12>(a, s);
   if (a.keybits <= 16) return launch_tam_kb<16>(a, s);
   return hipErrorInvalidValue;
+}
+
+int tam_class(const TamArgs& a) {
+  const int R = (a.nv + 63) / 64;
+  const int rc = R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : R <= 32 ? 3 : R <= 64 ? 4 : -1;
+  const int kc = a.keybits <= 12 ? 0 : a.keybits <= 16 ? 1 : -1;
+  return (rc < 0 || kc < 0) ? -1 : kc * 5 + rc;
+}
+
+size_t tam_lds_bytes(const TamArgs& a) {
+  const int KB = a.keybits <= 12 ? 12 : 16;
+  return (size_t)2 * a.nv * sizeof(int32_t) + (size_t)NW * (1 << (KB / 2)) * sizeof(uint32_t);
+}
+
+hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
+                            int64_t blocks, size_t lds, hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return hipSuccess;
+  static const int Rs[5] = {4, 8, 16, 32, 64};
+  if (cls < 0 || cls >= 10) return hipErrorInvalidValue;
+  if (cls >= 5) return launch_tam_batch_kb<16>(Rs[cls - 5], items, prefix, n, blocks, lds, s);
+  return launch_tam_batch_kb<12>(Rs[cls], items, prefix, n, blocks, lds, s);
+}
+
+hipError_t launch_stage_reduce_batch(const StageArgs* items, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_reduce_batch_kernel, dim3(n), dim3(TB), 0, s, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_keys_batch(const RankArgs* reqs, const int64_t* prefix, int n,
+                                  int64_t total, uint64_t* keys, hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_keys_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     s, reqs, prefix, n, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_gather_batch(const RankArgs* reqs, const int64_t* row_prefix,
+                                    const int64_t* key_prefix, int n, int64_t total,
+                                    const uint64_t* sorted, PoseRow* rows, hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_gather_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                     0, s, reqs, row_prefix, key_prefix, n, sorted, rows);
+  return hipGetLastError();
 }
 
 hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s) {

@@ -51,6 +51,14 @@ struct RayArgs {
 hipError_t launch_raycast(const RayArgs& a, hipStream_t s);   // ranges into zbuf
 hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, argm, keys
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
+// Several requests in one launch each. reqs: device RayArgs[n]; prefix:
+// device int64[n + 1] block offsets (ray cast: chunks of a.chunk rays with the
+// walk-word traversal, refill at 16 idle lanes; SMAD: one block per
+// hypothesis). Every request of a ray-cast batch needs walk words.
+hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
+                                int64_t blocks, hipStream_t s);
+hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
+                             int max_ns, hipStream_t s);
 // Walk words from the squared EDT: four row-major planes, one per major
 // direction of travel (+x, -x, +y, -y). A word is 0 for an occupied cell,
 // else s | run << 8 with s = 1 + free-space radius byte and run = free
@@ -64,6 +72,12 @@ hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
                               hipStream_t s);
 hipError_t sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
                          int n, hipStream_t s);
+// stable segmented sorts; offsets: device int64[nseg + 1]
+hipError_t seg_sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
+                                  uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t n,
+                                  int nseg, const int64_t* offsets, hipStream_t s);
+hipError_t seg_sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
+                             int64_t n, int nseg, const int64_t* offsets, hipStream_t s);
 
 // ---- TAM -----------------------------------------------------------------
 struct TamArgs {
@@ -95,6 +109,8 @@ struct StageArgs {
 };
 hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s);
 
+
+
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 
 // rank keys: ((~T bits) << 32 | rank) for ranks [0, n)
@@ -109,5 +125,30 @@ struct PoseRow {
 hipError_t launch_rank_gather(const uint64_t* sorted, const uint64_t* best,
                               const int32_t* order, const double* smad, int n, PoseRow* rows,
                               hipStream_t s);
+
+// ---- batched TAM / stage control / ranking -------------------------------
+// Kernel class of a TAM argument set (keys per lane x histogram bits), -1 if
+// unsupported; items of one launch share a class.
+int tam_class(const TamArgs& a);
+size_t tam_lds_bytes(const TamArgs& a);
+// items: device TamArgs[n] (each a rank range of one request); prefix:
+// device int64[n + 1] block offsets, nb x ceil(Nt / 16) blocks per item.
+hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
+                            int64_t blocks, size_t lds, hipStream_t s);
+// items: device StageArgs[n], one workgroup each
+hipError_t launch_stage_reduce_batch(const StageArgs* items, int n, hipStream_t s);
+
+struct RankArgs {
+  const uint64_t* best;      // per rank
+  const int32_t* order;      // hypothesis per rank
+  const double* smad;        // per hypothesis
+};
+// keys[prefix[r] + i] for ranks i < prefix[r + 1] - prefix[r] of request r
+hipError_t launch_rank_keys_batch(const RankArgs* reqs, const int64_t* prefix, int n,
+                                  int64_t total, uint64_t* keys, hipStream_t s);
+// rows[row_prefix[r] + i] from sorted[key_prefix[r] + i]
+hipError_t launch_rank_gather_batch(const RankArgs* reqs, const int64_t* row_prefix,
+                                    const int64_t* key_prefix, int n, int64_t total,
+                                    const uint64_t* sorted, PoseRow* rows, hipStream_t s);
 
 }  // namespace reloc

@@ -20,11 +20,13 @@
 #include "reloc.h"
 #include "reloc_internal.h"
 
-using namespace reloc;
+#include "runtime_internal.h"
+
+namespace reloc {
 
 namespace {
-
 thread_local std::string g_err = "no error";
+}  // namespace
 
 int32_t fail(int32_t code, const char* fmt, ...) {
   char buf[512];
@@ -36,12 +38,7 @@ int32_t fail(int32_t code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(RELOC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-  } while (0)
+
 
 constexpr int kMaxNs = 4096;
 constexpr int kMaxDim = 32768;
@@ -85,11 +82,6 @@ uint64_t splitmix64(uint64_t x) {
 }
 
 // ---- scan preprocessing (eq. 11-16, 25-26) ---------------------------------
-struct Prep {
-  reloc_scan_info info{};
-  std::vector<int2> runs;         // (panoramic start, length) per FoV run
-  std::vector<int32_t> vj, vzq;   // valid beams: panoramic index, range in Q8 cells
-};
 
 int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double res, Prep* out) {
   if (!sc || !p) return fail(RELOC_E_INVALID, "null scan or params");
@@ -175,10 +167,6 @@ int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double re
 }
 
 // ---- likelihood table for TAM (eq. 23) --------------------------------------
-struct Lut {
-  std::vector<int32_t> q;   // Q26 likelihood per selection key
-  int kcap = 1, key_off = 2, keybits = 12;
-};
 
 int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
   const double zh = p->z_hit, sg = p->sigma_hit, zr = p->z_rand, dm = p->d_max;
@@ -209,114 +197,9 @@ int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
   return RELOC_OK;
 }
 
-}  // namespace
 
 // ============================================================================
-struct DevMap {
-  int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
-  double res = 0.05, ox = 0, oy = 0;
-  uint64_t* bits = nullptr;
-  uint16_t* walk = nullptr;       // null when the map exceeds kWalkMaxCells
-  uint32_t* kmap = nullptr;
-  std::vector<int8_t> occ;        // host copy for the sampler
-  std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
-  int n_sets = 0;
-};
 
-struct HypSet {
-  int map_id = -1;
-  int n = 0;
-  int32_t* dev = nullptr;         // [n][2]
-  std::vector<int32_t> host;
-};
-
-struct Request {
-  int map_id = -1, set_id = -1, n_hyp = 0;
-  Prep prep;
-  reloc_search_params prm{};
-  float rmax = 0.f;
-  int rcells = 0;
-  Lut lut;
-  // device tables
-  int2* raydirs = nullptr;
-  float2* kap = nullptr;
-  int4* dir_i = nullptr;
-  float4* dir_f = nullptr;
-  float* zbuf = nullptr;
-  int2* runs = nullptr;
-  int32_t* base = nullptr;
-  int32_t* zq = nullptr;
-  int2* dirs = nullptr;
-  int32_t* dlut = nullptr;
-  // device work
-  double* smad = nullptr;
-  int32_t* argm = nullptr;
-  uint64_t* keys = nullptr;
-  uint64_t* keys2 = nullptr;
-  int32_t* vals = nullptr;
-  int32_t* order = nullptr;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0;
-  uint64_t* best = nullptr;
-  uint64_t* stage = nullptr;
-  int32_t* flag = nullptr;
-  PoseRow* rows = nullptr;
-  int rows_cap = 0;
-  std::vector<void*> owned;
-};
-
-struct reloc_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  reloc_allocator alloc{};
-  bool has_alloc = false;
-  size_t budget = 0, used = 0;
-  std::map<void*, size_t> sizes;
-  std::recursive_mutex mu;
-  std::map<int, DevMap> maps;
-  std::map<int, HypSet> sets;
-  std::map<int, Request> reqs;
-  int next_id = 1;
-  hipEvent_t ev[6] = {};
-  void* pinned = nullptr;         // small pinned staging buffer
-
-  void* dalloc(size_t bytes) {
-    if (bytes == 0) bytes = 1;
-    bytes = (bytes + 255) & ~(size_t)255;
-    if (used + bytes > budget) {
-      fail(RELOC_E_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu", used, bytes,
-           budget);
-      return nullptr;
-    }
-    void* p = nullptr;
-    if (has_alloc) {
-      p = alloc.alloc(bytes, alloc.user);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      p = nullptr;
-    }
-    if (!p) {
-      fail(RELOC_E_NOMEM, "device allocation of %zu bytes failed", bytes);
-      return nullptr;
-    }
-    sizes[p] = bytes;
-    used += bytes;
-    return p;
-  }
-  void dfree(void* p) {
-    if (!p) return;
-    auto it = sizes.find(p);
-    if (it == sizes.end()) return;
-    used -= it->second;
-    sizes.erase(it);
-    if (has_alloc)
-      alloc.free(p, alloc.user);
-    else
-      (void)hipFree(p);
-  }
-};
-
-namespace {
 
 int32_t set_device(reloc_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
@@ -328,19 +211,7 @@ void release_request(reloc_ctx* c, Request& r) {
   r.owned.clear();
 }
 
-template <typename T>
-T* req_alloc(reloc_ctx* c, Request& r, size_t count) {
-  void* p = c->dalloc(count * sizeof(T));
-  if (p) r.owned.push_back(p);
-  return (T*)p;
-}
 
-template <typename T>
-int32_t upload(reloc_ctx* c, T* dst, const T* src, size_t count) {
-  if (count == 0) return RELOC_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
-  return RELOC_OK;
-}
 
 int32_t ensure_khost(reloc_ctx* c, DevMap& m) {
   if (!m.khost.empty()) return RELOC_OK;
@@ -492,7 +363,6 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   }
   std::vector<int32_t> base(R.prep.vj.size());
   for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
-  if (int32_t e = build_lut(&R.prm, m.res, &R.lut)) return e;
   const int n = R.n_hyp, nv = I.n_valid;
   R.raydirs = req_alloc<int2>(c, R, Ns);
   R.kap = req_alloc<float2>(c, R, Ns);
@@ -627,7 +497,66 @@ int32_t validate_search(const reloc_search_params* p) {
   return RELOC_OK;
 }
 
-}  // namespace
+int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                     const reloc_search_params* params, Request* R) {
+  if (int32_t e = validate_search(params)) return e;
+  auto mi = c->maps.find(map_id);
+  if (mi == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
+  auto si = c->sets.find(set_id);
+  if (si == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
+  if (si->second.map_id != map_id)
+    return fail(RELOC_E_INVALID, "set %d belongs to another map", set_id);
+  R->map_id = map_id;
+  R->set_id = set_id;
+  R->prm = *params;
+  R->n_hyp = params->n_hyp > 0 ? std::min(params->n_hyp, si->second.n) : si->second.n;
+  if (int32_t e = preprocess(scan, params, mi->second.res, &R->prep)) return e;
+  if (int32_t e = build_lut(params, mi->second.res, &R->lut)) return e;
+  R->rmax = scan->range_max;
+  R->rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
+  return RELOC_OK;
+}
+
+size_t request_bytes(const Request& R) {
+  const reloc_scan_info& I = R.prep.info;
+  const size_t n = (size_t)std::max(1, R.n_hyp), Ns = (size_t)I.Ns;
+  const size_t stages = (n + (size_t)R.prm.batch_k - 1) / (size_t)R.prm.batch_k;
+  size_t b = n * (4 * Ns + 8 + 4 + 8 + 8 + 4 + 4 + 8);        // ranges, work buffers
+  b += Ns * (8 + 8 + 16 + 16) + (size_t)I.Ng * 8 + R.prep.runs.size() * 8;
+  b += R.prep.vj.size() * 8 + R.lut.q.size() * 4 + stages * 12;
+  b += (size_t)std::min<size_t>(n, (size_t)R.prm.k_out) * sizeof(PoseRow);
+  b += 2 * n * 12 + (1 << 20);                                  // sort scratch
+  b += 32 * 256;                                                // allocation rounding
+  return b;
+}
+
+void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, int n,
+                   reloc_pose* out) {
+  const DevMap& m = c->maps.at(R.map_id);
+  const HypSet& hs = c->sets.at(R.set_id);
+  const reloc_scan_info& I = R.prep.info;
+  for (int i = 0; i < n; ++i) {
+    const PoseRow& w = rows[i];
+    reloc_pose& p = out[i];
+    const int ix = hs.host[2 * w.hyp], iy = hs.host[2 * w.hyp + 1];
+    p.x = m.ox + ((double)ix + 0.5) * m.res;
+    p.y = m.oy + ((double)iy + 0.5) * m.res;
+    double th = (2.0 * M_PI * (double)w.k) / (double)I.Ntheta;
+    if (th >= M_PI) th -= 2.0 * M_PI;
+    p.theta = th;
+    uint32_t tb32 = w.tbits;
+    std::memcpy(&p.tam, &tb32, sizeof(float));
+    p.smad = (float)w.smad;
+    p.hyp = w.hyp;
+    p.k = w.k;
+    p.rank = w.rank;
+    p.stage = w.rank / R.prm.batch_k;
+  }
+}
+
+}  // namespace reloc
+
+using namespace reloc;
 
 // ============================================================================
 extern "C" {
@@ -692,6 +621,7 @@ int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* str
 
 void reloc_ctx_destroy(reloc_ctx* c) {
   if (!c) return;
+  ctx_stop_serving(c);
   {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     (void)hipSetDevice(c->device);
@@ -870,6 +800,7 @@ int32_t reloc_free_hypotheses(reloc_ctx* c, int32_t set_id) {
   if (it == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
   for (auto& kv : c->reqs)
     if (kv.second.set_id == set_id) return fail(RELOC_E_BUSY, "set %d used by a request", set_id);
+  if (serve_holds_set(c, set_id)) return fail(RELOC_E_BUSY, "set %d used by a queued request", set_id);
   (void)hipStreamSynchronize(c->stream);
   c->dfree(it->second.dev);
   c->maps[it->second.map_id].n_sets -= 1;
@@ -893,23 +824,10 @@ int32_t reloc_prepare(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_
                       const reloc_search_params* params, int32_t* request_id) {
   if (!c || !request_id) return fail(RELOC_E_INVALID, "null argument");
   *request_id = -1;
-  if (int32_t e = validate_search(params)) return e;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
-  auto mi = c->maps.find(map_id);
-  if (mi == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
-  auto si = c->sets.find(set_id);
-  if (si == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
-  if (si->second.map_id != map_id)
-    return fail(RELOC_E_INVALID, "set %d belongs to another map", set_id);
-  if (int32_t e = set_device(c)) return e;
   Request R;
-  R.map_id = map_id;
-  R.set_id = set_id;
-  R.prm = *params;
-  R.n_hyp = params->n_hyp > 0 ? std::min(params->n_hyp, si->second.n) : si->second.n;
-  if (int32_t e = preprocess(scan, params, mi->second.res, &R.prep)) return e;
-  R.rmax = scan->range_max;
-  R.rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
+  if (int32_t e = init_request(c, map_id, set_id, scan, params, &R)) return e;
+  if (int32_t e = set_device(c)) return e;
   if (int32_t e = build_request(c, R)) {
     release_request(c, R);
     return e;
@@ -990,24 +908,7 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     HIP_TRY(hipMemcpyAsync(rows.data(), R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(c->ev[4], s));
   HIP_TRY(hipStreamSynchronize(s));
-  const HypSet& hs = c->sets[R.set_id];
-  for (int i = 0; i < nrow; ++i) {
-    const PoseRow& w = rows[i];
-    reloc_pose& p = out[i];
-    const int ix = hs.host[2 * w.hyp], iy = hs.host[2 * w.hyp + 1];
-    p.x = m.ox + ((double)ix + 0.5) * m.res;
-    p.y = m.oy + ((double)iy + 0.5) * m.res;
-    double th = (2.0 * M_PI * (double)w.k) / (double)I.Ntheta;
-    if (th >= M_PI) th -= 2.0 * M_PI;
-    p.theta = th;
-    uint32_t tb32 = w.tbits;
-    std::memcpy(&p.tam, &tb32, sizeof(float));
-    p.smad = (float)w.smad;
-    p.hyp = w.hyp;
-    p.k = w.k;
-    p.rank = w.rank;
-    p.stage = w.rank / K;
-  }
+  rows_to_poses(c, R, rows.data(), nrow, out);
   *n_out = nrow;
   if (st) {
     std::memset(st, 0, sizeof *st);

@@ -1,0 +1,201 @@
+// Host-side state of libreloc shared by the single-request driver
+// (runtime.cpp) and the batched / serving driver (batch.cpp).
+#ifndef RELOC_RUNTIME_INTERNAL_H
+#define RELOC_RUNTIME_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "reloc.h"
+#include "reloc_internal.h"
+
+namespace reloc {
+
+// Sets the thread-local error message; returns code.
+int32_t fail(int32_t code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RELOC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+// ---- scan preprocessing (eq. 11-16, 25-26) ---------------------------------
+struct Prep {
+  reloc_scan_info info{};
+  std::vector<int2> runs;         // (panoramic start, length) per FoV run
+  std::vector<int32_t> vj, vzq;   // valid beams: panoramic index, range in Q8 cells
+};
+int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double res, Prep* out);
+
+// ---- likelihood table for TAM (eq. 23) --------------------------------------
+struct Lut {
+  std::vector<int32_t> q;   // Q26 likelihood per selection key
+  int kcap = 1, key_off = 2, keybits = 12;
+};
+int32_t build_lut(const reloc_search_params* p, double res, Lut* L);
+
+struct ServeState;   // batch.cpp
+
+}  // namespace reloc
+
+using reloc::fail;
+using reloc::Lut;
+using reloc::PoseRow;
+using reloc::Prep;
+
+struct DevMap {
+  int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
+  double res = 0.05, ox = 0, oy = 0;
+  uint64_t* bits = nullptr;
+  uint16_t* walk = nullptr;       // null when the map exceeds kWalkMaxCells
+  uint32_t* kmap = nullptr;
+  std::vector<int8_t> occ;        // host copy for the sampler
+  std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
+  int n_sets = 0;
+};
+
+struct HypSet {
+  int map_id = -1;
+  int n = 0;
+  int32_t* dev = nullptr;         // [n][2]
+  std::vector<int32_t> host;
+};
+
+struct Request {
+  int map_id = -1, set_id = -1, n_hyp = 0;
+  Prep prep;
+  reloc_search_params prm{};
+  float rmax = 0.f;
+  int rcells = 0;
+  Lut lut;
+  // device tables
+  int2* raydirs = nullptr;
+  float2* kap = nullptr;
+  int4* dir_i = nullptr;
+  float4* dir_f = nullptr;
+  float* zbuf = nullptr;
+  int2* runs = nullptr;
+  int32_t* base = nullptr;
+  int32_t* zq = nullptr;
+  int2* dirs = nullptr;
+  int32_t* dlut = nullptr;
+  // device work
+  double* smad = nullptr;
+  int32_t* argm = nullptr;
+  uint64_t* keys = nullptr;
+  uint64_t* keys2 = nullptr;
+  int32_t* vals = nullptr;
+  int32_t* order = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  uint64_t* best = nullptr;
+  uint64_t* stage = nullptr;
+  int32_t* flag = nullptr;
+  PoseRow* rows = nullptr;
+  int rows_cap = 0;
+  std::vector<void*> owned;
+};
+
+struct reloc_ctx {
+  reloc::ServeState* serve = nullptr;   // batch staging and the submit / poll scheduler
+
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  reloc_allocator alloc{};
+  bool has_alloc = false;
+  size_t budget = 0, used = 0;
+  std::map<void*, size_t> sizes;
+  std::recursive_mutex mu;
+  std::map<int, DevMap> maps;
+  std::map<int, HypSet> sets;
+  std::map<int, Request> reqs;
+  int next_id = 1;
+  hipEvent_t ev[6] = {};
+  void* pinned = nullptr;         // small pinned staging buffer
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (used + bytes > budget) {
+      fail(RELOC_E_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu", used, bytes,
+           budget);
+      return nullptr;
+    }
+    void* p = nullptr;
+    if (has_alloc) {
+      p = alloc.alloc(bytes, alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (!p) {
+      fail(RELOC_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+      return nullptr;
+    }
+    sizes[p] = bytes;
+    used += bytes;
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = sizes.find(p);
+    if (it == sizes.end()) return;
+    used -= it->second;
+    sizes.erase(it);
+    if (has_alloc)
+      alloc.free(p, alloc.user);
+    else
+      (void)hipFree(p);
+  }
+};
+
+namespace reloc {
+
+int32_t set_device(reloc_ctx* c);
+void release_request(reloc_ctx* c, Request& r);
+int32_t validate_search(const reloc_search_params* p);
+// Host preprocessing of a request (no device work): fills R's map, set,
+// parameters, Prep and limits. build_request then allocates and uploads.
+int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
+                     const reloc_search_params* params, Request* R);
+int32_t build_request(reloc_ctx* c, Request& R);
+RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps);
+TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out);
+// Device bytes build_request will allocate for R (admission control).
+size_t request_bytes(const Request& R);
+// Converts device result rows to poses in world coordinates.
+void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, int n,
+                   reloc_pose* out);
+void ctx_stop_serving(reloc_ctx* c);
+// true while a queued or running served request uses the set
+bool serve_holds_set(reloc_ctx* c, int32_t set_id);
+
+template <typename T>
+T* req_alloc(reloc_ctx* c, Request& r, size_t count) {
+  void* p = c->dalloc(count * sizeof(T));
+  if (p) r.owned.push_back(p);
+  return (T*)p;
+}
+
+template <typename T>
+int32_t upload(reloc_ctx* c, T* dst, const T* src, size_t count) {
+  if (count == 0) return RELOC_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return RELOC_OK;
+}
+
+}  // namespace reloc
+
+#endif  // RELOC_RUNTIME_INTERNAL_H

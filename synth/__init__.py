@@ -9,9 +9,11 @@ from .maps import (MapSpec, rooms_map, warehouse_map, tiled_rooms_map,
                    mixed_map, perturb_map, rasterize)
 from .scans import ScanSpec, true_pose, lidar_scan, feasible_cells
 from .configs import CONFIGS, make_config, make_micro
+from .multi import MultiWorkload, Query, make_batched, make_serving
 
 __all__ = [
     "MapSpec", "rooms_map", "warehouse_map", "tiled_rooms_map", "mixed_map",
     "perturb_map", "rasterize", "ScanSpec", "true_pose", "lidar_scan",
     "feasible_cells", "CONFIGS", "make_config", "make_micro",
+    "MultiWorkload", "Query", "make_batched", "make_serving",
 ]
