@@ -122,6 +122,169 @@ def cpu_baseline(w, hyp, n_theta, batch_k, stages_gpu, budget_s):
                       % (steps, len(hyp), n_tam, n_theta, dt)}
 
 
+def _load_multi(ctx, w):
+    mids, sids = [], []
+    for m, occ in enumerate(w.maps):
+        mid = ctx.load_map(occ, w.resolution)
+        sid, _ = ctx.sample_hypotheses(mid, w.sample["n_target"][m], w.sample["min_spacing"],
+                                       w.sample["robot_radius"], seed=w.sample["seeds"][m])
+        mids.append(mid)
+        sids.append(sid)
+    return mids, sids
+
+
+def _scan_args(q):
+    return (q.ranges, q.angle_min, q.angle_increment, q.range_min, q.range_max)
+
+
+def bench_batched(args):
+    """64 queries over 8 resident maps: the batched form (one reloc_run_batch)
+    against the plain path (reloc_run of one request after another)."""
+    import numpy as np
+    import torch
+    import paper_2511_01219_amd as reloc
+    from synth import make_batched
+    log("generating the batched workload")
+    w = make_batched(64)
+    ctx = reloc.Context(0)
+    mids, sids = _load_multi(ctx, w)
+    rids = [ctx.prepare(mids[q.map_index], sids[q.map_index], *_scan_args(q), n_hyp=q.n_hyp,
+                        k_out=10, **q.search) for q in w.queries]
+    log("%d requests prepared, %d hypotheses" % (len(rids), sum(q.n_hyp for q in w.queries)))
+    for _ in range(args.warmup):
+        ref = ctx.run_batch(rids)
+        plain = [ctx.run(r) for r in rids]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain = [ctx.run(r) for r in rids]
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.run_batch(rids)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    same = all(a[0][0]["hyp"] == b[0][0]["hyp"] and a[0][0]["k"] == b[0][0]["k"] and
+               a[0][0]["tam"] == b[0][0]["tam"] and a[1]["n_eval"] == b[1]["n_eval"]
+               for a, b in zip(plain, res))
+    evals = sum(st["smad_evals"] + st["tam_evals"] for _, st in res)
+    st0 = res[0][1]
+    out = {
+        "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
+        "value": evals / t_batch, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32+f32+f64", "data": "synthetic",
+        "config": {"workload": "batched: 64 queries over 8 maps (rooms and warehouse at "
+                               "500^2, 1000^2, 2000^2, 4000^2), 1k-50k hypotheses, FoV "
+                               "180-360 deg, 360-1080 beams, N_theta 360, top-64, tau 0.95",
+                   "n_queries": len(rids), "n_hyp_total": int(sum(st["n_hyp"] for _, st in res))},
+        "plain": {"value": evals / t_plain, "ms_per_step": t_plain * 1e3},
+        "speedup_vs_plain": t_plain / t_batch,
+        "identical_to_plain": bool(same),
+        "phases_ms": {k: st0[k] for k in ("ms_raycast", "ms_smad", "ms_sort", "ms_tam",
+                                          "ms_rank")},
+        "stages": {"max": int(max(st["stages"] for _, st in res)),
+                   "total": int(sum(st["stages"] for _, st in res))},
+    }
+    for r in rids:
+        ctx.release(r)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Open-loop Poisson replay over 16 resident maps: served (reloc_submit /
+    reloc_poll, continuous batching) against plain FIFO (reloc_relocalize of
+    one request after another in arrival order) on the same trace."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2511_01219_amd as reloc
+    from synth import make_serving
+    log("generating the serving workload")
+    w = make_serving(1.0, args.requests)        # arrivals at rate 1, rescaled per rate
+    ctx = reloc.Context(0)
+    mids, sids = _load_multi(ctx, w)
+    qs = w.queries
+    base = np.array([q.arrival for q in qs])
+
+    def call_args(q):
+        return (mids[q.map_index], sids[q.map_index]) + _scan_args(q)
+
+    for q in qs[:8]:                            # warm-up
+        ctx.relocalize(*call_args(q), n_hyp=q.n_hyp, **q.search)
+    torch.cuda.synchronize()
+    rows = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        arr = base / rate
+        # served
+        ctx.serve_configure(max_inflight=args.max_inflight, max_admit=args.max_inflight)
+        sub = []
+        start = time.perf_counter()
+
+        def submitter():
+            for i, q in enumerate(qs):
+                d = start + arr[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tc = time.perf_counter()
+                sub.append((i, ctx.submit(*call_args(q), n_hyp=q.n_hyp, **q.search), tc))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat_s, fin_s, served = [], [], {}
+        idx = 0
+        while idx < len(qs):
+            while idx >= len(sub):
+                time.sleep(0.0002)
+            i, t, tc = sub[idx]
+            idx += 1
+            poses, st = ctx.poll(t, wait_ms=-1)
+            done = tc + st["ms_total"] * 1e-3
+            lat_s.append(done - (start + arr[i]))
+            fin_s.append(done)
+            served[i] = (poses[0]["hyp"], poses[0]["k"], poses[0]["tam"],
+                         st["smad_evals"] + st["tam_evals"])
+        th.join()
+        span_s = max(fin_s) - start
+        sstats = ctx.serve_stats()
+        # plain FIFO
+        lat_f, same = [], True
+        start = time.perf_counter()
+        for i, q in enumerate(qs):
+            d = start + arr[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            poses, st = ctx.relocalize(*call_args(q), n_hyp=q.n_hyp, **q.search)
+            lat_f.append(time.perf_counter() - (start + arr[i]))
+            same &= served[i][:3] == (poses[0]["hyp"], poses[0]["k"], poses[0]["tam"])
+        span_f = time.perf_counter() - start
+        evals = sum(v[3] for v in served.values())
+        rows.append({
+            "rate_per_s": rate, "requests": len(qs),
+            "served": {"p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat_s, 99) * 1e3),
+                       "evals_per_s": evals / span_s, "req_per_s": len(qs) / span_s,
+                       "rounds": int(sstats["ticks"])},
+            "fifo": {"p50_ms": float(np.percentile(lat_f, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat_f, 99) * 1e3),
+                     "evals_per_s": evals / span_f, "req_per_s": len(qs) / span_f},
+            "identical_best_pose": bool(same)})
+        log("rate %.0f/s: served p50 %.1f ms p99 %.1f ms, fifo p50 %.1f ms p99 %.1f ms"
+            % (rate, rows[-1]["served"]["p50_ms"], rows[-1]["served"]["p99_ms"],
+               rows[-1]["fifo"]["p50_ms"], rows[-1]["fifo"]["p99_ms"]))
+    out = {"metric": "p50/p99 relocalization latency and evals/s under Poisson load",
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "serving: 16 maps (4 each of 1000^2, 2000^2, 3000^2, "
+                                  "4000^2), 2k-40k hypotheses, FoV 270/360 deg, 540-1440 "
+                                  "beams, N_theta 360, top-64, tau 0.95",
+                      "requests_per_rate": len(qs), "max_inflight": args.max_inflight},
+           "serving": rows}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +295,11 @@ def main():
     ap.add_argument("--variant", type=int, default=0,
                     help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="plain-large",
+                    choices=("plain-large", "batched", "serving"))
+    ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
+    ap.add_argument("--max-inflight", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -139,6 +307,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import numpy as np
     import torch

@@ -275,9 +275,11 @@ int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
  * and the TAM stages of all requests advance together: each step launches
  * TAM over a rank range of every unfinished request and one stage-control
  * kernel that reduces each of its stages on the device (Sec. III pipeline,
- * batch-wise early termination). A range covers 1, 2, 4, ... up to 32
- * consecutive stages; stages after the first whose best T exceeds tau are
- * discarded, so every request gets exactly the result of reloc_run.
+ * batch-wise early termination). A range covers one stage in a request's
+ * first two steps, then 2, 4, ... up to 32 consecutive stages while that
+ * keeps the device no busier than it needs to be; stages after the first
+ * whose best T exceeds tau are discarded, so every request gets exactly the
+ * result of reloc_run.
  *   request_ids : host int32[n], distinct prepared requests
  *   out         : host reloc_pose[n * cap]; request i's poses at out + i*cap
  *   n_out       : host int32[n] poses written per request

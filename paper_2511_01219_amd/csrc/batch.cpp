@@ -9,9 +9,11 @@
 //           of every unfinished request plus one stage-control launch that
 //           reduces every stage of the tick on the device; the host reads
 //           one flag per stage. A request's range covers `spec` consecutive
-//           stages (1, 2, 4, ... up to kMaxSpec); stages after the first one
-//           whose best T exceeds tau are discarded, so the evaluated set and
-//           every result equal those of the one-stage-at-a-time path;
+//           stages (1 for its first two ticks, then 2, 4, ... up to
+//           kMaxSpec, and never more than keeps the device busy next to the
+//           other requests); stages after the first one whose best T exceeds
+//           tau are discarded, so the evaluated set and every result equal
+//           those of the one-stage-at-a-time path;
 //   rank  : one segmented sort and one gather for every finished request.
 // The scheduler repeats admission -> front of the admitted requests -> one
 // tick of everything in flight -> rank of the finished ones, so requests
@@ -26,7 +28,8 @@ namespace reloc {
 
 namespace {
 
-constexpr int kMaxSpec = 32;   // stages of one request in one tick, at most
+constexpr int kMaxSpec = 32;          // stages of one request in one tick, at most
+constexpr int64_t kFillBlocks = 16384;  // TAM workgroups that keep every CU busy in a tick
 
 // Contiguous buffers of one front-phase group: SMAD sort keys / values, the
 // SMAD order and the per-rank best of every request of the group.
@@ -51,7 +54,7 @@ struct Flight {
   int rid = -1;                     // key in c->reqs
   std::shared_ptr<Arena> arena;
   int64_t off = 0;                  // first hypothesis of the request in the arena
-  int next_rank = 0, spec = 1, stages = 0, n_eval = 0;
+  int next_rank = 0, spec = 1, stages = 0, n_eval = 0, ticks = 0;
   bool done = false, stopped = false;
   int32_t status = RELOC_OK;
   std::chrono::steady_clock::time_point t_start;
@@ -111,10 +114,7 @@ struct ServeState {
 
 namespace {
 
-ServeState* state(reloc_ctx* c) {
-  if (!c->serve) c->serve = new ServeState();
-  return c->serve;
-}
+ServeState* state(reloc_ctx* c) { return c->serve; }
 
 // Copies the blob to device memory (after the stream has drained, so the
 // pinned buffer is free); *dev receives the device address of offset 0.
@@ -242,6 +242,7 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
     f.off = hpre[i];
     f.next_rank = 0;
     f.spec = 1;
+    f.ticks = 0;
     f.stages = 0;
     f.n_eval = 0;
     f.done = false;
@@ -258,19 +259,26 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
   for (Flight* f : F)
     if (!f->done) live.push_back(f);
   if (live.empty()) return RELOC_OK;
+  // stages per request this tick: the speculation schedule, capped so that
+  // the tick does not run far beyond what fills the device
+  std::vector<int> nst(live.size());
   size_t n_entries = 0;
-  for (Flight* f : live) {
+  for (size_t j = 0; j < live.size(); ++j) {
+    const Flight* f = live[j];
     const Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
     const int left = (R.n_hyp - f->next_rank + K - 1) / K;
-    n_entries += (size_t)std::min(f->spec, left);
+    const int64_t bps = (int64_t)K * ((R.prep.info.Ntheta + 15) / 16);
+    const int64_t cap = std::max<int64_t>(1, kFillBlocks / ((int64_t)live.size() * bps));
+    nst[j] = (int)std::min<int64_t>(std::min(f->spec, left), cap);
+    n_entries += (size_t)nst[j];
   }
   if (int32_t e = ensure_stage_cap(c, S, n_entries)) return e;
-  for (Flight* f : live) {
+  for (size_t j = 0; j < live.size(); ++j) {
+    Flight* f = live[j];
     Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
-    const int left = (R.n_hyp - f->next_rank + K - 1) / K;
-    const int ns = std::min(f->spec, left);
+    const int ns = nst[j];
     const int nb = std::min(ns * K, R.n_hyp - f->next_rank);
     TamArgs a = tam_args(c, R, f->next_rank, nb, nullptr);
     a.order = f->arena->order + f->off;
@@ -347,7 +355,7 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
       f->done = true;
       continue;
     }
-    f->spec = std::min(kMaxSpec, f->spec * 2);
+    if (++f->ticks >= 2) f->spec = std::min(kMaxSpec, f->spec * 2);
     if (R.prm.deadline_s > 0 &&
         std::chrono::duration<double>(now - f->t_start).count() > R.prm.deadline_s) {
       f->done = true;
@@ -570,6 +578,8 @@ void serve_loop(reloc_ctx* c) {
 
 }  // namespace
 
+ServeState* serve_create() { return new ServeState(); }
+
 bool serve_holds_set(reloc_ctx* c, int32_t set_id) {
   if (!c->serve) return false;
   std::lock_guard<std::mutex> lk(c->serve->qmu);
@@ -669,7 +679,6 @@ int32_t reloc_serve_configure(reloc_ctx* c, const reloc_serve_config* cfg) {
   if (!c || !cfg) return fail(RELOC_E_INVALID, "null argument");
   if (cfg->max_inflight < 1 || cfg->max_admit < 1)
     return fail(RELOC_E_INVALID, "max_inflight and max_admit must be >= 1");
-  std::lock_guard<std::recursive_mutex> cl(c->mu);
   ServeState& S = *state(c);
   std::lock_guard<std::mutex> lk(S.qmu);
   S.cfg = *cfg;
@@ -681,17 +690,21 @@ int32_t reloc_submit(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
   if (!c || !ticket) return fail(RELOC_E_INVALID, "null argument");
   *ticket = 0;
   auto t = std::make_unique<Ticket>();
+  t->t_submit = std::chrono::steady_clock::now();
   {
-    std::lock_guard<std::recursive_mutex> cl(c->mu);
+    // host preprocessing only: the registry lock, not the context lock, so
+    // that submit does not wait for the scheduler's device work; held until
+    // the ticket is registered so the set cannot be freed in between
+    std::lock_guard<std::mutex> rg(c->reg_mu);
     if (int32_t e = init_request(c, map_id, set_id, scan, params, &t->R)) return e;
     ServeState& S = *state(c);
     std::lock_guard<std::mutex> lk(S.qmu);
+    if (S.stop) return fail(RELOC_E_INVALID, "context is shutting down");
     if (!S.running) {
       S.worker = std::thread(serve_loop, c);
       S.running = true;
     }
     t->id = S.next_ticket++;
-    t->t_submit = std::chrono::steady_clock::now();
     *ticket = t->id;
     S.pending.push_back(t.get());
     S.tickets[t->id] = std::move(t);
@@ -706,12 +719,7 @@ int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* o
                    int32_t* n_out, reloc_stats* st) {
   if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
   *n_out = 0;
-  ServeState* S = nullptr;
-  {
-    std::lock_guard<std::recursive_mutex> cl(c->mu);
-    S = c->serve;
-  }
-  if (!S) return fail(RELOC_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  ServeState* S = c->serve;
   std::unique_lock<std::mutex> lk(S->qmu);
   auto it = S->tickets.find(ticket);
   if (it == S->tickets.end())
@@ -739,12 +747,7 @@ int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* o
 int32_t reloc_serve_stats_get(reloc_ctx* c, reloc_serve_stats* out) {
   if (!c || !out) return fail(RELOC_E_INVALID, "null argument");
   std::memset(out, 0, sizeof *out);
-  ServeState* S = nullptr;
-  {
-    std::lock_guard<std::recursive_mutex> cl(c->mu);
-    S = c->serve;
-  }
-  if (!S) return RELOC_OK;
+  ServeState* S = c->serve;
   std::lock_guard<std::mutex> lk(S->qmu);
   *out = S->stats;
   return RELOC_OK;

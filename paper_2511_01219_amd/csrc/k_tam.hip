@@ -12,9 +12,10 @@
 // selection of the k_mid smallest integer keys: key = 2 * min(k, kcap) for
 // in-map endpoints and a host-chosen odd key for off-map ones (d = d_max).
 // kcap is where l(k) has converged to within 1e-10 of its limit. The
-// threshold key comes from a two-level LDS histogram; sums are exact
-// integers (l in Q26 fixed point from a host table, sqrt(k) in Q16, k
-// itself), so the result does not depend on lane order or co-scheduling.
+// threshold key comes from a bitwise search whose counts are wavefront
+// ballots; sums are exact integers (l in Q26 fixed point from a host table,
+// sqrt(k) in Q16, k itself), so the result does not depend on lane order or
+// co-scheduling.
 // The median of eq. 27 is always the top-k_mid mean (top-k means are
 // non-increasing in k and k_low <= k_mid <= k_full).
 #include <cmath>
@@ -40,53 +41,24 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Smallest bin b of the NB-bin histogram h at which the cumulative count
-// reaches `need` (>= 1), and the count strictly below b. Lane l owns bins
-// [l*P, (l+1)*P).
-template <int P>
-__device__ __forceinline__ void find_bin(const uint32_t* h, int lane, int need, int* bin,
-                                         int* below) {
-  int loc = 0;
-#pragma unroll
-  for (int p = 0; p < P; ++p) loc += (int)h[lane * P + p];
-  int incl = loc;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += v;
-  }
-  const unsigned long long m = __ballot(incl >= need);
-  const int first = m ? __ffsll((unsigned long long)m) - 1 : 63;
-  int b = 0, bl = 0;
-  if (lane == first) {
-    int acc = incl - loc;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int c = (int)h[lane * P + p];
-      if (acc + c >= need) {
-        b = lane * P + p;
-        bl = acc;
-        break;
-      }
-      acc += c;
-    }
-  }
-  *bin = __shfl(b, first, 64);
-  *below = __shfl(bl, first, 64);
-}
-
-// One workgroup's work: rank a.r0 + i, orientations [16 kb, 16 kb + 16).
+// One workgroup's work: rank a.r0 + i, orientations [16 kb, 16 kb + 16);
+// wavefront w takes orientations 16 kb + w + 4 g, g = 0..3.
+//
+// Per (p, theta) the valid beams are spread over the lanes, SB per lane at a
+// time: all SB direction loads, then all SB EDT gathers, are issued before
+// any is used. The per-orientation integer sums are parked in lane g; the
+// FP64 tail (eq. 27-31) then runs once for the four orientations in lanes
+// 0..3, and one atomic max per wavefront publishes the best (T, ~k).
 template <int R, int KB>
 __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
-  constexpr int LB2 = KB / 2;
-  constexpr int NB = 1 << LB2;        // bins per level (level 1: key >> LB2)
-  constexpr int P = NB / 64;
+  constexpr int SB = 4;               // keys per lane in flight together
+  constexpr int G = THETA_PER_BLOCK / NW;
   int32_t* sbase = smem;              // [nv]
   int32_t* szq = smem + a.nv;         // [nv]
-  uint32_t* hist_all = (uint32_t*)(smem + 2 * a.nv);   // [NW][NB]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  uint32_t* hist = hist_all + wv * NB;
+  const int nv = a.nv;
 
-  for (int v = tid; v < a.nv; v += TB) {
+  for (int v = tid; v < nv; v += TB) {
     sbase[v] = a.beam_base[v];
     szq[v] = a.beam_zq[v];
   }
@@ -97,98 +69,130 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   const int k0 = kb * THETA_PER_BLOCK;
   __syncthreads();
 
-  for (int it = 0; it < THETA_PER_BLOCK / NW; ++it) {
-    const int k = k0 + wv + NW * it;
-    const bool active = k < a.Nt;
+  // per-orientation results parked in lane g
+  int64_t p_sl = 0;
+  uint64_t p_sumk = 0, p_sumsq = 0;
+  int p_noff = 0;
+
+  for (int g = 0; g < G; ++g) {
+    const int k = k0 + wv + NW * g;
+    if (k >= a.Nt) break;                       // wavefront-uniform
     uint32_t keys[R];
     uint64_t sumk = 0, sumsq = 0;
     int noff = 0;
-    if (active) {
-      const int ok = (int)(((int64_t)a.o * k) % a.Ng);
+    const int ok = (int)(((int64_t)a.o * k) % a.Ng);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int v = lane + 64 * i;
-        uint32_t key = NOKEY;
-        if (v < a.nv) {
+    for (int i0 = 0; i0 < R; i0 += SB) {
+      if (64 * i0 < nv) {                       // wavefront-uniform
+        int2 U[SB];
+        int zq[SB];
+#pragma unroll
+        for (int s2 = 0; s2 < SB; ++s2) {
+          const int v = min(lane + 64 * (i0 + s2), nv - 1);
           int t = sbase[v] + ok;
           if (t >= a.Ng) t -= a.Ng;
-          const int2 U = a.dirs[t];
-          const int64_t zq = szq[v];
-          const int64_t ex = (X20 + zq * U.x) >> 28;
-          const int64_t ey = (Y20 + zq * U.y) >> 28;
-          if ((uint64_t)ex < (uint64_t)a.W && (uint64_t)ey < (uint64_t)a.H) {
-            const uint32_t kk = a.kmap[(size_t)ey * a.W + (size_t)ex];
-            key = 2u * min(kk, (uint32_t)a.kcap);
-            sumk += kk;
-            sumsq += sqrt_q16(kk);
-          } else {
-            key = (uint32_t)a.key_off;
-            ++noff;
-          }
+          zq[s2] = szq[v];
+          U[s2] = a.dirs[t];
         }
-        keys[i] = key;
+        uint32_t kk[SB];
+        bool in[SB];
+#pragma unroll
+        for (int s2 = 0; s2 < SB; ++s2) {
+          // the shifted endpoint is a cell index within a few thousand of
+          // the map, so its low 32 bits are the whole value
+          const int ex = (int)((X20 + (int64_t)zq[s2] * U[s2].x) >> 28);
+          const int ey = (int)((Y20 + (int64_t)zq[s2] * U[s2].y) >> 28);
+          in[s2] = (uint32_t)ex < (uint32_t)a.W && (uint32_t)ey < (uint32_t)a.H;
+          const uint32_t idx = in[s2] ? (uint32_t)ey * (uint32_t)a.W + (uint32_t)ex : 0u;
+          kk[s2] = a.kmap[idx];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < SB; ++s2) {
+          const bool valid = lane + 64 * (i0 + s2) < nv;
+          uint32_t key = NOKEY;
+          if (valid) {
+            if (in[s2]) {
+              key = 2u * min(kk[s2], (uint32_t)a.kcap);
+              sumk += kk[s2];
+              sumsq += sqrt_q16(kk[s2]);
+            } else {
+              key = (uint32_t)a.key_off;
+              ++noff;
+            }
+          }
+          keys[i0 + s2] = key;
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < SB; ++s2) keys[i0 + s2] = NOKEY;
       }
     }
-    // level 1: coarse histogram of key >> LB2
+    // k_mid-th smallest key: bitwise search for the largest t with fewer
+    // than k_mid keys below it; counts from wavefront ballots
+    uint32_t tkey = 0;
+    for (int bit = KB - 1; bit >= 0; --bit) {
+      const uint32_t cand = tkey | (1u << bit);
+      int cnt = 0;
 #pragma unroll
-    for (int p = 0; p < P; ++p) hist[lane * P + p] = 0;
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (keys[i] != NOKEY) atomicAdd(&hist[keys[i] >> LB2], 1u);
+      for (int q = 0; q < R; ++q)
+        if (64 * q < nv) cnt += __popcll(__ballot(keys[q] < cand));
+      if (cnt < a.kmid) tkey = cand;
     }
-    __syncthreads();
-    int b1 = 0, below1 = 0;
-    if (active) find_bin<P>(hist, lane, a.kmid, &b1, &below1);
-    __syncthreads();
-    // level 2: fine histogram inside the threshold bin
+    int below = 0;
 #pragma unroll
-    for (int p = 0; p < P; ++p) hist[lane * P + p] = 0;
-    __syncthreads();
-    if (active) {
+    for (int q = 0; q < R; ++q)
+      if (64 * q < nv) below += __popcll(__ballot(keys[q] < tkey));
+    int64_t sl = 0;
 #pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (keys[i] != NOKEY && (int)(keys[i] >> LB2) == b1)
-          atomicAdd(&hist[keys[i] & (NB - 1)], 1u);
-    }
-    __syncthreads();
-    if (active) {
-      int b2 = 0, below2 = 0;
-      find_bin<P>(hist, lane, a.kmid - below1, &b2, &below2);
-      const uint32_t tkey = ((uint32_t)b1 << LB2) | (uint32_t)b2;
-      const int below = below1 + below2;
-      int64_t sl = 0;
+    for (int i0 = 0; i0 < R; i0 += SB) {
+      if (64 * i0 < nv) {
+        int32_t lv[SB];
 #pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (keys[i] < tkey) sl += a.lut[keys[i]];
-      sl = wave_sum(sl);
-      sumk = wave_sum(sumk);
-      sumsq = wave_sum(sumsq);
-      noff = wave_sum(noff);
-      if (lane == 0) {
-        sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
-        const double Lbar = (double)sl / (67108864.0 * (double)a.kmid);
-        const double Pl = exp(Lbar);
-        const double nv = (double)a.nv;
-        const double sum_d = a.res * ((double)sumsq / 65536.0) + (double)noff * a.d_max;
-        const double sum_d2 = a.res * a.res * (double)sumk + (double)noff * a.d_max * a.d_max;
-        const double dbar = sum_d / nv;
-        double var = sum_d2 / nv - dbar * dbar;
-        if (var < 0.0) var = 0.0;
-        const double dmin = 0.5 * a.res;
-        const double dt = fmin(fmax(dbar, dmin), a.d_max);
-        const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
-        const double c = exp(-0.5 * var);
-        const float T = (float)cbrt(Pl * sd * c);
-        if (a.T_out) a.T_out[(size_t)i * a.Nt + k] = T;
-        const uint64_t packed =
-            ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
-        atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
+        for (int s2 = 0; s2 < SB; ++s2)
+          lv[s2] = a.lut[keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u];
+#pragma unroll
+        for (int s2 = 0; s2 < SB; ++s2)
+          if (keys[i0 + s2] < tkey) sl += lv[s2];
       }
     }
-    __syncthreads();
+    sl = wave_sum(sl);
+    sumk = wave_sum(sumk);
+    sumsq = wave_sum(sumsq);
+    noff = wave_sum(noff);
+    sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
+    if (lane == g) {
+      p_sl = sl;
+      p_sumk = sumk;
+      p_sumsq = sumsq;
+      p_noff = noff;
+    }
   }
+  // FP64 tail for the parked orientations, one per lane
+  const int k = k0 + wv + NW * lane;
+  const bool mine = lane < G && k < a.Nt;
+  uint64_t packed = 0;
+  if (mine) {
+    const double Lbar = (double)p_sl / (67108864.0 * (double)a.kmid);
+    const double Pl = exp(Lbar);
+    const double nvd = (double)nv;
+    const double sum_d = a.res * ((double)p_sumsq / 65536.0) + (double)p_noff * a.d_max;
+    const double sum_d2 = a.res * a.res * (double)p_sumk + (double)p_noff * a.d_max * a.d_max;
+    const double dbar = sum_d / nvd;
+    double var = sum_d2 / nvd - dbar * dbar;
+    if (var < 0.0) var = 0.0;
+    const double dmin = 0.5 * a.res;
+    const double dt = fmin(fmax(dbar, dmin), a.d_max);
+    const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
+    const double c = exp(-0.5 * var);
+    const float T = (float)cbrt(Pl * sd * c);
+    if (a.T_out) a.T_out[(size_t)i * a.Nt + k] = T;
+    packed = ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+  }
+  for (int off = G / 2; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(packed, off, 64);
+    packed = o > packed ? o : packed;
+  }
+  if (lane == 0 && packed) atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
 }
 
 template <int R, int KB>
@@ -222,8 +226,7 @@ __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict
 
 template <int R, int KB>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)2 * a.nv * sizeof(int32_t) +
-                     (size_t)NW * (1 << (KB / 2)) * sizeof(uint32_t);
+  const size_t lds = (size_t)2 * a.nv * sizeof(int32_t);
   dim3 grid((a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK, a.nb);
   hipLaunchKernelGGL((tam_kernel<R, KB>), grid, dim3(TB), lds, s, a);
   return hipGetLastError();
@@ -367,10 +370,7 @@ int tam_class(const TamArgs& a) {
   return (rc < 0 || kc < 0) ? -1 : kc * 5 + rc;
 }
 
-size_t tam_lds_bytes(const TamArgs& a) {
-  const int KB = a.keybits <= 12 ? 12 : 16;
-  return (size_t)2 * a.nv * sizeof(int32_t) + (size_t)NW * (1 << (KB / 2)) * sizeof(uint32_t);
-}
+size_t tam_lds_bytes(const TamArgs& a) { return (size_t)2 * a.nv * sizeof(int32_t); }
 
 hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
                             int64_t blocks, size_t lds, hipStream_t s) {

@@ -324,6 +324,7 @@ int32_t new_set(reloc_ctx* c, int map_id, std::vector<int32_t>&& xy, int32_t* se
   }
   const int id = c->next_id++;
   c->maps[map_id].n_sets += 1;
+  std::lock_guard<std::mutex> rg(c->reg_mu);
   c->sets[id] = std::move(hs);
   *set_id = id;
   return RELOC_OK;
@@ -614,6 +615,7 @@ int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* str
   HIP_TRY(hipMemGetInfo(&fr, &tot));
   c->budget = hbm_budget ? hbm_budget : fr;
   for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+  c->serve = serve_create();
   HIP_TRY(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
   *out = c.release();
   return RELOC_OK;
@@ -701,7 +703,10 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
     return fail(RELOC_E_DEVICE, "map upload failed: %s", hipGetErrorString(e));
   }
   const int id = c->next_id++;
-  c->maps[id] = std::move(m);
+  {
+    std::lock_guard<std::mutex> rg(c->reg_mu);
+    c->maps[id] = std::move(m);
+  }
   *map_id = id;
   return RELOC_OK;
 }
@@ -716,6 +721,7 @@ int32_t reloc_unload_map(reloc_ctx* c, int32_t map_id) {
   c->dfree(it->second.bits);
   c->dfree(it->second.walk);
   c->dfree(it->second.kmap);
+  std::lock_guard<std::mutex> rg(c->reg_mu);
   c->maps.erase(it);
   return RELOC_OK;
 }
@@ -800,6 +806,9 @@ int32_t reloc_free_hypotheses(reloc_ctx* c, int32_t set_id) {
   if (it == c->sets.end()) return fail(RELOC_E_NOTFOUND, "unknown hypothesis set %d", set_id);
   for (auto& kv : c->reqs)
     if (kv.second.set_id == set_id) return fail(RELOC_E_BUSY, "set %d used by a request", set_id);
+  // registry lock first: a concurrent submit either sees the set gone or
+  // has registered its ticket before this check
+  std::lock_guard<std::mutex> rg(c->reg_mu);
   if (serve_holds_set(c, set_id)) return fail(RELOC_E_BUSY, "set %d used by a queued request", set_id);
   (void)hipStreamSynchronize(c->stream);
   c->dfree(it->second.dev);

@@ -110,6 +110,7 @@ struct Request {
 
 struct reloc_ctx {
   reloc::ServeState* serve = nullptr;   // batch staging and the submit / poll scheduler
+  std::mutex reg_mu;                    // guards the maps / sets registries for submit
 
   int device = 0;
   hipStream_t stream = nullptr;
@@ -178,6 +179,7 @@ size_t request_bytes(const Request& R);
 // Converts device result rows to poses in world coordinates.
 void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, int n,
                    reloc_pose* out);
+ServeState* serve_create();
 void ctx_stop_serving(reloc_ctx* c);
 // true while a queued or running served request uses the set
 bool serve_holds_set(reloc_ctx* c, int32_t set_id);
