@@ -193,6 +193,86 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_stress(args):
+    """Stress: 8000 x 8000 mixed map, 200 000 hypotheses, panoramic 1440-beam
+    scan (perturbed environment, 15 % clutter), 1440 orientations, top-256
+    per stage, tau 0.95; one relocalization per step."""
+    import numpy as np
+    import torch
+    import paper_2511_01219_amd as reloc
+    from synth import make_config
+    log("generating the stress workload")
+    w = make_config(5)
+    ctx = reloc.Context(0)
+    m = ctx.load_map(w.occ, w.resolution, w.origin)
+    s = w.sample
+    sid, n_hyp = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
+                                       seed=s["seed"])
+    hyp = ctx.read_hypotheses(sid)
+    n_theta, batch_k = 1440, 256
+    rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
+                      w.range_max, n_theta=n_theta, batch_k=batch_k, tau=0.95, k_out=10)
+    log("map %dx%d, %d hypotheses" % (w.occ.shape[1], w.occ.shape[0], n_hyp))
+    for _ in range(args.warmup):
+        ctx.run(rid)
+    torch.cuda.synchronize()
+    lat, evals, ray_ms, tam_ms = [], 0, [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        poses, st = ctx.run(rid)
+        lat.append(time.perf_counter() - ts)
+        evals += st["smad_evals"] + st["tam_evals"]
+        ray_ms.append(st["ms_raycast"])
+        tam_ms.append(st["ms_tam"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = {
+        "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
+        "value": evals / elapsed, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32+f32+f64", "data": "synthetic",
+        "config": {"workload": "stress: mixed 8000x8000 @0.05 m, 200000 hypotheses, 360 deg "
+                               "1440 beams (perturbed map, 15 % clutter), 0.25 deg TAM, "
+                               "top-256 per stage, tau 0.95", "n_hyp": n_hyp},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
+                     "stages": st["stages"], "early_stopped": st["early_stopped"],
+                     "rays": st["rays"], "raycast_ms": float(np.mean(ray_ms)),
+                     "smad_ms": st["ms_smad"], "tam_ms": float(np.mean(tam_ms)),
+                     "tam_lookups": st["tam_lookups"]},
+        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
+        "true_pose": list(w.pose),
+    }
+    ctx.release(rid)
+    if not args.no_cpu:
+        # the oracle on a seeded 1 % subsample: ray cast + SMAD of 1 % of the
+        # hypotheses and TAM of 1 % of the evaluated (hypothesis, orientation) set
+        import oracle
+        pr = oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                         range_min=w.range_min, range_max=w.range_max, n_theta=n_theta)
+        k = oracle.edt(w.occ)
+        sub = np.sort(np.random.default_rng([5, 6]).choice(n_hyp, n_hyp // 100, replace=False))
+        n_tam = max(1, st["n_eval"] // 100)
+        t1 = time.perf_counter()
+        _, z = oracle.raycast(w.occ, hyp[sub], pr["Ns"], pr["Ng"], w.resolution, w.range_max)
+        oracle.smad(z, pr)
+        q = np.repeat(hyp[sub[:n_tam]], n_theta, axis=0)
+        oracle.tam(k, w.resolution, pr, q, np.tile(np.arange(n_theta), n_tam))
+        dt = time.perf_counter() - t1
+        ev = len(sub) * pr["n_shifts"] + n_tam * n_theta
+        out["cpu_baseline"] = {"value": ev / dt, "unit": "evals/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "1 %% subsample: ray cast + SMAD of %d hypotheses, "
+                                         "TAM of %d x %d; %.1f s (x100 extrapolation of the "
+                                         "step: %.1f s)" % (len(sub), n_tam, n_theta, dt,
+                                                            100 * dt)}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args):
     """Open-loop Poisson replay over 16 resident maps: served (reloc_submit /
     reloc_poll, continuous batching) against plain FIFO (reloc_relocalize of
@@ -296,7 +376,7 @@ def main():
                     help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plain-large",
-                    choices=("plain-large", "batched", "serving"))
+                    choices=("plain-large", "batched", "serving", "stress"))
     ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
@@ -311,6 +391,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "stress":
+        return bench_stress(args)
 
     import numpy as np
     import torch
