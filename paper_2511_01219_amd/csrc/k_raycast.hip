@@ -145,24 +145,24 @@ struct SkipRay {
 __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix0, int iy0,
                                           int W, int H, int rcells, uint32_t plane_bytes,
                                           const WalkMap& sm) {
-  const int ux = di.x, uy = di.y;
-  const int ax = abs(ux), ay = abs(uy);
-  r.xmaj = ax >= ay;
-  r.a = r.xmaj ? ax : ay;
-  r.b = r.xmaj ? ay : ax;
-  const int ox = ux < 0 ? -1 : 1, oy = uy < 0 ? -W : W;
-  r.om = r.xmaj ? ox : oy;
-  r.on = r.xmaj ? oy : ox;
-  const int lx = min(rcells, ux > 0 ? W - 1 - ix0 : (ux < 0 ? ix0 : rcells));
-  const int ly = min(rcells, uy > 0 ? H - 1 - iy0 : (uy < 0 ? iy0 : rcells));
-  r.la = r.xmaj ? lx : ly;
-  r.lb = r.xmaj ? ly : lx;
-  r.pbase = (uint32_t)di.z * plane_bytes;
+  const int code = di.z;
+  r.xmaj = (code & 1) != 0;
+  const bool mneg = (code & 2) != 0, nneg = (code & 4) != 0;
+  r.a = di.x;
+  r.b = di.y;
+  const int sM = r.xmaj ? 1 : W, sN = r.xmaj ? W : 1;
+  r.om = mneg ? -sM : sM;
+  r.on = nneg ? -sN : sN;
+  const int pM = r.xmaj ? ix0 : iy0, eM = r.xmaj ? W : H;
+  const int pN = r.xmaj ? iy0 : ix0, eN = r.xmaj ? H : W;
+  r.la = min(rcells, mneg ? pM : eM - 1 - pM);
+  r.lb = r.b == 0 ? rcells : min(rcells, nneg ? pN : eN - 1 - pN);
+  r.pbase = (uint32_t)((r.xmaj ? 0 : 2) + (mneg ? 1 : 0)) * plane_bytes;
   r.inv = __int_as_float(di.w);
   r.f = df.x;
   r.r = df.y;
-  r.kmaj = r.xmaj ? df.z : df.w;
-  r.kmin = r.xmaj ? df.w : df.z;
+  r.kmaj = df.z;
+  r.kmin = df.w;
   r.Dm = (r.b - r.a) << 7;
   r.na = r.nb = r.it = 0;
   r.off = iy0 * W + ix0;
@@ -290,6 +290,9 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   const int64_t total = (int64_t)a.n_hyp * Ns;
   const int64_t q0 = (int64_t)block * a.chunk;
   const int pool = (int)min((int64_t)a.chunk, total - q0);
+  // hypothesis and direction of the chunk's first ray (wavefront-uniform)
+  const int h0 = (int)(q0 / Ns);
+  const int j0 = (int)(q0 - (int64_t)h0 * Ns);
   const float inv_ns = 1.0f / (float)Ns;
   const WalkMap sm = make_walkmap(a);
   const uint32_t plane_bytes = a.walk_bytes >> 2;
@@ -299,11 +302,18 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   bool dry = pool <= 64;
   SkipRay r;
   auto start = [&](int qq) {
-    const int64_t g = q0 + qq;
-    int h = (int)((float)g * inv_ns);
-    int64_t jj = g - (int64_t)h * Ns;
-    h += jj < 0 ? -1 : (jj >= Ns ? 1 : 0);
-    jj = g - (int64_t)h * Ns;
+    // t < Ns + chunk < 2^13: the float quotient is within one of t / Ns
+    const int t = j0 + qq;
+    int dh = (int)((float)t * inv_ns);
+    int jj = t - dh * Ns;
+    if (jj < 0) {
+      --dh;
+      jj += Ns;
+    } else if (jj >= Ns) {
+      ++dh;
+      jj -= Ns;
+    }
+    const int h = h0 + dh;
     const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
     off0 = iy0 * W + ix0;
     skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, plane_bytes, sm);
@@ -325,23 +335,21 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
         busy = false;
       }
     }
+    // one back edge: the state is updated in place on every path
     const unsigned long long idle = __ballot(!busy);
-    if (dry) {
-      if (idle == ~0ull) break;
-      continue;
-    }
     const int cnt = __popcll(idle);
-    if (cnt >= REFILL) {
+    if (dry && cnt == 64) break;
+    if (!dry && cnt >= REFILL) {
       const int base = next;
       next += cnt;
       dry = next >= pool;
-      if (!busy) {
-        q = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-        if (q < pool) {
-          start(q);
-          busy = true;
-        }
+      const int qn = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(idle >> 32),
+                                __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+      if (!busy && qn < pool) {
+        q = qn;
+        start(q);
+        busy = true;
       }
     }
   }

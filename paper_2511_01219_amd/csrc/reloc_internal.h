@@ -22,8 +22,9 @@ struct RayArgs {
   const uint64_t* bits;
   const uint16_t* walk;      // [4][H][W] walk words (see launch_walkmap), or null
   uint32_t walk_bytes;
-  const int4* dir_i;         // [Ns] (Ux, Uy, walk plane, bits of 1/(256 |U_minor|))
-  const float4* dir_f;       // [Ns] (f, r, kappa_x, kappa_y) per direction
+  const int4* dir_i;         // [Ns] (|U_major|, |U_minor|, code, bits of 1/(256 |U_minor|));
+                             // code bit 0 x major, bit 1 U_major < 0, bit 2 U_minor < 0
+  const float4* dir_f;       // [Ns] (f, r, kappa_major, kappa_minor) per direction
   int variant;               // 0: bit tiles; 1-4: distance skipping with wavefront
                              // ray refill once 1 / 8 / 16 / 32 lanes are idle
   int W, H, tpr;

@@ -350,17 +350,20 @@ int32_t build_request(reloc_ctx* c, Request& R) {
     const int ax = std::abs(rd[j].x), ay = std::abs(rd[j].y);
     const bool xmaj = ax >= ay;
     const int amaj = xmaj ? ax : ay, bmin = xmaj ? ay : ax;
-    di[j].x = rd[j].x;
-    di[j].y = rd[j].y;
-    // walk plane of the major direction of travel: +x, -x, +y, -y
-    di[j].z = xmaj ? (rd[j].x < 0 ? 1 : 0) : (rd[j].y < 0 ? 3 : 2);
+    // (a, b, code, bits of 1/(256 b)) with a = |U_major|, b = |U_minor|;
+    // code bit 0: x is the major axis, bit 1: U_major < 0, bit 2: U_minor < 0
+    const int umaj = xmaj ? rd[j].x : rd[j].y, umin = xmaj ? rd[j].y : rd[j].x;
+    di[j].x = amaj;
+    di[j].y = bmin;
+    di[j].z = (xmaj ? 1 : 0) | (umaj < 0 ? 2 : 0) | (umin < 0 ? 4 : 0);
     const float inv = bmin > 0 ? (float)(1.0 / (256.0 * bmin)) : INFINITY;
     std::memcpy(&di[j].w, &inv, sizeof(float));
     const double nrm = std::sqrt((double)ax * ax + (double)ay * ay);
+    // (f, r, kappa_major, kappa_minor)
     df[j].x = (float)((double)amaj / nrm * 0.99999);   // rounds down a hair
     df[j].y = (float)((double)bmin / (double)amaj);
-    df[j].z = kp[j].x;
-    df[j].w = kp[j].y;
+    df[j].z = xmaj ? kp[j].x : kp[j].y;
+    df[j].w = xmaj ? kp[j].y : kp[j].x;
   }
   std::vector<int32_t> base(R.prep.vj.size());
   for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
