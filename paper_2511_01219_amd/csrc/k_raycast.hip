@@ -297,7 +297,7 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   const WalkMap sm = make_walkmap(a);
   const uint32_t plane_bytes = a.walk_bytes >> 2;
   int next = 64;
-  int q = lane, off0 = 0;
+  int q = lane, off0 = 0, oh = 0, oj = 0;   // oh, oj: hypothesis and direction of the ray
   bool busy = q < pool;
   bool dry = pool <= 64;
   SkipRay r;
@@ -313,7 +313,9 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
       ++dh;
       jj -= Ns;
     }
-    const int h = h0 + dh;
+    const int h = a.perm ? a.perm[h0 + dh] : h0 + dh;
+    oh = h;
+    oj = jj;
     const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
     off0 = iy0 * W + ix0;
     skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, plane_bytes, sm);
@@ -328,7 +330,7 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
           z = 0.f;
           hit = -1;
         }
-        const size_t o = (size_t)(q0 + q);
+        const size_t o = (size_t)oh * Ns + oj;
         a.zbuf[o] = z;
         if (a.dbg_hit) a.dbg_hit[o] = hit;
         if (a.dbg_steps) a.dbg_steps[o] = r.it;
@@ -355,9 +357,19 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   }
 }
 
+// Workgroup b of an n-workgroup grid runs on XCD b % 8 (round-robin
+// dispatch). The returned index gives every XCD one contiguous slice of
+// [0, n), walked in dispatch order, so one XCD's L2 serves rays from one
+// compact run of the casting order.
+__device__ __forceinline__ int xcd_slice(int b, int n) {
+  const int x = b & 7, i = b >> 3;
+  const int q = n >> 3, rem = n & 7;
+  return x * q + min(x, rem) + i;
+}
+
 template <int REFILL>
 __global__ __launch_bounds__(64) void raycast_skip_kernel(RayArgs a) {
-  raycast_skip_run<REFILL>(a, blockIdx.x);
+  raycast_skip_run<REFILL>(a, xcd_slice(blockIdx.x, gridDim.x));
 }
 
 // Index of the segment holding item t: prefix[r] <= t < prefix[r + 1]
@@ -377,8 +389,9 @@ template <int REFILL>
 __global__ __launch_bounds__(64) void raycast_skip_batch_kernel(const RayArgs* __restrict__ reqs,
                                                                 const int64_t* __restrict__ prefix,
                                                                 int n) {
-  const int r = find_segment(prefix, n, blockIdx.x);
-  raycast_skip_run<REFILL>(reqs[r], (int)(blockIdx.x - prefix[r]));
+  const int t = xcd_slice(blockIdx.x, gridDim.x);
+  const int r = find_segment(prefix, n, t);
+  raycast_skip_run<REFILL>(reqs[r], (int)(t - prefix[r]));
 }
 
 // Bit-tile ray cast: one workgroup per hypothesis, rays from a shared counter.

@@ -45,6 +45,7 @@ struct RayArgs {
   uint64_t* keys;            // [n_hyp] sort key = bits of SMAD
   int32_t* vals;             // [n_hyp] hypothesis index
   float* zbuf;                // [n_hyp][Ns] synthetic ranges (ray cast -> SMAD)
+  const int32_t* perm;       // [n_hyp] casting order (Morton order of the cells), or null
   int chunk;                 // skip variant: rays owned by one wavefront
   int32_t* dbg_hit;          // optional [n_hyp][Ns]
   int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray

@@ -378,6 +378,7 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.dirs = req_alloc<int2>(c, R, Ng);
   R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
   R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
+  R.perm = req_alloc<int32_t>(c, R, n);
   R.smad = req_alloc<double>(c, R, n);
   R.argm = req_alloc<int32_t>(c, R, n);
   R.keys = req_alloc<uint64_t>(c, R, n);
@@ -407,6 +408,26 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   if (int32_t e = upload(c, R.zq, R.prep.vzq.data(), R.prep.vzq.size())) return e;
   if (int32_t e = upload(c, R.dirs, U.data(), U.size())) return e;
   if (int32_t e = upload(c, R.dlut, R.lut.q.data(), R.lut.q.size())) return e;
+  // casting order: Morton (Z-order) of the hypothesis cells, so that the rays
+  // in flight on one XCD start in one compact region of the map
+  std::vector<std::pair<uint32_t, int32_t>> mc(n);
+  {
+    const std::vector<int32_t>& xy = c->sets[R.set_id].host;
+    auto spread = [](uint32_t v) {
+      v &= 0xFFFF;
+      v = (v | (v << 8)) & 0x00FF00FF;
+      v = (v | (v << 4)) & 0x0F0F0F0F;
+      v = (v | (v << 2)) & 0x33333333;
+      v = (v | (v << 1)) & 0x55555555;
+      return v;
+    };
+    for (int h = 0; h < n; ++h)
+      mc[h] = {spread((uint32_t)xy[2 * h]) | (spread((uint32_t)xy[2 * h + 1]) << 1), h};
+    std::sort(mc.begin(), mc.end());
+  }
+  std::vector<int32_t> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = mc[i].second;
+  if (int32_t e = upload(c, R.perm, perm.data(), perm.size())) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
   return RELOC_OK;
 }
@@ -429,6 +450,7 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
     a.chunk = (int)std::max<int64_t>(256, std::min<int64_t>(2048, rays / 4096));
   }
   a.zbuf = R.zbuf;
+  a.perm = R.perm;
   a.W = m.W;
   a.H = m.H;
   a.tpr = m.tpr;

@@ -86,6 +86,7 @@ struct Request {
   int4* dir_i = nullptr;
   float4* dir_f = nullptr;
   float* zbuf = nullptr;
+  int32_t* perm = nullptr;        // hypotheses in Morton order of their cells
   int2* runs = nullptr;
   int32_t* base = nullptr;
   int32_t* zq = nullptr;
