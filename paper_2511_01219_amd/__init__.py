@@ -70,6 +70,24 @@ def search_params(**kw) -> _abi.reloc_search_params:
     return p
 
 
+_POSE_FIELDS = tuple(f for f, _ in _abi.reloc_pose._fields_)
+_STAT_FIELDS = tuple(f for f, _ in _abi.reloc_stats._fields_)
+
+
+def _poses(out, n):
+    res = []
+    for i in range(n):
+        o = out[i]
+        res.append({f: getattr(o, f) for f in _POSE_FIELDS})
+    return res
+
+
+def _stats(st, code):
+    d = {f: getattr(st, f) for f in _STAT_FIELDS}
+    d["status"] = code
+    return d
+
+
 class _Scan:
     """Keeps the host buffers of a reloc_scan alive."""
 
@@ -230,10 +248,7 @@ class Context:
         code = _check(self._lib.reloc_run(self._h, int(request_id), out, int(cap), C.byref(n),
                                           C.byref(st)),
                       allow=(E_TIMEOUT,) if allow_timeout else ())
-        poses = [{f: getattr(out[i], f) for f, _ in out[i]._fields_} for i in range(n.value)]
-        stats = {f: getattr(st, f) for f, _ in st._fields_}
-        stats["status"] = code
-        return poses, stats
+        return _poses(out, n.value), _stats(st, code)
 
     def release(self, request_id: int):
         _check(self._lib.reloc_release(self._h, int(request_id)))

@@ -181,12 +181,17 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   if (n == 0) return RELOC_OK;
   auto A = std::make_shared<Arena>();
   A->c = c;
-  std::vector<int64_t> hpre(n + 1, 0), bpre(n + 1, 0);
+  std::vector<int64_t> hpre(n + 1, 0), bpre(n + 1, 0), spre(n + 1, 0);
   int max_ns = 1;
   for (int i = 0; i < n; ++i) {
     const Request& R = c->reqs.at(F[i]->rid);
     hpre[i + 1] = hpre[i] + R.n_hyp;
     max_ns = std::max(max_ns, R.prep.info.Ns);
+  }
+  const int wpb = smad_per_block(max_ns);
+  for (int i = 0; i < n; ++i) {
+    const int nh = (int)(hpre[i + 1] - hpre[i]);
+    spre[i + 1] = spre[i] + (nh + wpb - 1) / wpb;
   }
   const int64_t N = hpre[n];
   if (N > INT32_MAX) return fail(RELOC_E_INVALID, "batch holds more than 2^31 hypotheses");
@@ -206,6 +211,7 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
     RayArgs a = ray_args(c, R, nullptr, nullptr);
     a.keys = A->keys + hpre[i];
     a.vals = A->vals + hpre[i];
+    a.best0 = A->best + hpre[i];      // the SMAD kernel clears the per-rank best
     const int64_t rays = (int64_t)R.n_hyp * a.Ns;
     const int64_t blocks = a.walk ? (rays + a.chunk - 1) / a.chunk : 0;
     bpre[i + 1] = bpre[i] + blocks;
@@ -215,21 +221,22 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   const size_t o_ra = bl.add(ra.data(), n);
   const size_t o_bp = bl.add(bpre.data(), n + 1);
   const size_t o_hp = bl.add(hpre.data(), n + 1);
+  const size_t o_sp = bl.add(spre.data(), n + 1);
   uint8_t* d = nullptr;
   if (int32_t e = commit(c, S, bl, &d)) return e;
   const RayArgs* d_ra = (const RayArgs*)(d + o_ra);
   const int64_t* d_bp = (const int64_t*)(d + o_bp);
   const int64_t* d_hp = (const int64_t*)(d + o_hp);
+  const int64_t* d_sp = (const int64_t*)(d + o_sp);
   hipStream_t s = c->stream;
   HIP_TRY(hipEventRecord(c->ev[0], s));
   for (int i = 0; i < n; ++i)
     if (!ra[i].walk) HIP_TRY(launch_raycast(ra[i], s));   // maps without walk words
   HIP_TRY(launch_raycast_batch(d_ra, d_bp, n, bpre[n], s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
-  HIP_TRY(launch_smad_batch(d_ra, d_hp, n, hpre[n], max_ns, s));
+  HIP_TRY(launch_smad_batch(d_ra, d_sp, n, spre[n], max_ns, s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
   HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp, s));
-  HIP_TRY(launch_fill_u64(A->best, 0, (size_t)N, s));
   HIP_TRY(hipEventRecord(c->ev[3], s));
   if (pt) {
     pt->raycast += elapsed(c->ev[0], c->ev[1]);

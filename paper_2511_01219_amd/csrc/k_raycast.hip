@@ -416,16 +416,23 @@ __global__ __launch_bounds__(RT) void raycast_bits_kernel(RayArgs a) {
   }
 }
 
-// ------------------------------------------------------------ SMAD epilogue
-// S[1..Ns] hold the ranges; turns them into prefix sums and scores every shift
-__device__ void smad_epilogue(const RayArgs& a, double* S, int h) {
-  __shared__ double wsum[RT / 64];
-  __shared__ double rv[RT / 64];
-  __shared__ int rm[RT / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// ------------------------------------------------------------------- SMAD
+// SMAD of hypothesis h (eq. 16-20) by one wavefront from its ranges in
+// zbuf: cyclic prefix sums S[0..Ns] in LDS (private to the wavefront), then
+// every shift m scored from K interval sums, and the minimum with the
+// smallest m on ties. Every partial sum is exact (see the file header), so
+// lane order does not matter.
+__device__ __forceinline__ void smad_wave(const RayArgs& a, int h, double* S) {
+  const int lane = threadIdx.x & 63;
   const int Ns = a.Ns;
-  const int c = (Ns + RT - 1) / RT;
-  const int b0 = 1 + tid * c, b1 = min(Ns + 1, b0 + c);
+  const float* z = a.zbuf + (size_t)h * Ns;
+  for (int i = lane; i < Ns; i += 64) S[i + 1] = (double)z[i];
+  if (lane == 0) S[0] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // lane l owns S[1 + l c .. 1 + (l + 1) c)
+  const int c = (Ns + 63) >> 6;
+  const int b0 = 1 + lane * c, b1 = min(Ns + 1, b0 + c);
   double local = 0.0;
   for (int i = b0; i < b1; ++i) local += S[i];
   double incl = local;
@@ -433,22 +440,18 @@ __device__ void smad_epilogue(const RayArgs& a, double* S, int h) {
     const double v = __shfl_up(incl, off, 64);
     if (lane >= off) incl += v;
   }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
   double run = incl - local;
-  for (int q = 0; q < wv; ++q) run += wsum[q];
   for (int i = b0; i < b1; ++i) {
     run += S[i];
     S[i] = run;
   }
-  if (tid == 0) S[0] = 0.0;
-  __syncthreads();
-
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   const double total = S[Ns];
   double bv = INFINITY;
   int bm = INT_MAX;
-  for (int s = tid; s < a.n_shifts; s += RT) {
-    const int m = s * a.n_enum;
+  for (int sh = lane; sh < a.n_shifts; sh += 64) {
+    const int m = sh * a.n_enum;
     double tot = 0.0;
     for (int r = 0; r < a.n_runs; ++r) {
       const int2 rr = a.runs[r];
@@ -474,43 +477,33 @@ __device__ void smad_epilogue(const RayArgs& a, double* S, int h) {
     }
   }
   if (lane == 0) {
-    rv[wv] = bv;
-    rm[wv] = bm;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int q = 1; q < RT / 64; ++q)
-      if (rv[q] < bv || (rv[q] == bv && rm[q] < bm)) {
-        bv = rv[q];
-        bm = rm[q];
-      }
     a.smad[h] = bv;
     a.argm[h] = bm;
     a.keys[h] = (uint64_t)__double_as_longlong(bv);
     a.vals[h] = h;
+    if (a.best0) a.best0[h] = 0;
   }
 }
 
-// SMAD of one hypothesis per workgroup from its ranges in zbuf.
-__device__ __forceinline__ void smad_run(const RayArgs& a, int h, double* S) {
-  const float* z = a.zbuf + (size_t)h * a.Ns;
-  for (int j = threadIdx.x; j < a.Ns; j += RT) S[j + 1] = (double)z[j];
-  __syncthreads();
-  smad_epilogue(a, S, h);
-}
-
-__global__ __launch_bounds__(RT) void smad_kernel(RayArgs a) {
-  extern __shared__ double S[];   // [Ns + 1]
-  smad_run(a, blockIdx.x, S);
+// wpb hypotheses per workgroup, one wavefront each
+__global__ __launch_bounds__(RT) void smad_kernel(RayArgs a, int wpb) {
+  extern __shared__ double S[];
+  const int w = threadIdx.x >> 6;
+  const int h = blockIdx.x * wpb + w;
+  if (h < a.n_hyp) smad_wave(a, h, S + (size_t)w * (a.Ns + 1));
 }
 
 // SMAD of several requests: request r owns blocks [prefix[r], prefix[r + 1]),
-// one per hypothesis.
+// wpb hypotheses each.
 __global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restrict__ reqs,
-                                                        const int64_t* __restrict__ prefix, int n) {
+                                                        const int64_t* __restrict__ prefix, int n,
+                                                        int wpb) {
   extern __shared__ double S[];
   const int r = find_segment(prefix, n, blockIdx.x);
-  smad_run(reqs[r], (int)(blockIdx.x - prefix[r]), S);
+  const RayArgs& a = reqs[r];
+  const int w = threadIdx.x >> 6;
+  const int h = (int)(blockIdx.x - prefix[r]) * wpb + w;
+  if (h < a.n_hyp) smad_wave(a, h, S + (size_t)w * (a.Ns + 1));
 }
 
 }  // namespace
@@ -532,10 +525,16 @@ hipError_t launch_raycast(const RayArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int smad_per_block(int max_ns) {
+  return std::max(1, std::min(RT / 64, (48 * 1024) / ((max_ns + 1) * (int)sizeof(double))));
+}
+
 hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
-  const size_t lds = (size_t)(a.Ns + 1) * sizeof(double);
-  hipLaunchKernelGGL(smad_kernel, dim3(a.n_hyp), dim3(RT), lds, s, a);
+  const int wpb = smad_per_block(a.Ns);
+  const size_t lds = (size_t)wpb * (a.Ns + 1) * sizeof(double);
+  hipLaunchKernelGGL(smad_kernel, dim3((a.n_hyp + wpb - 1) / wpb), dim3(64 * wpb), lds, s, a,
+                     wpb);
   return hipGetLastError();
 }
 
@@ -550,8 +549,10 @@ hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int 
 hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
                              int max_ns, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return hipSuccess;
-  const size_t lds = (size_t)(max_ns + 1) * sizeof(double);
-  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(RT), lds, s, reqs, prefix, n);
+  const int wpb = smad_per_block(max_ns);
+  const size_t lds = (size_t)wpb * (max_ns + 1) * sizeof(double);
+  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, reqs,
+                     prefix, n, wpb);
   return hipGetLastError();
 }
 

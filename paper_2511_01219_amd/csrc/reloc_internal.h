@@ -46,6 +46,7 @@ struct RayArgs {
   int32_t* vals;             // [n_hyp] hypothesis index
   float* zbuf;                // [n_hyp][Ns] synthetic ranges (ray cast -> SMAD)
   const int32_t* perm;       // [n_hyp] casting order (Morton order of the cells), or null
+  uint64_t* best0;           // SMAD kernel: per-rank best to clear ([n_hyp]), or null
   int chunk;                 // skip variant: rays owned by one wavefront
   int32_t* dbg_hit;          // optional [n_hyp][Ns]
   int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray
@@ -55,8 +56,9 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, a
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
 // Several requests in one launch each. reqs: device RayArgs[n]; prefix:
 // device int64[n + 1] block offsets (ray cast: chunks of a.chunk rays with the
-// walk-word traversal, refill at 16 idle lanes; SMAD: one block per
-// hypothesis). Every request of a ray-cast batch needs walk words.
+// walk-word traversal, refill at 16 idle lanes; SMAD: smad_per_block(max Ns)
+// hypotheses per block). Every request of a ray-cast batch needs walk words.
+int smad_per_block(int max_ns);
 hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
                                 int64_t blocks, hipStream_t s);
 hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
@@ -74,6 +76,12 @@ hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
                               hipStream_t s);
 hipError_t sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
                          int n, hipStream_t s);
+// Stable sort of (key, input position) for n <= kSmallSortMax in two
+// launches; ktmp / vtmp are scratch of n entries. vout receives input
+// positions (the value of key i is i); kout (sorted keys) may be null.
+constexpr int kSmallSortMax = 65536;
+hipError_t small_sort_pairs_u64(const uint64_t* kin, uint64_t* ktmp, int32_t* vtmp,
+                                uint64_t* kout, int32_t* vout, int n, hipStream_t s);
 // stable segmented sorts; offsets: device int64[nseg + 1]
 hipError_t seg_sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
                                   uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t n,
@@ -127,6 +135,11 @@ struct PoseRow {
 hipError_t launch_rank_gather(const uint64_t* sorted, const uint64_t* best,
                               const int32_t* order, const double* smad, int n, PoseRow* rows,
                               hipStream_t s);
+
+// Ranking of n <= 2048 ranks in one launch (T desc, rank asc), first nrow rows.
+constexpr int kRankSmallMax = 2048;
+hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
+                             const double* smad, int nrow, PoseRow* rows, hipStream_t s);
 
 // ---- batched TAM / stage control / ranking -------------------------------
 // Kernel class of a TAM argument set (keys per lane x histogram bits), -1 if

@@ -451,6 +451,7 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
   }
   a.zbuf = R.zbuf;
   a.perm = R.perm;
+  a.best0 = nullptr;
   a.W = m.W;
   a.H = m.H;
   a.tpr = m.tpr;
@@ -506,11 +507,52 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   return a;
 }
 
+// stable SMAD order of the request (after the SMAD kernel)
+int32_t smad_order(reloc_ctx* c, Request& R) {
+  if (R.n_hyp <= kSmallSortMax) {
+    HIP_TRY(small_sort_pairs_u64(R.keys, R.keys2, R.vals, nullptr, R.order, R.n_hyp, c->stream));
+  } else {
+    size_t tb = R.tmp_bytes;
+    HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, c->stream));
+  }
+  return RELOC_OK;
+}
+
 // ray cast + SMAD for all hypotheses, then the stable SMAD order
 int32_t run_smad_order(reloc_ctx* c, Request& R) {
   HIP_TRY(launch_raycast_smad(ray_args(c, R, nullptr, nullptr), c->stream));
-  size_t tb = R.tmp_bytes;
-  HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, c->stream));
+  return smad_order(c, R);
+}
+
+// ranking of ranks [0, n_eval) (T desc, rank asc); the first nrow rows are
+// copied to host_rows (pinned) on the stream
+int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* host_rows) {
+  hipStream_t s = c->stream;
+  if (n_eval <= kRankSmallMax) {
+    HIP_TRY(launch_rank_small(R.best, n_eval, R.order, R.smad, nrow, R.rows, s));
+  } else {
+    HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
+    size_t tb = R.tmp_bytes;
+    HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
+    HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, nrow, R.rows, s));
+  }
+  if (nrow > 0)
+    HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  return RELOC_OK;
+}
+
+// pinned host buffer for result rows, grown on demand
+int32_t pinned_rows(reloc_ctx* c, size_t n, PoseRow** out) {
+  const size_t need = std::max<size_t>(1, n) * sizeof(PoseRow);
+  if (need > c->prows_cap) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->prows) (void)hipHostFree(c->prows);
+    c->prows = nullptr;
+    c->prows_cap = 0;
+    HIP_TRY(hipHostMalloc(&c->prows, need, hipHostMallocDefault));
+    c->prows_cap = need;
+  }
+  *out = (PoseRow*)c->prows;
   return RELOC_OK;
 }
 
@@ -666,6 +708,7 @@ void reloc_ctx_destroy(reloc_ctx* c) {
     for (auto& e : c->ev)
       if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->prows) (void)hipHostFree(c->prows);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -896,31 +939,45 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   const DevMap& m = c->maps[R.map_id];
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = c->stream;
-  const RayArgs ra = ray_args(c, R, nullptr, nullptr);
+  RayArgs ra = ray_args(c, R, nullptr, nullptr);
+  ra.best0 = R.best;                 // the SMAD kernel clears the per-rank best
   HIP_TRY(hipEventRecord(c->ev[0], s));
   HIP_TRY(launch_raycast(ra, s));
   HIP_TRY(hipEventRecord(c->ev[5], s));
   HIP_TRY(launch_smad(ra, s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
-  size_t tb = R.tmp_bytes;
-  HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, s));
-  HIP_TRY(launch_fill_u64(R.best, 0, (size_t)R.n_hyp, s));
+  if (int32_t e = smad_order(c, R)) return e;
   HIP_TRY(hipEventRecord(c->ev[2], s));
   const int K = R.prm.batch_k;
   int stages = 0, stopped = 0, n_eval = 0;
   int32_t status = RELOC_OK;
   int32_t* hflag = (int32_t*)c->pinned;
+  const int ncap = std::min(R.rows_cap, std::max(0, cap));
+  PoseRow* hrows = nullptr;
+  if (int32_t e = pinned_rows(c, (size_t)ncap, &hrows)) return e;
+  bool ranked = false;   // rows of the final n_eval already on the host
+  int nrow = 0;
   for (int r0 = 0; r0 < R.n_hyp; r0 += K) {
     const int nb = std::min(K, R.n_hyp - r0);
     HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
     StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stages, R.flag + stages};
     HIP_TRY(launch_stage_reduce(sa, s));
     HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // the first stage's ranking is issued before its stop flag is read: when
+    // the search stops there (or has no second stage) the result is ready at
+    // the same synchronisation
+    const bool spec = r0 == 0;
+    if (spec) {
+      HIP_TRY(hipEventRecord(c->ev[3], s));
+      if (int32_t e = enqueue_rank(c, R, nb, std::min(ncap, nb), hrows)) return e;
+      HIP_TRY(hipEventRecord(c->ev[4], s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     ++stages;
     n_eval = r0 + nb;
-    if (*hflag) {
-      stopped = 1;
+    if (*hflag || n_eval >= R.n_hyp) {
+      stopped = *hflag ? 1 : 0;
+      ranked = spec;
       break;
     }
     if (R.prm.deadline_s > 0) {
@@ -931,18 +988,14 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
       }
     }
   }
-  HIP_TRY(hipEventRecord(c->ev[3], s));
-  HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
-  tb = R.tmp_bytes;
-  HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
-  const int nrow = std::min(std::min(R.rows_cap, n_eval), std::max(0, cap));
-  HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, nrow, R.rows, s));
-  std::vector<PoseRow> rows(nrow);
-  if (nrow > 0)
-    HIP_TRY(hipMemcpyAsync(rows.data(), R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipEventRecord(c->ev[4], s));
+  nrow = std::min(ncap, n_eval);
+  if (!ranked) {
+    HIP_TRY(hipEventRecord(c->ev[3], s));
+    if (int32_t e = enqueue_rank(c, R, n_eval, nrow, hrows)) return e;
+    HIP_TRY(hipEventRecord(c->ev[4], s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
-  rows_to_poses(c, R, rows.data(), nrow, out);
+  rows_to_poses(c, R, hrows, nrow, out);
   *n_out = nrow;
   if (st) {
     std::memset(st, 0, sizeof *st);

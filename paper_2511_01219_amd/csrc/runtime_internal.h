@@ -127,6 +127,8 @@ struct reloc_ctx {
   int next_id = 1;
   hipEvent_t ev[6] = {};
   void* pinned = nullptr;         // small pinned staging buffer
+  void* prows = nullptr;          // pinned result rows
+  size_t prows_cap = 0;
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 1;
