@@ -447,7 +447,9 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
   a.variant = kv[R.prm.variant];
   {
     const int64_t rays = (int64_t)R.n_hyp * I.Ns;
-    a.chunk = (int)std::max<int64_t>(256, std::min<int64_t>(2048, rays / 4096));
+    // many short chunks balance the waves across the CUs (a wave's cost
+    // varies with its rays' lengths); measured flat between 256 and 512
+    a.chunk = (int)std::max<int64_t>(256, std::min<int64_t>(1024, rays / 49152));
   }
   a.zbuf = R.zbuf;
   a.perm = R.perm;
