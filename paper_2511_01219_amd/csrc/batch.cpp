@@ -183,15 +183,19 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   A->c = c;
   std::vector<int64_t> hpre(n + 1, 0), bpre(n + 1, 0), spre(n + 1, 0);
   int max_ns = 1;
+  bool all_pano = true;
   for (int i = 0; i < n; ++i) {
     const Request& R = c->reqs.at(F[i]->rid);
     hpre[i + 1] = hpre[i] + R.n_hyp;
     max_ns = std::max(max_ns, R.prep.info.Ns);
+    all_pano &= R.prep.info.n_shifts == 1;
   }
-  const int wpb = smad_per_block(max_ns);
+  int wpb;
+  size_t smad_lds;
+  smad_layout(max_ns, all_pano, &wpb, &smad_lds);
   for (int i = 0; i < n; ++i) {
     const int nh = (int)(hpre[i + 1] - hpre[i]);
-    spre[i + 1] = spre[i] + (nh + wpb - 1) / wpb;
+    spre[i + 1] = spre[i] + (wpb ? (nh + wpb - 1) / wpb : nh);
   }
   const int64_t N = hpre[n];
   if (N > INT32_MAX) return fail(RELOC_E_INVALID, "batch holds more than 2^31 hypotheses");
@@ -234,7 +238,7 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
     if (!ra[i].walk) HIP_TRY(launch_raycast(ra[i], s));   // maps without walk words
   HIP_TRY(launch_raycast_batch(d_ra, d_bp, n, bpre[n], s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
-  HIP_TRY(launch_smad_batch(d_ra, d_sp, n, spre[n], max_ns, s));
+  HIP_TRY(launch_smad_batch(d_ra, d_sp, n, spre[n], wpb, smad_lds, s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
   HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp, s));
   HIP_TRY(hipEventRecord(c->ev[3], s));

@@ -485,12 +485,132 @@ __device__ __forceinline__ void smad_wave(const RayArgs& a, int h, double* S) {
   }
 }
 
-// wpb hypotheses per workgroup, one wavefront each
+// Panoramic scans score the single shift m = 0: the interval sums are plain
+// masked sums of the ranges (exact in any order), no prefix array needed.
+__device__ __forceinline__ void smad_wave_pano(const RayArgs& a, int h) {
+  const int lane = threadIdx.x & 63;
+  const int Ns = a.Ns;
+  const float* z = a.zbuf + (size_t)h * Ns;
+  double tot = 0.0;
+  for (int j = lane; j < Ns; j += 64) {
+    const double zj = (double)z[j];
+    for (int r = 0; r < a.n_runs; ++r) {
+      const int2 rr = a.runs[r];
+      int d = j - rr.x;
+      if (d < 0) d += Ns;
+      if (d < rr.y) tot += zj;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+  if (lane == 0) {
+    const double v = fabs(a.zbar - tot / (double)a.nfov);
+    a.smad[h] = v;
+    a.argm[h] = 0;
+    a.keys[h] = (uint64_t)__double_as_longlong(v);
+    a.vals[h] = h;
+    if (a.best0) a.best0[h] = 0;
+  }
+}
+
+// One workgroup per hypothesis (long non-panoramic scans): S[1..Ns] hold the
+// ranges; prefix sums by all 256 threads, shifts spread over the workgroup.
+__device__ void smad_block(const RayArgs& a, double* S, int h) {
+  __shared__ double wsum[RT / 64];
+  __shared__ double rv[RT / 64];
+  __shared__ int rm[RT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int Ns = a.Ns;
+  const int c = (Ns + RT - 1) / RT;
+  const int b0 = 1 + tid * c, b1 = min(Ns + 1, b0 + c);
+  double local = 0.0;
+  for (int i = b0; i < b1; ++i) local += S[i];
+  double incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const double v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  double run = incl - local;
+  for (int q = 0; q < wv; ++q) run += wsum[q];
+  for (int i = b0; i < b1; ++i) {
+    run += S[i];
+    S[i] = run;
+  }
+  if (tid == 0) S[0] = 0.0;
+  __syncthreads();
+
+  const double total = S[Ns];
+  double bv = INFINITY;
+  int bm = INT_MAX;
+  for (int s = tid; s < a.n_shifts; s += RT) {
+    const int m = s * a.n_enum;
+    double tot = 0.0;
+    for (int r = 0; r < a.n_runs; ++r) {
+      const int2 rr = a.runs[r];
+      const int t1 = rr.x + m + rr.y, t0 = rr.x + m;
+      const int q1 = t1 >= 2 * Ns ? 2 : (t1 >= Ns ? 1 : 0);
+      const int q0 = t0 >= 2 * Ns ? 2 : (t0 >= Ns ? 1 : 0);
+      const double c1 = (double)q1 * total + S[t1 - q1 * Ns];
+      const double c0 = (double)q0 * total + S[t0 - q0 * Ns];
+      tot += c1 - c0;
+    }
+    const double v = fabs(a.zbar - tot / (double)a.nfov);
+    if (v < bv) {
+      bv = v;
+      bm = m;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int om = __shfl_xor(bm, off, 64);
+    if (ov < bv || (ov == bv && om < bm)) {
+      bv = ov;
+      bm = om;
+    }
+  }
+  if (lane == 0) {
+    rv[wv] = bv;
+    rm[wv] = bm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < RT / 64; ++q)
+      if (rv[q] < bv || (rv[q] == bv && rm[q] < bm)) {
+        bv = rv[q];
+        bm = rm[q];
+      }
+    a.smad[h] = bv;
+    a.argm[h] = bm;
+    a.keys[h] = (uint64_t)__double_as_longlong(bv);
+    a.vals[h] = h;
+    if (a.best0) a.best0[h] = 0;
+  }
+}
+
+// SMAD of hypothesis h of request a by the layout smad_layout chose:
+// wpb > 0: wpb hypotheses per workgroup, one wavefront each (prefix sums in
+// LDS unless the scan is panoramic); wpb == 0: one workgroup.
+__device__ __forceinline__ void smad_dispatch(const RayArgs& a, int blk, int wpb, double* S) {
+  if (wpb == 0) {
+    const int h = blk;
+    for (int j = threadIdx.x; j < a.Ns; j += RT) S[j + 1] = (double)a.zbuf[(size_t)h * a.Ns + j];
+    __syncthreads();
+    smad_block(a, S, h);
+    return;
+  }
+  const int w = threadIdx.x >> 6;
+  const int h = blk * wpb + w;
+  if (h >= a.n_hyp) return;
+  if (a.n_shifts == 1)
+    smad_wave_pano(a, h);
+  else
+    smad_wave(a, h, S + (size_t)w * (a.Ns + 1));
+}
+
 __global__ __launch_bounds__(RT) void smad_kernel(RayArgs a, int wpb) {
   extern __shared__ double S[];
-  const int w = threadIdx.x >> 6;
-  const int h = blockIdx.x * wpb + w;
-  if (h < a.n_hyp) smad_wave(a, h, S + (size_t)w * (a.Ns + 1));
+  smad_dispatch(a, blockIdx.x, wpb, S);
 }
 
 // SMAD of several requests: request r owns blocks [prefix[r], prefix[r + 1]),
@@ -500,10 +620,7 @@ __global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restric
                                                         int wpb) {
   extern __shared__ double S[];
   const int r = find_segment(prefix, n, blockIdx.x);
-  const RayArgs& a = reqs[r];
-  const int w = threadIdx.x >> 6;
-  const int h = (int)(blockIdx.x - prefix[r]) * wpb + w;
-  if (h < a.n_hyp) smad_wave(a, h, S + (size_t)w * (a.Ns + 1));
+  smad_dispatch(reqs[r], (int)(blockIdx.x - prefix[r]), wpb, S);
 }
 
 }  // namespace
@@ -525,16 +642,26 @@ hipError_t launch_raycast(const RayArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int smad_per_block(int max_ns) {
-  return std::max(1, std::min(RT / 64, (48 * 1024) / ((max_ns + 1) * (int)sizeof(double))));
+void smad_layout(int max_ns, bool all_pano, int* wpb, size_t* lds) {
+  if (all_pano) {
+    *wpb = RT / 64;
+    *lds = 0;
+  } else if (max_ns <= 1024) {
+    *wpb = RT / 64;
+    *lds = (size_t)(RT / 64) * (max_ns + 1) * sizeof(double);
+  } else {
+    *wpb = 0;
+    *lds = (size_t)(max_ns + 1) * sizeof(double);
+  }
 }
 
 hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
   if (a.n_hyp <= 0) return hipSuccess;
-  const int wpb = smad_per_block(a.Ns);
-  const size_t lds = (size_t)wpb * (a.Ns + 1) * sizeof(double);
-  hipLaunchKernelGGL(smad_kernel, dim3((a.n_hyp + wpb - 1) / wpb), dim3(64 * wpb), lds, s, a,
-                     wpb);
+  int wpb;
+  size_t lds;
+  smad_layout(a.Ns, a.n_shifts == 1, &wpb, &lds);
+  const int blocks = wpb ? (a.n_hyp + wpb - 1) / wpb : a.n_hyp;
+  hipLaunchKernelGGL(smad_kernel, dim3(blocks), dim3(RT), lds, s, a, wpb);
   return hipGetLastError();
 }
 
@@ -547,12 +674,10 @@ hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int 
 }
 
 hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
-                             int max_ns, hipStream_t s) {
+                             int wpb, size_t lds, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return hipSuccess;
-  const int wpb = smad_per_block(max_ns);
-  const size_t lds = (size_t)wpb * (max_ns + 1) * sizeof(double);
-  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, reqs,
-                     prefix, n, wpb);
+  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(RT), lds, s, reqs, prefix, n,
+                     wpb);
   return hipGetLastError();
 }
 

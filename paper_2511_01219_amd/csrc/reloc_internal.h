@@ -56,13 +56,17 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, a
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
 // Several requests in one launch each. reqs: device RayArgs[n]; prefix:
 // device int64[n + 1] block offsets (ray cast: chunks of a.chunk rays with the
-// walk-word traversal, refill at 16 idle lanes; SMAD: smad_per_block(max Ns)
-// hypotheses per block). Every request of a ray-cast batch needs walk words.
-int smad_per_block(int max_ns);
+// walk-word traversal, refill at 16 idle lanes; SMAD: wpb hypotheses per
+// block, or one when wpb == 0). Every request of a ray-cast batch needs walk
+// words.
+// SMAD kernel layout for scans of up to max_ns beams: wpb hypotheses per
+// 256-thread workgroup (one wavefront each), or 0 for one workgroup per
+// hypothesis; lds = dynamic LDS bytes.
+void smad_layout(int max_ns, bool all_pano, int* wpb, size_t* lds);
 hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
                                 int64_t blocks, hipStream_t s);
 hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
-                             int max_ns, hipStream_t s);
+                             int wpb, size_t lds, hipStream_t s);
 // Walk words from the squared EDT: four row-major planes, one per major
 // direction of travel (+x, -x, +y, -y). A word is 0 for an occupied cell,
 // else s | run << 8 with s = 1 + free-space radius byte and run = free

@@ -218,6 +218,27 @@ def test_raycast_smad_fov_runs_and_skips(ctx, c1):
     _cleanup(ctx, m, sid, rid)
 
 
+@pytest.mark.parametrize("fov_deg,n_beams", [(180.0, 1080), (360.0, 720), (240.0, 480),
+                                             (90.0, 1024)])
+def test_smad_kernel_layouts(ctx, c1, fov_deg, n_beams):
+    """Every SMAD kernel layout: one workgroup per hypothesis (non-panoramic,
+    Ns > 1024), the panoramic single-shift sum, one wavefront per hypothesis;
+    SMAD and argmin bit-exact, order identical."""
+    from synth import ScanSpec, lidar_scan
+    w, k, hyp = c1
+    spec = ScanSpec(fov_deg, n_beams, 12.0, 0.02, 0.02, 0.05, 0.0)
+    ranges, amin, ainc, _ = lidar_scan(w.occ, w.resolution, w.origin, w.pose, spec,
+                                       np.random.default_rng([1, 7]))
+    _case("smad layout: FoV %.0f deg, %d beams" % (fov_deg, n_beams))
+    m, sid, rid, pr = _raycast_case(ctx, w.occ, hyp, ranges, amin, ainc, 12.0, n_theta=360)
+    _, orr = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], 0.05, 12.0)
+    s, a, o = ctx.debug_smad(rid, len(hyp))
+    os_, oa = oracle.smad(orr, pr)
+    assert (s.view(np.uint64) == os_.view(np.uint64)).all() and (a == oa).all()
+    assert (o == np.lexsort((np.arange(len(hyp)), os_))).all()
+    _cleanup(ctx, m, sid, rid)
+
+
 @pytest.mark.parametrize("variant", [0, 1])
 def test_raycast_smad_c2_full_size(ctx, c2, variant):
     """Full-size plain-large workload, same launch as the benchmark (variant
