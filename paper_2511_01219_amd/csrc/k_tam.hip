@@ -195,10 +195,22 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   if (lane == 0 && packed) atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
 }
 
+// Workgroup b of an n-workgroup grid runs on XCD b % 8 (round-robin
+// dispatch); the returned index gives every XCD one contiguous slice of
+// [0, n), so the orientation tiles of one hypothesis (whose endpoints touch
+// nearly the same EDT cells) share one XCD's L2.
+__device__ __forceinline__ int xcd_slice(int b, int n) {
+  const int x = b & 7, i = b >> 3;
+  const int q = n >> 3, rem = n & 7;
+  return x * q + min(x, rem) + i;
+}
+
 template <int R, int KB>
 __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
   extern __shared__ int32_t smem[];
-  tam_block<R, KB>(a, blockIdx.y, blockIdx.x, smem);
+  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  const int L = xcd_slice(blockIdx.x, gridDim.x);
+  tam_block<R, KB>(a, L / ntb, L % ntb, smem);
 }
 
 // Index of the segment holding item t: prefix[e] <= t < prefix[e + 1].
@@ -217,18 +229,19 @@ template <int R, int KB>
 __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict__ items,
                                                        const int64_t* __restrict__ prefix, int n) {
   extern __shared__ int32_t smem[];
-  const int e = find_segment(prefix, n, blockIdx.x);
+  const int t = xcd_slice(blockIdx.x, gridDim.x);
+  const int e = find_segment(prefix, n, t);
   const TamArgs& a = items[e];
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  const int local = (int)(blockIdx.x - prefix[e]);
+  const int local = (int)(t - prefix[e]);
   tam_block<R, KB>(a, local / ntb, local % ntb, smem);
 }
 
 template <int R, int KB>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
   const size_t lds = (size_t)2 * a.nv * sizeof(int32_t);
-  dim3 grid((a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK, a.nb);
-  hipLaunchKernelGGL((tam_kernel<R, KB>), grid, dim3(TB), lds, s, a);
+  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  hipLaunchKernelGGL((tam_kernel<R, KB>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
   return hipGetLastError();
 }
 
