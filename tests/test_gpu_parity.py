@@ -399,6 +399,25 @@ def test_relocalize_c1_end_to_end(ctx, c1, tau, K):
     ctx.unload_map(m)
 
 
+@pytest.mark.parametrize("tau", [None, 0.95])
+def test_relocalize_tied_smad(ctx, c1, tau):
+    """Every hypothesis three times: every SMAD value is tied three ways, so
+    the first stage's K smallest (SMAD, index) pairs and the later full order
+    must break ties by index exactly as the oracle's stable order does."""
+    w, k, hyp = c1
+    hyp3 = np.repeat(hyp, 3, axis=0)
+    _case("relocalize c1 tied SMAD, 900 hyps, tau=%s" % tau)
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp3)
+    poses, st = ctx.relocalize(m, sid, **_scan(w), n_theta=360, batch_k=16, tau=tau, k_out=10)
+    ref = _oracle_run(w, k, hyp3, 360, 16, tau)
+    _compare_runs(poses, st, ref, tau, 16)
+    for p in poses:
+        assert p["hyp"] == int(ref["order"][p["rank"]])
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
 def test_relocalize_edge_cases(ctx, c1):
     w, k, hyp = c1
     m = ctx.load_map(w.occ, 0.05)
