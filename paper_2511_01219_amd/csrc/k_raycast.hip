@@ -165,7 +165,7 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.kmin = df.w;
   r.Dm = (r.b - r.a) << 7;
   r.na = r.nb = r.it = 0;
-  r.off = iy0 * W + ix0;
+  r.off = (int)__umul24(iy0, W) + ix0;
   r.v = sm.at(r.pbase, r.off);
 }
 
@@ -187,6 +187,9 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 //    float estimate of that count is within one of it; Dm is evaluated in
 //    wrapping 32-bit arithmetic (exact, the true value is within one step of
 //    the window) and one correction lands in the window.
+// Every product here has factors below 2^23 (counts below 2^12 for ranges
+// under 64 m at >= 1/32 m cells, |U| <= 2^20, strides <= 32768) and only its
+// low 32 bits are used, so the full-rate 24-bit multiplies are exact.
 __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off0, float* z,
                                           int* hit) {
   ++r.it;
@@ -196,13 +199,14 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   if (r.Dm < 0) {
     const float est = fminf((float)(-r.Dm) * r.inv, 256.f);
     kr = min((int)(r.v >> 8), (int)ceilf(est));
-    if (kr > 0 && r.Dm + (r.b << 8) * (kr - 1) >= 0) --kr;
+    if (kr > 0 && r.Dm + (int)(((uint32_t)r.b & 0x1FFFFFu) * ((uint32_t)(kr - 1) & 0xFFu) << 8) >= 0)
+      --kr;
   }
   if (kr >= J) {
     if (kr > 0) {
       r.na += kr;
-      r.Dm += (r.b << 8) * kr;
-      r.off += kr * r.om;
+      r.Dm += (int)(((uint32_t)r.b & 0x1FFFFFu) * ((uint32_t)kr & 0x1FFu) << 8);
+      r.off += __mul24(kr, r.om);
       if (r.na > r.la) {
         *z = 0.f;
         *hit = -1;
@@ -212,15 +216,14 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   } else {
     const int na = r.na + J;
     int nb = (int)floorf(((float)na - 0.5f) * r.r - 0.5f) + 1;
-    int Dm = (int)((uint32_t)(128 + 256 * na) * (uint32_t)r.b -
-                   (uint32_t)(128 + 256 * nb) * (uint32_t)r.a);
+    int Dm = (int)(__umul24(128 + 256 * na, r.b) - __umul24(128 + 256 * nb, r.a));
     const int dB = r.a << 8;
     if (Dm >= (r.b << 8)) { ++nb; Dm -= dB; }
     if (Dm < ((r.b - r.a) << 8)) { --nb; Dm += dB; }
     r.na = na;
     r.nb = nb;
     r.Dm = Dm;
-    r.off = off0 + na * r.om + nb * r.on;
+    r.off = off0 + __mul24(na, r.om) + __mul24(nb, r.on);
     if (na > r.la || nb > r.lb) {
       *z = 0.f;
       *hit = -1;
@@ -305,7 +308,7 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
     // t < Ns + chunk < 2^13: the float quotient is within one of t / Ns
     const int t = j0 + qq;
     int dh = (int)((float)t * inv_ns);
-    int jj = t - dh * Ns;
+    int jj = t - __mul24(dh, Ns);
     if (jj < 0) {
       --dh;
       jj += Ns;
@@ -317,7 +320,7 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
     oh = h;
     oj = jj;
     const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
-    off0 = iy0 * W + ix0;
+    off0 = (int)__umul24(iy0, W) + ix0;
     skip_init(r, a.dir_i[jj], a.dir_f[jj], ix0, iy0, W, H, rcells, plane_bytes, sm);
   };
   if (busy) start(q);
