@@ -376,7 +376,7 @@ def main():
                     help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plain-large",
-                    choices=("plain-large", "batched", "serving", "stress"))
+                    choices=("plain-large", "plain-small", "batched", "serving", "stress"))
     ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
@@ -411,9 +411,10 @@ def main():
         log("calibration copy of %d MiB done" % args.calibrate_copy)
         del src, dst
     tau = None if args.tau.lower() in ("none", "nan") else float(args.tau)
-    n_theta, batch_k = 720, 64
-    log("generating the plain-large workload")
-    w = make_config(2)
+    small = args.workload == "plain-small"
+    n_theta, batch_k = (360, 10) if small else (720, 64)
+    log("generating the %s workload" % args.workload)
+    w = make_config(1 if small else 2)
     ctx = reloc.Context(0)
     m = ctx.load_map(w.occ, w.resolution, w.origin)
     s = w.sample
@@ -482,8 +483,10 @@ def main():
         "vs_baseline": None,
         "dtype": "int32+f32+f64",
         "data": "synthetic",
-        "config": {"workload": "plain-large: warehouse 2000x2000 @0.05 m, 20000 hypotheses, "
-                               "270 deg 720 beams, 0.5 deg TAM, top-64 per stage",
+        "config": {"workload": ("plain-small: rooms 200x200 @0.05 m, 300 hypotheses, 270 deg "
+                                "360 beams, 1 deg TAM, top-10 per stage") if small else
+                               ("plain-large: warehouse 2000x2000 @0.05 m, 20000 hypotheses, "
+                                "270 deg 720 beams, 0.5 deg TAM, top-64 per stage"),
                    "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},

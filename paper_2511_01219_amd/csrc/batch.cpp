@@ -638,12 +638,10 @@ extern "C" {
 
 int32_t reloc_run_batch(reloc_ctx* c, int32_t n, const int32_t* request_ids, reloc_pose* out,
                         int32_t cap, int32_t* n_out, int32_t* status, reloc_stats* stats) {
+  for (int i = 0; n_out && i < n; ++i) n_out[i] = 0;
+  for (int i = 0; status && i < n; ++i) status[i] = RELOC_E_PENDING;
   if (!c || n < 0 || (n > 0 && (!request_ids || !n_out || !status)) || (!out && cap > 0))
     return fail(RELOC_E_INVALID, "null argument");
-  for (int i = 0; i < n; ++i) {
-    n_out[i] = 0;
-    status[i] = RELOC_E_PENDING;
-  }
   if (n == 0) return RELOC_OK;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   for (int i = 0; i < n; ++i) {
@@ -698,8 +696,8 @@ int32_t reloc_serve_configure(reloc_ctx* c, const reloc_serve_config* cfg) {
 
 int32_t reloc_submit(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
                      const reloc_search_params* params, uint64_t* ticket) {
+  if (ticket) *ticket = 0;
   if (!c || !ticket) return fail(RELOC_E_INVALID, "null argument");
-  *ticket = 0;
   auto t = std::make_unique<Ticket>();
   t->t_submit = std::chrono::steady_clock::now();
   {
@@ -728,8 +726,8 @@ int32_t reloc_submit(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
 
 int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* out, int32_t cap,
                    int32_t* n_out, reloc_stats* st) {
+  if (n_out) *n_out = 0;
   if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
-  *n_out = 0;
   ServeState* S = c->serve;
   std::unique_lock<std::mutex> lk(S->qmu);
   auto it = S->tickets.find(ticket);

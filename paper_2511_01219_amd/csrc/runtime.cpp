@@ -720,8 +720,8 @@ size_t reloc_ctx_bytes(const reloc_ctx* c) { return c ? c->used : 0; }
 
 int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
                        int32_t* map_id) {
+  if (map_id) *map_id = -1;
   if (!c || !d || !occ || !map_id) return fail(RELOC_E_INVALID, "null argument");
-  *map_id = -1;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   if (d->width < 1 || d->height < 1 || d->width > kMaxDim || d->height > kMaxDim)
     return fail(RELOC_E_INVALID, "map size %dx%d outside 1..%d", d->width, d->height, kMaxDim);
@@ -811,8 +811,9 @@ int32_t reloc_read_edt(reloc_ctx* c, int32_t map_id, uint32_t* k_out) {
 
 int32_t reloc_sample_hypotheses(reloc_ctx* c, int32_t map_id, const reloc_sample_params* p,
                                 int32_t* set_id, int32_t* n_out) {
+  if (n_out) *n_out = 0;
+  if (set_id) *set_id = -1;
   if (!c || !p || !set_id || !n_out) return fail(RELOC_E_INVALID, "null argument");
-  *n_out = 0;
   *set_id = -1;
   if (p->n_target < 1) return fail(RELOC_E_INVALID, "n_target must be >= 1");
   if (!(p->min_spacing >= 0) || !(p->robot_radius >= 0))
@@ -834,8 +835,8 @@ int32_t reloc_sample_hypotheses(reloc_ctx* c, int32_t map_id, const reloc_sample
 
 int32_t reloc_set_hypotheses(reloc_ctx* c, int32_t map_id, const int32_t* cell_xy, int32_t n,
                              int32_t* set_id) {
+  if (set_id) *set_id = -1;
   if (!c || !cell_xy || !set_id) return fail(RELOC_E_INVALID, "null argument");
-  *set_id = -1;
   if (n < 1) return fail(RELOC_E_INVALID, "empty hypothesis set");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   auto it = c->maps.find(map_id);
@@ -901,8 +902,8 @@ int32_t reloc_scan_info_get(const reloc_scan* scan, const reloc_search_params* p
 
 int32_t reloc_prepare(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
                       const reloc_search_params* params, int32_t* request_id) {
+  if (request_id) *request_id = -1;
   if (!c || !request_id) return fail(RELOC_E_INVALID, "null argument");
-  *request_id = -1;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   Request R;
   if (int32_t e = init_request(c, map_id, set_id, scan, params, &R)) return e;
@@ -930,8 +931,8 @@ int32_t reloc_release(reloc_ctx* c, int32_t request_id) {
 
 int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap,
                   int32_t* n_out, reloc_stats* st) {
+  if (n_out) *n_out = 0;
   if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
-  *n_out = 0;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   auto it = c->reqs.find(request_id);
   if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);

@@ -153,3 +153,45 @@ def test_search_param_defaults():
     assert tuple(p.alpha_mid_pm) == (900, 700) and tuple(p.alpha_low_pm) == (700, 500)
     q = reloc.search_params(tau=None)
     assert math.isnan(q.tau)
+
+
+def test_null_context_calls_are_invalid():
+    """Every entry point rejects a null context with RELOC_E_INVALID and
+    writes zero counts; no device is needed."""
+    import ctypes as C
+    lib = reloc.lib()
+    n = C.c_int32(7)
+    st = np.zeros(4, np.int32)
+    assert lib.reloc_run(None, 1, None, 0, C.byref(n), None) == reloc.E_INVALID
+    assert n.value == 0
+    ids = np.array([1, 2], np.int32)
+    n_out = np.full(2, 9, np.int32)
+    assert lib.reloc_run_batch(None, 2, ids.ctypes.data, None, 0, n_out.ctypes.data,
+                               st.ctypes.data, None) == reloc.E_INVALID
+    t = C.c_uint64(5)
+    assert lib.reloc_submit(None, 1, 1, None, None, C.byref(t)) == reloc.E_INVALID
+    assert t.value == 0
+    n.value = 3
+    assert lib.reloc_poll(None, 1, 0, None, 0, C.byref(n), None) == reloc.E_INVALID
+    assert lib.reloc_serve_configure(None, None) == reloc.E_INVALID
+    assert lib.reloc_serve_stats_get(None, None) == reloc.E_INVALID
+    assert lib.reloc_prepare(None, 1, 1, None, None, C.byref(n)) == reloc.E_INVALID
+    assert lib.reloc_release(None, 1) == reloc.E_INVALID
+
+
+def test_multi_map_generators_are_seeded():
+    """The batched and serving workloads are functions of their seeds: two
+    calls give identical maps, queries and arrival times."""
+    from synth import make_batched, make_serving
+    a = make_batched(6, sizes=(120, 160), n_range=(50, 500))
+    b = make_batched(6, sizes=(120, 160), n_range=(50, 500))
+    assert all((x == y).all() for x, y in zip(a.maps, b.maps))
+    for p, q in zip(a.queries, b.queries):
+        assert p.map_index == q.map_index and p.n_hyp == q.n_hyp and p.pose == q.pose
+        assert np.array_equal(p.ranges, q.ranges, equal_nan=True)
+        assert (360.0 * p.n_beams / p.fov_deg) == int(360.0 * p.n_beams / p.fov_deg)
+    s1 = make_serving(100.0, 8, sizes=(120,), per_size=2, n_range=(50, 500))
+    s2 = make_serving(100.0, 8, sizes=(120,), per_size=2, n_range=(50, 500))
+    arr = [q.arrival for q in s1.queries]
+    assert arr == [q.arrival for q in s2.queries]
+    assert arr[0] == 0.0 and all(x < y for x, y in zip(arr, arr[1:]))
