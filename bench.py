@@ -299,7 +299,7 @@ def bench_serving(args):
     for rate in [float(x) for x in args.rates.split(",")]:
         arr = base / rate
         # served
-        ctx.serve_configure(max_inflight=args.max_inflight, max_admit=args.max_inflight)
+        ctx.serve_configure(max_inflight=args.max_inflight, max_admit=args.max_admit)
         sub = []
         start = time.perf_counter()
 
@@ -359,7 +359,8 @@ def bench_serving(args):
            "config": {"workload": "serving: 16 maps (4 each of 1000^2, 2000^2, 3000^2, "
                                   "4000^2), 2k-40k hypotheses, FoV 270/360 deg, 540-1440 "
                                   "beams, N_theta 360, top-64, tau 0.95",
-                      "requests_per_rate": len(qs), "max_inflight": args.max_inflight},
+                      "requests_per_rate": len(qs), "max_inflight": args.max_inflight,
+                      "max_admit": args.max_admit},
            "serving": rows}
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -380,6 +381,7 @@ def main():
     ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
+    ap.add_argument("--max-admit", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()

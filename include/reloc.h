@@ -276,10 +276,10 @@ int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
  * TAM over a rank range of every unfinished request and one stage-control
  * kernel that reduces each of its stages on the device (Sec. III pipeline,
  * batch-wise early termination). A range covers one stage in a request's
- * first two steps, then 2, 4, ... up to 32 consecutive stages while that
- * keeps the device no busier than it needs to be; stages after the first
- * whose best T exceeds tau are discarded, so every request gets exactly the
- * result of reloc_run.
+ * first two steps, then 2, 4, ... up to 32 consecutive stages, granted
+ * oldest request first out of a per-step budget of TAM workgroups (at least
+ * one stage each); stages after the first whose best T exceeds tau are
+ * discarded, so every request gets exactly the result of reloc_run.
  *   request_ids : host int32[n], distinct prepared requests
  *   out         : host reloc_pose[n * cap]; request i's poses at out + i*cap
  *   n_out       : host int32[n] poses written per request
@@ -313,7 +313,7 @@ int32_t reloc_run_batch(reloc_ctx* ctx, int32_t n, const int32_t* request_ids,
 typedef struct {
   int32_t max_inflight;   /* requests on the device at once (64) */
   size_t hbm_reserve;     /* bytes of the context budget left free (0) */
-  int32_t max_admit;      /* requests admitted per round (64) */
+  int32_t max_admit;      /* requests admitted per round (16) */
 } reloc_serve_config;
 
 /* Replaces the scheduler configuration (takes effect at the next round). */

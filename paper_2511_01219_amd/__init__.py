@@ -286,7 +286,7 @@ class Context:
         return res
 
     # -- serving ----------------------------------------------------------------------
-    def serve_configure(self, max_inflight: int = 64, hbm_reserve: int = 0, max_admit: int = 64):
+    def serve_configure(self, max_inflight: int = 64, hbm_reserve: int = 0, max_admit: int = 16):
         cfg = _abi.reloc_serve_config(int(max_inflight), int(hbm_reserve), int(max_admit))
         _check(self._lib.reloc_serve_configure(self._h, C.byref(cfg)))
 

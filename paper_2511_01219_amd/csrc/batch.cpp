@@ -10,10 +10,11 @@
 //           reduces every stage of the tick on the device; the host reads
 //           one flag per stage. A request's range covers `spec` consecutive
 //           stages (1 for its first two ticks, then 2, 4, ... up to
-//           kMaxSpec, and never more than keeps the device busy next to the
-//           other requests); stages after the first one whose best T exceeds
-//           tau are discarded, so the evaluated set and every result equal
-//           those of the one-stage-at-a-time path;
+//           kMaxSpec), granted oldest request first out of a per-tick budget
+//           of TAM workgroups, at least one stage each; stages after the
+//           first one whose best T exceeds tau are discarded, so the
+//           evaluated set and every result equal those of the
+//           one-stage-at-a-time path;
 //   rank  : one segmented sort and one gather for every finished request.
 // The scheduler repeats admission -> front of the admitted requests -> one
 // tick of everything in flight -> rank of the finished ones, so requests
@@ -29,7 +30,7 @@ namespace reloc {
 namespace {
 
 constexpr int kMaxSpec = 32;          // stages of one request in one tick, at most
-constexpr int64_t kFillBlocks = 16384;  // TAM workgroups that keep every CU busy in a tick
+constexpr int64_t kTickBlocks = 65536;  // TAM workgroups one tick may grant beyond one stage each
 
 // Contiguous buffers of one front-phase group: SMAD sort keys / values, the
 // SMAD order and the per-rank best of every request of the group.
@@ -107,7 +108,7 @@ struct ServeState {
   std::map<uint64_t, std::unique_ptr<Ticket>> tickets;
   uint64_t next_ticket = 1;
   std::vector<Flight> active;       // touched by the worker only
-  reloc_serve_config cfg{64, 0, 64};
+  reloc_serve_config cfg{64, 0, 16};
   reloc_serve_stats stats{};
   int32_t worker_error = RELOC_OK;
 };
@@ -270,18 +271,25 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
   for (Flight* f : F)
     if (!f->done) live.push_back(f);
   if (live.empty()) return RELOC_OK;
-  // stages per request this tick: the speculation schedule, capped so that
-  // the tick does not run far beyond what fills the device
+  // stages per request this tick: the speculation schedule, granted oldest
+  // request first out of a budget of TAM workgroups, at least one stage each
+  std::vector<size_t> by_age(live.size());
+  for (size_t j = 0; j < live.size(); ++j) by_age[j] = j;
+  std::stable_sort(by_age.begin(), by_age.end(), [&](size_t x, size_t y) {
+    return live[x]->t_start < live[y]->t_start;
+  });
   std::vector<int> nst(live.size());
   size_t n_entries = 0;
-  for (size_t j = 0; j < live.size(); ++j) {
+  int64_t budget = kTickBlocks;
+  for (size_t j : by_age) {
     const Flight* f = live[j];
     const Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
     const int left = (R.n_hyp - f->next_rank + K - 1) / K;
     const int64_t bps = (int64_t)K * ((R.prep.info.Ntheta + 15) / 16);
-    const int64_t cap = std::max<int64_t>(1, kFillBlocks / ((int64_t)live.size() * bps));
+    const int64_t cap = std::max<int64_t>(1, budget / bps);
     nst[j] = (int)std::min<int64_t>(std::min(f->spec, left), cap);
+    budget -= nst[j] * bps;
     n_entries += (size_t)nst[j];
   }
   if (int32_t e = ensure_stage_cap(c, S, n_entries)) return e;
