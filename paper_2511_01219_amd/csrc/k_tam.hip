@@ -53,15 +53,12 @@ template <int R, int KB>
 __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
   constexpr int SB = 4;               // keys per lane in flight together
   constexpr int G = THETA_PER_BLOCK / NW;
-  int32_t* sbase = smem;              // [nv]
-  int32_t* szq = smem + a.nv;         // [nv]
+  int2* sbz = (int2*)smem;            // [nvp] (direction base, Q8 range)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = a.nv;
 
-  for (int v = tid; v < nv; v += TB) {
-    sbase[v] = a.beam_base[v];
-    szq[v] = a.beam_zq[v];
-  }
+  const int nvp = (nv + 255) & ~255;
+  for (int v = tid; v < nvp; v += TB) sbz[v] = a.beams[v];
   const int r = a.r0 + i;
   const int hyp = a.order[r];
   const int64_t X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
@@ -88,11 +85,10 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
         int zq[SB];
 #pragma unroll
         for (int s2 = 0; s2 < SB; ++s2) {
-          const int v = min(lane + 64 * (i0 + s2), nv - 1);
-          int t = sbase[v] + ok;
-          if (t >= a.Ng) t -= a.Ng;
-          zq[s2] = szq[v];
-          U[s2] = a.dirs[t];
+          // padded beams and a doubled direction table: no clamp, no wrap
+          const int2 bz = sbz[lane + 64 * (i0 + s2)];
+          zq[s2] = bz.y;
+          U[s2] = a.dirs[bz.x + ok];
         }
         uint32_t kk[SB];
         bool in[SB];
@@ -239,7 +235,7 @@ __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict
 
 template <int R, int KB>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)2 * a.nv * sizeof(int32_t);
+  const size_t lds = (size_t)((a.nv + 255) & ~255) * sizeof(int2);
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   hipLaunchKernelGGL((tam_kernel<R, KB>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
   return hipGetLastError();
@@ -383,7 +379,7 @@ int tam_class(const TamArgs& a) {
   return (rc < 0 || kc < 0) ? -1 : kc * 5 + rc;
 }
 
-size_t tam_lds_bytes(const TamArgs& a) { return (size_t)2 * a.nv * sizeof(int32_t); }
+size_t tam_lds_bytes(const TamArgs& a) { return (size_t)((a.nv + 255) & ~255) * sizeof(int2); }
 
 hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
                             int64_t blocks, size_t lds, hipStream_t s) {

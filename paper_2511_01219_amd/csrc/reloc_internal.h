@@ -100,10 +100,10 @@ struct TamArgs {
   const int32_t* hyp_xy;
   const int32_t* order;      // hypothesis index per SMAD rank
   int r0, nb;                // ranks [r0, r0 + nb)
-  const int32_t* beam_base;  // [nv] (b * j_v) mod Ng
-  const int32_t* beam_zq;    // [nv] range in Q8 cells
+  const int2* beams;         // [nvp] ((b * j_v) mod Ng, range in Q8 cells), padded
+                             // with (0, 0) to nvp = nv rounded up to 256
   int nv;
-  const int2* dirs;          // [Ng] direction table
+  const int2* dirs;          // [2 Ng] direction table, stored twice
   int Ng, o, Nt;             // o = Ng / Nt
   const int32_t* lut;        // [n_keys] likelihood per selection key, Q26
   int kcap, key_off, keybits;

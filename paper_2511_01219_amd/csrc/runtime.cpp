@@ -373,9 +373,9 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.dir_i = req_alloc<int4>(c, R, Ns);
   R.dir_f = req_alloc<float4>(c, R, Ns);
   R.runs = req_alloc<int2>(c, R, R.prep.runs.size());
-  R.base = req_alloc<int32_t>(c, R, nv);
-  R.zq = req_alloc<int32_t>(c, R, nv);
-  R.dirs = req_alloc<int2>(c, R, Ng);
+  const int nvp = (nv + 255) / 256 * 256;
+  R.beams = req_alloc<int2>(c, R, nvp);
+  R.dirs = req_alloc<int2>(c, R, 2 * (size_t)Ng);
   R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
   R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
   R.perm = req_alloc<int32_t>(c, R, n);
@@ -404,9 +404,13 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   if (int32_t e = upload(c, R.dir_i, di.data(), di.size())) return e;
   if (int32_t e = upload(c, R.dir_f, df.data(), df.size())) return e;
   if (int32_t e = upload(c, R.runs, R.prep.runs.data(), R.prep.runs.size())) return e;
-  if (int32_t e = upload(c, R.base, base.data(), base.size())) return e;
-  if (int32_t e = upload(c, R.zq, R.prep.vzq.data(), R.prep.vzq.size())) return e;
-  if (int32_t e = upload(c, R.dirs, U.data(), U.size())) return e;
+  std::vector<int2> beams(nvp, int2{0, 0});
+  for (int v = 0; v < nv; ++v) beams[v] = int2{base[v], R.prep.vzq[v]};
+  if (int32_t e = upload(c, R.beams, beams.data(), beams.size())) return e;
+  std::vector<int2> U2(2 * (size_t)Ng);
+  std::copy(U.begin(), U.end(), U2.begin());
+  std::copy(U.begin(), U.end(), U2.begin() + Ng);
+  if (int32_t e = upload(c, R.dirs, U2.data(), U2.size())) return e;
   if (int32_t e = upload(c, R.dlut, R.lut.q.data(), R.lut.q.size())) return e;
   // casting order: Morton (Z-order) of the hypothesis cells, so that the rays
   // in flight on one XCD start in one compact region of the map
@@ -490,8 +494,7 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   a.order = R.order;
   a.r0 = r0;
   a.nb = nb;
-  a.beam_base = R.base;
-  a.beam_zq = R.zq;
+  a.beams = R.beams;
   a.nv = I.n_valid;
   a.dirs = R.dirs;
   a.Ng = I.Ng;

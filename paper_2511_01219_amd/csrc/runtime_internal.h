@@ -88,8 +88,7 @@ struct Request {
   float* zbuf = nullptr;
   int32_t* perm = nullptr;        // hypotheses in Morton order of their cells
   int2* runs = nullptr;
-  int32_t* base = nullptr;
-  int32_t* zq = nullptr;
+  int2* beams = nullptr;          // valid beams (direction base, Q8 range), padded
   int2* dirs = nullptr;
   int32_t* dlut = nullptr;
   // device work
