@@ -51,7 +51,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // 0..3, and one atomic max per wavefront publishes the best (T, ~k).
 template <int R, int KB>
 __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
-  constexpr int SB = 4;               // keys per lane in flight together
+  constexpr int SB = R >= 32 ? 8 : 4;  // keys per lane in flight together
   constexpr int G = THETA_PER_BLOCK / NW;
   int2* sbz = (int2*)smem;            // [nvp] (direction base, Q8 range)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
