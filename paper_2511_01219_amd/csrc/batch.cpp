@@ -68,6 +68,7 @@ struct Ticket {
   Request R;                        // host part prepared at submit
   bool done = false;
   int32_t status = RELOC_E_PENDING;
+  std::string msg;                  // error text when status is an error
   std::vector<reloc_pose> poses;
   reloc_stats st{};
   std::chrono::steady_clock::time_point t_submit;
@@ -458,8 +459,11 @@ void fill_stats(const Request& R, const Flight& f, const PhaseTimes& pt, float t
 // ---- serving worker --------------------------------------------------------
 
 void finish_ticket(ServeState& S, Ticket* t, int32_t status) {
+  // the scheduler thread's own error text (thread-local) travels with the ticket
+  const std::string msg = status != RELOC_OK ? reloc_last_error() : "";
   std::lock_guard<std::mutex> lk(S.qmu);
   t->status = status;
+  t->msg = msg;
   t->done = true;
   if (status == RELOC_OK || status == RELOC_E_TIMEOUT)
     ++S.stats.completed;
@@ -755,9 +759,10 @@ int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* o
   for (int i = 0; i < n; ++i) out[i] = t->poses[i];
   *n_out = n;
   if (st) *st = t->st;
+  const std::string msg = t->msg;
   S->tickets.erase(it);
   if (status != RELOC_OK && status != RELOC_E_TIMEOUT)
-    return fail(status, "request failed with status %d", status);
+    return fail(status, "request failed: %s", msg.c_str());
   return status;
 }
 

@@ -57,7 +57,9 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = a.nv;
 
-  const int nvp = (nv + 255) & ~255;
+  // every gather batch below reads whole 64 x SB slices of the padded table
+  static_assert(64 * SB <= kTamBeamPad, "gather batch beyond the beam padding");
+  const int nvp = tam_beams_padded(nv);
   for (int v = tid; v < nvp; v += TB) sbz[v] = a.beams[v];
   const int r = a.r0 + i;
   const int hyp = a.order[r];
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict
 
 template <int R, int KB>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)((a.nv + 255) & ~255) * sizeof(int2);
+  const size_t lds = (size_t)tam_beams_padded(a.nv) * sizeof(int2);
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   hipLaunchKernelGGL((tam_kernel<R, KB>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
   return hipGetLastError();
@@ -277,6 +279,17 @@ __device__ __forceinline__ void stage_reduce_run(const StageArgs& a) {
 }
 
 __global__ void stage_reduce_kernel(StageArgs a) { stage_reduce_run(a); }
+
+// stages [0, gridDim.x) of K ranks each starting at a.r0 (the last one
+// ends at n), one workgroup each
+__global__ void stage_reduce_multi_kernel(StageArgs a, int K, int n) {
+  StageArgs b = a;
+  b.r0 = a.r0 + (int)blockIdx.x * K;
+  b.nb = min(K, n - b.r0);
+  b.stage_out = a.stage_out + blockIdx.x;
+  b.flag_out = a.flag_out + blockIdx.x;
+  stage_reduce_run(b);
+}
 
 // one workgroup per stage entry
 __global__ void stage_reduce_batch_kernel(const StageArgs* __restrict__ items) {
@@ -379,7 +392,7 @@ int tam_class(const TamArgs& a) {
   return (rc < 0 || kc < 0) ? -1 : kc * 5 + rc;
 }
 
-size_t tam_lds_bytes(const TamArgs& a) { return (size_t)((a.nv + 255) & ~255) * sizeof(int2); }
+size_t tam_lds_bytes(const TamArgs& a) { return (size_t)tam_beams_padded(a.nv) * sizeof(int2); }
 
 hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
                             int64_t blocks, size_t lds, hipStream_t s) {
@@ -388,6 +401,12 @@ hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix
   if (cls < 0 || cls >= 10) return hipErrorInvalidValue;
   if (cls >= 5) return launch_tam_batch_kb<16>(Rs[cls - 5], items, prefix, n, blocks, lds, s);
   return launch_tam_batch_kb<12>(Rs[cls], items, prefix, n, blocks, lds, s);
+}
+
+hipError_t launch_stage_reduce_multi(const StageArgs& a, int K, int ns, int n, hipStream_t s) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_reduce_multi_kernel, dim3(ns), dim3(TB), 0, s, a, K, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_stage_reduce_batch(const StageArgs* items, int n, hipStream_t s) {

@@ -101,7 +101,7 @@ struct TamArgs {
   const int32_t* order;      // hypothesis index per SMAD rank
   int r0, nb;                // ranks [r0, r0 + nb)
   const int2* beams;         // [nvp] ((b * j_v) mod Ng, range in Q8 cells), padded
-                             // with (0, 0) to nvp = nv rounded up to 256
+                             // with (0, 0) to nvp = tam_beams_padded(nv)
   int nv;
   const int2* dirs;          // [2 Ng] direction table, stored twice
   int Ng, o, Nt;             // o = Ng / Nt
@@ -113,6 +113,12 @@ struct TamArgs {
   uint64_t* best;            // [>= r0 + nb] packed (T bits, ~k) per rank
 };
 hipError_t launch_tam(const TamArgs& a, hipStream_t s);
+// Beam-table length the TAM kernels read: nv rounded up to 512, a whole
+// gather batch of every kernel class (64 lanes x up to 8 keys).
+constexpr int kTamBeamPad = 512;
+__host__ __device__ inline int tam_beams_padded(int nv) {
+  return (nv + kTamBeamPad - 1) / kTamBeamPad * kTamBeamPad;
+}
 
 struct StageArgs {
   const uint64_t* best;      // per rank
@@ -122,6 +128,9 @@ struct StageArgs {
   int32_t* flag_out;         // [1] 1 = stop
 };
 hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s);
+// ns consecutive stages of K ranks from a.r0 (the last ends at n); stage j
+// writes a.stage_out[j], a.flag_out[j]
+hipError_t launch_stage_reduce_multi(const StageArgs& a, int K, int ns, int n, hipStream_t s);
 
 
 

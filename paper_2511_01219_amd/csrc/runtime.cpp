@@ -41,6 +41,7 @@ int32_t fail(int32_t code, const char* fmt, ...) {
 
 
 constexpr int kMaxNs = 4096;
+constexpr int64_t kPlainFillBlocks = 4096;   // TAM workgroups one plain-path launch aims at
 constexpr int kMaxDim = 32768;
 constexpr int kMaxNg = 1 << 20;
 
@@ -373,7 +374,7 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.dir_i = req_alloc<int4>(c, R, Ns);
   R.dir_f = req_alloc<float4>(c, R, Ns);
   R.runs = req_alloc<int2>(c, R, R.prep.runs.size());
-  const int nvp = (nv + 255) / 256 * 256;
+  const int nvp = tam_beams_padded(nv);
   R.beams = req_alloc<int2>(c, R, nvp);
   R.dirs = req_alloc<int2>(c, R, 2 * (size_t)Ng);
   R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
@@ -963,26 +964,46 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   if (int32_t e = pinned_rows(c, (size_t)ncap, &hrows)) return e;
   bool ranked = false;   // rows of the final n_eval already on the host
   int nrow = 0;
-  for (int r0 = 0; r0 < R.n_hyp; r0 += K) {
-    const int nb = std::min(K, R.n_hyp - r0);
+  // stages too small to fill the device are launched several at a time
+  // (their flags read at one synchronisation; stages after the first that
+  // stops are discarded, so the result is that of one stage at a time)
+  const int64_t bps = (int64_t)K * ((I.Ntheta + 15) / 16);
+  const int per = (int)std::min<int64_t>(512, std::max<int64_t>(1, kPlainFillBlocks / bps));
+  for (int r0 = 0; r0 < R.n_hyp;) {
+    const int left = (R.n_hyp - r0 + K - 1) / K;
+    const int ns = std::min(per, left);
+    const int nb = std::min(ns * K, R.n_hyp - r0);
     HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
     StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stages, R.flag + stages};
-    HIP_TRY(launch_stage_reduce(sa, s));
-    HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_stage_reduce_multi(sa, K, ns, R.n_hyp, s));
+    HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     // the first stage's ranking is issued before its stop flag is read: when
     // the search stops there (or has no second stage) the result is ready at
     // the same synchronisation
-    const bool spec = r0 == 0;
+    const bool spec = r0 == 0 && ns == 1;
     if (spec) {
       HIP_TRY(hipEventRecord(c->ev[3], s));
       if (int32_t e = enqueue_rank(c, R, nb, std::min(ncap, nb), hrows)) return e;
       HIP_TRY(hipEventRecord(c->ev[4], s));
     }
     HIP_TRY(hipStreamSynchronize(s));
-    ++stages;
-    n_eval = r0 + nb;
-    if (*hflag || n_eval >= R.n_hyp) {
-      stopped = *hflag ? 1 : 0;
+    int hit = -1;
+    for (int j = 0; j < ns; ++j)
+      if (hflag[j]) {
+        hit = j;
+        break;
+      }
+    if (hit >= 0) {
+      stages += hit + 1;
+      n_eval = std::min(R.n_hyp, r0 + (hit + 1) * K);
+      stopped = 1;
+      ranked = spec;
+      break;
+    }
+    stages += ns;
+    r0 += nb;
+    n_eval = r0;
+    if (n_eval >= R.n_hyp) {
       ranked = spec;
       break;
     }

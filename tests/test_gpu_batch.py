@@ -233,3 +233,30 @@ def test_serve_poisson_trace_small(ctx):
     for mid, sid in zip(mids, sids):
         ctx.free_hypotheses(sid)
         ctx.unload_map(mid)
+
+
+def test_batch_tam_mixed_beam_tables(ctx):
+    """Regression: one TAM class launch serving two requests whose beam
+    tables differ in length (about 1045 and 1950 valid beams, both in the
+    32-keys-per-lane class). Every gather batch reads only the request's own
+    padded table; results equal the plain path's."""
+    from synth import ScanSpec, lidar_scan, make_config
+    w = make_config(1)
+    mid = ctx.load_map(w.occ, w.resolution)
+    sid, _ = ctx.sample_hypotheses(mid, 200, 0.3, 0.21, seed=11)
+    rids = []
+    for n_beams in (1100, 2048, 1100):
+        spec = ScanSpec(360.0, n_beams, 12.0, 0.02, 0.02, 0.05, 0.0)
+        ranges, amin, ainc, _ = lidar_scan(w.occ, w.resolution, w.origin, w.pose, spec,
+                                           np.random.default_rng([11, n_beams]))
+        rids.append(ctx.prepare(mid, sid, ranges, amin, ainc, 0.02, 12.0, n_theta=360,
+                                batch_k=16, tau=None, k_out=8))
+    _case("batch TAM with mixed beam tables: 1100, 2048, 1100 beams")
+    plain = [ctx.run(r, cap=8) for r in rids]
+    batch = ctx.run_batch(rids, cap=8)
+    for a, b in zip(plain, batch):
+        _same(a, b)
+    for r in rids:
+        ctx.release(r)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(mid)
