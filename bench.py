@@ -212,7 +212,9 @@ def bench_stress(args):
     n_theta, batch_k = 1440, 256
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
                       w.range_max, n_theta=n_theta, batch_k=batch_k, tau=0.95, k_out=10)
-    log("map %dx%d, %d hypotheses" % (w.occ.shape[1], w.occ.shape[0], n_hyp))
+    tv, tc, tms = ctx.autotune(rid, reps=2)
+    log("map %dx%d, %d hypotheses; autotuned ray cast: variant %d, %d rays per chunk"
+        % (w.occ.shape[1], w.occ.shape[0], n_hyp, tv, tc))
     for _ in range(args.warmup):
         ctx.run(rid)
     torch.cuda.synchronize()
@@ -245,6 +247,7 @@ def bench_stress(args):
                      "tam_lookups": st["tam_lookups"]},
         "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
         "true_pose": list(w.pose),
+        "autotune": {"variant": tv, "chunk": tc, "ms": tms},
     }
     ctx.release(rid)
     if not args.no_cpu:
@@ -426,6 +429,13 @@ def main():
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
                       w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
                       variant=args.variant)
+    tuned = None
+    if args.variant == 0:
+        # the ray-cast launch shape is picked on this GPU for this request
+        # (every shape gives bit-identical results), outside the timed region
+        tv, tc, tms = ctx.autotune(rid, reps=3)
+        tuned = {"variant": tv, "chunk": tc, "ms": tms}
+        log("autotuned ray cast: variant %d, %d rays per chunk, %.3f ms" % (tv, tc, tms))
     log("map %dx%d, %d hypotheses, warmup %d" % (w.occ.shape[1], w.occ.shape[0], n_hyp,
                                                args.warmup))
     for _ in range(args.warmup):
@@ -465,7 +475,8 @@ def main():
     achieved = crossings * DDA_OPS_PER_STEP / t_ray
     traffic = measured_traffic()
     kname = {1: "raycast_bits_kernel", 2: "raycast_skip_kernel<1>", 3: "raycast_skip_kernel<8>",
-             4: "raycast_skip_kernel<16>", 5: "raycast_skip_kernel<32>"}.get(args.variant or 4)
+             4: "raycast_skip_kernel<16>", 5: "raycast_skip_kernel<32>"}.get(
+                 tuned["variant"] if tuned else (args.variant or 4))
     roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "TOP/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
@@ -501,6 +512,7 @@ def main():
         "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
         "true_pose": list(w.pose),
         "roofline": roofline,
+        "autotune": tuned,
     }
     ctx.release(rid)
     if not args.no_cpu:

@@ -343,6 +343,21 @@ typedef struct {
 int32_t reloc_serve_stats_get(reloc_ctx* ctx, reloc_serve_stats* out);
 
 /* ------------------------------------------------------------------------
+ * Autotuning. Times the ray-cast kernel of a prepared request over a grid
+ * of launch shapes (lane-refill threshold 8 / 16 / 32 idle lanes x 256,
+ * 384, 512, 768, 1024 rays per chunk; every shape gives bit-identical
+ * ranges), each warmed once and then launched reps times, and keeps the
+ * fastest for the request's later runs (reloc_run, reloc_run_batch).
+ * variant_out: the chosen public variant (3, 4, 5); chunk_out: rays per
+ * chunk; ms_out: its mean kernel time. Any of them may be NULL. Requests on
+ * maps without walk words (above 2^28 cells) keep the bit-tile kernel and
+ * report their current settings. Errors: RELOC_E_INVALID (reps < 1),
+ * RELOC_E_NOTFOUND, RELOC_E_DEVICE.
+ * ---------------------------------------------------------------------- */
+int32_t reloc_autotune(reloc_ctx* ctx, int32_t request_id, int32_t reps, int32_t* variant_out,
+                       int32_t* chunk_out, float* ms_out);
+
+/* ------------------------------------------------------------------------
  * Parity / inspection entry points (same kernels as reloc_run).
  * ---------------------------------------------------------------------- */
 

@@ -264,6 +264,14 @@ class Context:
         finally:
             self.release(rid)
 
+    def autotune(self, request_id: int, reps: int = 3):
+        """Picks the fastest ray-cast launch shape for the request; returns
+        (variant, rays per chunk, mean kernel ms)."""
+        v, ch, ms = C.c_int32(), C.c_int32(), C.c_float()
+        _check(self._lib.reloc_autotune(self._h, int(request_id), int(reps), C.byref(v),
+                                        C.byref(ch), C.byref(ms)))
+        return v.value, ch.value, ms.value
+
     # -- batched form -------------------------------------------------------------
     def run_batch(self, request_ids: Sequence[int], cap: int = 64):
         """Runs prepared requests together; returns [(poses, stats)] in order.

@@ -454,7 +454,9 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
     const int64_t rays = (int64_t)R.n_hyp * I.Ns;
     // many short chunks balance the waves across the CUs (a wave's cost
     // varies with its rays' lengths); measured flat between 256 and 512
-    a.chunk = (int)std::max<int64_t>(256, std::min<int64_t>(1024, rays / 49152));
+    a.chunk = R.tuned_chunk > 0
+                  ? R.tuned_chunk
+                  : (int)std::max<int64_t>(256, std::min<int64_t>(1024, rays / 49152));
   }
   a.zbuf = R.zbuf;
   a.perm = R.perm;
@@ -1062,6 +1064,53 @@ int32_t reloc_relocalize(reloc_ctx* c, int32_t map_id, int32_t set_id, const rel
   reloc_release(c, rid);
   g_err = msg;
   return e;
+}
+
+int32_t reloc_autotune(reloc_ctx* c, int32_t request_id, int32_t reps, int32_t* variant_out,
+                       int32_t* chunk_out, float* ms_out) {
+  if (variant_out) *variant_out = 0;
+  if (chunk_out) *chunk_out = 0;
+  if (ms_out) *ms_out = 0.f;
+  if (!c || reps < 1) return fail(RELOC_E_INVALID, "null ctx or reps < 1");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  if (int32_t e = set_device(c)) return e;
+  Request& R = it->second;
+  hipStream_t s = c->stream;
+  float best_ms = -1.f;
+  int best_v = R.prm.variant, best_c = R.tuned_chunk;
+  if (c->maps.at(R.map_id).walk) {
+    // lane-refill threshold (public variants 3, 4, 5: 8, 16, 32 idle lanes)
+    // x rays per chunk; every shape gives bit-identical ranges
+    static const int variants[3] = {3, 4, 5};
+    static const int chunks[5] = {256, 384, 512, 768, 1024};
+    for (int v : variants)
+      for (int ch : chunks) {
+        R.prm.variant = v;
+        R.tuned_chunk = ch;
+        const RayArgs a = ray_args(c, R, nullptr, nullptr);
+        HIP_TRY(launch_raycast(a, s));   // warm-up
+        HIP_TRY(hipEventRecord(c->ev[0], s));
+        for (int r = 0; r < reps; ++r) HIP_TRY(launch_raycast(a, s));
+        HIP_TRY(hipEventRecord(c->ev[5], s));
+        HIP_TRY(hipEventSynchronize(c->ev[5]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[5]));
+        ms /= (float)reps;
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best_v = v;
+          best_c = ch;
+        }
+      }
+    R.prm.variant = best_v;
+    R.tuned_chunk = best_c;
+  }
+  if (variant_out) *variant_out = R.prm.variant;
+  if (chunk_out) *chunk_out = R.tuned_chunk;
+  if (ms_out) *ms_out = best_ms < 0.f ? 0.f : best_ms;
+  return RELOC_OK;
 }
 
 int32_t reloc_debug_raycast(reloc_ctx* c, int32_t request_id, int32_t* hit_cell, float* range,

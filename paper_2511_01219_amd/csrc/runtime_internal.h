@@ -79,6 +79,7 @@ struct Request {
   reloc_search_params prm{};
   float rmax = 0.f;
   int rcells = 0;
+  int tuned_chunk = 0;            // rays per ray-cast chunk chosen by reloc_autotune (0: rule)
   Lut lut;
   // device tables
   int2* raydirs = nullptr;

@@ -260,3 +260,21 @@ def test_batch_tam_mixed_beam_tables(ctx):
         ctx.release(r)
     ctx.free_hypotheses(sid)
     ctx.unload_map(mid)
+
+
+def test_batch_and_serve_deadline(ctx, multi, loaded):
+    """deadline_s in the batched form and in serving: the request ends with
+    E_TIMEOUT after the stages it ran and returns their ranking."""
+    mids, sids = loaded
+    q = max(multi.queries, key=lambda x: x.n_hyp)
+    _case("deadline batch / serve: %d hypotheses" % q.n_hyp)
+    r = _prepare(ctx, loaded, q, tau=None, batch_k=4, deadline_s=1e-9)
+    (poses, st), = ctx.run_batch([r])
+    assert st["status"] == reloc.E_TIMEOUT
+    assert 0 < st["n_eval"] < st["n_hyp"] and len(poses) > 0
+    ctx.release(r)
+    t = ctx.submit(mids[q.map_index], sids[q.map_index], **_args(q),
+                   **_search(q, tau=None, batch_k=4, deadline_s=1e-9))
+    poses, st = ctx.poll(t, wait_ms=60000)
+    assert st["status"] == reloc.E_TIMEOUT
+    assert 0 < st["n_eval"] < st["n_hyp"] and len(poses) > 0

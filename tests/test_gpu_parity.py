@@ -418,6 +418,53 @@ def test_relocalize_tied_smad(ctx, c1, tau):
     ctx.unload_map(m)
 
 
+def test_autotune_keeps_results(ctx, c1):
+    """The autotuner only picks a launch shape: ranges, SMAD, order and the
+    ranked poses are bit-identical before and after."""
+    w, k, hyp = c1
+    _case("autotune c1")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=360, batch_k=10, tau=None, k_out=10)
+    pr = _oprep(w, 360)
+    a_hit, a_rng = ctx.debug_raycast(rid, len(hyp), pr["Ns"])
+    a_poses, a_st = ctx.run(rid)
+    v, ch, ms = ctx.autotune(rid, reps=1)
+    assert v in (3, 4, 5) and ch in (256, 384, 512, 768, 1024) and ms > 0
+    b_hit, b_rng = ctx.debug_raycast(rid, len(hyp), pr["Ns"])
+    b_poses, b_st = ctx.run(rid)
+    assert (a_hit == b_hit).all() and (a_rng.view(np.uint32) == b_rng.view(np.uint32)).all()
+    assert [(p["hyp"], p["k"], p["tam"]) for p in a_poses] == \
+        [(p["hyp"], p["k"], p["tam"]) for p in b_poses]
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.autotune(rid, reps=0)
+    assert ei.value.code == reloc.E_INVALID
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_deadline_returns_best_so_far(ctx, c1):
+    """deadline_s: the plain path stops with E_TIMEOUT after the stages it
+    has run and returns their ranking."""
+    w, k, hyp = c1
+    _case("deadline plain c1")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    rid = ctx.prepare(m, sid, **_scan(w), n_theta=360, batch_k=1, tau=None, k_out=5,
+                      deadline_s=1e-9)
+    poses, st = ctx.run(rid, allow_timeout=True)
+    assert st["status"] == reloc.E_TIMEOUT
+    assert 0 < st["n_eval"] < len(hyp) and len(poses) == min(5, st["n_eval"])
+    assert st["tam_evals"] == st["n_eval"] * 360
+    # the ranking is that of the evaluated ranks [0, n_eval): T desc, rank asc
+    ne = st["n_eval"]
+    _, ts, ks = ctx.debug_tam(rid, 0, ne, 360, want_T=False)
+    top = np.lexsort((np.arange(ne), -ts.astype(np.float64)))[:5]
+    assert [p["rank"] for p in poses] == [int(r) for r in top]
+    assert [p["k"] for p in poses] == [int(ks[r]) for r in top]
+    assert all(np.float32(p["tam"]) == ts[r] for p, r in zip(poses, top))
+    _cleanup(ctx, m, sid, rid)
+
+
 def test_relocalize_edge_cases(ctx, c1):
     w, k, hyp = c1
     m = ctx.load_map(w.occ, 0.05)
