@@ -71,8 +71,11 @@ def _declare(L):
     L.orc_tam.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
                           f64, f64, f64, f64, i32, vp, vp, vp, i32]
     L.orc_stages.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
-                             f64, f64, f64, f64, i32, vp, vp, i32, f64, vp, vp, vp,
-                             vp, vp, i32]
+                             f64, f64, f64, f64, i32, vp, vp, i32, f64, i32, i32, i32,
+                             vp, vp, vp, vp, vp, vp, i32]
+    L.orc_refine.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
+                             f64, f64, f64, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp,
+                             i32]
     L.orc_sample.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, i32,
                              f64, f64, u64, i32, vp, vp]
     L.orc_num_threads.argtypes = []
@@ -187,8 +190,17 @@ def tam(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_k: np.ndarra
     return out
 
 
+def refine_span(pr: Dict, refine_dirs: int = -1) -> int:
+    """Heading half-width of the refinement lattice in Ng-grid steps (-1:
+    one orientation step, Ng / N_theta)."""
+    return pr["Ng"] // pr["Ntheta"] if refine_dirs < 0 else int(refine_dirs)
+
+
 def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2,
-           z_rand=0.0, d_max=2.0, all_T=False, threads: int = 0) -> Dict:
+           z_rand=0.0, d_max=2.0, all_T=False, threads: int = 0, refine_k: int = 0,
+           refine_cells: int = 3, refine_dirs: int = -1) -> Dict:
+    """Batched multi-stage inference with optional local refinement of each
+    batch's refine_k best poses (Sec. III pipeline text, Remark 2)."""
     kmap = np.ascontiguousarray(kmap, dtype=np.int64)
     H, W = kmap.shape
     hyp = np.ascontiguousarray(hyp_xy, dtype=np.int32).reshape(-1, 2)
@@ -197,6 +209,7 @@ def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2
     order = np.empty(n, dtype=np.int32)
     tstar = np.zeros(n, dtype=np.float64)
     kstar = np.full(n, -1, dtype=np.int32)
+    ref = np.zeros((n, 4), dtype=np.int64)
     info = np.zeros(4, dtype=np.int64)
     allT = np.zeros((n, pr["Ntheta"]), dtype=np.float64) if all_T else None
     lib().orc_stages(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
@@ -204,13 +217,41 @@ def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2
                      pr["k_low"], z_hit, sigma_hit, z_rand, d_max, n, _p(hyp),
                      _p(smad_v), batch_k,
                      float("nan") if tau is None else float(tau),
-                     _p(order), _p(tstar), _p(kstar), _p(info), _p(allT), threads)
+                     int(refine_k), int(refine_cells), refine_span(pr, refine_dirs),
+                     _p(order), _p(tstar), _p(kstar), _p(ref), _p(info), _p(allT), threads)
     ne = int(info[2])
     out = dict(order=order, stages=int(info[0]), early_stopped=bool(info[1]),
-               n_eval=ne, tstar=tstar[:ne], kstar=kstar[:ne])
+               n_eval=ne, tstar=tstar[:ne], kstar=kstar[:ne],
+               refined=ref[:ne, 0].astype(bool), ref_dxy=ref[:ne, 1:3].copy(),
+               ref_g=ref[:ne, 3].copy())
     if all_T:
         out["all_T"] = allT[:ne]
     return out
+
+
+def refine(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_g: np.ndarray,
+           refine_cells: int = 3, refine_dirs: int = -1, z_hit: float = 1.0,
+           sigma_hit: float = 0.2, z_rand: float = 0.0, d_max: float = 2.0,
+           all_T: bool = False, threads: int = 0):
+    """Local refinement of poses (cell xy, heading index g on the Ng grid):
+    refined T, (dx, dy), refined g, and optionally the T of every lattice
+    point in raster order (NaN where not visited)."""
+    kmap = np.ascontiguousarray(kmap, dtype=np.int64)
+    H, W = kmap.shape
+    q_xy = np.ascontiguousarray(q_xy, dtype=np.int32).reshape(-1, 2)
+    q_g = np.ascontiguousarray(q_g, dtype=np.int64)
+    nq = len(q_g)
+    h, s = int(refine_cells), refine_span(pr, refine_dirs)
+    L = (2 * s + 1) * (2 * h + 1) ** 2
+    T = np.empty(nq, dtype=np.float64)
+    dxy = np.empty((nq, 2), dtype=np.int32)
+    g = np.empty(nq, dtype=np.int64)
+    allv = np.empty((nq, L), dtype=np.float64) if all_T else None
+    lib().orc_refine(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
+                     _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
+                     pr["k_low"], z_hit, sigma_hit, z_rand, d_max, h, s, nq, _p(q_xy),
+                     _p(q_g), _p(T), _p(dxy), _p(g), _p(allv), threads)
+    return (T, dxy, g, allv) if all_T else (T, dxy, g)
 
 
 def sample(occ: np.ndarray, kmap: np.ndarray, res: float, origin=(0.0, 0.0),
@@ -248,7 +289,8 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
                d_max: float = 2.0, n_skip_beam: int = 1, n_skip_enum: int = 1,
                alpha_mid_pm=(900, 700), alpha_low_pm=(700, 500), thr: int = 65,
                kmap: Optional[np.ndarray] = None, threads: int = 0,
-               keep: bool = False) -> Dict:
+               keep: bool = False, refine_k: int = 0, refine_cells: int = 3,
+               refine_dirs: int = -1) -> Dict:
     """The whole hot path, step by step, in the paper's order."""
     if kmap is None:
         kmap = edt(occ, thr)
@@ -260,7 +302,8 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
                         threads=threads)
     sm, am = smad(zhat, pr, threads=threads)
     st = stages(kmap, res, pr, hyp_xy, sm, batch_k, tau, z_hit, sigma_hit, z_rand,
-                d_max, threads=threads)
+                d_max, threads=threads, refine_k=refine_k, refine_cells=refine_cells,
+                refine_dirs=refine_dirs)
     ne = st["n_eval"]
     ranks = np.arange(ne)
     rank_order = np.lexsort((ranks, -st["tstar"]))     # T desc, rank asc
@@ -269,15 +312,22 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
     for r in rank_order[:k_out]:
         h = int(st["order"][r])
         k = int(st["kstar"][r])
-        poses.append(dict(x=origin[0] + (hyp[h, 0] + 0.5) * res,
-                          y=origin[1] + (hyp[h, 1] + 0.5) * res,
-                          theta=heading(k, pr["Ntheta"]), tam=float(st["tstar"][r]),
+        cx = int(hyp[h, 0] + st["ref_dxy"][r, 0])
+        cy = int(hyp[h, 1] + st["ref_dxy"][r, 1])
+        g = int(st["ref_g"][r])
+        poses.append(dict(x=origin[0] + (cx + 0.5) * res,
+                          y=origin[1] + (cy + 0.5) * res,
+                          theta=(heading(g, pr["Ng"]) if st["refined"][r]
+                                 else heading(k, pr["Ntheta"])),
+                          tam=float(st["tstar"][r]),
                           smad=float(sm[h]), hyp=h, k=k, rank=int(r),
-                          stage=int(r) // batch_k))
+                          stage=int(r) // batch_k, cx=cx, cy=cy, g=g,
+                          refined=bool(st["refined"][r])))
     out = dict(poses=poses, prep=pr, stages=st["stages"],
                early_stopped=st["early_stopped"], n_eval=ne,
                smad_evals=len(sm) * pr["n_shifts"], tam_evals=ne * pr["Ntheta"])
     if keep:
         out.update(hit=hit, zhat=zhat, smad=sm, argm=am, order=st["order"],
-                   tstar=st["tstar"], kstar=st["kstar"], kmap=kmap)
+                   tstar=st["tstar"], kstar=st["kstar"], kmap=kmap,
+                   refined=st["refined"], ref_dxy=st["ref_dxy"], ref_g=st["ref_g"])
     return out

@@ -480,13 +480,16 @@ struct TamCtx {
   double z_hit, sigma, z_rand, d_max;
 };
 
-static void tam_eval(const TamCtx& c, int ix, int iy, int k, double* out,
+// The heading is given as its index g on the Ng direction grid: heading
+// theta_k of eq. 22 is g = o*k; the local refinement below also visits the
+// headings between them.
+static void tam_eval(const TamCtx& c, int ix, int iy, i64 g, double* out,
                      std::vector<double>& l, std::vector<double>& d) {
   const i64 X = 256 * (i64)ix + 128, Y = 256 * (i64)iy + 128;
-  const int b = c.Ng / c.Ns, o = c.Ng / c.Nt;
+  const int b = c.Ng / c.Ns;
   l.resize(c.nv); d.resize(c.nv);
   for (int v = 0; v < c.nv; ++v) {
-    const i64 t = ((i64)b * c.vj[v] + (i64)o * k) % c.Ng;
+    const i64 t = ((i64)b * c.vj[v] + g) % c.Ng;
     const i64 ex = floor_div(X * (1LL << 20) + (i64)c.vzq[v] * c.U[2 * t], 1LL << 28);
     const i64 ey = floor_div(Y * (1LL << 20) + (i64)c.vzq[v] * c.U[2 * t + 1], 1LL << 28);
     double dist;
@@ -542,7 +545,84 @@ int orc_tam(int W, int H, const i64* kmap, double res, int Ns, int Nt,
     std::vector<double> l, d;
 #pragma omp for schedule(dynamic, 16)
     for (int i = 0; i < nq; ++i)
-      tam_eval(c, q_xy[2 * i], q_xy[2 * i + 1], q_k[i], out + 8 * (size_t)i, l, d);
+      tam_eval(c, q_xy[2 * i], q_xy[2 * i + 1], (Ng / Nt) * (i64)q_k[i], out + 8 * (size_t)i,
+               l, d);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Local refinement of a pose (Sec. III pipeline text: the top-k poses of a
+// batch are refined by a local operator G and re-evaluated with TAM; Remark
+// 2 names ICP as one such G). The paper fixes neither the operator nor its
+// parameters. Reading used here: G is an exhaustive TAM search over the
+// lattice of poses next to the pose (cell (ix, iy), heading index g0 on the
+// Ng direction grid):
+//   cells (ix + dx, iy + dy), |dx|, |dy| <= h; headings g0 + dg (mod Ng),
+//   |dg| <= s; raster index q = ((dg + s)(2h + 1) + dy + h)(2h + 1) + dx + h.
+// Lattice cells other than the pose's own cell that lie off the map or are
+// occupied (EDT k == 0) are not visited, at any heading. The refined pose
+// maximises T; among equal T the pose itself wins, then the smaller raster
+// index.
+// Because the pose itself is a lattice point, the refined T is never below
+// its unrefined T.
+// all (optional): [L] the T of every lattice point in raster order, NaN for
+// the cells not visited.
+// ---------------------------------------------------------------------------
+static void refine_one(const TamCtx& c, int ix, int iy, i64 g0, int h, int s, double* bestT,
+                       int* bdx, int* bdy, i64* bg, double* all, std::vector<double>& l,
+                       std::vector<double>& d) {
+  const int w = 2 * h + 1;
+  double out[8];
+  double best = 0.0;
+  i64 bkey = -1;
+  for (int dg = -s; dg <= s; ++dg)
+    for (int dy = -h; dy <= h; ++dy)
+      for (int dx = -h; dx <= h; ++dx) {
+        const i64 q = ((i64)(dg + s) * w + (dy + h)) * w + (dx + h);
+        const bool own = dx == 0 && dy == 0, centre = own && dg == 0;
+        const int x = ix + dx, y = iy + dy;
+        if (!own && (x < 0 || x >= c.W || y < 0 || y >= c.H || c.kmap[(i64)y * c.W + x] == 0)) {
+          if (all) all[q] = std::numeric_limits<double>::quiet_NaN();
+          continue;
+        }
+        const i64 g = ((g0 + dg) % c.Ng + c.Ng) % c.Ng;
+        tam_eval(c, x, y, g, out, l, d);
+        if (all) all[q] = out[0];
+        const i64 key = centre ? 0 : q + 1;
+        if (bkey < 0 || out[0] > best || (out[0] == best && key < bkey)) {
+          best = out[0];
+          bkey = key;
+          *bdx = dx;
+          *bdy = dy;
+          *bg = g;
+        }
+      }
+  *bestT = best;
+}
+
+// Refinement of nq poses (cell q_xy, heading index q_g on the Ng grid).
+int orc_refine(int W, int H, const i64* kmap, double res, int Ns, int Nt,
+               int nv, const int32_t* vj, const int32_t* vzq, i64 kfull, i64 kmid, i64 klow,
+               double z_hit, double sigma, double z_rand, double d_max, int h, int s,
+               int nq, const int32_t* q_xy, const i64* q_g, double* T, int32_t* dxy, i64* g,
+               double* all, int threads) {
+  const i64 Ng = (i64)Ns / gcd64(Ns, Nt) * Nt;
+  std::vector<int32_t> U(2 * (size_t)Ng);
+  orc_dirs((int)Ng, U.data());
+  TamCtx c{W, H, kmap, res, Ns, Nt, (int)Ng, U.data(), nv, vj, vzq, kfull, kmid, klow,
+           z_hit, sigma, z_rand, d_max};
+  const size_t L = (size_t)(2 * s + 1) * (2 * h + 1) * (2 * h + 1);
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#endif
+#pragma omp parallel
+  {
+    std::vector<double> l, d;
+#pragma omp for schedule(dynamic, 1)
+    for (int i = 0; i < nq; ++i)
+      refine_one(c, q_xy[2 * i], q_xy[2 * i + 1], q_g[i], h, s, T + i, dxy + 2 * i,
+                 dxy + 2 * i + 1, g + i, all ? all + L * i : nullptr, l, d);
   }
   return 0;
 }
@@ -554,18 +634,23 @@ int orc_tam(int W, int H, const i64* kmap, double res, int Ns, int Nt,
 //   per hypothesis theta* = argmax_k T (ties: smallest k) (eq. 22);
 //   batch best T*_b = max over the batch (ties: earlier rank); stop when
 //   T*_b > tau (tau NaN: never); otherwise continue until exhausted.
-// The local refinement (ICP) between TAM and the threshold test is not part
-// of this path: the threshold is tested on the unrefined batch best.
-// Outputs per rank r < n_eval: hyp[r] = pi[r], tstar[r], kstar[r];
+// Local refinement (kr > 0): after a batch's TAM, its kr best hypotheses by
+// (T* desc, rank asc) are refined by refine_one around (cell, o*k*) and
+// their T* replaced by the refined T before the batch best is taken, so the
+// threshold is tested on the best re-evaluated T. With kr == 0 the threshold
+// is tested on the unrefined batch best.
+// Outputs per rank r < n_eval: hyp[r] = pi[r], tstar[r] (refined T where
+// refined), kstar[r]; ref[4r..4r+3] = (refined 1/0, dx, dy, heading index g
+// on the Ng grid) with (0, 0, 0, o*k*) for unrefined ranks;
 // stage_info: [0] stages run, [1] stopped early (1/0), [2] n_eval.
-// all_T (optional): [n_eval][Nt] every TAM value, rank-major.
+// all_T (optional): [n_eval][Nt] every (unrefined) TAM value, rank-major.
 // ---------------------------------------------------------------------------
 int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
                int nv, const int32_t* vj, const int32_t* vzq, i64 kfull, i64 kmid, i64 klow,
                double z_hit, double sigma, double z_rand, double d_max,
                int n_hyp, const int32_t* hyp_xy, const double* smad, int K, double tau,
-               int32_t* order, double* tstar, int32_t* kstar, i64* stage_info,
-               double* all_T, int threads) {
+               int kr, int rh, int rs, int32_t* order, double* tstar, int32_t* kstar,
+               i64* ref, i64* stage_info, double* all_T, int threads) {
   std::vector<int32_t> pi(n_hyp);
   std::iota(pi.begin(), pi.end(), 0);
   std::stable_sort(pi.begin(), pi.end(), [&](int32_t a, int32_t b) {
@@ -593,12 +678,39 @@ int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
         double best = 0.0;
         int bk = -1;
         for (int k = 0; k < Nt; ++k) {
-          tam_eval(c, hyp_xy[2 * h], hyp_xy[2 * h + 1], k, out, l, d);
+          tam_eval(c, hyp_xy[2 * h], hyp_xy[2 * h + 1], (Ng / Nt) * (i64)k, out, l, d);
           if (all_T) all_T[(size_t)r * Nt + k] = out[0];
           if (bk < 0 || out[0] > best) { best = out[0]; bk = k; }
         }
         tstar[r] = best;
         kstar[r] = bk;
+      }
+    }
+    const i64 o = Ng / Nt;
+    for (int r = b0; r < b1; ++r) {
+      ref[4 * r] = 0; ref[4 * r + 1] = 0; ref[4 * r + 2] = 0;
+      ref[4 * r + 3] = o * kstar[r];
+    }
+    if (kr > 0) {
+      std::vector<int> sel(b1 - b0);
+      std::iota(sel.begin(), sel.end(), b0);
+      std::stable_sort(sel.begin(), sel.end(), [&](int a, int b2) { return tstar[a] > tstar[b2]; });
+      const int nsel = std::min(kr, b1 - b0);
+#pragma omp parallel
+      {
+        std::vector<double> l, d;
+#pragma omp for schedule(dynamic, 1)
+        for (int j = 0; j < nsel; ++j) {
+          const int r = sel[j];
+          const int hh = pi[r];
+          double T;
+          int dx = 0, dy = 0;
+          i64 g = 0;
+          refine_one(c, hyp_xy[2 * hh], hyp_xy[2 * hh + 1], o * kstar[r], rh, rs, &T, &dx, &dy,
+                     &g, nullptr, l, d);
+          tstar[r] = T;
+          ref[4 * r] = 1; ref[4 * r + 1] = dx; ref[4 * r + 2] = dy; ref[4 * r + 3] = g;
+        }
       }
     }
     ++stages;
