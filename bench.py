@@ -385,6 +385,10 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
     ap.add_argument("--max-admit", type=int, default=16)
+    ap.add_argument("--refine-k", type=int, default=0,
+                    help="plain workloads: poses refined per stage (local TAM lattice search)")
+    ap.add_argument("--refine-cells", type=int, default=3,
+                    help="refinement lattice half-width in cells")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -428,7 +432,8 @@ def main():
     hyp = ctx.read_hypotheses(sid)
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
                       w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
-                      variant=args.variant)
+                      variant=args.variant, refine_k=args.refine_k,
+                      refine_cells=args.refine_cells)
     tuned = None
     if args.variant == 0:
         # the ray-cast launch shape is picked on this GPU for this request
@@ -500,7 +505,9 @@ def main():
                                 "360 beams, 1 deg TAM, top-10 per stage") if small else
                                ("plain-large: warehouse 2000x2000 @0.05 m, 20000 hypotheses, "
                                 "270 deg 720 beams, 0.5 deg TAM, top-64 per stage"),
-                   "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k},
+                   "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k,
+                   "refine_k": args.refine_k,
+                   "refine_cells": args.refine_cells if args.refine_k else None},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
@@ -508,8 +515,10 @@ def main():
                      "device_ms": float(np.mean(tot_ms)), "raycast_ms": float(np.mean(ray_ms)),
                      "smad_ms": float(np.mean(smad_ms)),
                      "tam_ms": float(np.mean(tam_ms)), "rays": st["rays"],
-                     "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"]},
-        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
+                     "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"],
+                     "refined": st["refined"], "refine_points": st["refine_points"]},
+        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k", "g",
+                                               "refined")},
         "true_pose": list(w.pose),
         "roofline": roofline,
         "autotune": tuned,

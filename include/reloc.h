@@ -199,6 +199,21 @@ typedef struct {
                              distance skipping with wavefront ray refill once 1, 8,
                              16, 32 lanes are idle. Every variant gives
                              bit-identical results. */
+  /* Local refinement (Sec. III pipeline: the top-k poses of each batch are
+   * refined by a local operator and re-evaluated with TAM before the
+   * threshold test; Remark 2). The operator here is an exhaustive TAM
+   * search over the lattice of poses next to the pose: cells (ix + dx,
+   * iy + dy) with |dx|, |dy| <= refine_cells, headings g* + dg on the Ng
+   * direction grid (heading index g = g* + dg mod Ng, theta = 2 pi g / Ng)
+   * with |dg| <= refine_dirs, g* = (Ng / N_theta) k*. Lattice cells other
+   * than the pose's own that are off the map or occupied are skipped. The
+   * refined pose has the largest T; ties go to the pose itself, then to the
+   * smaller raster index ((dg + s)(2h + 1) + dy + h)(2h + 1) + dx + h. The
+   * refined T replaces the pose's T in the batch best and the ranking. */
+  int32_t refine_k;       /* poses refined per batch (0: none; <= 64) */
+  int32_t refine_cells;   /* h, lattice half-width in cells (3; <= 15) */
+  int32_t refine_dirs;    /* s, heading half-width in Ng steps (-1: Ng / N_theta);
+                             the lattice (2s + 1)(2h + 1)^2 holds <= 65536 points */
 } reloc_search_params;
 
 /* Fills the defaults listed above. */
@@ -220,14 +235,18 @@ typedef struct {
 int32_t reloc_scan_info_get(const reloc_scan* scan, const reloc_search_params* params,
                             double resolution, reloc_scan_info* out);
 
-/* One ranked pose hypothesis (eq. 8-9). x, y: world cell centre; theta:
- * heading k * 2*pi / N_theta wrapped to [-pi, pi); tam: T (eq. 31) at
- * theta*; smad: SMAD(p) (eq. 20) as FP32; hyp: index in the set; k:
- * orientation index; rank: position in the SMAD order; stage: batch index. */
+/* One ranked pose hypothesis (eq. 8-9). x, y: world centre of cell (cx,
+ * cy); theta: heading wrapped to [-pi, pi), k * 2*pi / N_theta, or g * 2*pi
+ * / Ng for a refined pose; tam: T (eq. 31) at that pose; smad: SMAD(p) (eq.
+ * 20) of the hypothesis as FP32; hyp: index in the set; k: orientation
+ * index (-1 for a refined pose); rank: position in the SMAD order; stage:
+ * batch index; g: heading index on the Ng direction grid; refined: 1 when
+ * the pose came out of the local refinement. */
 typedef struct {
   double x, y, theta;
   float tam, smad;
   int32_t hyp, k, rank, stage;
+  int32_t cx, cy, g, refined;
 } reloc_pose;
 
 typedef struct {
@@ -237,9 +256,12 @@ typedef struct {
   int64_t tam_lookups;  /* tam_evals x N'_Z */
   int32_t n_hyp, stages, early_stopped, n_eval;
   /* device time (hipEvents on the context's stream): whole run; ray-cast
-   * kernel; SMAD kernel; SMAD order; TAM stages with stage control;
-   * ranking and result copy */
+   * kernel; SMAD kernel; SMAD order; TAM stages with refinement and stage
+   * control; ranking and result copy */
   float ms_total, ms_raycast, ms_sort, ms_tam, ms_rank, ms_smad;
+  /* local refinement: poses refined; lattice points considered (refined
+   * poses x (2s + 1)(2h + 1)^2, skipped cells included) */
+  int64_t refined, refine_points;
 } reloc_stats;
 
 /* ------------------------------------------------------------------------
@@ -249,8 +271,9 @@ typedef struct {
  * reloc_run then executes the whole hot path on the device:
  *   ray cast + SMAD for every hypothesis -> stable sort by (SMAD, index) ->
  *   stages of batch_k hypotheses: TAM over N_theta orientations, theta* per
- *   hypothesis (ties: smallest k), batch best (ties: earlier rank), stop when
- *   it exceeds tau -> all evaluated poses ranked by (T desc, rank asc).
+ *   hypothesis (ties: smallest k), local refinement of the batch's refine_k
+ *   best poses (optional), batch best (ties: earlier rank), stop when it
+ *   exceeds tau -> all evaluated poses ranked by (T desc, rank asc).
  * out: host reloc_pose[cap]; *n_out = min(cap, k_out, evaluated).
  * stats may be NULL.
  * ---------------------------------------------------------------------- */

@@ -51,7 +51,9 @@ class reloc_search_params(C.Structure):
                 ("tau", C.c_double), ("n_hyp", C.c_int32), ("z_hit", C.c_double),
                 ("sigma_hit", C.c_double), ("z_rand", C.c_double), ("d_max", C.c_double),
                 ("alpha_mid_pm", C.c_int32 * 2), ("alpha_low_pm", C.c_int32 * 2),
-                ("deadline_s", C.c_double), ("variant", C.c_int32)]
+                ("deadline_s", C.c_double), ("variant", C.c_int32),
+                ("refine_k", C.c_int32), ("refine_cells", C.c_int32),
+                ("refine_dirs", C.c_int32)]
 
 
 class reloc_scan_info(C.Structure):
@@ -64,7 +66,9 @@ class reloc_scan_info(C.Structure):
 class reloc_pose(C.Structure):
     _fields_ = [("x", C.c_double), ("y", C.c_double), ("theta", C.c_double),
                 ("tam", C.c_float), ("smad", C.c_float), ("hyp", C.c_int32),
-                ("k", C.c_int32), ("rank", C.c_int32), ("stage", C.c_int32)]
+                ("k", C.c_int32), ("rank", C.c_int32), ("stage", C.c_int32),
+                ("cx", C.c_int32), ("cy", C.c_int32), ("g", C.c_int32),
+                ("refined", C.c_int32)]
 
 
 class reloc_stats(C.Structure):
@@ -73,7 +77,8 @@ class reloc_stats(C.Structure):
                 ("early_stopped", C.c_int32), ("n_eval", C.c_int32),
                 ("ms_total", C.c_float), ("ms_raycast", C.c_float), ("ms_sort", C.c_float),
                 ("ms_tam", C.c_float), ("ms_rank", C.c_float),
-                ("ms_smad", C.c_float)]
+                ("ms_smad", C.c_float), ("refined", C.c_int64),
+                ("refine_points", C.c_int64)]
 
 
 class reloc_serve_config(C.Structure):

@@ -29,7 +29,7 @@ namespace reloc {
 
 namespace {
 
-constexpr int kMaxSpec = 32;          // stages of one request in one tick, at most
+constexpr int kMaxSpec = kMaxTickStages;
 constexpr int64_t kTickBlocks = 65536;  // TAM workgroups one tick may grant beyond one stage each
 
 // Contiguous buffers of one front-phase group: SMAD sort keys / values, the
@@ -346,6 +346,19 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     HIP_TRY(launch_tam_batch(k, (const TamArgs*)(d + o_items[k]), (const int64_t*)(d + o_pre[k]),
                              (int)items[k].size(), blocks[k], lds[k], s));
   }
+  // local refinement of each stage's best poses, per refining request
+  for (Flight* f : live) {
+    Request& R = c->reqs.at(f->rid);
+    const int kr = R.prm.refine_k;
+    if (kr <= 0) continue;
+    RefineArgs fa = refine_args(c, R, f->tstages * kr);
+    fa.t.order = f->arena->order + f->off;
+    fa.t.best = f->arena->best + f->off;
+    HIP_TRY(launch_refine_select(fa.t.best, f->next_rank, R.prm.batch_k, R.n_hyp, f->tstages,
+                                 kr, R.rsel, R.rbest, s));
+    HIP_TRY(launch_refine(fa, s));
+    HIP_TRY(launch_refine_commit(fa, s));
+  }
   HIP_TRY(launch_stage_reduce_batch((const StageArgs*)(d + o_st), (int)st.size(), s));
   HIP_TRY(hipMemcpyAsync(S.hflag, S.dflag, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(c->ev[4], s));
@@ -454,6 +467,11 @@ void fill_stats(const Request& R, const Flight& f, const PhaseTimes& pt, float t
   st->ms_sort = pt.sort;
   st->ms_tam = pt.tam;
   st->ms_rank = pt.rank;
+  const int kr = R.prm.refine_k, K = R.prm.batch_k;
+  if (kr > 0) {
+    for (int b = 0; b < f.stages; ++b) st->refined += std::min(kr, std::min(K, R.n_hyp - b * K));
+    st->refine_points = st->refined * R.ref_L;
+  }
 }
 
 // ---- serving worker --------------------------------------------------------

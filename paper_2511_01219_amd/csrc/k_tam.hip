@@ -41,16 +41,84 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// One workgroup's work: rank a.r0 + i, orientations [16 kb, 16 kb + 16);
-// wavefront w takes orientations 16 kb + w + 4 g, g = 0..3.
+// The 16 poses of one workgroup come from a pose source: has(j) tells
+// whether pose j of the tile is evaluated, pose(j) gives its Q20 origin and
+// heading direction index (false when it is not evaluated), tie(j) the low
+// word that orders equal T in
+// the atomic max (larger wins), record(j, T) an optional per-pose output,
+// and dst the packed (T bits, tie) word the tile's best is folded into.
 //
-// Per (p, theta) the valid beams are spread over the lanes, SB per lane at a
+// Orientation tile: hypothesis cell (X20, Y20), orientations [k0, k0 + 16)
+// of eq. 22, heading index o k on the Ng grid; ties go to the smaller k.
+struct ThetaSrc {
+  static constexpr bool kPrefix = true;   // the evaluated poses are a prefix
+  int64_t X20, Y20;
+  int k0, Nt, o, Ng;
+  float* T_row;           // optional [Nt]
+  uint64_t* dst;
+  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+    const int k = k0 + j;
+    if (k >= Nt) return false;
+    x = X20;
+    y = Y20;
+    ok = (int)(((int64_t)o * k) % Ng);
+    return true;
+  }
+  __device__ __forceinline__ bool has(int j) const { return k0 + j < Nt; }
+  __device__ __forceinline__ uint32_t tie(int j) const { return 0xFFFFFFFFu - (uint32_t)(k0 + j); }
+  __device__ __forceinline__ void record(int j, float T) const {
+    if (T_row) T_row[k0 + j] = T;
+  }
+};
+
+// Refinement lattice tile: points [q0, q0 + 16) of the lattice around the
+// pose (cell (ix, iy), heading index g0): q = ((dg + s) w + dy + h) w + dx + h,
+// w = 2h + 1. Cells other than the pose's own that lie off the map or are
+// occupied (k == 0) are not evaluated. Ties go to the pose itself (q = qc),
+// then to the smaller q.
+struct LatticeSrc {
+  static constexpr bool kPrefix = false;
+  int ix, iy, g0, h, s, w, L, q0, W, H, Ng;
+  const uint32_t* kmap;
+  uint64_t* dst;
+  __device__ __forceinline__ bool has(int j) const {
+    const int q = q0 + j;
+    if (q >= L) return false;
+    const int t = q / w;
+    const int dx = q - t * w - h, dy = t % w - h;
+    if (dx == 0 && dy == 0) return true;
+    const int cx = ix + dx, cy = iy + dy;
+    if ((uint32_t)cx >= (uint32_t)W || (uint32_t)cy >= (uint32_t)H) return false;
+    return kmap[(size_t)cy * (size_t)W + (size_t)cx] != 0u;
+  }
+  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+    if (!has(j)) return false;
+    const int q = q0 + j, t = q / w;
+    const int dx = q - t * w - h, dy = t % w - h, dg = t / w - s;
+    const int cx = ix + dx, cy = iy + dy;
+    x = (int64_t)(256 * cx + 128) * (int64_t)(1 << 20);
+    y = (int64_t)(256 * cy + 128) * (int64_t)(1 << 20);
+    int g = (g0 + dg) % Ng;
+    ok = g < 0 ? g + Ng : g;
+    return true;
+  }
+  __device__ __forceinline__ uint32_t tie(int j) const {
+    const int q = q0 + j, qc = (s * w + h) * w + h;
+    return 0xFFFFFFFFu - (uint32_t)(q == qc ? 0 : q + 1);
+  }
+  __device__ __forceinline__ void record(int, float) const {}
+};
+
+// One workgroup's work: the 16 poses of a tile; wavefront w takes poses
+// w + 4 g, g = 0..3.
+//
+// Per pose the valid beams are spread over the lanes, SB per lane at a
 // time: all SB direction loads, then all SB EDT gathers, are issued before
-// any is used. The per-orientation integer sums are parked in lane g; the
-// FP64 tail (eq. 27-31) then runs once for the four orientations in lanes
-// 0..3, and one atomic max per wavefront publishes the best (T, ~k).
-template <int R, int KB>
-__device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
+// any is used. The per-pose integer sums are parked in lane g; the FP64 tail
+// (eq. 27-31) then runs once for the four poses in lanes 0..3, and one
+// atomic max per wavefront publishes the best (T, tie).
+template <int R, int KB, class Src>
+__device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32_t* smem) {
   constexpr int SB = R >= 32 ? 8 : 4;  // keys per lane in flight together
   constexpr int G = THETA_PER_BLOCK / NW;
   int2* sbz = (int2*)smem;            // [nvp] (direction base, Q8 range)
@@ -61,25 +129,23 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   static_assert(64 * SB <= kTamBeamPad, "gather batch beyond the beam padding");
   const int nvp = tam_beams_padded(nv);
   for (int v = tid; v < nvp; v += TB) sbz[v] = a.beams[v];
-  const int r = a.r0 + i;
-  const int hyp = a.order[r];
-  const int64_t X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
-  const int64_t Y20 = (int64_t)(256 * a.hyp_xy[2 * hyp + 1] + 128) * (int64_t)(1 << 20);
-  const int k0 = kb * THETA_PER_BLOCK;
   __syncthreads();
 
-  // per-orientation results parked in lane g
+  // per-pose results parked in lane g
   int64_t p_sl = 0;
   uint64_t p_sumk = 0, p_sumsq = 0;
   int p_noff = 0;
 
   for (int g = 0; g < G; ++g) {
-    const int k = k0 + wv + NW * g;
-    if (k >= a.Nt) break;                       // wavefront-uniform
+    int64_t X20, Y20;
+    int ok;
+    if (!src.pose(wv + NW * g, X20, Y20, ok)) {         // wavefront-uniform
+      if (Src::kPrefix) break;
+      continue;
+    }
     uint32_t keys[R];
     uint64_t sumk = 0, sumsq = 0;
     int noff = 0;
-    const int ok = (int)(((int64_t)a.o * k) % a.Ng);
 #pragma unroll
     for (int i0 = 0; i0 < R; i0 += SB) {
       if (64 * i0 < nv) {                       // wavefront-uniform
@@ -165,9 +231,9 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
       p_noff = noff;
     }
   }
-  // FP64 tail for the parked orientations, one per lane
-  const int k = k0 + wv + NW * lane;
-  const bool mine = lane < G && k < a.Nt;
+  // FP64 tail for the parked poses, one per lane
+  const int j = wv + NW * lane;
+  const bool mine = lane < G && src.has(j);
   uint64_t packed = 0;
   if (mine) {
     const double Lbar = (double)p_sl / (67108864.0 * (double)a.kmid);
@@ -183,14 +249,31 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
     const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
     const double c = exp(-0.5 * var);
     const float T = (float)cbrt(Pl * sd * c);
-    if (a.T_out) a.T_out[(size_t)i * a.Nt + k] = T;
-    packed = ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+    src.record(j, T);
+    packed = ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)src.tie(j);
   }
   for (int off = G / 2; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(packed, off, 64);
     packed = o > packed ? o : packed;
   }
-  if (lane == 0 && packed) atomicMax((unsigned long long*)&a.best[r], (unsigned long long)packed);
+  if (lane == 0 && packed) atomicMax((unsigned long long*)src.dst, (unsigned long long)packed);
+}
+
+// Orientation tile kb of rank a.r0 + i.
+template <int R, int KB>
+__device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
+  const int r = a.r0 + i;
+  const int hyp = a.order[r];
+  ThetaSrc src;
+  src.X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
+  src.Y20 = (int64_t)(256 * a.hyp_xy[2 * hyp + 1] + 128) * (int64_t)(1 << 20);
+  src.k0 = kb * THETA_PER_BLOCK;
+  src.Nt = a.Nt;
+  src.o = a.o;
+  src.Ng = a.Ng;
+  src.T_row = a.T_out ? a.T_out + (size_t)i * a.Nt : nullptr;
+  src.dst = &a.best[r];
+  tam_tile<R, KB>(a, src, smem);
 }
 
 // Workgroup b of an n-workgroup grid runs on XCD b % 8 (round-robin
@@ -209,6 +292,116 @@ __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   const int L = xcd_slice(blockIdx.x, gridDim.x);
   tam_block<R, KB>(a, L / ntb, L % ntb, smem);
+}
+
+// Local refinement, lattice tiles: workgroup b covers slot b / tiles and
+// lattice points [16 (b % tiles), + 16) around that slot's rank (its cell
+// and heading o k*, k* read from the rank's packed TAM best).
+template <int R, int KB>
+__global__ __launch_bounds__(TB) void refine_kernel(RefineArgs a) {
+  extern __shared__ int32_t smem[];
+  const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  const int b = xcd_slice(blockIdx.x, gridDim.x);
+  const int slot = b / tiles, tile = b - slot * tiles;
+  const int r = a.sel[slot];
+  if (r < 0) return;                           // workgroup-uniform
+  const TamArgs& t = a.t;
+  const int hyp = t.order[r];
+  const int kstar = (int)(0xFFFFFFFFu - (uint32_t)(t.best[r] & 0xFFFFFFFFu));
+  LatticeSrc src;
+  src.ix = t.hyp_xy[2 * hyp];
+  src.iy = t.hyp_xy[2 * hyp + 1];
+  src.g0 = (int)(((int64_t)t.o * kstar) % t.Ng);
+  src.h = a.h;
+  src.s = a.s;
+  src.w = 2 * a.h + 1;
+  src.L = a.L;
+  src.q0 = tile * THETA_PER_BLOCK;
+  src.W = t.W;
+  src.H = t.H;
+  src.Ng = t.Ng;
+  src.kmap = t.kmap;
+  src.dst = &a.rbest[slot];
+  tam_tile<R, KB>(t, src, smem);
+}
+
+// Refinement selection, one workgroup per stage b: the kr best ranks of
+// [r0 + b K, min(r0 + (b + 1) K, n)) by (T desc, rank asc), found as kr
+// successive maxima of the unique key (T bits, ~rank) below the previous
+// one; slot b kr + j gets the j-th (or -1) and its lattice best is cleared.
+__global__ __launch_bounds__(TB) void refine_select_kernel(const uint64_t* __restrict__ best,
+                                                           int r0, int K, int n, int kr,
+                                                           int32_t* __restrict__ sel,
+                                                           uint64_t* __restrict__ rbest) {
+  __shared__ unsigned long long red[NW];
+  __shared__ unsigned long long prev_s;
+  const int lo = r0 + (int)blockIdx.x * K, hi = min(lo + K, n);
+  unsigned long long prev = ~0ull;
+  for (int j = 0; j < kr; ++j) {
+    unsigned long long m = 0;
+    for (int r = lo + (int)threadIdx.x; r < hi; r += TB) {
+      const unsigned long long key =
+          ((best[r] >> 32) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)r);
+      if (key < prev && key > m) m = key;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(m, off, 64);
+      if (o > m) m = o;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < NW; ++q)
+        if (red[q] > m) m = red[q];
+      const int slot = (int)blockIdx.x * kr + j;
+      sel[slot] = m ? (int)(0xFFFFFFFFu - (uint32_t)(m & 0xFFFFFFFFu)) : -1;
+      rbest[slot] = 0;
+      prev_s = m;
+    }
+    __syncthreads();
+    prev = prev_s;
+  }
+}
+
+// Folds each slot's lattice best into its rank's packed word: (T bits,
+// code), code = g << 10 | (dy + 15) << 5 | (dx + 15) with bit 31 clear, so
+// the ranking kernels (which report ~low) give refined poses a negative k.
+__global__ void refine_commit_kernel(RefineArgs a) {
+  const int slot = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (slot >= a.n_slots) return;
+  const int r = a.sel[slot];
+  if (r < 0) return;
+  const uint64_t v = a.rbest[slot];
+  if (v == 0) return;
+  const uint32_t tie = 0xFFFFFFFFu - (uint32_t)(v & 0xFFFFFFFFu);
+  const int w = 2 * a.h + 1, qc = (a.s * w + a.h) * w + a.h;
+  const int q = tie == 0u ? qc : (int)tie - 1;
+  const int t = q / w;
+  const int dx = q - t * w - a.h, dy = t % w - a.h, dg = t / w - a.s;
+  const int kstar = (int)(0xFFFFFFFFu - (uint32_t)(a.t.best[r] & 0xFFFFFFFFu));
+  int g = (int)(((int64_t)a.t.o * kstar + dg) % a.t.Ng);
+  if (g < 0) g += a.t.Ng;
+  const uint32_t code = ((uint32_t)g << 10) | ((uint32_t)(dy + 15) << 5) | (uint32_t)(dx + 15);
+  a.t.best[r] = (v & 0xFFFFFFFF00000000ull) | (uint64_t)code;
+}
+
+template <int R, int KB>
+hipError_t launch_refine_t(const RefineArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)tam_beams_padded(a.t.nv) * sizeof(int2);
+  const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  hipLaunchKernelGGL((refine_kernel<R, KB>), dim3(tiles * a.n_slots), dim3(TB), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_refine_kb(const RefineArgs& a, hipStream_t s) {
+  const int R = (a.t.nv + 63) / 64;
+  if (R <= 4) return launch_refine_t<4, KB>(a, s);
+  if (R <= 8) return launch_refine_t<8, KB>(a, s);
+  if (R <= 16) return launch_refine_t<16, KB>(a, s);
+  if (R <= 32) return launch_refine_t<32, KB>(a, s);
+  if (R <= 64) return launch_refine_t<64, KB>(a, s);
+  return hipErrorInvalidValue;
 }
 
 // Index of the segment holding item t: prefix[e] <= t < prefix[e + 1].
@@ -383,6 +576,30 @@ hipError_t launch_tam(const TamArgs& a, hipStream_t s) {
   if (a.keybits <= 12) return launch_tam_kb<12>(a, s);
   if (a.keybits <= 16) return launch_tam_kb<16>(a, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_refine_select(const uint64_t* best, int r0, int K, int n, int ns, int kr,
+                                int32_t* sel, uint64_t* rbest, hipStream_t s) {
+  if (ns <= 0 || kr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_select_kernel, dim3(ns), dim3(TB), 0, s, best, r0, K, n, kr, sel,
+                     rbest);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(const RefineArgs& a, hipStream_t s) {
+  if (a.n_slots <= 0) return hipSuccess;
+  const int w = 2 * a.h + 1;
+  if (a.h < 0 || a.h > 15 || a.s < 0 || a.s >= a.t.Ng || a.L != (2 * a.s + 1) * w * w)
+    return hipErrorInvalidValue;
+  if (a.t.keybits <= 12) return launch_refine_kb<12>(a, s);
+  if (a.t.keybits <= 16) return launch_refine_kb<16>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_refine_commit(const RefineArgs& a, hipStream_t s) {
+  if (a.n_slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_commit_kernel, dim3((a.n_slots + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 int tam_class(const TamArgs& a) {

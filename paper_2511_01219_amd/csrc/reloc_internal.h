@@ -120,6 +120,27 @@ __host__ __device__ inline int tam_beams_padded(int nv) {
   return (nv + kTamBeamPad - 1) / kTamBeamPad * kTamBeamPad;
 }
 
+// Local refinement of each stage's best poses: an exhaustive TAM search over
+// the lattice of poses next to each (cells within +-h, headings within +-s
+// steps of the Ng direction grid; off-map and occupied cells other than the
+// pose's own are skipped; ties to the pose itself, then the smaller raster
+// index q = ((dg + s)(2h + 1) + dy + h)(2h + 1) + dx + h).
+struct RefineArgs {
+  TamArgs t;                 // TAM tables of the request; t.best per rank
+  const int32_t* sel;        // [n_slots] rank refined in each slot, -1 none
+  uint64_t* rbest;           // [n_slots] lattice best (T bits, ~tie key)
+  int n_slots;
+  int h, s, L;               // half-widths (cells, headings), lattice size
+};
+// Slots [b kr, (b + 1) kr) of stage b < ns (ranks [r0 + b K, ...) up to n):
+// its kr best ranks by (T desc, rank asc), or -1; clears their rbest.
+hipError_t launch_refine_select(const uint64_t* best, int r0, int K, int n, int ns, int kr,
+                                int32_t* sel, uint64_t* rbest, hipStream_t s);
+// Lattice TAM of every slot into rbest (atomic max of (T bits, ~tie key)).
+hipError_t launch_refine(const RefineArgs& a, hipStream_t s);
+// best[sel[j]] = (refined T bits, g << 10 | (dy + 15) << 5 | (dx + 15)).
+hipError_t launch_refine_commit(const RefineArgs& a, hipStream_t s);
+
 struct StageArgs {
   const uint64_t* best;      // per rank
   int r0, nb;

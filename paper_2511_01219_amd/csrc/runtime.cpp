@@ -388,6 +388,12 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.order = req_alloc<int32_t>(c, R, n);
   R.best = req_alloc<uint64_t>(c, R, n);
   const int max_stages = (n + R.prm.batch_k - 1) / R.prm.batch_k;
+  if (R.prm.refine_k > 0) {
+    // slots for one launch of the plain path or one tick of the batched one
+    R.ref_slots = std::max(plain_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k;
+    R.rsel = req_alloc<int32_t>(c, R, R.ref_slots);
+    R.rbest = req_alloc<uint64_t>(c, R, R.ref_slots);
+  }
   R.stage = req_alloc<uint64_t>(c, R, max_stages);
   R.flag = req_alloc<int32_t>(c, R, max_stages);
   R.rows_cap = std::max(1, std::min(n, R.prm.k_out));
@@ -515,6 +521,26 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   return a;
 }
 
+RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots) {
+  RefineArgs a;
+  a.t = tam_args(c, R, 0, 0, nullptr);
+  a.sel = R.rsel;
+  a.rbest = R.rbest;
+  a.n_slots = n_slots;
+  a.h = R.ref_h;
+  a.s = R.ref_s;
+  a.L = R.ref_L;
+  return a;
+}
+
+int plain_stages_per_launch(const Request& R) {
+  const int64_t K = R.prm.batch_k;
+  const int64_t bps = K * ((R.prep.info.Ntheta + 15) / 16);
+  const int64_t stages = (R.n_hyp + K - 1) / K;
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>(stages, std::min<int64_t>(512, kPlainFillBlocks / bps)));
+}
+
 // stable SMAD order of the request (after the SMAD kernel)
 int32_t smad_order(reloc_ctx* c, Request& R) {
   if (R.n_hyp <= kSmallSortMax) {
@@ -570,6 +596,24 @@ int32_t validate_search(const reloc_search_params* p) {
   if (p->k_out <= 0) return fail(RELOC_E_INVALID, "k_out must be >= 1");
   if (p->n_theta < 0 || p->n_hyp < 0) return fail(RELOC_E_INVALID, "negative n_theta / n_hyp");
   if (p->variant < 0 || p->variant > 5) return fail(RELOC_E_INVALID, "variant must be in 0..5");
+  if (p->refine_k < 0 || p->refine_k > 64) return fail(RELOC_E_INVALID, "refine_k must be in 0..64");
+  if (p->refine_cells < 0 || p->refine_cells > 15)
+    return fail(RELOC_E_INVALID, "refine_cells must be in 0..15");
+  if (p->refine_dirs < -1) return fail(RELOC_E_INVALID, "refine_dirs must be >= -1");
+  return RELOC_OK;
+}
+
+int32_t refine_lattice(const reloc_search_params* p, const reloc_scan_info& I, int* h, int* s,
+                       int* L) {
+  const int64_t hh = p->refine_cells;
+  const int64_t ss = p->refine_dirs < 0 ? I.Ng / I.Ntheta : p->refine_dirs;
+  const int64_t LL = (2 * ss + 1) * (2 * hh + 1) * (2 * hh + 1);
+  if (ss >= I.Ng) return fail(RELOC_E_INVALID, "refine_dirs %lld >= Ng = %d", (long long)ss, I.Ng);
+  if (LL > 65536)
+    return fail(RELOC_E_INVALID, "refinement lattice of %lld points exceeds 65536", (long long)LL);
+  *h = (int)hh;
+  *s = (int)ss;
+  *L = (int)LL;
   return RELOC_OK;
 }
 
@@ -590,6 +634,9 @@ int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
   if (int32_t e = build_lut(params, mi->second.res, &R->lut)) return e;
   R->rmax = scan->range_max;
   R->rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
+  if (params->refine_k > 0)
+    if (int32_t e = refine_lattice(params, R->prep.info, &R->ref_h, &R->ref_s, &R->ref_L))
+      return e;
   return RELOC_OK;
 }
 
@@ -601,6 +648,8 @@ size_t request_bytes(const Request& R) {
   b += Ns * (8 + 8 + 16 + 16) + (size_t)I.Ng * 8 + R.prep.runs.size() * 8;
   b += R.prep.vj.size() * 8 + R.lut.q.size() * 4 + stages * 12;
   b += (size_t)std::min<size_t>(n, (size_t)R.prm.k_out) * sizeof(PoseRow);
+  if (R.prm.refine_k > 0)
+    b += (size_t)std::max(plain_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
   b += 2 * n * 12 + (1 << 20);                                  // sort scratch
   b += 32 * 256;                                                // allocation rounding
   return b;
@@ -614,17 +663,33 @@ void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, in
   for (int i = 0; i < n; ++i) {
     const PoseRow& w = rows[i];
     reloc_pose& p = out[i];
-    const int ix = hs.host[2 * w.hyp], iy = hs.host[2 * w.hyp + 1];
+    int ix = hs.host[2 * w.hyp], iy = hs.host[2 * w.hyp + 1];
+    double th;
+    if (w.k < 0) {
+      // refined: code = g << 10 | (dy + 15) << 5 | (dx + 15)
+      const uint32_t code = 0xFFFFFFFFu - (uint32_t)w.k;
+      ix += (int)(code & 31u) - 15;
+      iy += (int)((code >> 5) & 31u) - 15;
+      p.g = (int32_t)(code >> 10);
+      p.k = -1;
+      p.refined = 1;
+      th = (2.0 * M_PI * (double)p.g) / (double)I.Ng;
+    } else {
+      p.g = (int32_t)((int64_t)w.k * (I.Ng / I.Ntheta));
+      p.k = w.k;
+      p.refined = 0;
+      th = (2.0 * M_PI * (double)w.k) / (double)I.Ntheta;
+    }
+    p.cx = ix;
+    p.cy = iy;
     p.x = m.ox + ((double)ix + 0.5) * m.res;
     p.y = m.oy + ((double)iy + 0.5) * m.res;
-    double th = (2.0 * M_PI * (double)w.k) / (double)I.Ntheta;
     if (th >= M_PI) th -= 2.0 * M_PI;
     p.theta = th;
     uint32_t tb32 = w.tbits;
     std::memcpy(&p.tam, &tb32, sizeof(float));
     p.smad = (float)w.smad;
     p.hyp = w.hyp;
-    p.k = w.k;
     p.rank = w.rank;
     p.stage = w.rank / R.prm.batch_k;
   }
@@ -661,6 +726,9 @@ void reloc_search_defaults(reloc_search_params* p) {
   p->alpha_low_pm[1] = 500;
   p->deadline_s = 0.0;
   p->variant = 0;
+  p->refine_k = 0;
+  p->refine_cells = 3;
+  p->refine_dirs = -1;
 }
 
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
@@ -902,6 +970,10 @@ int32_t reloc_scan_info_get(const reloc_scan* scan, const reloc_search_params* p
   if (int32_t e = validate_search(params)) return e;
   Prep P;
   if (int32_t e = preprocess(scan, params, resolution, &P)) return e;
+  if (params->refine_k > 0) {
+    int h, s, L;
+    if (int32_t e = refine_lattice(params, P.info, &h, &s, &L)) return e;
+  }
   *out = P.info;
   return RELOC_OK;
 }
@@ -969,13 +1041,21 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   // stages too small to fill the device are launched several at a time
   // (their flags read at one synchronisation; stages after the first that
   // stops are discarded, so the result is that of one stage at a time)
-  const int64_t bps = (int64_t)K * ((I.Ntheta + 15) / 16);
-  const int per = (int)std::min<int64_t>(512, std::max<int64_t>(1, kPlainFillBlocks / bps));
+  const int per = plain_stages_per_launch(R);
+  const int kr = R.prm.refine_k;
   for (int r0 = 0; r0 < R.n_hyp;) {
     const int left = (R.n_hyp - r0 + K - 1) / K;
     const int ns = std::min(per, left);
     const int nb = std::min(ns * K, R.n_hyp - r0);
     HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
+    if (kr > 0) {
+      // each stage's kr best poses: lattice search, then their refined T
+      // replaces T* before the stage's best is taken
+      HIP_TRY(launch_refine_select(R.best, r0, K, R.n_hyp, ns, kr, R.rsel, R.rbest, s));
+      const RefineArgs fa = refine_args(c, R, ns * kr);
+      HIP_TRY(launch_refine(fa, s));
+      HIP_TRY(launch_refine_commit(fa, s));
+    }
     StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stages, R.flag + stages};
     HIP_TRY(launch_stage_reduce_multi(sa, K, ns, R.n_hyp, s));
     HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1036,6 +1116,11 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     st->stages = stages;
     st->early_stopped = stopped;
     st->n_eval = n_eval;
+    if (kr > 0) {
+      for (int b = 0; b < stages; ++b)
+        st->refined += std::min(kr, std::min(K, R.n_hyp - b * K));
+      st->refine_points = st->refined * R.ref_L;
+    }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[4]);
     st->ms_total = ms;

@@ -48,6 +48,9 @@ int32_t build_lut(const reloc_search_params* p, double res, Lut* L);
 
 struct ServeState;   // batch.cpp
 
+// Stages of one request in one batched tick, at most.
+constexpr int kMaxTickStages = 32;
+
 }  // namespace reloc
 
 using reloc::fail;
@@ -102,6 +105,10 @@ struct Request {
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   uint64_t* best = nullptr;
+  // local refinement: lattice half-widths and size, slots per launch
+  int ref_h = 0, ref_s = 0, ref_L = 0, ref_slots = 0;
+  int32_t* rsel = nullptr;        // [ref_slots] refined rank per slot
+  uint64_t* rbest = nullptr;      // [ref_slots] lattice best per slot
   uint64_t* stage = nullptr;
   int32_t* flag = nullptr;
   PoseRow* rows = nullptr;
@@ -170,6 +177,11 @@ namespace reloc {
 int32_t set_device(reloc_ctx* c);
 void release_request(reloc_ctx* c, Request& r);
 int32_t validate_search(const reloc_search_params* p);
+// Refinement lattice of a request: half-widths h (cells), s (Ng headings;
+// refine_dirs < 0 means Ng / N_theta) and size L = (2s + 1)(2h + 1)^2;
+// RELOC_E_INVALID when s >= Ng or L > 65536.
+int32_t refine_lattice(const reloc_search_params* p, const reloc_scan_info& I, int* h, int* s,
+                       int* L);
 // Host preprocessing of a request (no device work): fills R's map, set,
 // parameters, Prep and limits. build_request then allocates and uploads.
 int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
@@ -177,6 +189,10 @@ int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
 int32_t build_request(reloc_ctx* c, Request& R);
 RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps);
 TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out);
+RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots);
+// Stages per TAM launch of the plain path (several when a stage alone
+// cannot fill the device).
+int plain_stages_per_launch(const Request& R);
 // Device bytes build_request will allocate for R (admission control).
 size_t request_bytes(const Request& R);
 // Converts device result rows to poses in world coordinates.

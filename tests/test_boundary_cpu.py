@@ -153,6 +153,28 @@ def test_search_param_defaults():
     assert tuple(p.alpha_mid_pm) == (900, 700) and tuple(p.alpha_low_pm) == (700, 500)
     q = reloc.search_params(tau=None)
     assert math.isnan(q.tau)
+    assert (p.refine_k, p.refine_cells, p.refine_dirs) == (0, 3, -1)
+
+
+def test_refinement_limits():
+    """Refinement parameters are checked on the host: refine_k in 0..64,
+    refine_cells in 0..15, refine_dirs >= -1 and below Ng, and the lattice
+    (2s + 1)(2h + 1)^2 at most 65536 points."""
+    z = np.full(360, 2.0, np.float32)
+    inc = 2 * math.pi / 360
+
+    def info(**kw):
+        return reloc.scan_info(z, -math.pi, inc, 0.05, n_theta=90, **kw)
+
+    assert info(refine_k=64, refine_cells=15, refine_dirs=-1)["Ng"] == 360
+    assert info(refine_k=1, refine_cells=15, refine_dirs=33)["Ng"] == 360   # 67 * 961 points
+    for kw in (dict(refine_k=65), dict(refine_k=-1), dict(refine_k=1, refine_cells=16),
+               dict(refine_k=1, refine_cells=-1), dict(refine_k=1, refine_dirs=-2),
+               dict(refine_k=1, refine_dirs=360), dict(refine_k=1, refine_cells=15,
+                                                      refine_dirs=34)):
+        with pytest.raises(reloc.RelocError) as ei:
+            info(**kw)
+        assert ei.value.code == reloc.E_INVALID, kw
 
 
 def test_null_context_calls_are_invalid():
