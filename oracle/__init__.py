@@ -71,11 +71,12 @@ def _declare(L):
     L.orc_tam.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
                           f64, f64, f64, f64, i32, vp, vp, vp, i32]
     L.orc_stages.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
-                             f64, f64, f64, f64, i32, vp, vp, i32, f64, i32, i32, i32,
+                             f64, f64, f64, f64, i32, vp, vp, i32, f64, i32, i32, i32, i32,
                              vp, vp, vp, vp, vp, vp, i32]
     L.orc_refine.argtypes = [i32, i32, vp, f64, i32, i32, i32, vp, vp, i64, i64, i64,
-                             f64, f64, f64, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp,
+                             f64, f64, f64, f64, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp,
                              i32]
+    L.orc_caer.argtypes = [i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, i32]
     L.orc_sample.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, i32,
                              f64, f64, u64, i32, vp, vp]
     L.orc_num_threads.argtypes = []
@@ -154,6 +155,7 @@ def prep(ranges: np.ndarray, angle_min: float, angle_increment: float,
                n_skip_enum=n_skip_enum, range_max=float(np.float32(range_max)))
     valid = bs == 2
     out["fov_j"] = np.ascontiguousarray(bj[bs >= 1])
+    out["fov_z"] = np.ascontiguousarray(bz[bs >= 1])
     out["valid_j"] = np.ascontiguousarray(bj[valid])
     out["valid_zq"] = np.ascontiguousarray(bq[valid])
     return out
@@ -173,16 +175,38 @@ def smad(zhat: np.ndarray, pr: Dict, all_shifts: bool = False, threads: int = 0)
     return (s, a, allv) if all_shifts else (s, a)
 
 
+def caer(zhat: np.ndarray, pr: Dict, all_shifts: bool = False, threads: int = 0):
+    """CAER per hypothesis (FP64) and argmin shift m (eq. 21)."""
+    zhat = np.ascontiguousarray(zhat, dtype=np.float32)
+    n, Ns = zhat.shape
+    assert Ns == pr["Ns"]
+    nsh = (Ns + pr["n_skip_enum"] - 1) // pr["n_skip_enum"]
+    c = np.empty(n, dtype=np.float64)
+    a = np.empty(n, dtype=np.int32)
+    allv = np.empty((n, nsh), dtype=np.float64) if all_shifts else None
+    lib().orc_caer(n, Ns, _p(zhat), len(pr["fov_j"]), _p(pr["fov_j"]), _p(pr["fov_z"]),
+                   pr["n_skip_enum"], _p(c), _p(a), _p(allv), threads)
+    return (c, a, allv) if all_shifts else (c, a)
+
+
+# columns of tam(); FINE_COL[m] is the score of fine metric m (0 TAM,
+# 1 TAM_mean, 2 baseline, 3 LF)
+TAM_COLS = ("T", "P", "s_d", "c", "Lbar", "mean_full", "mean_mid", "mean_low", "LF",
+            "baseline", "T_mean")
+FINE_COL = (0, 10, 9, 8)
+
+
 def tam(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_k: np.ndarray,
         z_hit: float = 1.0, sigma_hit: float = 0.2, z_rand: float = 0.0,
         d_max: float = 2.0, threads: int = 0) -> np.ndarray:
-    """[nq, 8] = T, P, s_d, c, Lbar, top-k_full / k_mid / k_low means, for
-    each query (cell xy, heading k)."""
+    """[nq, 11] = T, P, s_d, c, Lbar, top-k_full / k_mid / k_low means, LF
+    (eq. 32), baseline (eq. 33), T_mean (eq. 34), for each query (cell xy,
+    heading k)."""
     kmap = np.ascontiguousarray(kmap, dtype=np.int64)
     H, W = kmap.shape
     q_xy = np.ascontiguousarray(q_xy, dtype=np.int32).reshape(-1, 2)
     q_k = np.ascontiguousarray(q_k, dtype=np.int32)
-    out = np.empty((len(q_k), 8), dtype=np.float64)
+    out = np.empty((len(q_k), len(TAM_COLS)), dtype=np.float64)
     lib().orc_tam(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
                   _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
                   pr["k_low"], z_hit, sigma_hit, z_rand, d_max, len(q_k), _p(q_xy),
@@ -198,7 +222,7 @@ def refine_span(pr: Dict, refine_dirs: int = -1) -> int:
 
 def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2,
            z_rand=0.0, d_max=2.0, all_T=False, threads: int = 0, refine_k: int = 0,
-           refine_cells: int = 3, refine_dirs: int = -1) -> Dict:
+           refine_cells: int = 3, refine_dirs: int = -1, fine_metric: int = 0) -> Dict:
     """Batched multi-stage inference with optional local refinement of each
     batch's refine_k best poses (Sec. III pipeline text, Remark 2)."""
     kmap = np.ascontiguousarray(kmap, dtype=np.int64)
@@ -216,7 +240,7 @@ def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2
                      _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
                      pr["k_low"], z_hit, sigma_hit, z_rand, d_max, n, _p(hyp),
                      _p(smad_v), batch_k,
-                     float("nan") if tau is None else float(tau),
+                     float("nan") if tau is None else float(tau), int(fine_metric),
                      int(refine_k), int(refine_cells), refine_span(pr, refine_dirs),
                      _p(order), _p(tstar), _p(kstar), _p(ref), _p(info), _p(allT), threads)
     ne = int(info[2])
@@ -232,7 +256,7 @@ def stages(kmap, res, pr, hyp_xy, smad_v, batch_k, tau, z_hit=1.0, sigma_hit=0.2
 def refine(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_g: np.ndarray,
            refine_cells: int = 3, refine_dirs: int = -1, z_hit: float = 1.0,
            sigma_hit: float = 0.2, z_rand: float = 0.0, d_max: float = 2.0,
-           all_T: bool = False, threads: int = 0):
+           all_T: bool = False, threads: int = 0, fine_metric: int = 0):
     """Local refinement of poses (cell xy, heading index g on the Ng grid):
     refined T, (dx, dy), refined g, and optionally the T of every lattice
     point in raster order (NaN where not visited)."""
@@ -249,7 +273,8 @@ def refine(kmap: np.ndarray, res: float, pr: Dict, q_xy: np.ndarray, q_g: np.nda
     allv = np.empty((nq, L), dtype=np.float64) if all_T else None
     lib().orc_refine(W, H, _p(kmap), res, pr["Ns"], pr["Ntheta"], pr["N_valid"],
                      _p(pr["valid_j"]), _p(pr["valid_zq"]), pr["k_full"], pr["k_mid"],
-                     pr["k_low"], z_hit, sigma_hit, z_rand, d_max, h, s, nq, _p(q_xy),
+                     pr["k_low"], z_hit, sigma_hit, z_rand, d_max, int(fine_metric), h, s,
+                     nq, _p(q_xy),
                      _p(q_g), _p(T), _p(dxy), _p(g), _p(allv), threads)
     return (T, dxy, g, allv) if all_T else (T, dxy, g)
 
@@ -290,7 +315,8 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
                alpha_mid_pm=(900, 700), alpha_low_pm=(700, 500), thr: int = 65,
                kmap: Optional[np.ndarray] = None, threads: int = 0,
                keep: bool = False, refine_k: int = 0, refine_cells: int = 3,
-               refine_dirs: int = -1) -> Dict:
+               refine_dirs: int = -1, coarse_metric: int = 0,
+               fine_metric: int = 0) -> Dict:
     """The whole hot path, step by step, in the paper's order."""
     if kmap is None:
         kmap = edt(occ, thr)
@@ -300,10 +326,17 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
         raise ValueError("scan rejected: %d" % pr["status"])
     hit, zhat = raycast(occ, hyp_xy, pr["Ns"], pr["Ng"], res, range_max, thr,
                         threads=threads)
-    sm, am = smad(zhat, pr, threads=threads)
+    # coarse metric: 0 SMAD (prefix sums), 1 SMAD (direct sums; the same
+    # values), 2 CAER, 3 none (the set's own order)
+    if coarse_metric in (0, 1):
+        sm, am = smad(zhat, pr, threads=threads)
+    elif coarse_metric == 2:
+        sm, am = caer(zhat, pr, threads=threads)
+    else:
+        sm, am = np.zeros(len(zhat)), np.zeros(len(zhat), np.int32)
     st = stages(kmap, res, pr, hyp_xy, sm, batch_k, tau, z_hit, sigma_hit, z_rand,
                 d_max, threads=threads, refine_k=refine_k, refine_cells=refine_cells,
-                refine_dirs=refine_dirs)
+                refine_dirs=refine_dirs, fine_metric=fine_metric)
     ne = st["n_eval"]
     ranks = np.arange(ne)
     rank_order = np.lexsort((ranks, -st["tstar"]))     # T desc, rank asc
@@ -325,7 +358,10 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
                           refined=bool(st["refined"][r])))
     out = dict(poses=poses, prep=pr, stages=st["stages"],
                early_stopped=st["early_stopped"], n_eval=ne,
-               smad_evals=len(sm) * pr["n_shifts"], tam_evals=ne * pr["Ntheta"])
+               smad_evals=len(sm) * (pr["n_shifts"] if coarse_metric in (0, 1) else
+                                     -(-pr["Ns"] // pr["n_skip_enum"]) if coarse_metric == 2
+                                     else 0),
+               tam_evals=ne * pr["Ntheta"])
     if keep:
         out.update(hit=hit, zhat=zhat, smad=sm, argm=am, order=st["order"],
                    tstar=st["tstar"], kstar=st["kstar"], kmap=kmap,

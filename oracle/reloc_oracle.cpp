@@ -459,6 +459,42 @@ int orc_smad(int n_hyp, int Ns, const float* zhat, int n_fov_beams,
 }
 
 // ---------------------------------------------------------------------------
+// CAER (eq. 21, Remark 5), the beam-level coarse metric of the ablation:
+//   CAER(m) = (sum over FoV beams i, in FoV order, of
+//              |z'_i - zhat[(j_i + m) mod Ns]|) / N_FoV,
+// z'_i the measured range of FoV beam i (0 when invalid), m = 0, n_enum,
+// 2 n_enum, ... < Ns. Unlike SMAD it is not rotation invariant, so every
+// shift is scored even for panoramic scans; CAER(p) = min over m (ties:
+// smallest m).
+// ---------------------------------------------------------------------------
+int orc_caer(int n_hyp, int Ns, const float* zhat, int n_fov_beams, const int32_t* fov_j,
+             const double* fov_z, int n_enum, double* caer, int32_t* argm, double* all_out,
+             int threads) {
+  const int nsh = (Ns + n_enum - 1) / n_enum;
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#endif
+#pragma omp parallel for schedule(static)
+  for (int h = 0; h < n_hyp; ++h) {
+    const float* z = zhat + (size_t)h * Ns;
+    double best = 0.0;
+    int bm = -1;
+    for (int s = 0; s < nsh; ++s) {
+      const int m = s * n_enum;
+      double acc = 0.0;
+      for (int i = 0; i < n_fov_beams; ++i)
+        acc += std::fabs(fov_z[i] - (double)z[(fov_j[i] + m) % Ns]);
+      const double v = acc / (double)n_fov_beams;
+      if (all_out) all_out[(size_t)h * nsh + s] = v;
+      if (bm < 0 || v < best) { best = v; bm = m; }
+    }
+    caer[h] = best;
+    argm[h] = bm;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // TAM at pose (p, theta_k) (eq. 22-31), literal.
 //   endpoint of valid beam v at heading k: direction t = (b*j_v + o*k) mod Ng
 //   with b = Ng/Ns, o = Ng/Ntheta; e = floor((X*2^20 + zq*U_t) / 2^28) per
@@ -469,7 +505,11 @@ int orc_smad(int n_hyp, int Ns, const float* zhat, int n_fov_beams,
 //   dbar, population variance of d (two passes); dt = clamp(dbar, res/2,
 //   d_max); s_d = 1 - (dt - res/2)/(d_max - res/2) (29); c = exp(-var/2)
 //   (30); T = cbrt(P * s_d * c) (31).
-// out[8*i + 0..7] = T, P, s_d, c, Lbar, mean top-k_full, top-k_mid, top-k_low
+// out[11*i + 0..10] = T, P, s_d, c, Lbar, mean top-k_full, top-k_mid,
+// top-k_low, and the ablation metrics of Sec. IV (Case 3):
+//   LF = sum of l_i over the N'_Z valid beams (eq. 32, in beam order);
+//   baseline = (exp(LF / N'_Z) s_d)^(1/2) (eq. 33);
+//   T_mean = (P + s_d + c) / 3 (eq. 34);
 // for query i = (cell, heading k).
 // ---------------------------------------------------------------------------
 struct TamCtx {
@@ -478,7 +518,12 @@ struct TamCtx {
   int nv; const int32_t* vj; const int32_t* vzq;
   i64 kfull, kmid, klow;
   double z_hit, sigma, z_rand, d_max;
+  int fine;   // score that picks theta* and ranks poses: 0 T, 1 T_mean, 2 baseline, 3 LF
 };
+
+constexpr int TOUT = 11;   // values per TAM evaluation
+// column of tam_eval's output holding the score of each fine metric
+inline int fine_col(int fine) { return fine == 1 ? 10 : fine == 2 ? 9 : fine == 3 ? 8 : 0; }
 
 // The heading is given as its index g on the Ng direction grid: heading
 // theta_k of eq. 22 is g = o*k; the local refinement below also visits the
@@ -526,6 +571,11 @@ static void tam_eval(const TamCtx& c, int ix, int iy, i64 g, double* out,
   out[0] = std::cbrt(P * sd * cc);
   out[1] = P; out[2] = sd; out[3] = cc; out[4] = Lbar;
   out[5] = mf; out[6] = mm; out[7] = ml;
+  double lf = 0.0;
+  for (int v = 0; v < c.nv; ++v) lf += l[v];
+  out[8] = lf;
+  out[9] = std::sqrt(std::exp(lf / (double)c.nv) * sd);
+  out[10] = (P + sd + cc) / 3.0;
 }
 
 int orc_tam(int W, int H, const i64* kmap, double res, int Ns, int Nt,
@@ -536,7 +586,7 @@ int orc_tam(int W, int H, const i64* kmap, double res, int Ns, int Nt,
   std::vector<int32_t> U(2 * (size_t)Ng);
   orc_dirs((int)Ng, U.data());
   TamCtx c{W, H, kmap, res, Ns, Nt, (int)Ng, U.data(), nv, vj, vzq, kfull, kmid, klow,
-           z_hit, sigma, z_rand, d_max};
+           z_hit, sigma, z_rand, d_max, 0};
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -545,8 +595,8 @@ int orc_tam(int W, int H, const i64* kmap, double res, int Ns, int Nt,
     std::vector<double> l, d;
 #pragma omp for schedule(dynamic, 16)
     for (int i = 0; i < nq; ++i)
-      tam_eval(c, q_xy[2 * i], q_xy[2 * i + 1], (Ng / Nt) * (i64)q_k[i], out + 8 * (size_t)i,
-               l, d);
+      tam_eval(c, q_xy[2 * i], q_xy[2 * i + 1], (Ng / Nt) * (i64)q_k[i],
+               out + TOUT * (size_t)i, l, d);
   }
   return 0;
 }
@@ -573,7 +623,8 @@ static void refine_one(const TamCtx& c, int ix, int iy, i64 g0, int h, int s, do
                        int* bdx, int* bdy, i64* bg, double* all, std::vector<double>& l,
                        std::vector<double>& d) {
   const int w = 2 * h + 1;
-  double out[8];
+  double out[TOUT];
+  const int col = fine_col(c.fine);
   double best = 0.0;
   i64 bkey = -1;
   for (int dg = -s; dg <= s; ++dg)
@@ -588,10 +639,10 @@ static void refine_one(const TamCtx& c, int ix, int iy, i64 g0, int h, int s, do
         }
         const i64 g = ((g0 + dg) % c.Ng + c.Ng) % c.Ng;
         tam_eval(c, x, y, g, out, l, d);
-        if (all) all[q] = out[0];
+        if (all) all[q] = out[col];
         const i64 key = centre ? 0 : q + 1;
-        if (bkey < 0 || out[0] > best || (out[0] == best && key < bkey)) {
-          best = out[0];
+        if (bkey < 0 || out[col] > best || (out[col] == best && key < bkey)) {
+          best = out[col];
           bkey = key;
           *bdx = dx;
           *bdy = dy;
@@ -601,17 +652,18 @@ static void refine_one(const TamCtx& c, int ix, int iy, i64 g0, int h, int s, do
   *bestT = best;
 }
 
-// Refinement of nq poses (cell q_xy, heading index q_g on the Ng grid).
+// Refinement of nq poses (cell q_xy, heading index q_g on the Ng grid) by
+// the score of fine metric `fine`.
 int orc_refine(int W, int H, const i64* kmap, double res, int Ns, int Nt,
                int nv, const int32_t* vj, const int32_t* vzq, i64 kfull, i64 kmid, i64 klow,
-               double z_hit, double sigma, double z_rand, double d_max, int h, int s,
+               double z_hit, double sigma, double z_rand, double d_max, int fine, int h, int s,
                int nq, const int32_t* q_xy, const i64* q_g, double* T, int32_t* dxy, i64* g,
                double* all, int threads) {
   const i64 Ng = (i64)Ns / gcd64(Ns, Nt) * Nt;
   std::vector<int32_t> U(2 * (size_t)Ng);
   orc_dirs((int)Ng, U.data());
   TamCtx c{W, H, kmap, res, Ns, Nt, (int)Ng, U.data(), nv, vj, vzq, kfull, kmid, klow,
-           z_hit, sigma, z_rand, d_max};
+           z_hit, sigma, z_rand, d_max, fine};
   const size_t L = (size_t)(2 * s + 1) * (2 * h + 1) * (2 * h + 1);
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
@@ -629,7 +681,9 @@ int orc_refine(int W, int H, const i64* kmap, double res, int Ns, int Nt,
 
 // ---------------------------------------------------------------------------
 // Batched multi-stage inference (Sec. III, Fig. 1 pipeline text; eq. 8-9,
-// 22; early termination). Given the SMAD of every hypothesis:
+// 22; early termination). Given the coarse score of every hypothesis (SMAD,
+// or an ablation's CAER; all equal for no ordering) and the fine metric
+// `fine` that stands for T below (0 TAM, 1 T_mean, 2 baseline, 3 LF):
 //   order pi = ascending (SMAD, index); batch b = pi[bK, (b+1)K);
 //   per hypothesis theta* = argmax_k T (ties: smallest k) (eq. 22);
 //   batch best T*_b = max over the batch (ties: earlier rank); stop when
@@ -649,7 +703,7 @@ int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
                int nv, const int32_t* vj, const int32_t* vzq, i64 kfull, i64 kmid, i64 klow,
                double z_hit, double sigma, double z_rand, double d_max,
                int n_hyp, const int32_t* hyp_xy, const double* smad, int K, double tau,
-               int kr, int rh, int rs, int32_t* order, double* tstar, int32_t* kstar,
+               int fine, int kr, int rh, int rs, int32_t* order, double* tstar, int32_t* kstar,
                i64* ref, i64* stage_info, double* all_T, int threads) {
   std::vector<int32_t> pi(n_hyp);
   std::iota(pi.begin(), pi.end(), 0);
@@ -661,7 +715,8 @@ int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
   std::vector<int32_t> U(2 * (size_t)Ng);
   orc_dirs((int)Ng, U.data());
   TamCtx c{W, H, kmap, res, Ns, Nt, (int)Ng, U.data(), nv, vj, vzq, kfull, kmid, klow,
-           z_hit, sigma, z_rand, d_max};
+           z_hit, sigma, z_rand, d_max, fine};
+  const int col = fine_col(fine);
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -671,7 +726,7 @@ int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
 #pragma omp parallel
     {
       std::vector<double> l, d;
-      double out[8];
+      double out[TOUT];
 #pragma omp for schedule(dynamic, 1)
       for (int r = b0; r < b1; ++r) {
         const int h = pi[r];
@@ -679,8 +734,8 @@ int orc_stages(int W, int H, const i64* kmap, double res, int Ns, int Nt,
         int bk = -1;
         for (int k = 0; k < Nt; ++k) {
           tam_eval(c, hyp_xy[2 * h], hyp_xy[2 * h + 1], (Ng / Nt) * (i64)k, out, l, d);
-          if (all_T) all_T[(size_t)r * Nt + k] = out[0];
-          if (bk < 0 || out[0] > best) { best = out[0]; bk = k; }
+          if (all_T) all_T[(size_t)r * Nt + k] = out[col];
+          if (bk < 0 || out[col] > best) { best = out[col]; bk = k; }
         }
         tstar[r] = best;
         kstar[r] = bk;

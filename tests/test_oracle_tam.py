@@ -113,7 +113,7 @@ def test_median_identity_and_bounds():
     q = np.stack([xs[pick], ys[pick]], 1)
     k = rng.integers(0, 360, 200)
     out = oracle.tam(kmap, RES, pr, q, k)
-    T, P, sd, c, Lbar, mf, mm, ml = out.T
+    T, P, sd, c, Lbar, mf, mm, ml = out.T[:8]
     assert (ml >= mm).all() and (mm >= mf).all()
     assert (Lbar == mm).all()
     assert ((sd >= 0) & (sd <= 1)).all() and ((c > 0) & (c <= 1)).all()
