@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: CUs x SIMDs x lanes x clock
 DDA_OPS_PER_STEP = 10                      # compare, 2 selects, D update, 2 bounds, 3 address, 1 bit test
+FP64_ADD_PEAK = 256 * 4 * 16 * 2.4e9       # FP64 adds/s (lane-ops; FP64 runs at the FP32 rate)
+COARSE = {"smad": 0, "smad-direct": 1, "caer": 2, "none": 3}
+FINE = {"tam": 0, "tam-mean": 1, "baseline": 2, "lf": 3}
 RAYCAST_SOURCES = ("paper_2511_01219_amd/csrc/k_raycast.hip",
                    "paper_2511_01219_amd/csrc/reloc_internal.h")
 TRAFFIC_FILE = "profiles/raycast_skip_kernel_plain-large_traffic.txt"
@@ -389,6 +392,10 @@ def main():
                     help="plain workloads: poses refined per stage (local TAM lattice search)")
     ap.add_argument("--refine-cells", type=int, default=3,
                     help="refinement lattice half-width in cells")
+    ap.add_argument("--coarse", default="smad", choices=tuple(COARSE),
+                    help="plain workloads: coarse metric (ablation)")
+    ap.add_argument("--fine", default="tam", choices=tuple(FINE),
+                    help="plain workloads: fine metric (ablation)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -433,7 +440,8 @@ def main():
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
                       w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
                       variant=args.variant, refine_k=args.refine_k,
-                      refine_cells=args.refine_cells)
+                      refine_cells=args.refine_cells, coarse_metric=COARSE[args.coarse],
+                      fine_metric=FINE[args.fine])
     tuned = None
     if args.variant == 0:
         # the ray-cast launch shape is picked on this GPU for this request
@@ -507,7 +515,8 @@ def main():
                                 "270 deg 720 beams, 0.5 deg TAM, top-64 per stage"),
                    "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k,
                    "refine_k": args.refine_k,
-                   "refine_cells": args.refine_cells if args.refine_k else None},
+                   "refine_cells": args.refine_cells if args.refine_k else None,
+                   "coarse": args.coarse, "fine": args.fine},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
@@ -523,6 +532,22 @@ def main():
         "roofline": roofline,
         "autotune": tuned,
     }
+    if COARSE[args.coarse] in (1, 2):
+        # the direct coarse kernel: one FP64 subtract and one FP64 add (of an
+        # absolute value) per (hypothesis, shift, FoV beam) term for CAER, one
+        # add for direct-sum SMAD; FP64 add peak = 256 CUs x 64 lanes x 2.4 GHz
+        info = reloc.scan_info(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                               w.range_min, w.range_max, n_theta=n_theta)
+        caer = COARSE[args.coarse] == 2
+        nsh = info["Ns"] if caer else info["n_shifts"]
+        terms = n_hyp * nsh * info["n_fov"]
+        t_c = float(np.mean(smad_ms)) * 1e-3
+        ops = terms * (2 if caer else 1)
+        out["coarse_roofline"] = {"kernel": "coarse_direct_kernel", "bound": "alu",
+                                  "achieved": ops / t_c / 1e12, "peak": FP64_ADD_PEAK / 1e12,
+                                  "unit": "TOP/s (fp64 lane-ops)",
+                                  "frac": ops / t_c / FP64_ADD_PEAK, "terms": terms,
+                                  "avg_ms": t_c * 1e3}
     ctx.release(rid)
     if not args.no_cpu:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)

@@ -214,6 +214,17 @@ typedef struct {
   int32_t refine_cells;   /* h, lattice half-width in cells (3; <= 15) */
   int32_t refine_dirs;    /* s, heading half-width in Ng steps (-1: Ng / N_theta);
                              the lattice (2s + 1)(2h + 1)^2 holds <= 65536 points */
+  /* Ablation metrics (Sec. IV, Case 3). coarse_metric orders the
+   * hypotheses: 0 SMAD with prefix sums (eq. 17-20); 1 SMAD by direct sums
+   * (the same values, the ablation's "without prefix-sum acceleration");
+   * 2 CAER (eq. 21: mean of |z'_i - zhat_{i+m}| over the FoV beams, every
+   * shift m scored, also for panoramic scans); 3 none (no ray cast, the
+   * set's own order). fine_metric is the score T that picks theta*, ranks
+   * poses and is tested against tau: 0 TAM (eq. 31); 1 TAM_mean (eq. 34);
+   * 2 baseline (eq. 33); 3 LF (eq. 32, a sum of log-likelihoods, <= 0 up to
+   * 1e-6 per beam). */
+  int32_t coarse_metric;
+  int32_t fine_metric;
 } reloc_search_params;
 
 /* Fills the defaults listed above. */

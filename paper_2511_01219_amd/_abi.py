@@ -53,7 +53,8 @@ class reloc_search_params(C.Structure):
                 ("alpha_mid_pm", C.c_int32 * 2), ("alpha_low_pm", C.c_int32 * 2),
                 ("deadline_s", C.c_double), ("variant", C.c_int32),
                 ("refine_k", C.c_int32), ("refine_cells", C.c_int32),
-                ("refine_dirs", C.c_int32)]
+                ("refine_dirs", C.c_int32), ("coarse_metric", C.c_int32),
+                ("fine_metric", C.c_int32)]
 
 
 class reloc_scan_info(C.Structure):

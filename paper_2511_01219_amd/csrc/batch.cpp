@@ -241,6 +241,9 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   HIP_TRY(launch_raycast_batch(d_ra, d_bp, n, bpre[n], s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
   HIP_TRY(launch_smad_batch(d_ra, d_sp, n, spre[n], wpb, smad_lds, s));
+  // requests with another coarse metric overwrite their keys (ablations)
+  for (int i = 0; i < n; ++i)
+    if (ra[i].coarse != 0) HIP_TRY(launch_coarse(ra[i], s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
   HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp, s));
   HIP_TRY(hipEventRecord(c->ev[3], s));
@@ -265,8 +268,8 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
 
 // One tick over the unfinished flights of F.
 int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* pt) {
-  std::vector<TamArgs> items[10];
-  std::vector<Flight*> owner[10];
+  std::vector<TamArgs> items[kTamClasses];
+  std::vector<Flight*> owner[kTamClasses];
   std::vector<StageArgs> st;
   std::vector<Flight*> live;
   for (Flight* f : F)
@@ -318,10 +321,10 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     }
   }
   Blob bl;
-  size_t o_items[10], o_pre[10];
-  int64_t blocks[10];
-  size_t lds[10];
-  for (int k = 0; k < 10; ++k) {
+  size_t o_items[kTamClasses], o_pre[kTamClasses];
+  int64_t blocks[kTamClasses];
+  size_t lds[kTamClasses];
+  for (int k = 0; k < kTamClasses; ++k) {
     const int m = (int)items[k].size();
     blocks[k] = 0;
     lds[k] = 0;
@@ -341,7 +344,7 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
   if (int32_t e = commit(c, S, bl, &d)) return e;
   hipStream_t s = c->stream;
   HIP_TRY(hipEventRecord(c->ev[3], s));
-  for (int k = 0; k < 10; ++k) {
+  for (int k = 0; k < kTamClasses; ++k) {
     if (!blocks[k]) continue;
     HIP_TRY(launch_tam_batch(k, (const TamArgs*)(d + o_items[k]), (const int64_t*)(d + o_pre[k]),
                              (int)items[k].size(), blocks[k], lds[k], s));
@@ -454,9 +457,9 @@ void fill_stats(const Request& R, const Flight& f, const PhaseTimes& pt, float t
   const reloc_scan_info& I = R.prep.info;
   std::memset(st, 0, sizeof *st);
   st->n_hyp = R.n_hyp;
-  st->smad_evals = (int64_t)R.n_hyp * I.n_shifts;
+  st->smad_evals = coarse_evals(R);
   st->tam_evals = (int64_t)f.n_eval * I.Ntheta;
-  st->rays = (int64_t)R.n_hyp * I.Ns;
+  st->rays = (int64_t)R.n_hyp * I.Ns;   // the batched front casts every request
   st->tam_lookups = st->tam_evals * I.n_valid;
   st->stages = f.stages;
   st->early_stopped = f.stopped ? 1 : 0;

@@ -626,6 +626,86 @@ __global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restric
   smad_dispatch(reqs[r], (int)(blockIdx.x - prefix[r]), wpb, S);
 }
 
+// ------------------------------------------------- direct coarse metrics
+// SMAD by direct sums (eq. 16-20 without the prefix sums of eq. 17-18) or
+// CAER (eq. 21) of hypothesis blockIdx.x by one workgroup. The synthetic
+// ranges are stored twice in LDS as FP64, so index j + m never wraps; each
+// thread scores the shifts m = s n_enum, s = tid, tid + 256, ..., summing
+// its FoV beams one at a time in beam order (the order the definition is
+// written in, so the sums equal a sequential evaluation bit for bit). SMAD
+// scores the shifts of eq. 20 (m = 0 only for panoramic scans); CAER is not
+// rotation invariant and scores every shift.
+__global__ __launch_bounds__(RT) void coarse_direct_kernel(RayArgs a) {
+  extern __shared__ double Z[];            // [2 Ns]
+  __shared__ double rv[RT / 64];
+  __shared__ int rm[RT / 64];
+  const int h = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int Ns = a.Ns;
+  const float* z = a.zbuf + (size_t)h * Ns;
+  for (int i = tid; i < Ns; i += RT) {
+    const double v = (double)z[i];
+    Z[i] = v;
+    Z[i + Ns] = v;
+  }
+  __syncthreads();
+  const bool caer = a.coarse == 2;
+  const int nsh = caer ? (Ns + a.n_enum - 1) / a.n_enum : a.n_shifts;
+  const int nf = a.nfov;
+  double bv = INFINITY;
+  int bm = INT_MAX;
+  for (int s = tid; s < nsh; s += RT) {
+    const int m = s * a.n_enum;
+    double acc = 0.0;
+    if (caer) {
+      for (int i = 0; i < nf; ++i) acc += fabs(a.fov_z[i] - Z[a.fov_j[i] + m]);
+    } else {
+      for (int i = 0; i < nf; ++i) acc += Z[a.fov_j[i] + m];
+    }
+    const double mean = acc / (double)nf;
+    const double v = caer ? mean : fabs(a.zbar - mean);
+    if (v < bv) {
+      bv = v;
+      bm = m;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int om = __shfl_xor(bm, off, 64);
+    if (ov < bv || (ov == bv && om < bm)) {
+      bv = ov;
+      bm = om;
+    }
+  }
+  if (lane == 0) {
+    rv[wv] = bv;
+    rm[wv] = bm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < RT / 64; ++q)
+      if (rv[q] < bv || (rv[q] == bv && rm[q] < bm)) {
+        bv = rv[q];
+        bm = rm[q];
+      }
+    a.smad[h] = bv;
+    a.argm[h] = bm;
+    a.keys[h] = (uint64_t)__double_as_longlong(bv);
+    a.vals[h] = h;
+    if (a.best0) a.best0[h] = 0;
+  }
+}
+
+// No coarse ordering: every key 0, so the stable sort keeps the set's order.
+__global__ __launch_bounds__(RT) void coarse_none_kernel(RayArgs a) {
+  const int h = blockIdx.x * RT + threadIdx.x;
+  if (h >= a.n_hyp) return;
+  a.smad[h] = 0.0;
+  a.argm[h] = 0;
+  a.keys[h] = 0;
+  a.vals[h] = h;
+  if (a.best0) a.best0[h] = 0;
+}
+
 }  // namespace
 
 hipError_t launch_raycast(const RayArgs& a, hipStream_t s) {
@@ -684,9 +764,31 @@ hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, 
   return hipGetLastError();
 }
 
+hipError_t launch_coarse(const RayArgs& a, hipStream_t s) {
+  if (a.n_hyp <= 0) return hipSuccess;
+  switch (a.coarse) {
+    case 0:
+      return launch_smad(a, s);
+    case 1:
+    case 2:
+      if (a.nfov <= 0 || !a.fov_z || !a.fov_j) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(coarse_direct_kernel, dim3(a.n_hyp), dim3(RT),
+                         (size_t)2 * a.Ns * sizeof(double), s, a);
+      return hipGetLastError();
+    case 3:
+      hipLaunchKernelGGL(coarse_none_kernel, dim3((a.n_hyp + RT - 1) / RT), dim3(RT), 0, s, a);
+      return hipGetLastError();
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
-  const hipError_t e = launch_raycast(a, s);
-  return e != hipSuccess ? e : launch_smad(a, s);
+  if (a.coarse != 3) {
+    const hipError_t e = launch_raycast(a, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_coarse(a, s);
 }
 
 // Walk words from the squared EDT. The radius byte is 1 + s with

@@ -18,6 +18,11 @@
 // co-scheduling.
 // The median of eq. 27 is always the top-k_mid mean (top-k means are
 // non-increasing in k and k_low <= k_mid <= k_full).
+//
+// The score may also be one of the ablation metrics of Sec. IV (Case 3):
+// T_mean (eq. 34) from the same sums, or baseline (eq. 33) and LF (eq. 32)
+// from the sum of l over every valid beam (no selection). Scores are packed
+// with score_key, which orders negative LF values correctly.
 #include <cmath>
 
 #include "reloc_internal.h"
@@ -117,7 +122,7 @@ struct LatticeSrc {
 // any is used. The per-pose integer sums are parked in lane g; the FP64 tail
 // (eq. 27-31) then runs once for the four poses in lanes 0..3, and one
 // atomic max per wavefront publishes the best (T, tie).
-template <int R, int KB, class Src>
+template <int R, int KB, bool FULL, class Src>
 __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32_t* smem) {
   constexpr int SB = R >= 32 ? 8 : 4;  // keys per lane in flight together
   constexpr int G = THETA_PER_BLOCK / NW;
@@ -191,39 +196,57 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
         for (int s2 = 0; s2 < SB; ++s2) keys[i0 + s2] = NOKEY;
       }
     }
-    // k_mid-th smallest key: bitwise search for the largest t with fewer
-    // than k_mid keys below it; counts from wavefront ballots
-    uint32_t tkey = 0;
-    for (int bit = KB - 1; bit >= 0; --bit) {
-      const uint32_t cand = tkey | (1u << bit);
-      int cnt = 0;
+    int64_t sl = 0;
+    if constexpr (!FULL) {
+      // TAM and T_mean: the top-k_mid sum of eq. 24-27. The k_mid-th
+      // smallest key: bitwise search for the largest t with fewer than
+      // k_mid keys below it; counts from wavefront ballots
+      uint32_t tkey = 0;
+      for (int bit = KB - 1; bit >= 0; --bit) {
+        const uint32_t cand = tkey | (1u << bit);
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (64 * q < nv) cnt += __popcll(__ballot(keys[q] < cand));
+        if (cnt < a.kmid) tkey = cand;
+      }
+      int below = 0;
 #pragma unroll
       for (int q = 0; q < R; ++q)
-        if (64 * q < nv) cnt += __popcll(__ballot(keys[q] < cand));
-      if (cnt < a.kmid) tkey = cand;
-    }
-    int below = 0;
+        if (64 * q < nv) below += __popcll(__ballot(keys[q] < tkey));
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (64 * q < nv) below += __popcll(__ballot(keys[q] < tkey));
-    int64_t sl = 0;
+      for (int i0 = 0; i0 < R; i0 += SB) {
+        if (64 * i0 < nv) {
+          int32_t lv[SB];
 #pragma unroll
-    for (int i0 = 0; i0 < R; i0 += SB) {
-      if (64 * i0 < nv) {
-        int32_t lv[SB];
+          for (int s2 = 0; s2 < SB; ++s2)
+            lv[s2] = a.lut[keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u];
 #pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2)
-          lv[s2] = a.lut[keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u];
-#pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2)
-          if (keys[i0 + s2] < tkey) sl += lv[s2];
+          for (int s2 = 0; s2 < SB; ++s2)
+            if (keys[i0 + s2] < tkey) sl += lv[s2];
+        }
       }
+      sl = wave_sum(sl);
+      sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
+    } else {
+      // baseline and LF: the sum of l over every valid beam (eq. 32)
+#pragma unroll
+      for (int i0 = 0; i0 < R; i0 += SB) {
+        if (64 * i0 < nv) {
+          int32_t lv[SB];
+#pragma unroll
+          for (int s2 = 0; s2 < SB; ++s2)
+            lv[s2] = a.lut[keys[i0 + s2] != NOKEY ? keys[i0 + s2] : 0u];
+#pragma unroll
+          for (int s2 = 0; s2 < SB; ++s2)
+            if (keys[i0 + s2] != NOKEY) sl += lv[s2];
+        }
+      }
+      sl = wave_sum(sl);
     }
-    sl = wave_sum(sl);
     sumk = wave_sum(sumk);
     sumsq = wave_sum(sumsq);
     noff = wave_sum(noff);
-    sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
     if (lane == g) {
       p_sl = sl;
       p_sumk = sumk;
@@ -236,8 +259,6 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   const bool mine = lane < G && src.has(j);
   uint64_t packed = 0;
   if (mine) {
-    const double Lbar = (double)p_sl / (67108864.0 * (double)a.kmid);
-    const double Pl = exp(Lbar);
     const double nvd = (double)nv;
     const double sum_d = a.res * ((double)p_sumsq / 65536.0) + (double)p_noff * a.d_max;
     const double sum_d2 = a.res * a.res * (double)p_sumk + (double)p_noff * a.d_max * a.d_max;
@@ -247,10 +268,19 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     const double dmin = 0.5 * a.res;
     const double dt = fmin(fmax(dbar, dmin), a.d_max);
     const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
-    const double c = exp(-0.5 * var);
-    const float T = (float)cbrt(Pl * sd * c);
+    double v;
+    if constexpr (!FULL) {
+      const double Lbar = (double)p_sl / (67108864.0 * (double)a.kmid);
+      const double Pl = exp(Lbar);
+      const double c = exp(-0.5 * var);
+      v = a.fine == 0 ? cbrt(Pl * sd * c) : (Pl + sd + c) / 3.0;   // eq. 31 / eq. 34
+    } else {
+      const double lf = (double)p_sl / 67108864.0;                 // eq. 32
+      v = a.fine == 3 ? lf : sqrt(exp(lf / nvd) * sd);               // eq. 33
+    }
+    const float T = (float)v;
     src.record(j, T);
-    packed = ((uint64_t)__float_as_uint(T) << 32) | (uint64_t)src.tie(j);
+    packed = ((uint64_t)score_key(T) << 32) | (uint64_t)src.tie(j);
   }
   for (int off = G / 2; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(packed, off, 64);
@@ -260,7 +290,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
 }
 
 // Orientation tile kb of rank a.r0 + i.
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32_t* smem) {
   const int r = a.r0 + i;
   const int hyp = a.order[r];
@@ -273,7 +303,7 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   src.Ng = a.Ng;
   src.T_row = a.T_out ? a.T_out + (size_t)i * a.Nt : nullptr;
   src.dst = &a.best[r];
-  tam_tile<R, KB>(a, src, smem);
+  tam_tile<R, KB, FULL>(a, src, smem);
 }
 
 // Workgroup b of an n-workgroup grid runs on XCD b % 8 (round-robin
@@ -286,18 +316,18 @@ __device__ __forceinline__ int xcd_slice(int b, int n) {
   return x * q + min(x, rem) + i;
 }
 
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
   extern __shared__ int32_t smem[];
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   const int L = xcd_slice(blockIdx.x, gridDim.x);
-  tam_block<R, KB>(a, L / ntb, L % ntb, smem);
+  tam_block<R, KB, FULL>(a, L / ntb, L % ntb, smem);
 }
 
 // Local refinement, lattice tiles: workgroup b covers slot b / tiles and
 // lattice points [16 (b % tiles), + 16) around that slot's rank (its cell
 // and heading o k*, k* read from the rank's packed TAM best).
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void refine_kernel(RefineArgs a) {
   extern __shared__ int32_t smem[];
   const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
@@ -322,7 +352,7 @@ __global__ __launch_bounds__(TB) void refine_kernel(RefineArgs a) {
   src.Ng = t.Ng;
   src.kmap = t.kmap;
   src.dst = &a.rbest[slot];
-  tam_tile<R, KB>(t, src, smem);
+  tam_tile<R, KB, FULL>(t, src, smem);
 }
 
 // Refinement selection, one workgroup per stage b: the kr best ranks of
@@ -385,22 +415,23 @@ __global__ void refine_commit_kernel(RefineArgs a) {
   a.t.best[r] = (v & 0xFFFFFFFF00000000ull) | (uint64_t)code;
 }
 
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 hipError_t launch_refine_t(const RefineArgs& a, hipStream_t s) {
   const size_t lds = (size_t)tam_beams_padded(a.t.nv) * sizeof(int2);
   const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  hipLaunchKernelGGL((refine_kernel<R, KB>), dim3(tiles * a.n_slots), dim3(TB), lds, s, a);
+  hipLaunchKernelGGL((refine_kernel<R, KB, FULL>), dim3(tiles * a.n_slots), dim3(TB), lds, s,
+                     a);
   return hipGetLastError();
 }
 
-template <int KB>
+template <int KB, bool FULL>
 hipError_t launch_refine_kb(const RefineArgs& a, hipStream_t s) {
   const int R = (a.t.nv + 63) / 64;
-  if (R <= 4) return launch_refine_t<4, KB>(a, s);
-  if (R <= 8) return launch_refine_t<8, KB>(a, s);
-  if (R <= 16) return launch_refine_t<16, KB>(a, s);
-  if (R <= 32) return launch_refine_t<32, KB>(a, s);
-  if (R <= 64) return launch_refine_t<64, KB>(a, s);
+  if (R <= 4) return launch_refine_t<4, KB, FULL>(a, s);
+  if (R <= 8) return launch_refine_t<8, KB, FULL>(a, s);
+  if (R <= 16) return launch_refine_t<16, KB, FULL>(a, s);
+  if (R <= 32) return launch_refine_t<32, KB, FULL>(a, s);
+  if (R <= 64) return launch_refine_t<64, KB, FULL>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -416,7 +447,7 @@ __device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_
 
 // TAM over several rank ranges (of one or several requests) in one launch:
 // item e owns blocks [prefix[e], prefix[e + 1]) = nb x ceil(Nt / 16).
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict__ items,
                                                        const int64_t* __restrict__ prefix, int n) {
   extern __shared__ int32_t smem[];
@@ -425,25 +456,25 @@ __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict
   const TamArgs& a = items[e];
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   const int local = (int)(t - prefix[e]);
-  tam_block<R, KB>(a, local / ntb, local % ntb, smem);
+  tam_block<R, KB, FULL>(a, local / ntb, local % ntb, smem);
 }
 
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
   const size_t lds = (size_t)tam_beams_padded(a.nv) * sizeof(int2);
   const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  hipLaunchKernelGGL((tam_kernel<R, KB>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
+  hipLaunchKernelGGL((tam_kernel<R, KB, FULL>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
   return hipGetLastError();
 }
 
-template <int KB>
+template <int KB, bool FULL>
 hipError_t launch_tam_kb(const TamArgs& a, hipStream_t s) {
   const int R = (a.nv + 63) / 64;
-  if (R <= 4) return launch_tam_t<4, KB>(a, s);
-  if (R <= 8) return launch_tam_t<8, KB>(a, s);
-  if (R <= 16) return launch_tam_t<16, KB>(a, s);
-  if (R <= 32) return launch_tam_t<32, KB>(a, s);
-  if (R <= 64) return launch_tam_t<64, KB>(a, s);
+  if (R <= 4) return launch_tam_t<4, KB, FULL>(a, s);
+  if (R <= 8) return launch_tam_t<8, KB, FULL>(a, s);
+  if (R <= 16) return launch_tam_t<16, KB, FULL>(a, s);
+  if (R <= 32) return launch_tam_t<32, KB, FULL>(a, s);
+  if (R <= 64) return launch_tam_t<64, KB, FULL>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -466,7 +497,7 @@ __device__ __forceinline__ void stage_reduce_run(const StageArgs& a) {
     for (int q = 1; q < TB / 64; ++q)
       if (red[q] > best) best = red[q];
     a.stage_out[0] = best;
-    const float T = __uint_as_float((uint32_t)(best >> 32));
+    const float T = score_of_key((uint32_t)(best >> 32));
     a.flag_out[0] = ((double)T > a.tau) ? 1 : 0;
   }
 }
@@ -550,22 +581,22 @@ __global__ void rank_gather_batch_kernel(const RankArgs* __restrict__ reqs,
   rows[t] = row;
 }
 
-template <int R, int KB>
+template <int R, int KB, bool FULL>
 hipError_t launch_tam_batch_t(const TamArgs* items, const int64_t* prefix, int n, int64_t blocks,
                               size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((tam_batch_kernel<R, KB>), dim3((unsigned)blocks), dim3(TB), lds, s, items,
-                     prefix, n);
+  hipLaunchKernelGGL((tam_batch_kernel<R, KB, FULL>), dim3((unsigned)blocks), dim3(TB), lds, s,
+                     items, prefix, n);
   return hipGetLastError();
 }
 
-template <int KB>
+template <int KB, bool FULL>
 hipError_t launch_tam_batch_kb(int R, const TamArgs* items, const int64_t* prefix, int n,
                                int64_t blocks, size_t lds, hipStream_t s) {
-  if (R <= 4) return launch_tam_batch_t<4, KB>(items, prefix, n, blocks, lds, s);
-  if (R <= 8) return launch_tam_batch_t<8, KB>(items, prefix, n, blocks, lds, s);
-  if (R <= 16) return launch_tam_batch_t<16, KB>(items, prefix, n, blocks, lds, s);
-  if (R <= 32) return launch_tam_batch_t<32, KB>(items, prefix, n, blocks, lds, s);
-  if (R <= 64) return launch_tam_batch_t<64, KB>(items, prefix, n, blocks, lds, s);
+  if (R <= 4) return launch_tam_batch_t<4, KB, FULL>(items, prefix, n, blocks, lds, s);
+  if (R <= 8) return launch_tam_batch_t<8, KB, FULL>(items, prefix, n, blocks, lds, s);
+  if (R <= 16) return launch_tam_batch_t<16, KB, FULL>(items, prefix, n, blocks, lds, s);
+  if (R <= 32) return launch_tam_batch_t<32, KB, FULL>(items, prefix, n, blocks, lds, s);
+  if (R <= 64) return launch_tam_batch_t<64, KB, FULL>(items, prefix, n, blocks, lds, s);
   return hipErrorInvalidValue;
 }
 
@@ -573,8 +604,10 @@ hipError_t launch_tam_batch_kb(int R, const TamArgs* items, const int64_t* prefi
 
 hipError_t launch_tam(const TamArgs& a, hipStream_t s) {
   if (a.nb <= 0) return hipSuccess;
-  if (a.keybits <= 12) return launch_tam_kb<12>(a, s);
-  if (a.keybits <= 16) return launch_tam_kb<16>(a, s);
+  if (a.fine < 0 || a.fine > 3) return hipErrorInvalidValue;
+  const bool full = a.fine >= 2;
+  if (a.keybits <= 12) return full ? launch_tam_kb<12, true>(a, s) : launch_tam_kb<12, false>(a, s);
+  if (a.keybits <= 16) return full ? launch_tam_kb<16, true>(a, s) : launch_tam_kb<16, false>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -591,8 +624,12 @@ hipError_t launch_refine(const RefineArgs& a, hipStream_t s) {
   const int w = 2 * a.h + 1;
   if (a.h < 0 || a.h > 15 || a.s < 0 || a.s >= a.t.Ng || a.L != (2 * a.s + 1) * w * w)
     return hipErrorInvalidValue;
-  if (a.t.keybits <= 12) return launch_refine_kb<12>(a, s);
-  if (a.t.keybits <= 16) return launch_refine_kb<16>(a, s);
+  if (a.t.fine < 0 || a.t.fine > 3) return hipErrorInvalidValue;
+  const bool full = a.t.fine >= 2;
+  if (a.t.keybits <= 12)
+    return full ? launch_refine_kb<12, true>(a, s) : launch_refine_kb<12, false>(a, s);
+  if (a.t.keybits <= 16)
+    return full ? launch_refine_kb<16, true>(a, s) : launch_refine_kb<16, false>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -606,7 +643,8 @@ int tam_class(const TamArgs& a) {
   const int R = (a.nv + 63) / 64;
   const int rc = R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : R <= 32 ? 3 : R <= 64 ? 4 : -1;
   const int kc = a.keybits <= 12 ? 0 : a.keybits <= 16 ? 1 : -1;
-  return (rc < 0 || kc < 0) ? -1 : kc * 5 + rc;
+  if (rc < 0 || kc < 0 || a.fine < 0 || a.fine > 3) return -1;
+  return (a.fine >= 2 ? 10 : 0) + kc * 5 + rc;
 }
 
 size_t tam_lds_bytes(const TamArgs& a) { return (size_t)tam_beams_padded(a.nv) * sizeof(int2); }
@@ -615,9 +653,14 @@ hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix
                             int64_t blocks, size_t lds, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return hipSuccess;
   static const int Rs[5] = {4, 8, 16, 32, 64};
-  if (cls < 0 || cls >= 10) return hipErrorInvalidValue;
-  if (cls >= 5) return launch_tam_batch_kb<16>(Rs[cls - 5], items, prefix, n, blocks, lds, s);
-  return launch_tam_batch_kb<12>(Rs[cls], items, prefix, n, blocks, lds, s);
+  if (cls < 0 || cls >= kTamClasses) return hipErrorInvalidValue;
+  const int R = Rs[cls % 5];
+  switch (cls / 5) {
+    case 0: return launch_tam_batch_kb<12, false>(R, items, prefix, n, blocks, lds, s);
+    case 1: return launch_tam_batch_kb<16, false>(R, items, prefix, n, blocks, lds, s);
+    case 2: return launch_tam_batch_kb<12, true>(R, items, prefix, n, blocks, lds, s);
+    default: return launch_tam_batch_kb<16, true>(R, items, prefix, n, blocks, lds, s);
+  }
 }
 
 hipError_t launch_stage_reduce_multi(const StageArgs& a, int K, int ns, int n, hipStream_t s) {

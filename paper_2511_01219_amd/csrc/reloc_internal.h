@@ -50,9 +50,18 @@ struct RayArgs {
   int chunk;                 // skip variant: rays owned by one wavefront
   int32_t* dbg_hit;          // optional [n_hyp][Ns]
   int32_t* dbg_steps;        // optional [n_hyp][Ns] traversal iterations per ray
+  // coarse metric that orders the hypotheses: 0 SMAD by prefix sums
+  // (eq. 17-20, smad_kernel); 1 SMAD by direct sums and 2 CAER (eq. 21),
+  // both by coarse_direct_kernel; 3 none (zero keys: the set's own order)
+  int coarse;
+  const double* fov_z;       // [nfov] measured z' of each FoV beam in beam order (0 invalid)
+  const int32_t* fov_j;      // [nfov] panoramic index of each FoV beam
 };
 hipError_t launch_raycast(const RayArgs& a, hipStream_t s);   // ranges into zbuf
 hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, argm, keys
+// The coarse metric a.coarse (prefix-sum SMAD, direct-sum SMAD, CAER or
+// none) into smad, argm, keys, vals (and best0 cleared); none needs no ranges.
+hipError_t launch_coarse(const RayArgs& a, hipStream_t s);
 hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
 // Several requests in one launch each. reqs: device RayArgs[n]; prefix:
 // device int64[n + 1] block offsets (ray cast: chunks of a.chunk rays with the
@@ -109,8 +118,10 @@ struct TamArgs {
   int kcap, key_off, keybits;
   int kmid;
   double res, d_max;
+  int fine;                  // score: 0 T (eq. 31), 1 T_mean (eq. 34), 2 baseline (eq. 33),
+                             // 3 LF (eq. 32)
   float* T_out;              // optional [nb][Nt]
-  uint64_t* best;            // [>= r0 + nb] packed (T bits, ~k) per rank
+  uint64_t* best;            // [>= r0 + nb] packed (score_key(T), ~k) per rank
 };
 hipError_t launch_tam(const TamArgs& a, hipStream_t s);
 // Beam-table length the TAM kernels read: nv rounded up to 512, a whole
@@ -128,7 +139,7 @@ __host__ __device__ inline int tam_beams_padded(int nv) {
 struct RefineArgs {
   TamArgs t;                 // TAM tables of the request; t.best per rank
   const int32_t* sel;        // [n_slots] rank refined in each slot, -1 none
-  uint64_t* rbest;           // [n_slots] lattice best (T bits, ~tie key)
+  uint64_t* rbest;           // [n_slots] lattice best (score_key(T), ~tie key)
   int n_slots;
   int h, s, L;               // half-widths (cells, headings), lattice size
 };
@@ -136,16 +147,27 @@ struct RefineArgs {
 // its kr best ranks by (T desc, rank asc), or -1; clears their rbest.
 hipError_t launch_refine_select(const uint64_t* best, int r0, int K, int n, int ns, int kr,
                                 int32_t* sel, uint64_t* rbest, hipStream_t s);
-// Lattice TAM of every slot into rbest (atomic max of (T bits, ~tie key)).
+// Lattice TAM of every slot into rbest (atomic max of (score key, ~tie key)).
 hipError_t launch_refine(const RefineArgs& a, hipStream_t s);
-// best[sel[j]] = (refined T bits, g << 10 | (dy + 15) << 5 | (dx + 15)).
+// best[sel[j]] = (refined score key, g << 10 | (dy + 15) << 5 | (dx + 15)).
 hipError_t launch_refine_commit(const RefineArgs& a, hipStream_t s);
+
+// The packed per-rank words hold an order-preserving 32-bit key of the
+// score in their high half (larger score, larger key; negative scores too).
+__host__ __device__ inline uint32_t score_key(float v) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline float score_of_key(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __builtin_bit_cast(float, b);
+}
 
 struct StageArgs {
   const uint64_t* best;      // per rank
   int r0, nb;
   double tau;                // NaN: never stop
-  uint64_t* stage_out;       // [1] packed (T bits, ~rank)
+  uint64_t* stage_out;       // [1] packed (score_key(T), ~rank)
   int32_t* flag_out;         // [1] 1 = stop
 };
 hipError_t launch_stage_reduce(const StageArgs& a, hipStream_t s);
@@ -176,8 +198,10 @@ hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
                              const double* smad, int nrow, PoseRow* rows, hipStream_t s);
 
 // ---- batched TAM / stage control / ranking -------------------------------
-// Kernel class of a TAM argument set (keys per lane x histogram bits), -1 if
-// unsupported; items of one launch share a class.
+// Kernel class of a TAM argument set (keys per lane x key bits x whether
+// the score needs the full l sum), -1 if unsupported; items of one launch
+// share a class.
+constexpr int kTamClasses = 20;
 int tam_class(const TamArgs& a);
 size_t tam_lds_bytes(const TamArgs& a);
 // items: device TamArgs[n] (each a rank range of one request); prefix:

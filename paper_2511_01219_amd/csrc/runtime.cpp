@@ -125,6 +125,8 @@ int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double re
       const float z = sc->ranges[src];
       const bool ok = std::isfinite(z) && z >= sc->range_min && z <= sc->range_max;
       ++nfov;
+      P.fj.push_back(jj);
+      P.fz.push_back(ok ? (double)z : 0.0);
       if (ok) {
         sum += (double)z;
         ++nvalid;
@@ -378,6 +380,11 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.beams = req_alloc<int2>(c, R, nvp);
   R.dirs = req_alloc<int2>(c, R, 2 * (size_t)Ng);
   R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
+  const bool direct = R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2;
+  if (direct) {
+    R.fov_z = req_alloc<double>(c, R, R.prep.fz.size());
+    R.fov_j = req_alloc<int32_t>(c, R, R.prep.fj.size());
+  }
   R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
   R.perm = req_alloc<int32_t>(c, R, n);
   R.smad = req_alloc<double>(c, R, n);
@@ -419,6 +426,10 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   std::copy(U.begin(), U.end(), U2.begin() + Ng);
   if (int32_t e = upload(c, R.dirs, U2.data(), U2.size())) return e;
   if (int32_t e = upload(c, R.dlut, R.lut.q.data(), R.lut.q.size())) return e;
+  if (direct) {
+    if (int32_t e = upload(c, R.fov_z, R.prep.fz.data(), R.prep.fz.size())) return e;
+    if (int32_t e = upload(c, R.fov_j, R.prep.fj.data(), R.prep.fj.size())) return e;
+  }
   // casting order: Morton (Z-order) of the hypothesis cells, so that the rays
   // in flight on one XCD start in one compact region of the map
   std::vector<std::pair<uint32_t, int32_t>> mc(n);
@@ -489,6 +500,9 @@ RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps)
   a.vals = R.vals;
   a.dbg_hit = dbg_hit;
   a.dbg_steps = dbg_steps;
+  a.coarse = R.prm.coarse_metric;
+  a.fov_z = R.fov_z;
+  a.fov_j = R.fov_j;
   return a;
 }
 
@@ -516,6 +530,7 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   a.kmid = I.k_mid;
   a.res = m.res;
   a.d_max = R.prm.d_max;
+  a.fine = R.prm.fine_metric;
   a.T_out = T_out;
   a.best = R.best;
   return a;
@@ -600,7 +615,20 @@ int32_t validate_search(const reloc_search_params* p) {
   if (p->refine_cells < 0 || p->refine_cells > 15)
     return fail(RELOC_E_INVALID, "refine_cells must be in 0..15");
   if (p->refine_dirs < -1) return fail(RELOC_E_INVALID, "refine_dirs must be >= -1");
+  if (p->coarse_metric < 0 || p->coarse_metric > 3)
+    return fail(RELOC_E_INVALID, "coarse_metric must be in 0..3");
+  if (p->fine_metric < 0 || p->fine_metric > 3)
+    return fail(RELOC_E_INVALID, "fine_metric must be in 0..3");
   return RELOC_OK;
+}
+
+int64_t coarse_evals(const Request& R) {
+  const reloc_scan_info& I = R.prep.info;
+  switch (R.prm.coarse_metric) {
+    case 2: return (int64_t)R.n_hyp * ((I.Ns + R.prm.n_skip_enum - 1) / R.prm.n_skip_enum);
+    case 3: return 0;
+    default: return (int64_t)R.n_hyp * I.n_shifts;
+  }
 }
 
 int32_t refine_lattice(const reloc_search_params* p, const reloc_scan_info& I, int* h, int* s,
@@ -650,6 +678,7 @@ size_t request_bytes(const Request& R) {
   b += (size_t)std::min<size_t>(n, (size_t)R.prm.k_out) * sizeof(PoseRow);
   if (R.prm.refine_k > 0)
     b += (size_t)std::max(plain_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
+  if (R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2) b += (size_t)I.n_fov * 12;
   b += 2 * n * 12 + (1 << 20);                                  // sort scratch
   b += 32 * 256;                                                // allocation rounding
   return b;
@@ -686,8 +715,7 @@ void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, in
     p.y = m.oy + ((double)iy + 0.5) * m.res;
     if (th >= M_PI) th -= 2.0 * M_PI;
     p.theta = th;
-    uint32_t tb32 = w.tbits;
-    std::memcpy(&p.tam, &tb32, sizeof(float));
+    p.tam = score_of_key(w.tbits);
     p.smad = (float)w.smad;
     p.hyp = w.hyp;
     p.rank = w.rank;
@@ -729,6 +757,8 @@ void reloc_search_defaults(reloc_search_params* p) {
   p->refine_k = 0;
   p->refine_cells = 3;
   p->refine_dirs = -1;
+  p->coarse_metric = 0;
+  p->fine_metric = 0;
 }
 
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
@@ -1023,9 +1053,9 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   RayArgs ra = ray_args(c, R, nullptr, nullptr);
   ra.best0 = R.best;                 // the SMAD kernel clears the per-rank best
   HIP_TRY(hipEventRecord(c->ev[0], s));
-  HIP_TRY(launch_raycast(ra, s));
+  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));   // none needs no ranges
   HIP_TRY(hipEventRecord(c->ev[5], s));
-  HIP_TRY(launch_smad(ra, s));
+  HIP_TRY(launch_coarse(ra, s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
   if (int32_t e = smad_order(c, R)) return e;
   HIP_TRY(hipEventRecord(c->ev[2], s));
@@ -1109,9 +1139,9 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->n_hyp = R.n_hyp;
-    st->smad_evals = (int64_t)R.n_hyp * I.n_shifts;
+    st->smad_evals = coarse_evals(R);
     st->tam_evals = (int64_t)n_eval * I.Ntheta;
-    st->rays = (int64_t)R.n_hyp * I.Ns;
+    st->rays = R.prm.coarse_metric == 3 ? 0 : (int64_t)R.n_hyp * I.Ns;
     st->tam_lookups = st->tam_evals * I.n_valid;
     st->stages = stages;
     st->early_stopped = stopped;
@@ -1276,8 +1306,7 @@ int32_t reloc_debug_tam(reloc_ctx* c, int32_t request_id, int32_t r0, int32_t n,
   c->dfree(dT);
   if (e != hipSuccess) return fail(RELOC_E_DEVICE, "debug TAM failed: %s", hipGetErrorString(e));
   for (int i = 0; i < n; ++i) {
-    const uint32_t tb32 = (uint32_t)(best[i] >> 32);
-    if (tstar) std::memcpy(&tstar[i], &tb32, sizeof(float));
+    if (tstar) tstar[i] = score_of_key((uint32_t)(best[i] >> 32));
     if (kstar) kstar[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(best[i] & 0xFFFFFFFFu));
   }
   return RELOC_OK;

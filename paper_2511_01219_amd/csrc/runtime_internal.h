@@ -36,6 +36,8 @@ struct Prep {
   reloc_scan_info info{};
   std::vector<int2> runs;         // (panoramic start, length) per FoV run
   std::vector<int32_t> vj, vzq;   // valid beams: panoramic index, range in Q8 cells
+  std::vector<int32_t> fj;        // FoV beams in beam order: panoramic index
+  std::vector<double> fz;         //   and measured range z' (0 when invalid)
 };
 int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double res, Prep* out);
 
@@ -93,6 +95,8 @@ struct Request {
   int32_t* perm = nullptr;        // hypotheses in Morton order of their cells
   int2* runs = nullptr;
   int2* beams = nullptr;          // valid beams (direction base, Q8 range), padded
+  double* fov_z = nullptr;        // FoV beams' z' and panoramic index (direct coarse
+  int32_t* fov_j = nullptr;       // metrics only)
   int2* dirs = nullptr;
   int32_t* dlut = nullptr;
   // device work
@@ -177,6 +181,8 @@ namespace reloc {
 int32_t set_device(reloc_ctx* c);
 void release_request(reloc_ctx* c, Request& r);
 int32_t validate_search(const reloc_search_params* p);
+// Coarse-metric evaluations of a request (hypotheses x shifts scored).
+int64_t coarse_evals(const Request& R);
 // Refinement lattice of a request: half-widths h (cells), s (Ng headings;
 // refine_dirs < 0 means Ng / N_theta) and size L = (2s + 1)(2h + 1)^2;
 // RELOC_E_INVALID when s >= Ng or L > 65536.

@@ -154,6 +154,20 @@ def test_search_param_defaults():
     q = reloc.search_params(tau=None)
     assert math.isnan(q.tau)
     assert (p.refine_k, p.refine_cells, p.refine_dirs) == (0, 3, -1)
+    assert (p.coarse_metric, p.fine_metric) == (0, 0)
+
+
+def test_metric_choices_checked_on_host():
+    z = np.full(360, 2.0, np.float32)
+    inc = 2 * math.pi / 360
+    for cm in range(4):
+        for fm in range(4):
+            reloc.scan_info(z, -math.pi, inc, 0.05, coarse_metric=cm, fine_metric=fm)
+    for kw in (dict(coarse_metric=4), dict(coarse_metric=-1), dict(fine_metric=4),
+               dict(fine_metric=-1)):
+        with pytest.raises(reloc.RelocError) as ei:
+            reloc.scan_info(z, -math.pi, inc, 0.05, **kw)
+        assert ei.value.code == reloc.E_INVALID, kw
 
 
 def test_refinement_limits():
