@@ -80,6 +80,8 @@ def _declare(L):
     L.orc_sample.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, i32,
                              f64, f64, u64, i32, vp, vp]
     L.orc_num_threads.argtypes = []
+    L.orc_rrt.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, f64, f64, f64,
+                          i32, u64, i32, i32, vp, vp, vp, vp]
 
 
 def num_threads() -> int:
@@ -296,6 +298,31 @@ def sample(occ: np.ndarray, kmap: np.ndarray, res: float, origin=(0.0, 0.0),
     if st != 0:
         raise ValueError("orc_sample failed: %d" % st)
     return out[:int(n[0])].copy()
+
+
+def rrt(occ: np.ndarray, kmap: np.ndarray, res: float, p0, origin=(0.0, 0.0),
+        rho: float = 0.3, robot_radius: float = 0.21, eta_max: float = 0.6,
+        eps_gain: int = 2, seed: int = 0, max_rounds: int = 64,
+        max_nodes: int = 2_000_000, thr: int = 65) -> Dict:
+    """Traversability-constrained RRT sampling (Algorithm 1): tree nodes
+    [n, 2] (FP64, world), parents, representative cells [m, 2] (x, y) in node
+    order, and (rounds, attempts, nodes, N_sampling)."""
+    occ = np.ascontiguousarray(occ, dtype=np.int8)
+    kmap = np.ascontiguousarray(kmap, dtype=np.int64)
+    H, W = occ.shape
+    nodes = np.empty((max_nodes, 2), dtype=np.float64)
+    par = np.empty(max_nodes, dtype=np.int32)
+    cells = np.empty((max_nodes, 2), dtype=np.int32)
+    info = np.zeros(4, dtype=np.int64)
+    nc = lib().orc_rrt(W, H, _p(occ), thr, _p(kmap), res, origin[0], origin[1], p0[0], p0[1],
+                       rho, robot_radius, eta_max, eps_gain,
+                       ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), max_rounds, max_nodes,
+                       _p(nodes), _p(par), _p(cells), _p(info))
+    if nc < 0:
+        raise ValueError("orc_rrt failed: %d" % nc)
+    n = int(info[2])
+    return dict(nodes=nodes[:n].copy(), parent=par[:n].copy(), cells=cells[:nc].copy(),
+                rounds=int(info[0]), attempts=int(info[1]), n_sampling=int(info[3]))
 
 
 def heading(k: int, Ntheta: int) -> float:

@@ -863,6 +863,143 @@ int orc_sample(int W, int H, const int8_t* occ, int thr, const i64* kmap, double
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Traversability-constrained RRT sampling (Algorithm 1, Sec. III-A items
+// 1-7, Remark 4), literal, with a brute-force NearestNode. Readings where
+// the paper is silent:
+//   * random point: attempt t (counted over all rounds from 0) draws
+//     u = (mix64(seed + 2t) >> 11) 2^-53 and v from seed + 2t + 1;
+//     p_rand = (ox + u (W res), oy + v (H res)) (B = the map rectangle);
+//   * NearestNode: smallest FP64 (dx*dx + dy*dy), ties: smallest node index;
+//   * MinDistToObstacle(p) = sqrt(k) res of the cell holding p (EDT lookup);
+//     no occupied cell at all: infinite;
+//   * AdaptiveExpandDist: eta_max if d >= 2 r_robot, r_robot if d <= r_robot,
+//     else r_robot + (eta_max - r_robot)(d - r_robot) / r_robot;
+//   * ExtendPoint: p_rand itself when |p_rand - p_nearest| <= eta, else the
+//     point at distance eta towards it (s = eta / L; p = p_near + s v);
+//     L == 0 adds nothing;
+//   * TraversabilityCheck: the points p_near + (i/n)(p_new - p_near),
+//     i = 0..n, n = max(1, ceil(L / (res/2))), each in a known-free in-map
+//     cell with k >= ceil((r_robot/res)^2 - 1e-9) (d_obs >= r_robot);
+//   * VoxelDownsample: voxels of side rho from the map origin, each
+//     represented by its first node (smallest index); gain = new voxels;
+//   * the root p0 must pass the same cell test; rounds stop when gain <=
+//     eps_gain, after max_rounds, or when the tree holds max_nodes nodes.
+// Output: the nodes (x, y, parent) in insertion order, the representatives'
+// cells in node order without repeated cells, and info = (rounds, attempts,
+// nodes, N_sampling).
+// ---------------------------------------------------------------------------
+int orc_rrt(int W, int H, const int8_t* occ, int thr, const i64* kmap, double res, double ox,
+            double oy, double p0x, double p0y, double rho, double r_robot, double eta_max,
+            int eps_gain, u64 seed, int max_rounds, int max_nodes, double* nodes_xy,
+            int32_t* parent, int32_t* cells_xy, i64* info) {
+  for (int i = 0; i < 4; ++i) info[i] = 0;
+  const double q = r_robot / res;
+  const i64 Kr = (i64)std::ceil(q * q - 1e-9);
+  auto cell_of = [&](double x, double y, i64* cx, i64* cy) {
+    *cx = (i64)std::floor((x - ox) / res);
+    *cy = (i64)std::floor((y - oy) / res);
+  };
+  auto feasible = [&](double x, double y) {
+    i64 cx, cy;
+    cell_of(x, y, &cx, &cy);
+    if (cx < 0 || cx >= W || cy < 0 || cy >= H) return false;
+    const i64 c = cy * W + cx;
+    return is_free(occ[c], thr) && kmap[c] >= Kr;
+  };
+  if (!feasible(p0x, p0y)) return -5;
+  const i64 N = (i64)std::ceil((double)W * (double)H * res * res / (rho * rho));
+  info[3] = N;
+  std::vector<double> nx{p0x}, ny{p0y};
+  std::vector<int32_t> par{-1};
+  const double wx = (double)W * res, wy = (double)H * res;
+  const i64 VW = (i64)std::ceil(wx / rho) + 1;
+  std::vector<int32_t> reps;         // representative node per voxel, in node order
+  std::vector<uint8_t> have;         // voxel key -> represented
+  const i64 VH = (i64)std::ceil(wy / rho) + 1;
+  have.assign((size_t)(VW * VH), 0);
+  size_t scanned = 0;                // nodes already downsampled
+  i64 t = 0;
+  int rounds = 0;
+  bool full = false;
+  while (true) {
+    for (i64 i = 0; i < N && !full; ++i, ++t) {
+      const double u = (double)(mix64(seed + 2 * (u64)t) >> 11) * (1.0 / 9007199254740992.0);
+      const double v = (double)(mix64(seed + 2 * (u64)t + 1) >> 11) * (1.0 / 9007199254740992.0);
+      const double rx = ox + u * wx, ry = oy + v * wy;
+      // NearestNode (brute force)
+      size_t best = 0;
+      double bd = 0.0;
+      for (size_t j = 0; j < nx.size(); ++j) {
+        const double dx = nx[j] - rx, dy = ny[j] - ry;
+        const double d2 = dx * dx + dy * dy;
+        if (j == 0 || d2 < bd) { bd = d2; best = j; }
+      }
+      const double px = nx[best], py = ny[best];
+      // AdaptiveExpandDist
+      i64 cx, cy;
+      cell_of(px, py, &cx, &cy);
+      const i64 kk = kmap[cy * W + cx];
+      const double d = kk < 0 ? INFINITY : std::sqrt((double)kk) * res;
+      double eta;
+      if (d >= 2.0 * r_robot) eta = eta_max;
+      else if (d <= r_robot) eta = r_robot;
+      else eta = r_robot + (eta_max - r_robot) * (d - r_robot) / r_robot;
+      // ExtendPoint
+      const double vx = rx - px, vy = ry - py;
+      const double L = std::sqrt(vx * vx + vy * vy);
+      if (L == 0.0) continue;
+      double ex, ey;
+      if (L <= eta) { ex = rx; ey = ry; }
+      else { const double sc = eta / L; ex = px + vx * sc; ey = py + vy * sc; }
+      // InSamplingBoundary and TraversabilityCheck
+      if (!(ex >= ox && ex < ox + wx && ey >= oy && ey < oy + wy)) continue;
+      const double sx = ex - px, sy = ey - py;
+      const double Ls = std::sqrt(sx * sx + sy * sy);
+      const i64 n = std::max<i64>(1, (i64)std::ceil(Ls / (0.5 * res)));
+      bool ok = true;
+      for (i64 k2 = 0; k2 <= n && ok; ++k2) {
+        const double tt = (double)k2 / (double)n;
+        ok = feasible(px + sx * tt, py + sy * tt);
+      }
+      if (!ok) continue;
+      nx.push_back(ex);
+      ny.push_back(ey);
+      par.push_back((int32_t)best);
+      if ((int)nx.size() >= max_nodes) full = true;
+    }
+    ++rounds;
+    // VoxelDownsample over the new nodes (earlier voxels keep their node)
+    i64 gain = 0;
+    for (; scanned < nx.size(); ++scanned) {
+      const i64 vx = (i64)std::floor((nx[scanned] - ox) / rho);
+      const i64 vy = (i64)std::floor((ny[scanned] - oy) / rho);
+      const i64 key = vy * VW + vx;
+      if (!have[key]) { have[key] = 1; reps.push_back((int32_t)scanned); ++gain; }
+    }
+    if (gain <= eps_gain || rounds >= max_rounds || full) break;
+  }
+  for (size_t j = 0; j < nx.size(); ++j) {
+    nodes_xy[2 * j] = nx[j];
+    nodes_xy[2 * j + 1] = ny[j];
+    parent[j] = par[j];
+  }
+  std::vector<uint8_t> used((size_t)W * H, 0);
+  i64 nc = 0;
+  for (int32_t r : reps) {
+    i64 cx, cy;
+    cell_of(nx[r], ny[r], &cx, &cy);
+    const i64 c = cy * W + cx;
+    if (used[c]) continue;
+    used[c] = 1;
+    cells_xy[2 * nc] = (int32_t)cx;
+    cells_xy[2 * nc + 1] = (int32_t)cy;
+    ++nc;
+  }
+  info[0] = rounds; info[1] = t; info[2] = (i64)nx.size();
+  return (int)nc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
