@@ -147,6 +147,53 @@ int32_t reloc_sample_hypotheses(reloc_ctx* ctx, int32_t map_id,
                                 const reloc_sample_params* params, int32_t* set_id,
                                 int32_t* n_out);
 
+/* Traversability-constrained RRT sampling (Algorithm 1; Sec. III-A items
+ * 1-7; Remark 4), run on the host copy of the map (tree growth is
+ * sequential), producing a hypothesis set. Rounds of N_sampling =
+ * ceil(W H res^2 / rho^2) expansion attempts; attempt t (counted over all
+ * rounds from 0) draws p_rand = (ox + u W res, oy + v H res) with
+ * u = (splitmix64(seed + 2t) >> 11) 2^-53, v likewise from seed + 2t + 1;
+ *   NearestNode : smallest FP64 dx*dx + dy*dy, ties: smallest node index;
+ *   eta         : AdaptiveExpandDist of p_nearest from d = sqrt(k) res of its
+ *                 cell: eta_max if d >= 2 r_robot, r_robot if d <= r_robot,
+ *                 r_robot + (eta_max - r_robot)(d - r_robot)/r_robot between;
+ *   p_new       : p_rand when |p_rand - p_nearest| <= eta, else p_nearest +
+ *                 (eta / L)(p_rand - p_nearest); L == 0 adds nothing;
+ *   accepted    : p_new inside the map rectangle (InSamplingBoundary) and
+ *                 every point p_nearest + (i/n)(p_new - p_nearest), i = 0..n,
+ *                 n = max(1, ceil(L / (res/2))), in a known-free cell with
+ *                 k >= ceil((r_robot/res)^2 - 1e-9) (TraversabilityCheck);
+ *   VoxelDownsample: voxels of side rho from the map origin, each
+ *                 represented by its first node; gain = new voxels per round.
+ * Rounds stop when gain <= eps_gain, after max_rounds, or at max_nodes
+ * nodes. The set holds the representatives' cells in node order, without
+ * repeats. p0 (the tree root, Algorithm 1's map origin) must be traversable
+ * (RELOC_E_EMPTY otherwise).
+ *   info     : counts of the run (may be NULL);
+ *   nodes_xy : optional host double[2 * nodes_cap], the tree nodes (world);
+ *   parent   : optional host int32[nodes_cap], each node's parent (-1 root). */
+typedef struct {
+  double p0_x, p0_y;        /* tree root, world */
+  double rho;               /* sampling spacing (voxel side), metres (0.3) */
+  double robot_radius;      /* r_robot, metres (0.21) */
+  double eta_max;           /* maximum expansion distance, metres (0.6) */
+  int32_t eps_gain;         /* gain threshold (2) */
+  int32_t max_rounds;       /* at most this many rounds (64) */
+  int32_t max_nodes;        /* at most this many tree nodes (16 M) */
+  uint64_t seed;
+} reloc_rrt_params;
+
+typedef struct {
+  int64_t rounds, attempts, nodes, n_sampling;
+} reloc_rrt_info;
+
+/* Fills the defaults listed above (p0 = (0, 0)). */
+void reloc_rrt_defaults(reloc_rrt_params* p);
+
+int32_t reloc_sample_rrt(reloc_ctx* ctx, int32_t map_id, const reloc_rrt_params* params,
+                         int32_t* set_id, int32_t* n_out, reloc_rrt_info* info,
+                         double* nodes_xy, int32_t* parent, int32_t nodes_cap);
+
 /* A caller-supplied set: cell_xy = host int32[2*n] (ix, iy) pairs of free
  * in-map cells. */
 int32_t reloc_set_hypotheses(reloc_ctx* ctx, int32_t map_id, const int32_t* cell_xy,

@@ -212,6 +212,28 @@ class Context:
                                                  C.byref(sid), C.byref(n)))
         return sid.value, n.value
 
+    def sample_rrt(self, map_id: int, p0, rho: float = 0.3, robot_radius: float = 0.21,
+                   eta_max: float = 0.6, eps_gain: int = 2, seed: int = 0,
+                   max_rounds: int = 64, max_nodes: int = 16 << 20, tree_cap: int = 0):
+        """Traversability-constrained RRT hypothesis set (Algorithm 1): returns
+        (set_id, n, info) and, with tree_cap > 0, the first tree_cap nodes
+        ([n, 2] world) and parents."""
+        p = _abi.reloc_rrt_params(float(p0[0]), float(p0[1]), float(rho), float(robot_radius),
+                                  float(eta_max), int(eps_gain), int(max_rounds),
+                                  int(max_nodes), int(seed) & 0xFFFFFFFFFFFFFFFF)
+        sid, n = C.c_int32(), C.c_int32()
+        info = _abi.reloc_rrt_info()
+        nodes = np.empty((max(0, tree_cap), 2), dtype=np.float64) if tree_cap > 0 else None
+        par = np.empty(max(0, tree_cap), dtype=np.int32) if tree_cap > 0 else None
+        _check(self._lib.reloc_sample_rrt(self._h, int(map_id), C.byref(p), C.byref(sid),
+                                          C.byref(n), C.byref(info), _ptr(nodes), _ptr(par),
+                                          int(tree_cap)))
+        inf = {f: getattr(info, f) for f, _ in info._fields_}
+        if tree_cap > 0:
+            k = min(tree_cap, inf["nodes"])
+            return sid.value, n.value, inf, nodes[:k], par[:k]
+        return sid.value, n.value, inf
+
     def set_hypotheses(self, map_id: int, cell_xy: np.ndarray) -> int:
         xy = np.ascontiguousarray(cell_xy, dtype=np.int32).reshape(-1, 2)
         sid = C.c_int32()

@@ -93,6 +93,18 @@ class reloc_serve_stats(C.Structure):
                 ("busy_s", C.c_double)]
 
 
+class reloc_rrt_params(C.Structure):
+    _fields_ = [("p0_x", C.c_double), ("p0_y", C.c_double), ("rho", C.c_double),
+                ("robot_radius", C.c_double), ("eta_max", C.c_double),
+                ("eps_gain", C.c_int32), ("max_rounds", C.c_int32), ("max_nodes", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class reloc_rrt_info(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("attempts", C.c_int64), ("nodes", C.c_int64),
+                ("n_sampling", C.c_int64)]
+
+
 # name -> (restype, argtypes)
 PROTOS = {
     "reloc_version": (C.c_int32, []),
@@ -113,6 +125,11 @@ PROTOS = {
     "reloc_read_hypotheses": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
                                           C.POINTER(C.c_int32)]),
     "reloc_free_hypotheses": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "reloc_rrt_defaults": (None, [C.POINTER(reloc_rrt_params)]),
+    "reloc_sample_rrt": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(reloc_rrt_params),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(reloc_rrt_info), C.c_void_p, C.c_void_p,
+                                     C.c_int32]),
     "reloc_search_defaults": (None, [C.POINTER(reloc_search_params)]),
     "reloc_scan_info_get": (C.c_int32, [C.POINTER(reloc_scan), C.POINTER(reloc_search_params),
                                         C.c_double, C.POINTER(reloc_scan_info)]),

@@ -204,6 +204,16 @@ size_t request_bytes(const Request& R);
 // Converts device result rows to poses in world coordinates.
 void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, int n,
                    reloc_pose* out);
+// Host copy of the map's EDT (copied from the device on first use).
+int32_t ensure_khost(reloc_ctx* c, DevMap& m);
+// Registers a hypothesis set of (ix, iy) cells on the map.
+int32_t new_set(reloc_ctx* c, int map_id, std::vector<int32_t>&& xy, int32_t* set_id);
+// Traversability-constrained RRT on the host copy of a map (rrt.cpp):
+// hypothesis cells (x, y pairs), optionally the tree (x, y pairs and
+// parents), and the run's counts.
+int32_t rrt_sample(const DevMap& m, const reloc_rrt_params* p, std::vector<int32_t>* cells,
+                   std::vector<double>* nodes, std::vector<int32_t>* parents,
+                   reloc_rrt_info* info);
 ServeState* serve_create();
 void ctx_stop_serving(reloc_ctx* c);
 // true while a queued or running served request uses the set
