@@ -392,6 +392,8 @@ def main():
                     help="plain workloads: poses refined per stage (local TAM lattice search)")
     ap.add_argument("--refine-cells", type=int, default=3,
                     help="refinement lattice half-width in cells")
+    ap.add_argument("--sampler", default="grid", choices=("grid", "rrt"),
+                    help="plain workloads: hypothesis sampler (grid: fixed count; rrt: Alg. 1)")
     ap.add_argument("--coarse", default="smad", choices=tuple(COARSE),
                     help="plain workloads: coarse metric (ablation)")
     ap.add_argument("--fine", default="tam", choices=tuple(FINE),
@@ -437,6 +439,20 @@ def main():
     sid, n_hyp = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
                                        seed=s["seed"])
     hyp = ctx.read_hypotheses(sid)
+    rrt = None
+    if args.sampler == "rrt":
+        # Algorithm 1 from the first cell of the deterministic set as the
+        # tree root, spacing rho of the workload; the set replaces the grid one
+        p0 = ((hyp[0, 0] + 0.5) * w.resolution + w.origin[0],
+              (hyp[0, 1] + 0.5) * w.resolution + w.origin[1])
+        ctx.free_hypotheses(sid)
+        t0 = time.perf_counter()
+        sid, n_hyp, info = ctx.sample_rrt(m, p0, rho=s["min_spacing"],
+                                          robot_radius=s["robot_radius"], seed=s["seed"])
+        rrt = dict(info, seconds=time.perf_counter() - t0, n_hyp=n_hyp)
+        log("RRT: %d hypotheses from %d nodes in %d rounds, %.2f s" % (
+            n_hyp, info["nodes"], info["rounds"], rrt["seconds"]))
+        hyp = ctx.read_hypotheses(sid)
     rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
                       w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
                       variant=args.variant, refine_k=args.refine_k,
@@ -516,7 +532,7 @@ def main():
                    "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k,
                    "refine_k": args.refine_k,
                    "refine_cells": args.refine_cells if args.refine_k else None,
-                   "coarse": args.coarse, "fine": args.fine},
+                   "coarse": args.coarse, "fine": args.fine, "sampler": args.sampler},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
@@ -531,6 +547,7 @@ def main():
         "true_pose": list(w.pose),
         "roofline": roofline,
         "autotune": tuned,
+        "rrt": rrt,
     }
     if COARSE[args.coarse] in (1, 2):
         # the direct coarse kernel: one FP64 subtract and one FP64 add (of an

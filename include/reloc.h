@@ -350,6 +350,28 @@ int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
                          reloc_pose* out, int32_t cap, int32_t* n_out, reloc_stats* stats);
 
 /* ------------------------------------------------------------------------
+ * Dense sweeps (Sec. IV Case 1: Fig. 7's SMAD map over positions, Fig. 8's
+ * metrics over a translation x rotation lattice).
+ * reloc_coarse_scores runs the ray cast and the request's coarse metric for
+ * every hypothesis of its set (a set of all free cells gives the coarse map
+ * of Fig. 7) and returns, each optional (host, cap >= n_hyp entries, else
+ * RELOC_E_INVALID): the score
+ * (SMAD, or the ablation's CAER; FP64), its argmin shift m, and the stable
+ * ascending (score, index) order; stats (optional) gets the counts and the
+ * device time of the ray cast, the coarse kernel and the sort.
+ * reloc_score_poses evaluates the request's fine metric (fine_metric: TAM,
+ * TAM_mean, baseline or LF) at n explicit poses: host cell_xy[2n] (cells
+ * inside the map) and heading[n] (heading index g on the request's Ng
+ * direction grid, theta = 2 pi g / Ng); score: host float[n]; ms_out
+ * (optional): device time of the scoring kernel. RELOC_E_INVALID for a cell
+ * outside the map or a heading index outside [0, Ng).
+ * ---------------------------------------------------------------------- */
+int32_t reloc_coarse_scores(reloc_ctx* ctx, int32_t request_id, int32_t cap, double* score,
+                            int32_t* shift, int32_t* order, reloc_stats* stats);
+int32_t reloc_score_poses(reloc_ctx* ctx, int32_t request_id, const int32_t* cell_xy,
+                          const int32_t* heading, int32_t n, float* score, float* ms_out);
+
+/* ------------------------------------------------------------------------
  * Batched form: several prepared requests (any maps, scans and parameters)
  * run together. One ray-cast launch and one SMAD launch cover the
  * hypotheses of every request, one segmented sort gives every SMAD order,

@@ -286,6 +286,31 @@ class Context:
         finally:
             self.release(rid)
 
+    def coarse_scores(self, request_id: int, n_hyp: int):
+        """Coarse metric of the n_hyp hypotheses of the request: (score FP64,
+        argmin shift, stable order, stats)."""
+        n = int(n_hyp)
+        sc = np.empty(n, dtype=np.float64)
+        sh = np.empty(n, dtype=np.int32)
+        order = np.empty(n, dtype=np.int32)
+        st = _abi.reloc_stats()
+        _check(self._lib.reloc_coarse_scores(self._h, int(request_id), n, _ptr(sc), _ptr(sh),
+                                             _ptr(order), C.byref(st)))
+        return sc, sh, order, _stats(st, OK)
+
+    def score_poses(self, request_id: int, cell_xy, heading):
+        """Fine metric of the request at explicit poses (cells, heading index
+        on the Ng grid); returns (scores float32, kernel ms)."""
+        xy = np.ascontiguousarray(cell_xy, dtype=np.int32).reshape(-1, 2)
+        g = np.ascontiguousarray(heading, dtype=np.int32).reshape(-1)
+        if len(g) != len(xy):
+            raise ValueError("cell_xy and heading differ in length")
+        out = np.empty(len(g), dtype=np.float32)
+        ms = C.c_float()
+        _check(self._lib.reloc_score_poses(self._h, int(request_id), _ptr(xy), _ptr(g), len(g),
+                                           _ptr(out), C.byref(ms)))
+        return out, ms.value
+
     def autotune(self, request_id: int, reps: int = 3):
         """Picks the fastest ray-cast launch shape for the request; returns
         (variant, rays per chunk, mean kernel ms)."""

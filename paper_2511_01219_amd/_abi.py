@@ -153,6 +153,10 @@ PROTOS = {
     "reloc_serve_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(reloc_serve_stats)]),
     "reloc_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "reloc_coarse_scores": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(reloc_stats)]),
+    "reloc_score_poses": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.c_void_p, C.POINTER(C.c_float)]),
     "reloc_debug_raycast": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "reloc_debug_smad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,

@@ -57,6 +57,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // of eq. 22, heading index o k on the Ng grid; ties go to the smaller k.
 struct ThetaSrc {
   static constexpr bool kPrefix = true;   // the evaluated poses are a prefix
+  static constexpr bool kPublish = true;  // fold the tile's best into *dst
   int64_t X20, Y20;
   int k0, Nt, o, Ng;
   float* T_row;           // optional [Nt]
@@ -83,6 +84,7 @@ struct ThetaSrc {
 // then to the smaller q.
 struct LatticeSrc {
   static constexpr bool kPrefix = false;
+  static constexpr bool kPublish = true;
   int ix, iy, g0, h, s, w, L, q0, W, H, Ng;
   const uint32_t* kmap;
   uint64_t* dst;
@@ -112,6 +114,29 @@ struct LatticeSrc {
     return 0xFFFFFFFFu - (uint32_t)(q == qc ? 0 : q + 1);
   }
   __device__ __forceinline__ void record(int, float) const {}
+};
+
+// Explicit poses: poses [q0, q0 + 16) of a list of n (cell, heading index
+// on the Ng grid); each score is written out, nothing is reduced.
+struct PoseListSrc {
+  static constexpr bool kPrefix = true;
+  static constexpr bool kPublish = false;
+  const int32_t* xy;
+  const int32_t* g;
+  int q0, n;
+  float* out;
+  uint64_t* dst;
+  __device__ __forceinline__ bool has(int j) const { return q0 + j < n; }
+  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+    const int q = q0 + j;
+    if (q >= n) return false;
+    x = (int64_t)(256 * xy[2 * q] + 128) * (int64_t)(1 << 20);
+    y = (int64_t)(256 * xy[2 * q + 1] + 128) * (int64_t)(1 << 20);
+    ok = g[q];
+    return true;
+  }
+  __device__ __forceinline__ uint32_t tie(int) const { return 0u; }
+  __device__ __forceinline__ void record(int j, float T) const { out[q0 + j] = T; }
 };
 
 // One workgroup's work: the 16 poses of a tile; wavefront w takes poses
@@ -282,11 +307,13 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     src.record(j, T);
     packed = ((uint64_t)score_key(T) << 32) | (uint64_t)src.tie(j);
   }
-  for (int off = G / 2; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(packed, off, 64);
-    packed = o > packed ? o : packed;
+  if constexpr (Src::kPublish) {
+    for (int off = G / 2; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(packed, off, 64);
+      packed = o > packed ? o : packed;
+    }
+    if (lane == 0 && packed) atomicMax((unsigned long long*)src.dst, (unsigned long long)packed);
   }
-  if (lane == 0 && packed) atomicMax((unsigned long long*)src.dst, (unsigned long long)packed);
 }
 
 // Orientation tile kb of rank a.r0 + i.
@@ -432,6 +459,39 @@ hipError_t launch_refine_kb(const RefineArgs& a, hipStream_t s) {
   if (R <= 16) return launch_refine_t<16, KB, FULL>(a, s);
   if (R <= 32) return launch_refine_t<32, KB, FULL>(a, s);
   if (R <= 64) return launch_refine_t<64, KB, FULL>(a, s);
+  return hipErrorInvalidValue;
+}
+
+// Scores of an explicit pose list, 16 poses per workgroup.
+template <int R, int KB, bool FULL>
+__global__ __launch_bounds__(TB) void pose_kernel(PoseArgs a) {
+  extern __shared__ int32_t smem[];
+  PoseListSrc src;
+  src.xy = a.xy;
+  src.g = a.g;
+  src.q0 = (int)blockIdx.x * THETA_PER_BLOCK;
+  src.n = a.n;
+  src.out = a.out;
+  src.dst = nullptr;
+  tam_tile<R, KB, FULL>(a.t, src, smem);
+}
+
+template <int R, int KB, bool FULL>
+hipError_t launch_poses_t(const PoseArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)tam_beams_padded(a.t.nv) * sizeof(int2);
+  const int blocks = (a.n + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  hipLaunchKernelGGL((pose_kernel<R, KB, FULL>), dim3(blocks), dim3(TB), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KB, bool FULL>
+hipError_t launch_poses_kb(const PoseArgs& a, hipStream_t s) {
+  const int R = (a.t.nv + 63) / 64;
+  if (R <= 4) return launch_poses_t<4, KB, FULL>(a, s);
+  if (R <= 8) return launch_poses_t<8, KB, FULL>(a, s);
+  if (R <= 16) return launch_poses_t<16, KB, FULL>(a, s);
+  if (R <= 32) return launch_poses_t<32, KB, FULL>(a, s);
+  if (R <= 64) return launch_poses_t<64, KB, FULL>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -630,6 +690,17 @@ hipError_t launch_refine(const RefineArgs& a, hipStream_t s) {
     return full ? launch_refine_kb<12, true>(a, s) : launch_refine_kb<12, false>(a, s);
   if (a.t.keybits <= 16)
     return full ? launch_refine_kb<16, true>(a, s) : launch_refine_kb<16, false>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_score_poses(const PoseArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.t.fine < 0 || a.t.fine > 3) return hipErrorInvalidValue;
+  const bool full = a.t.fine >= 2;
+  if (a.t.keybits <= 12)
+    return full ? launch_poses_kb<12, true>(a, s) : launch_poses_kb<12, false>(a, s);
+  if (a.t.keybits <= 16)
+    return full ? launch_poses_kb<16, true>(a, s) : launch_poses_kb<16, false>(a, s);
   return hipErrorInvalidValue;
 }
 

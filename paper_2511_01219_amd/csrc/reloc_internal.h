@@ -131,6 +131,17 @@ __host__ __device__ inline int tam_beams_padded(int nv) {
   return (nv + kTamBeamPad - 1) / kTamBeamPad * kTamBeamPad;
 }
 
+// Scores (the request's fine metric) of n explicit poses: cell xy[2q],
+// xy[2q + 1] (in the map) and heading index g[q] on the Ng grid (< Ng).
+struct PoseArgs {
+  TamArgs t;
+  const int32_t* xy;         // [n][2]
+  const int32_t* g;          // [n]
+  int n;
+  float* out;                // [n]
+};
+hipError_t launch_score_poses(const PoseArgs& a, hipStream_t s);
+
 // Local refinement of each stage's best poses: an exhaustive TAM search over
 // the lattice of poses next to each (cells within +-h, headings within +-s
 // steps of the Ng direction grid; off-map and occupied cells other than the

@@ -1258,21 +1258,111 @@ int32_t reloc_debug_raycast(reloc_ctx* c, int32_t request_id, int32_t* hit_cell,
   return RELOC_OK;
 }
 
+int32_t reloc_coarse_scores(reloc_ctx* c, int32_t request_id, int32_t cap, double* score,
+                            int32_t* shift, int32_t* order, reloc_stats* st) {
+  if (st) std::memset(st, 0, sizeof *st);
+  if (!c) return fail(RELOC_E_INVALID, "null ctx");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  Request& R = it->second;
+  if ((score || shift || order) && cap < R.n_hyp)
+    return fail(RELOC_E_INVALID, "buffers of %d entries, the request has %d hypotheses", cap,
+                R.n_hyp);
+  if (int32_t e = set_device(c)) return e;
+  hipStream_t s = c->stream;
+  const RayArgs ra = ray_args(c, R, nullptr, nullptr);
+  HIP_TRY(hipEventRecord(c->ev[0], s));
+  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));
+  HIP_TRY(hipEventRecord(c->ev[1], s));
+  HIP_TRY(launch_coarse(ra, s));
+  HIP_TRY(hipEventRecord(c->ev[2], s));
+  if (int32_t e = smad_order(c, R)) return e;
+  HIP_TRY(hipEventRecord(c->ev[3], s));
+  const size_t n = (size_t)R.n_hyp;
+  if (score) HIP_TRY(hipMemcpyAsync(score, R.smad, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (shift) HIP_TRY(hipMemcpyAsync(shift, R.argm, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (order) HIP_TRY(hipMemcpyAsync(order, R.order, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    const reloc_scan_info& I = R.prep.info;
+    st->n_hyp = R.n_hyp;
+    st->smad_evals = coarse_evals(R);
+    st->rays = R.prm.coarse_metric == 3 ? 0 : (int64_t)R.n_hyp * I.Ns;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[3]);
+    st->ms_total = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    st->ms_raycast = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+    st->ms_smad = ms;
+    (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
+    st->ms_sort = ms;
+  }
+  return RELOC_OK;
+}
+
+int32_t reloc_score_poses(reloc_ctx* c, int32_t request_id, const int32_t* cell_xy,
+                          const int32_t* heading, int32_t n, float* score, float* ms_out) {
+  if (ms_out) *ms_out = 0.f;
+  if (!c || n < 0 || (n > 0 && (!cell_xy || !heading || !score)))
+    return fail(RELOC_E_INVALID, "null argument or negative n");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->reqs.find(request_id);
+  if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
+  Request& R = it->second;
+  const DevMap& m = c->maps[R.map_id];
+  const int Ng = R.prep.info.Ng;
+  for (int32_t i = 0; i < n; ++i) {
+    if (cell_xy[2 * i] < 0 || cell_xy[2 * i] >= m.W || cell_xy[2 * i + 1] < 0 ||
+        cell_xy[2 * i + 1] >= m.H)
+      return fail(RELOC_E_INVALID, "pose %d: cell (%d, %d) outside the map", i, cell_xy[2 * i],
+                  cell_xy[2 * i + 1]);
+    if (heading[i] < 0 || heading[i] >= Ng)
+      return fail(RELOC_E_INVALID, "pose %d: heading index %d outside [0, %d)", i, heading[i], Ng);
+  }
+  if (n == 0) return RELOC_OK;
+  if (int32_t e = set_device(c)) return e;
+  int32_t* dxy = (int32_t*)c->dalloc((size_t)n * 2 * sizeof(int32_t));
+  int32_t* dg = (int32_t*)c->dalloc((size_t)n * sizeof(int32_t));
+  float* dout = (float*)c->dalloc((size_t)n * sizeof(float));
+  auto release = [&]() {
+    c->dfree(dxy);
+    c->dfree(dg);
+    c->dfree(dout);
+  };
+  if (!dxy || !dg || !dout) {
+    release();
+    return RELOC_E_NOMEM;
+  }
+  hipStream_t s = c->stream;
+  PoseArgs a;
+  a.t = tam_args(c, R, 0, 0, nullptr);
+  a.xy = dxy;
+  a.g = dg;
+  a.n = n;
+  a.out = dout;
+  hipError_t e = hipMemcpyAsync(dxy, cell_xy, (size_t)n * 2 * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dg, heading, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(c->ev[0], s);
+  if (e == hipSuccess) e = launch_score_poses(a, s);
+  if (e == hipSuccess) e = hipEventRecord(c->ev[1], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(score, dout, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && ms_out) (void)hipEventElapsedTime(ms_out, c->ev[0], c->ev[1]);
+  release();
+  if (e != hipSuccess) return fail(RELOC_E_DEVICE, "pose scoring failed: %s", hipGetErrorString(e));
+  return RELOC_OK;
+}
+
 int32_t reloc_debug_smad(reloc_ctx* c, int32_t request_id, double* smad, int32_t* argmin,
                          int32_t* order) {
   if (!c) return fail(RELOC_E_INVALID, "null ctx");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   auto it = c->reqs.find(request_id);
   if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
-  if (int32_t e = set_device(c)) return e;
-  Request& R = it->second;
-  if (int32_t e = run_smad_order(c, R)) return e;
-  const size_t n = (size_t)R.n_hyp;
-  if (smad) HIP_TRY(hipMemcpyAsync(smad, R.smad, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  if (argmin) HIP_TRY(hipMemcpyAsync(argmin, R.argm, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  if (order) HIP_TRY(hipMemcpyAsync(order, R.order, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return RELOC_OK;
+  return reloc_coarse_scores(c, request_id, it->second.n_hyp, smad, argmin, order, nullptr);
 }
 
 int32_t reloc_debug_tam(reloc_ctx* c, int32_t request_id, int32_t r0, int32_t n, float* T,

@@ -214,6 +214,18 @@ def test_null_context_calls_are_invalid():
     assert lib.reloc_serve_stats_get(None, None) == reloc.E_INVALID
     assert lib.reloc_prepare(None, 1, 1, None, None, C.byref(n)) == reloc.E_INVALID
     assert lib.reloc_release(None, 1) == reloc.E_INVALID
+    sid = C.c_int32(4)
+    n.value = 6
+    p = _abi.reloc_rrt_params()
+    lib.reloc_rrt_defaults(C.byref(p))
+    assert (p.rho, p.robot_radius, p.eta_max, p.eps_gain) == (0.3, 0.21, 0.6, 2)
+    assert lib.reloc_sample_rrt(None, 1, C.byref(p), C.byref(sid), C.byref(n), None, None,
+                                None, 0) == reloc.E_INVALID
+    assert n.value == 0
+    assert lib.reloc_coarse_scores(None, 1, 0, None, None, None, None) == reloc.E_INVALID
+    ms = C.c_float(3.0)
+    assert lib.reloc_score_poses(None, 1, None, None, 0, None, C.byref(ms)) == reloc.E_INVALID
+    assert ms.value == 0.0
 
 
 def test_multi_map_generators_are_seeded():
