@@ -196,6 +196,72 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """Dense sweeps on the plain-small map (Sec. IV Case 1 analogues): the
+    SMAD map over every feasible cell (Fig. 7) and TAM and baseline over a
+    0.1 m x 10 deg lattice of 15 x 36 poses around the true pose (Fig. 8);
+    one step = both sweeps."""
+    import numpy as np
+    import torch
+    import paper_2511_01219_amd as reloc
+    from synth import make_config
+    w = make_config(1)
+    ctx = reloc.Context(0)
+    m = ctx.load_map(w.occ, w.resolution, w.origin)
+    k = ctx.read_edt(m)
+    F = (w.occ >= 0) & (w.occ < 65) & (k >= 18)
+    ys, xs = np.nonzero(F)
+    cells = np.stack([xs, ys], 1).astype(np.int32)
+    n = len(cells)
+    sid = ctx.set_hypotheses(m, cells)
+    scan = (w.ranges, w.angle_min, w.angle_increment, w.range_min, w.range_max)
+    rid = ctx.prepare(m, sid, *scan, n_theta=360, batch_k=10)
+    rid_b = ctx.prepare(m, sid, *scan, n_theta=360, batch_k=10, fine_metric=2)
+    Ng = 1440
+    c0 = np.floor((np.asarray(w.pose[:2]) - np.asarray(w.origin)) / w.resolution).astype(int)
+    g0 = int(round(w.pose[2] * Ng / (2 * math.pi))) % Ng
+    lx = np.array([(c0[0] + 2 * t, c0[1]) for t in range(-7, 8) for _ in range(36)], np.int32)
+    lg = np.array([(g0 + 40 * j) % Ng for _ in range(-7, 8) for j in range(36)], np.int32)
+    log("sweep: %d feasible cells, %d lattice poses" % (n, len(lg)))
+    for _ in range(args.warmup):
+        ctx.coarse_scores(rid, n)
+        ctx.score_poses(rid, lx, lg)
+        ctx.score_poses(rid_b, lx, lg)
+    torch.cuda.synchronize()
+    dev_c, dev_t, dev_b = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, _, st = ctx.coarse_scores(rid, n)
+        dev_c.append(st["ms_total"])
+        _, ms = ctx.score_poses(rid, lx, lg)
+        dev_t.append(ms)
+        _, ms = ctx.score_poses(rid_b, lx, lg)
+        dev_b.append(ms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    evals = args.steps * (st["smad_evals"] + 2 * len(lg))
+    out = {
+        "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
+        "value": evals / elapsed, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32+f32+f64", "data": "synthetic",
+        "config": {"workload": "sweep: plain-small map, SMAD over all %d feasible cells "
+                               "(480 shifts), TAM and baseline at 15 x 36 lattice poses" % n},
+        "heatmap": {"cells": n, "device_ms": float(np.mean(dev_c)),
+                    "rays_per_s": st["rays"] / (float(np.mean(dev_c)) * 1e-3),
+                    "smad_evals": st["smad_evals"]},
+        "lattice": {"poses": len(lg), "tam_ms": float(np.mean(dev_t)),
+                    "baseline_ms": float(np.mean(dev_b))},
+        "cpu_baseline": None,
+    }
+    ctx.release(rid)
+    ctx.release(rid_b)
+    ctx.free_hypotheses(sid)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_stress(args):
     """Stress: 8000 x 8000 mixed map, 200 000 hypotheses, panoramic 1440-beam
     scan (perturbed environment, 15 % clutter), 1440 orientations, top-256
@@ -383,7 +449,8 @@ def main():
                     help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plain-large",
-                    choices=("plain-large", "plain-small", "batched", "serving", "stress"))
+                    choices=("plain-large", "plain-small", "batched", "serving", "stress",
+                             "sweep"))
     ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
@@ -411,6 +478,8 @@ def main():
         return bench_serving(args)
     if args.workload == "stress":
         return bench_stress(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
     import torch

@@ -629,43 +629,97 @@ __global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restric
 // ------------------------------------------------- direct coarse metrics
 // SMAD by direct sums (eq. 16-20 without the prefix sums of eq. 17-18) or
 // CAER (eq. 21) of hypothesis blockIdx.x by one workgroup. The synthetic
-// ranges are stored twice in LDS as FP64, so index j + m never wraps; each
-// thread scores the shifts m = s n_enum, s = tid, tid + 256, ..., summing
-// its FoV beams one at a time in beam order (the order the definition is
-// written in, so the sums equal a sequential evaluation bit for bit). SMAD
+// ranges are stored three times over in LDS as FP32 (converting them back
+// to FP64 is exact), plus kZPad more, so an index run start (< Ns) + shift
+// (< Ns) + run offset (<= Ns + 1) never wraps. Each shift sums its FoV
+// beams one at a time in beam order (run by run), the order the definition
+// is written in, so the sums equal a sequential evaluation bit for bit. SMAD
 // scores the shifts of eq. 20 (m = 0 only for panoramic scans); CAER is not
 // rotation invariant and scores every shift.
+//
+// With n_enum = 1 a thread scores the shift pair (m, m + 1): beam t of a run
+// needs Z[j + t + m] and Z[j + t + m + 1], so 9 loads serve 8 beams of both
+// shifts; the loads of a batch are issued before any is used.
+constexpr int kZPad = 8;
+
+template <bool CAER>
+__device__ __forceinline__ double coarse_term(double acc, double zm, double zs) {
+  return CAER ? acc + fabs(zm - zs) : acc + zs;
+}
+
+template <bool CAER>
+__device__ __forceinline__ void coarse_pair(const RayArgs& a, const float* Z, int m,
+                                            double& acc0, double& acc1) {
+  int i = 0;                                   // FoV beam index (into fov_z)
+  for (int r = 0; r < a.n_runs; ++r) {
+    const int2 rr = a.runs[r];
+    const float* zb = Z + rr.x + m;
+    int t = 0;
+    for (; t + 8 <= rr.y; t += 8, i += 8) {
+      float f[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f[q] = zb[t + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double zm = CAER ? a.fov_z[i + q] : 0.0;
+        acc0 = coarse_term<CAER>(acc0, zm, (double)f[q]);
+        acc1 = coarse_term<CAER>(acc1, zm, (double)f[q + 1]);
+      }
+    }
+    for (; t < rr.y; ++t, ++i) {
+      const double zm = CAER ? a.fov_z[i] : 0.0;
+      acc0 = coarse_term<CAER>(acc0, zm, (double)zb[t]);
+      acc1 = coarse_term<CAER>(acc1, zm, (double)zb[t + 1]);
+    }
+  }
+}
+
+template <bool CAER>
 __global__ __launch_bounds__(RT) void coarse_direct_kernel(RayArgs a) {
-  extern __shared__ double Z[];            // [2 Ns]
+  extern __shared__ float Z[];             // [3 Ns + kZPad]
   __shared__ double rv[RT / 64];
   __shared__ int rm[RT / 64];
   const int h = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int Ns = a.Ns;
   const float* z = a.zbuf + (size_t)h * Ns;
   for (int i = tid; i < Ns; i += RT) {
-    const double v = (double)z[i];
+    const float v = z[i];
     Z[i] = v;
     Z[i + Ns] = v;
+    Z[i + 2 * Ns] = v;
   }
+  for (int i = tid; i < kZPad; i += RT) Z[3 * Ns + i] = z[i % Ns];
   __syncthreads();
-  const bool caer = a.coarse == 2;
-  const int nsh = caer ? (Ns + a.n_enum - 1) / a.n_enum : a.n_shifts;
-  const int nf = a.nfov;
+  const int nsh = CAER ? (Ns + a.n_enum - 1) / a.n_enum : a.n_shifts;
+  const double nfov = (double)a.nfov;
   double bv = INFINITY;
   int bm = INT_MAX;
-  for (int s = tid; s < nsh; s += RT) {
-    const int m = s * a.n_enum;
-    double acc = 0.0;
-    if (caer) {
-      for (int i = 0; i < nf; ++i) acc += fabs(a.fov_z[i] - Z[a.fov_j[i] + m]);
-    } else {
-      for (int i = 0; i < nf; ++i) acc += Z[a.fov_j[i] + m];
-    }
-    const double mean = acc / (double)nf;
-    const double v = caer ? mean : fabs(a.zbar - mean);
+  auto take = [&](double acc, int m) {
+    const double mean = acc / nfov;
+    const double v = CAER ? mean : fabs(a.zbar - mean);
     if (v < bv) {
       bv = v;
       bm = m;
+    }
+  };
+  if (a.n_enum == 1 && nsh >= 2) {
+    for (int m = 2 * tid; m < nsh; m += 2 * RT) {
+      double acc0 = 0.0, acc1 = 0.0;
+      coarse_pair<CAER>(a, Z, m, acc0, acc1);
+      take(acc0, m);
+      if (m + 1 < nsh) take(acc1, m + 1);
+    }
+  } else {
+    for (int sh = tid; sh < nsh; sh += RT) {
+      const int m = sh * a.n_enum;
+      double acc = 0.0;
+      int i = 0;
+      for (int r = 0; r < a.n_runs; ++r) {
+        const int2 rr = a.runs[r];
+        for (int t = 0; t < rr.y; ++t, ++i)
+          acc = coarse_term<CAER>(acc, CAER ? a.fov_z[i] : 0.0, (double)Z[rr.x + t + m]);
+      }
+      take(acc, m);
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -770,11 +824,15 @@ hipError_t launch_coarse(const RayArgs& a, hipStream_t s) {
     case 0:
       return launch_smad(a, s);
     case 1:
-    case 2:
-      if (a.nfov <= 0 || !a.fov_z || !a.fov_j) return hipErrorInvalidValue;
-      hipLaunchKernelGGL(coarse_direct_kernel, dim3(a.n_hyp), dim3(RT),
-                         (size_t)2 * a.Ns * sizeof(double), s, a);
+    case 2: {
+      if (a.nfov <= 0 || !a.fov_z) return hipErrorInvalidValue;
+      const size_t lds = ((size_t)3 * a.Ns + kZPad) * sizeof(float);
+      if (a.coarse == 2)
+        hipLaunchKernelGGL(coarse_direct_kernel<true>, dim3(a.n_hyp), dim3(RT), lds, s, a);
+      else
+        hipLaunchKernelGGL(coarse_direct_kernel<false>, dim3(a.n_hyp), dim3(RT), lds, s, a);
       return hipGetLastError();
+    }
     case 3:
       hipLaunchKernelGGL(coarse_none_kernel, dim3((a.n_hyp + RT - 1) / RT), dim3(RT), 0, s, a);
       return hipGetLastError();
