@@ -320,6 +320,15 @@ typedef struct {
   /* local refinement: poses refined; lattice points considered (refined
    * poses x (2s + 1)(2h + 1)^2, skipped cells included) */
   int64_t refined, refine_points;
+  /* Ambiguity (Remark 1, eq. 5). best_margin = T of the top-1 pose minus
+   * the best T among the evaluated poses distinct from it by the success
+   * criterion of Sec. IV-C (position >= 0.5 m away or heading >= 30 deg
+   * away); -1 when no evaluated pose is distinct. ambiguous: bit 0 = a
+   * stage's stop decision was within 1e-4 of tau (a batch best in
+   * [tau - 1e-4, tau + 1e-4]); bit 1 = best_margin <= 1e-4 |T1| + 1e-7 (the
+   * top-1 is numerically tied with a distinct pose). */
+  float best_margin;
+  int32_t ambiguous;
 } reloc_stats;
 
 /* ------------------------------------------------------------------------

@@ -325,6 +325,43 @@ def rrt(occ: np.ndarray, kmap: np.ndarray, res: float, p0, origin=(0.0, 0.0),
                 rounds=int(info[0]), attempts=int(info[1]), n_sampling=int(info[3]))
 
 
+def ambiguity(order, tstar, ref_dxy, ref_g, hyp_xy, Ng: int, res: float, batch_k: int,
+              tau) -> Dict:
+    """Ambiguity of a finished search (Remark 1): the top-1 pose by (T desc,
+    rank asc), the best T among the evaluated poses distinct from it by the
+    success criterion of Sec. IV-C (position >= 0.5 m away, heading >= 30
+    deg away on the Ng grid), best_margin = T1 - that T (-1 when none), and
+    ambiguous = bit 0: some stage's best within 1e-4 of tau, bit 1:
+    best_margin <= 1e-4 |T1| + 1e-7."""
+    ne = len(tstar)
+    hyp = np.asarray(hyp_xy).reshape(-1, 2)
+    ranks = np.lexsort((np.arange(ne), -np.asarray(tstar)))
+    r1 = int(ranks[0])
+    cell = hyp[np.asarray(order)[:ne]] + np.asarray(ref_dxy)
+    g = np.asarray(ref_g).astype(np.int64)
+    best2 = None
+    for r in range(ne):
+        ex = int(cell[r, 0] - cell[r1, 0])
+        ey = int(cell[r, 1] - cell[r1, 1])
+        dg = abs(int(g[r] - g[r1]))
+        if 2 * dg > Ng:
+            dg = Ng - dg
+        if float(ex * ex + ey * ey) * res * res >= 0.25 or 12 * dg >= Ng:
+            if best2 is None or tstar[r] > best2:
+                best2 = float(tstar[r])
+    t1 = float(tstar[r1])
+    margin = -1.0 if best2 is None else t1 - best2
+    amb = 0
+    if tau is not None:
+        for b0 in range(0, ne, batch_k):
+            tb = float(np.max(tstar[b0:b0 + batch_k]))
+            if tau - 1e-4 <= tb <= tau + 1e-4:
+                amb |= 1
+    if best2 is not None and margin <= 1e-4 * abs(t1) + 1e-7:
+        amb |= 2
+    return dict(top=r1, best_margin=margin, ambiguous=amb)
+
+
 def heading(k: int, Ntheta: int) -> float:
     """Heading of orientation index k, wrapped to [-pi, pi)."""
     th = (2.0 * math.pi * k) / Ntheta
@@ -383,7 +420,10 @@ def relocalize(occ: np.ndarray, res: float, origin, hyp_xy: np.ndarray,
                           smad=float(sm[h]), hyp=h, k=k, rank=int(r),
                           stage=int(r) // batch_k, cx=cx, cy=cy, g=g,
                           refined=bool(st["refined"][r])))
-    out = dict(poses=poses, prep=pr, stages=st["stages"],
+    amb = ambiguity(st["order"], st["tstar"], st["ref_dxy"], st["ref_g"], hyp, pr["Ng"], res,
+                    batch_k, tau)
+    out = dict(poses=poses, prep=pr, stages=st["stages"], best_margin=amb["best_margin"],
+               ambiguous=amb["ambiguous"],
                early_stopped=st["early_stopped"], n_eval=ne,
                smad_evals=len(sm) * (pr["n_shifts"] if coarse_metric in (0, 1) else
                                      -(-pr["Ns"] // pr["n_skip_enum"]) if coarse_metric == 2

@@ -79,7 +79,8 @@ class reloc_stats(C.Structure):
                 ("ms_total", C.c_float), ("ms_raycast", C.c_float), ("ms_sort", C.c_float),
                 ("ms_tam", C.c_float), ("ms_rank", C.c_float),
                 ("ms_smad", C.c_float), ("refined", C.c_int64),
-                ("refine_points", C.c_int64)]
+                ("refine_points", C.c_int64), ("best_margin", C.c_float),
+                ("ambiguous", C.c_int32)]
 
 
 class reloc_serve_config(C.Structure):

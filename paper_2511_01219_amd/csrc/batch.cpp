@@ -61,6 +61,8 @@ struct Flight {
   std::chrono::steady_clock::time_point t_start;
   int tentry = 0, tstages = 0, tnb = 0;   // the current tick
   uint64_t ticket = 0;                    // serving only
+  bool fragile = false;                   // a stop decision within 1e-4 of tau
+  uint64_t marg[3] = {0, 0, 0};           // ambiguity kernel output
 };
 
 struct Ticket {
@@ -98,6 +100,7 @@ struct ServeState {
   uint64_t* dstage = nullptr;
   int32_t* dflag = nullptr;
   int32_t* hflag = nullptr;
+  uint64_t* hstage = nullptr;
   size_t stage_cap = 0;
   // serving
   std::thread worker;
@@ -152,15 +155,18 @@ int32_t ensure_stage_cap(reloc_ctx* c, ServeState& S, size_t n) {
   c->dfree(S.dstage);
   c->dfree(S.dflag);
   if (S.hflag) (void)hipHostFree(S.hflag);
+  if (S.hstage) (void)hipHostFree(S.hstage);
   S.dstage = nullptr;
   S.dflag = nullptr;
   S.hflag = nullptr;
+  S.hstage = nullptr;
   S.stage_cap = 0;
   const size_t cap = std::max<size_t>(n, 1024);
   S.dstage = (uint64_t*)c->dalloc(cap * sizeof(uint64_t));
   S.dflag = (int32_t*)c->dalloc(cap * sizeof(int32_t));
   if (!S.dstage || !S.dflag) return RELOC_E_NOMEM;
   HIP_TRY(hipHostMalloc((void**)&S.hflag, cap * sizeof(int32_t), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&S.hstage, cap * sizeof(uint64_t), hipHostMallocDefault));
   S.stage_cap = cap;
   return RELOC_OK;
 }
@@ -364,6 +370,8 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
   }
   HIP_TRY(launch_stage_reduce_batch((const StageArgs*)(d + o_st), (int)st.size(), s));
   HIP_TRY(hipMemcpyAsync(S.hflag, S.dflag, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(S.hstage, S.dstage, st.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                         s));
   HIP_TRY(hipEventRecord(c->ev[4], s));
   HIP_TRY(hipStreamSynchronize(s));
   if (pt) pt->tam += elapsed(c->ev[3], c->ev[4]);
@@ -377,6 +385,13 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
         hit = b;
         break;
       }
+    if (!std::isnan(R.prm.tau)) {
+      const int used = hit >= 0 ? hit + 1 : f->tstages;
+      for (int b = 0; b < used; ++b) {
+        const double T = (double)score_of_key((uint32_t)(S.hstage[f->tentry + b] >> 32));
+        if (T >= R.prm.tau - 1e-4 && T <= R.prm.tau + 1e-4) f->fragile = true;
+      }
+    }
     if (hit >= 0) {
       f->stages += hit + 1;
       f->n_eval = std::min(R.n_hyp, f->next_rank + (hit + 1) * K);
@@ -409,12 +424,16 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   rows->assign(n, {});
   if (n == 0) return RELOC_OK;
   std::vector<int64_t> kpre(n + 1, 0), rpre(n + 1, 0);
+  std::vector<int> nrow(n, 0);
   std::vector<RankArgs> ra(n);
   for (int i = 0; i < n; ++i) {
     const Request& R = c->reqs.at(F[i]->rid);
     const int nr = std::max(0, std::min(std::min(R.rows_cap, F[i]->n_eval), cap[i]));
+    nrow[i] = nr;
     kpre[i + 1] = kpre[i] + F[i]->n_eval;
-    rpre[i + 1] = rpre[i] + nr;
+    // the device holds row 0 of every evaluated request (the ambiguity
+    // statistics read it)
+    rpre[i + 1] = rpre[i] + (F[i]->n_eval > 0 ? std::max(1, nr) : 0);
     ra[i] = RankArgs{F[i]->arena->best + F[i]->off, F[i]->arena->order + F[i]->off, R.smad};
   }
   const int64_t NK = kpre[n], NR = rpre[n];
@@ -423,10 +442,11 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   uint64_t* k1 = T.get<uint64_t>(NK);
   uint64_t* k2 = T.get<uint64_t>(NK);
   PoseRow* dr = T.get<PoseRow>(NR);
+  uint64_t* dmarg = T.get<uint64_t>(3 * (size_t)n);
   size_t tb = 0;
   HIP_TRY(seg_sort_keys_u64(nullptr, &tb, k1, k2, NK, n, nullptr, c->stream));
   void* tmp = T.get<uint8_t>(tb);
-  if (!k1 || !k2 || !dr || !tmp) return RELOC_E_NOMEM;
+  if (!k1 || !k2 || !dr || !dmarg || !tmp) return RELOC_E_NOMEM;
   Blob bl;
   const size_t o_ra = bl.add(ra.data(), n);
   const size_t o_kp = bl.add(kpre.data(), n + 1);
@@ -444,11 +464,27 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k2, dr, s));
   if (NR > 0)
     HIP_TRY(hipMemcpyAsync(host.data(), dr, NR * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  std::vector<uint64_t> hm(3 * (size_t)n, 0);
+  bool any_margin = false;
+  for (int i = 0; i < n; ++i) {
+    if (F[i]->n_eval <= 0) continue;
+    Request& R = c->reqs.at(F[i]->rid);
+    if (int32_t e = enqueue_margin(c, R, F[i]->arena->best + F[i]->off,
+                                   F[i]->arena->order + F[i]->off, dr + rpre[i], F[i]->n_eval,
+                                   nullptr, 0, dmarg + 3 * (size_t)i))
+      return e;
+    any_margin = true;
+  }
+  if (any_margin)
+    HIP_TRY(hipMemcpyAsync(hm.data(), dmarg, hm.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                           s));
   HIP_TRY(hipEventRecord(c->ev[5], s));
   HIP_TRY(hipStreamSynchronize(s));
   if (pt) pt->rank += elapsed(c->ev[4], c->ev[5]);
-  for (int i = 0; i < n; ++i)
-    (*rows)[i].assign(host.begin() + rpre[i], host.begin() + rpre[i + 1]);
+  for (int i = 0; i < n; ++i) {
+    (*rows)[i].assign(host.begin() + rpre[i], host.begin() + rpre[i] + nrow[i]);
+    for (int q = 0; q < 3; ++q) F[i]->marg[q] = hm[3 * (size_t)i + q];
+  }
   return RELOC_OK;
 }
 
@@ -470,6 +506,10 @@ void fill_stats(const Request& R, const Flight& f, const PhaseTimes& pt, float t
   st->ms_sort = pt.sort;
   st->ms_tam = pt.tam;
   st->ms_rank = pt.rank;
+  if (f.n_eval > 0)
+    fill_ambiguity(f.marg, f.fragile, st);
+  else
+    st->best_margin = -1.f;
   const int kr = R.prm.refine_k, K = R.prm.batch_k;
   if (kr > 0) {
     for (int b = 0; b < f.stages; ++b) st->refined += std::min(kr, std::min(K, R.n_hyp - b * K));
@@ -658,6 +698,7 @@ void ctx_stop_serving(reloc_ctx* c) {
   c->dfree(S->dflag);
   if (S->hbuf) (void)hipHostFree(S->hbuf);
   if (S->hflag) (void)hipHostFree(S->hflag);
+  if (S->hstage) (void)hipHostFree(S->hstage);
   S->dcv.notify_all();
   delete S;
   c->serve = nullptr;

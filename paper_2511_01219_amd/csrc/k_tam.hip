@@ -641,6 +641,74 @@ __global__ void rank_gather_batch_kernel(const RankArgs* __restrict__ reqs,
   rows[t] = row;
 }
 
+// Cell offset and heading index (Ng grid) of a rank's packed word: a
+// refined code (bit 31 of the low word clear) or ~k.
+__device__ __forceinline__ void decode_pose(uint64_t b, int o, int* dx, int* dy, int* g) {
+  const uint32_t low = (uint32_t)(b & 0xFFFFFFFFu);
+  if (low & 0x80000000u) {
+    *dx = 0;
+    *dy = 0;
+    *g = o * (int)(0xFFFFFFFFu - low);
+  } else {
+    *dx = (int)(low & 31u) - 15;
+    *dy = (int)((low >> 5) & 31u) - 15;
+    *g = (int)(low >> 10);
+  }
+}
+
+__global__ __launch_bounds__(TB) void margin_kernel(MarginArgs a) {
+  __shared__ unsigned long long red[NW];
+  const int r1 = a.top->rank;
+  if (r1 < 0 || r1 >= a.n_eval) {               // workgroup-uniform
+    if (threadIdx.x == 0) {
+      a.out[0] = 0;
+      a.out[1] = 0;
+      a.out[2] = 0;
+    }
+    return;
+  }
+  int dx1, dy1, g1;
+  decode_pose(a.best[r1], a.o, &dx1, &dy1, &g1);
+  const int h1 = a.order[r1];
+  const int x1 = a.hyp_xy[2 * h1] + dx1, y1 = a.hyp_xy[2 * h1 + 1] + dy1;
+  unsigned long long m = 0;
+  for (int r = threadIdx.x; r < a.n_eval; r += TB) {
+    const uint64_t b = a.best[r];
+    int dx, dy, g;
+    decode_pose(b, a.o, &dx, &dy, &g);
+    const int h = a.order[r];
+    const int64_t ex = (int64_t)(a.hyp_xy[2 * h] + dx - x1), ey = (int64_t)(a.hyp_xy[2 * h + 1] + dy - y1);
+    int dgc = g - g1;
+    if (dgc < 0) dgc = -dgc;
+    if (2 * dgc > a.Ng) dgc = a.Ng - dgc;
+    const bool far = (double)(ex * ex + ey * ey) * a.res * a.res >= 0.25 || 12 * dgc >= a.Ng;
+    if (!far) continue;
+    const unsigned long long key =
+        ((b >> 32) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)r);
+    if (key > m) m = key;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o2 = __shfl_xor(m, off, 64);
+    if (o2 > m) m = o2;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NW; ++q)
+      if (red[q] > m) m = red[q];
+    a.out[0] = m;
+    uint64_t frag = 0;
+    if (a.stage && !isnan(a.tau)) {
+      for (int b = 0; b < a.n_stages; ++b) {
+        const double T = (double)score_of_key((uint32_t)(a.stage[b] >> 32));
+        if (T >= a.tau - 1e-4 && T <= a.tau + 1e-4) frag = 1;
+      }
+    }
+    a.out[1] = frag;
+    a.out[2] = a.best[r1];
+  }
+}
+
 template <int R, int KB, bool FULL>
 hipError_t launch_tam_batch_t(const TamArgs* items, const int64_t* prefix, int n, int64_t blocks,
                               size_t lds, hipStream_t s) {
@@ -760,6 +828,12 @@ hipError_t launch_rank_gather_batch(const RankArgs* reqs, const int64_t* row_pre
   if (n <= 0 || total <= 0) return hipSuccess;
   hipLaunchKernelGGL(rank_gather_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
                      0, s, reqs, row_prefix, key_prefix, n, sorted, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_margin(const MarginArgs& a, hipStream_t s) {
+  if (a.n_eval <= 0) return hipSuccess;
+  hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(TB), 0, s, a);
   return hipGetLastError();
 }
 

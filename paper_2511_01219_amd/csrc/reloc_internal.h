@@ -203,6 +203,28 @@ hipError_t launch_rank_gather(const uint64_t* sorted, const uint64_t* best,
                               const int32_t* order, const double* smad, int n, PoseRow* rows,
                               hipStream_t s);
 
+// Ambiguity: the best evaluated pose distinct from the top-1 (row 0) by the
+// paper's success criterion (Sec. IV-C): position at least 0.5 m away,
+// (dx^2 + dy^2) res^2 >= 0.25 in FP64 over cells, or heading at least 30 deg
+// away, 12 * (circular distance in Ng steps) >= Ng. out[0] = its packed
+// (score key, ~rank), 0 when there is none; out[1] = 1 when a stage's stop
+// decision was within 1e-4 of tau (stage bests of the n_stages stages run;
+// stage may be null); out[2] = the top-1 rank's packed word (0 when the top
+// row names no evaluated rank). One workgroup.
+struct MarginArgs {
+  const uint64_t* best;      // [n_eval] packed per-rank words
+  const int32_t* order;      // hypothesis per rank
+  const int32_t* hyp_xy;     // cells of the set
+  const PoseRow* top;        // row 0 of the ranking
+  int n_eval, Ng, o;
+  double res;
+  const uint64_t* stage;     // [n_stages] packed stage bests
+  int n_stages, stopped;
+  double tau;                // NaN: no stop decisions
+  uint64_t* out;             // [3]: best distinct, stop fragility, top-1 word
+};
+hipError_t launch_margin(const MarginArgs& a, hipStream_t s);
+
 // Ranking of n <= 2048 ranks in one launch (T desc, rank asc), first nrow rows.
 constexpr int kRankSmallMax = 2048;
 hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,

@@ -577,17 +577,51 @@ int32_t run_smad_order(reloc_ctx* c, Request& R) {
 // copied to host_rows (pinned) on the stream
 int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* host_rows) {
   hipStream_t s = c->stream;
+  // the device always holds row 0 (the ambiguity statistics read it)
+  const int ndev = std::min(n_eval, std::max(1, nrow));
   if (n_eval <= kRankSmallMax) {
-    HIP_TRY(launch_rank_small(R.best, n_eval, R.order, R.smad, nrow, R.rows, s));
+    HIP_TRY(launch_rank_small(R.best, n_eval, R.order, R.smad, ndev, R.rows, s));
   } else {
     HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
     size_t tb = R.tmp_bytes;
     HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
-    HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, nrow, R.rows, s));
+    HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, ndev, R.rows, s));
   }
   if (nrow > 0)
     HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
   return RELOC_OK;
+}
+
+int32_t enqueue_margin(reloc_ctx* c, Request& R, const uint64_t* best, const int32_t* order,
+                       const PoseRow* rows, int n_eval, const uint64_t* stage, int n_stages,
+                       uint64_t* out) {
+  const reloc_scan_info& I = R.prep.info;
+  MarginArgs a;
+  a.best = best;
+  a.order = order;
+  a.hyp_xy = c->sets[R.set_id].dev;
+  a.top = rows;
+  a.n_eval = n_eval;
+  a.Ng = I.Ng;
+  a.o = I.Ng / I.Ntheta;
+  a.res = c->maps[R.map_id].res;
+  a.stage = stage;
+  a.n_stages = n_stages;
+  a.stopped = 0;
+  a.tau = R.prm.tau;
+  a.out = out;
+  HIP_TRY(launch_margin(a, c->stream));
+  return RELOC_OK;
+}
+
+void fill_ambiguity(const uint64_t* marg, bool fragile, reloc_stats* st) {
+  st->best_margin = -1.f;
+  st->ambiguous = (marg[1] || fragile) ? 1 : 0;
+  if (marg[2] == 0 || marg[0] == 0) return;
+  const float t1 = score_of_key((uint32_t)(marg[2] >> 32));
+  const float t2 = score_of_key((uint32_t)(marg[0] >> 32));
+  st->best_margin = t1 - t2;
+  if ((double)st->best_margin <= 1e-4 * std::fabs((double)t1) + 1e-7) st->ambiguous |= 2;
 }
 
 // pinned host buffer for result rows, grown on demand
@@ -1133,6 +1167,13 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     if (int32_t e = enqueue_rank(c, R, n_eval, nrow, hrows)) return e;
     HIP_TRY(hipEventRecord(c->ev[4], s));
   }
+  // ambiguity statistics, after the timed region (rows[0] is on the device);
+  // the kernel writes its three words straight into pinned host memory
+  uint64_t* hmarg = (uint64_t*)((char*)c->pinned + 2048);
+  if (st && n_eval > 0)
+    if (int32_t e = enqueue_margin(c, R, R.best, R.order, R.rows, n_eval, R.stage, stages,
+                                   hmarg))
+      return e;
   HIP_TRY(hipStreamSynchronize(s));
   rows_to_poses(c, R, hrows, nrow, out);
   *n_out = nrow;
@@ -1146,6 +1187,8 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     st->stages = stages;
     st->early_stopped = stopped;
     st->n_eval = n_eval;
+    if (n_eval > 0) fill_ambiguity(hmarg, false, st);
+    else st->best_margin = -1.f;
     if (kr > 0) {
       for (int b = 0; b < stages; ++b)
         st->refined += std::min(kr, std::min(K, R.n_hyp - b * K));

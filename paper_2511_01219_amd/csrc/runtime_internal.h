@@ -201,6 +201,15 @@ RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots);
 int plain_stages_per_launch(const Request& R);
 // Device bytes build_request will allocate for R (admission control).
 size_t request_bytes(const Request& R);
+// Ambiguity statistics from the margin kernel's three words (fragile: the
+// stop-decision bit when the caller tracked it itself).
+void fill_ambiguity(const uint64_t* marg, bool fragile, reloc_stats* st);
+// Launches the ambiguity kernel of a finished request: per-rank words best,
+// SMAD order, device rows (row 0 = top-1), stage bests (or null); writes
+// out[0..2] (device memory, or pinned host memory the device can address).
+int32_t enqueue_margin(reloc_ctx* c, Request& R, const uint64_t* best, const int32_t* order,
+                       const PoseRow* rows, int n_eval, const uint64_t* stage, int n_stages,
+                       uint64_t* out);
 // Converts device result rows to poses in world coordinates.
 void rows_to_poses(const reloc_ctx* c, const Request& R, const PoseRow* rows, int n,
                    reloc_pose* out);
