@@ -42,6 +42,7 @@ int32_t fail(int32_t code, const char* fmt, ...) {
 
 constexpr int kMaxNs = 4096;
 constexpr int64_t kPlainFillBlocks = 4096;   // TAM workgroups one plain-path launch aims at
+constexpr int kPlainMaxStages = 64;          // stages of a later plain-path launch, at most
 constexpr int kMaxDim = 32768;
 constexpr int kMaxNg = 1 << 20;
 
@@ -397,7 +398,7 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   const int max_stages = (n + R.prm.batch_k - 1) / R.prm.batch_k;
   if (R.prm.refine_k > 0) {
     // slots for one launch of the plain path or one tick of the batched one
-    R.ref_slots = std::max(plain_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k;
+    R.ref_slots = std::max(plain_max_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k;
     R.rsel = req_alloc<int32_t>(c, R, R.ref_slots);
     R.rbest = req_alloc<uint64_t>(c, R, R.ref_slots);
   }
@@ -546,6 +547,10 @@ RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots) {
   a.s = R.ref_s;
   a.L = R.ref_L;
   return a;
+}
+
+int plain_max_stages_per_launch(const Request& R) {
+  return std::max(plain_stages_per_launch(R), kPlainMaxStages);
 }
 
 int plain_stages_per_launch(const Request& R) {
@@ -711,7 +716,7 @@ size_t request_bytes(const Request& R) {
   b += R.prep.vj.size() * 8 + R.lut.q.size() * 4 + stages * 12;
   b += (size_t)std::min<size_t>(n, (size_t)R.prm.k_out) * sizeof(PoseRow);
   if (R.prm.refine_k > 0)
-    b += (size_t)std::max(plain_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
+    b += (size_t)std::max(plain_max_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
   if (R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2) b += (size_t)I.n_fov * 12;
   b += 2 * n * 12 + (1 << 20);                                  // sort scratch
   b += 32 * 256;                                                // allocation rounding
@@ -1105,7 +1110,13 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   // stages too small to fill the device are launched several at a time
   // (their flags read at one synchronisation; stages after the first that
   // stops are discarded, so the result is that of one stage at a time)
-  const int per = plain_stages_per_launch(R);
+  // the first two launches hold enough stages to fill the device; when the
+  // search goes on, each later launch holds twice as many as the one before,
+  // up to plain_max_stages_per_launch (fewer stop-flag round trips on long
+  // searches, no wasted stage when the search stops in its second launch)
+  int per = plain_stages_per_launch(R);
+  const int per_max = plain_max_stages_per_launch(R);
+  int launches = 0;
   const int kr = R.prm.refine_k;
   for (int r0 = 0; r0 < R.n_hyp;) {
     const int left = (R.n_hyp - r0 + K - 1) / K;
@@ -1153,6 +1164,7 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
       ranked = spec;
       break;
     }
+    if (++launches >= 2) per = std::min(per_max, 2 * per);
     if (R.prm.deadline_s > 0) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
       if (el > R.prm.deadline_s && n_eval < R.n_hyp) {

@@ -199,6 +199,9 @@ RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots);
 // Stages per TAM launch of the plain path (several when a stage alone
 // cannot fill the device).
 int plain_stages_per_launch(const Request& R);
+// Stages of the later plain-path launches, at most (each launch after the
+// first doubles the previous one up to this).
+int plain_max_stages_per_launch(const Request& R);
 // Device bytes build_request will allocate for R (admission control).
 size_t request_bytes(const Request& R);
 // Ambiguity statistics from the margin kernel's three words (fragile: the
