@@ -272,6 +272,18 @@ typedef struct {
    * 1e-6 per beam). */
   int32_t coarse_metric;
   int32_t fine_metric;
+  /* reloc_run launches the device work before its first stop-flag read (ray
+   * cast, coarse metric, order, first TAM launch with refinement and stage
+   * control, first ranking) kernel by kernel (0, the default), or replays
+   * it as a HIP graph captured on the request's second run (1). Graphs are
+   * used when the order and the first ranking run in the library's own
+   * kernels (n_hyp <= 65536, first ranking <= 2048 ranks) and the context's
+   * stream is not the null stream; results are identical either way. A
+   * replayed run times only ms_total (hipEvents around the graph launch and
+   * the later launches); its per-phase times read 0. The graph saves a few
+   * microseconds of launch overhead per run (about 3 % on a 300-hypothesis
+   * search): for serving loops that repeat one request. */
+  int32_t use_graph;
 } reloc_search_params;
 
 /* Fills the defaults listed above. */
@@ -315,7 +327,8 @@ typedef struct {
   int32_t n_hyp, stages, early_stopped, n_eval;
   /* device time (hipEvents on the context's stream): whole run; ray-cast
    * kernel; SMAD kernel; SMAD order; TAM stages with refinement and stage
-   * control; ranking and result copy */
+   * control; ranking and result copy (a run replaying its head graph sets
+   * ms_total only, the others are 0) */
   float ms_total, ms_raycast, ms_sort, ms_tam, ms_rank, ms_smad;
   /* local refinement: poses refined; lattice points considered (refined
    * poses x (2s + 1)(2h + 1)^2, skipped cells included) */

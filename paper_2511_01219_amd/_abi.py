@@ -54,7 +54,7 @@ class reloc_search_params(C.Structure):
                 ("deadline_s", C.c_double), ("variant", C.c_int32),
                 ("refine_k", C.c_int32), ("refine_cells", C.c_int32),
                 ("refine_dirs", C.c_int32), ("coarse_metric", C.c_int32),
-                ("fine_metric", C.c_int32)]
+                ("fine_metric", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class reloc_scan_info(C.Structure):

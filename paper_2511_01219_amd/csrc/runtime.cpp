@@ -211,8 +211,14 @@ int32_t set_device(reloc_ctx* c) {
 }
 
 void release_request(reloc_ctx* c, Request& r) {
+  drop_head(r);
   for (void* p : r.owned) c->dfree(p);
   r.owned.clear();
+}
+
+void drop_head(Request& r) {
+  if (r.head) (void)hipGraphExecDestroy(r.head);
+  r.head = nullptr;
 }
 
 
@@ -629,11 +635,64 @@ void fill_ambiguity(const uint64_t* marg, bool fragile, reloc_stats* st) {
   if ((double)st->best_margin <= 1e-4 * std::fabs((double)t1) + 1e-7) st->ambiguous |= 2;
 }
 
-// pinned host buffer for result rows, grown on demand
+// TAM stages [r0, r0 + nb) (ns of them, the first being stage number
+// `stage`) with refinement and stage control, then their stop flags to the
+// pinned hflag.
+int32_t enqueue_stages(reloc_ctx* c, Request& R, int r0, int ns, int nb, int stage,
+                       int32_t* hflag) {
+  hipStream_t s = c->stream;
+  const int K = R.prm.batch_k, kr = R.prm.refine_k;
+  HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
+  if (kr > 0) {
+    // each stage's kr best poses: lattice search, then their refined T
+    // replaces T* before the stage's best is taken
+    HIP_TRY(launch_refine_select(R.best, r0, K, R.n_hyp, ns, kr, R.rsel, R.rbest, s));
+    const RefineArgs fa = refine_args(c, R, ns * kr);
+    HIP_TRY(launch_refine(fa, s));
+    HIP_TRY(launch_refine_commit(fa, s));
+  }
+  StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stage, R.flag + stage};
+  HIP_TRY(launch_stage_reduce_multi(sa, K, ns, R.n_hyp, s));
+  HIP_TRY(hipMemcpyAsync(hflag, R.flag + stage, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  return RELOC_OK;
+}
+
+// The device work of a run up to its first stop-flag read, the same on
+// every run of the request: ray cast, coarse metric, order, the first ns0
+// stages (nb0 ranks) and, when that is one stage, its ranking with the rows
+// copied to the pinned hrows (the result is ready at the first
+// synchronisation when the search stops there). When timed, events 0, 5,
+// 1, 2 (and 3, 4 around the ranking) time the phases; a captured head is
+// not timed (event records inside a graph give no usable timestamps here).
+int32_t enqueue_head(reloc_ctx* c, Request& R, int ns0, int nb0, int32_t* hflag,
+                     PoseRow* hrows, bool timed) {
+  hipStream_t s = c->stream;
+  auto mark = [&](int i) { return timed ? hipEventRecord(c->ev[i], s) : hipSuccess; };
+  RayArgs ra = ray_args(c, R, nullptr, nullptr);
+  ra.best0 = R.best;                 // the coarse kernel clears the per-rank best
+  HIP_TRY(mark(0));
+  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));   // none needs no ranges
+  HIP_TRY(mark(5));
+  HIP_TRY(launch_coarse(ra, s));
+  HIP_TRY(mark(1));
+  if (int32_t e = smad_order(c, R)) return e;
+  HIP_TRY(mark(2));
+  if (int32_t e = enqueue_stages(c, R, 0, ns0, nb0, 0, hflag)) return e;
+  if (ns0 == 1) {
+    HIP_TRY(mark(3));
+    if (int32_t e = enqueue_rank(c, R, nb0, std::min(R.rows_cap, nb0), hrows)) return e;
+    HIP_TRY(mark(4));
+  }
+  return RELOC_OK;
+}
+
+// pinned host buffer for result rows, grown on demand; growing it drops
+// every captured head graph (they copy rows into the old buffer)
 int32_t pinned_rows(reloc_ctx* c, size_t n, PoseRow** out) {
   const size_t need = std::max<size_t>(1, n) * sizeof(PoseRow);
   if (need > c->prows_cap) {
     HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->reqs) drop_head(kv.second);
     if (c->prows) (void)hipHostFree(c->prows);
     c->prows = nullptr;
     c->prows_cap = 0;
@@ -798,6 +857,7 @@ void reloc_search_defaults(reloc_search_params* p) {
   p->refine_dirs = -1;
   p->coarse_metric = 0;
   p->fine_metric = 0;
+  p->use_graph = 0;
 }
 
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
@@ -1089,59 +1149,68 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   const DevMap& m = c->maps[R.map_id];
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = c->stream;
-  RayArgs ra = ray_args(c, R, nullptr, nullptr);
-  ra.best0 = R.best;                 // the SMAD kernel clears the per-rank best
-  HIP_TRY(hipEventRecord(c->ev[0], s));
-  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));   // none needs no ranges
-  HIP_TRY(hipEventRecord(c->ev[5], s));
-  HIP_TRY(launch_coarse(ra, s));
-  HIP_TRY(hipEventRecord(c->ev[1], s));
-  if (int32_t e = smad_order(c, R)) return e;
-  HIP_TRY(hipEventRecord(c->ev[2], s));
   const int K = R.prm.batch_k;
   int stages = 0, stopped = 0, n_eval = 0;
   int32_t status = RELOC_OK;
   int32_t* hflag = (int32_t*)c->pinned;
   const int ncap = std::min(R.rows_cap, std::max(0, cap));
   PoseRow* hrows = nullptr;
-  if (int32_t e = pinned_rows(c, (size_t)ncap, &hrows)) return e;
+  if (int32_t e = pinned_rows(c, (size_t)R.rows_cap, &hrows)) return e;
   bool ranked = false;   // rows of the final n_eval already on the host
   int nrow = 0;
-  // stages too small to fill the device are launched several at a time
-  // (their flags read at one synchronisation; stages after the first that
-  // stops are discarded, so the result is that of one stage at a time)
   // the first two launches hold enough stages to fill the device; when the
   // search goes on, each later launch holds twice as many as the one before,
   // up to plain_max_stages_per_launch (fewer stop-flag round trips on long
-  // searches, no wasted stage when the search stops in its second launch)
+  // searches, no wasted stage when the search stops in its second launch).
+  // Stages after the first one that stops are discarded, so the result is
+  // that of one stage at a time.
   int per = plain_stages_per_launch(R);
   const int per_max = plain_max_stages_per_launch(R);
   int launches = 0;
   const int kr = R.prm.refine_k;
+  bool replayed = false;
+  // the head: everything up to the first stop-flag read, replayed as a
+  // captured graph when possible
+  {
+    const int ns0 = std::min(per, (R.n_hyp + K - 1) / K);
+    const int nb0 = std::min(ns0 * K, R.n_hyp);
+    // captured on the request's second run (a one-shot relocalization would
+    // pay the capture and gain nothing)
+    const bool graph = R.prm.use_graph && s != nullptr && R.n_hyp <= kSmallSortMax &&
+                       (ns0 != 1 || nb0 <= kRankSmallMax) && (R.head || R.runs_done >= 1);
+    if (graph && !R.head) {
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int32_t e = enqueue_head(c, R, ns0, nb0, hflag, hrows, false);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s, &g);
+      if (e != RELOC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+      }
+      if (ec != hipSuccess) return fail(RELOC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&R.head, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        R.head = nullptr;
+        return fail(RELOC_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+      }
+    }
+    replayed = graph;
+    if (graph) {
+      HIP_TRY(hipEventRecord(c->ev[0], s));
+      HIP_TRY(hipGraphLaunch(R.head, s));
+      if (ns0 == 1) HIP_TRY(hipEventRecord(c->ev[4], s));
+    } else if (int32_t e = enqueue_head(c, R, ns0, nb0, hflag, hrows, true)) {
+      return e;
+    }
+  }
   for (int r0 = 0; r0 < R.n_hyp;) {
     const int left = (R.n_hyp - r0 + K - 1) / K;
     const int ns = std::min(per, left);
     const int nb = std::min(ns * K, R.n_hyp - r0);
-    HIP_TRY(launch_tam(tam_args(c, R, r0, nb, nullptr), s));
-    if (kr > 0) {
-      // each stage's kr best poses: lattice search, then their refined T
-      // replaces T* before the stage's best is taken
-      HIP_TRY(launch_refine_select(R.best, r0, K, R.n_hyp, ns, kr, R.rsel, R.rbest, s));
-      const RefineArgs fa = refine_args(c, R, ns * kr);
-      HIP_TRY(launch_refine(fa, s));
-      HIP_TRY(launch_refine_commit(fa, s));
-    }
-    StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stages, R.flag + stages};
-    HIP_TRY(launch_stage_reduce_multi(sa, K, ns, R.n_hyp, s));
-    HIP_TRY(hipMemcpyAsync(hflag, R.flag + stages, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    // the first stage's ranking is issued before its stop flag is read: when
-    // the search stops there (or has no second stage) the result is ready at
-    // the same synchronisation
     const bool spec = r0 == 0 && ns == 1;
-    if (spec) {
-      HIP_TRY(hipEventRecord(c->ev[3], s));
-      if (int32_t e = enqueue_rank(c, R, nb, std::min(ncap, nb), hrows)) return e;
-      HIP_TRY(hipEventRecord(c->ev[4], s));
+    if (r0 > 0) {
+      if (int32_t e = enqueue_stages(c, R, r0, ns, nb, stages, hflag)) return e;
     }
     HIP_TRY(hipStreamSynchronize(s));
     int hit = -1;
@@ -1187,6 +1256,7 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
                                    hmarg))
       return e;
   HIP_TRY(hipStreamSynchronize(s));
+  ++R.runs_done;
   rows_to_poses(c, R, hrows, nrow, out);
   *n_out = nrow;
   if (st) {
@@ -1209,16 +1279,18 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[4]);
     st->ms_total = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[5]);
-    st->ms_raycast = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[5], c->ev[1]);
-    st->ms_smad = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
-    st->ms_sort = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
-    st->ms_tam = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[3], c->ev[4]);
-    st->ms_rank = ms;
+    if (!replayed) {
+      (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[5]);
+      st->ms_raycast = ms;
+      (void)hipEventElapsedTime(&ms, c->ev[5], c->ev[1]);
+      st->ms_smad = ms;
+      (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+      st->ms_sort = ms;
+      (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
+      st->ms_tam = ms;
+      (void)hipEventElapsedTime(&ms, c->ev[3], c->ev[4]);
+      st->ms_rank = ms;
+    }
   }
   return status;
 }
@@ -1276,6 +1348,7 @@ int32_t reloc_autotune(reloc_ctx* c, int32_t request_id, int32_t reps, int32_t* 
       }
     R.prm.variant = best_v;
     R.tuned_chunk = best_c;
+    drop_head(R);                    // the captured head holds the old launch shape
   }
   if (variant_out) *variant_out = R.prm.variant;
   if (chunk_out) *chunk_out = R.tuned_chunk;

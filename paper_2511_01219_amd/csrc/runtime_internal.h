@@ -117,6 +117,8 @@ struct Request {
   int32_t* flag = nullptr;
   PoseRow* rows = nullptr;
   int rows_cap = 0;
+  hipGraphExec_t head = nullptr;  // captured head of reloc_run, or null
+  int runs_done = 0;              // completed runs (the head is captured on the second)
   std::vector<void*> owned;
 };
 
@@ -180,6 +182,8 @@ namespace reloc {
 
 int32_t set_device(reloc_ctx* c);
 void release_request(reloc_ctx* c, Request& r);
+// Destroys the request's captured head graph, if any.
+void drop_head(Request& r);
 int32_t validate_search(const reloc_search_params* p);
 // Coarse-metric evaluations of a request (hypotheses x shifts scored).
 int64_t coarse_evals(const Request& R);

@@ -156,6 +156,7 @@ def test_search_param_defaults():
     assert math.isnan(q.tau)
     assert (p.refine_k, p.refine_cells, p.refine_dirs) == (0, 3, -1)
     assert (p.coarse_metric, p.fine_metric) == (0, 0)
+    assert p.use_graph == 0   # the head graph is opt-in
 
 
 def test_metric_choices_checked_on_host():

@@ -1,0 +1,106 @@
+"""The captured head graph of reloc_run against launches kernel by kernel.
+
+A request's head (ray cast, coarse metric, order, first TAM launch with
+refinement and stage control, first ranking) is captured on its second run
+and replayed afterwards when the request asks for it (use_graph=1). Every replay, with other requests' eager work,
+debug entry points and synchronisations in between, must return exactly
+the poses and statistics of the same request run without graphs; so must
+replays after an autotuning pass (which re-captures) and sets above the
+graph limit (which run without one).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_01219_amd as reloc
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+
+TIMING = ("ms_total", "ms_raycast", "ms_sort", "ms_tam", "ms_rank", "ms_smad")
+
+
+def _case(msg):
+    print("[gpu case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = reloc.Context(0)
+    yield c
+    c.close()
+
+
+def _scan(w):
+    return (w.ranges, w.angle_min, w.angle_increment, w.range_min, w.range_max)
+
+
+def _same(a, b):
+    (pa, sa), (pb, sb) = a, b
+    assert pa == pb
+    for k in sa:
+        if k not in TIMING:
+            assert sa[k] == sb[k], k
+
+
+@pytest.mark.parametrize("which,kw", [
+    ("c1", dict(n_theta=360, batch_k=10, tau=0.95)),
+    ("c1", dict(n_theta=360, batch_k=300, tau=None)),
+    ("c1", dict(n_theta=360, batch_k=10, tau=None, refine_k=3)),
+    ("c1", dict(n_theta=360, batch_k=16, tau=0.8, coarse_metric=2, fine_metric=1)),
+    ("c2", dict(n_theta=720, batch_k=64, tau=0.95)),
+])
+def test_graph_replays_equal_eager(ctx, which, kw):
+    w = make_config(1 if which == "c1" else 2)
+    m = ctx.load_map(w.occ, w.resolution, w.origin)
+    s = w.sample
+    sid, n = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
+                                   seed=s["seed"])
+    _case("graph %s %s" % (which, kw))
+    kw = dict(kw, k_out=10)
+    rid_e = ctx.prepare(m, sid, *_scan(w), use_graph=0, **kw)
+    rid_g = ctx.prepare(m, sid, *_scan(w), use_graph=1, **kw)
+    ref = ctx.run(rid_e)
+    assert all(ref[1][k] > 0 for k in ("ms_total", "ms_smad", "ms_tam"))
+    for i in range(5):
+        got = ctx.run(rid_g)
+        _same(ref, got)
+        # a replay is timed as a whole (hipEvents around the graph launch)
+        assert got[1]["ms_total"] > 0
+        if i > 0:
+            assert all(got[1][k] == 0 for k in TIMING[1:])
+        # eager work of another request and a debug call on this one between replays
+        _same(ref, ctx.run(rid_e))
+        ctx.debug_smad(rid_g, n)
+        if i == 2:
+            ctx.autotune(rid_g, reps=1)
+    ctx.release(rid_e)
+    ctx.release(rid_g)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
+def test_graph_limit_falls_back(ctx):
+    """A set of more than 65 536 hypotheses runs its head kernel by kernel
+    (the order then uses the library's radix sort) with the same results."""
+    w = make_config(2)
+    k = oracle.edt(w.occ)
+    ys, xs = np.nonzero((w.occ >= 0) & (w.occ < 65) & (k >= 18))
+    pick = np.random.default_rng(17).choice(len(xs), 70000, replace=False)
+    hyp = np.stack([xs[pick], ys[pick]], 1).astype(np.int32)
+    m = ctx.load_map(w.occ, w.resolution, w.origin)
+    sid = ctx.set_hypotheses(m, hyp)
+    _case("graph limit, 70000 hypotheses")
+    kw = dict(n_theta=720, batch_k=64, tau=0.95, k_out=10)
+    rid_e = ctx.prepare(m, sid, *_scan(w), use_graph=0, **kw)
+    rid_g = ctx.prepare(m, sid, *_scan(w), use_graph=1, **kw)
+    ref = ctx.run(rid_e)
+    for _ in range(3):
+        _same(ref, ctx.run(rid_g))
+    ctx.release(rid_e)
+    ctx.release(rid_g)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
