@@ -94,35 +94,81 @@ def measured_traffic():
         return None
 
 
+def _oracle_steps(w, hyp, pr, k, n_tam, n_theta, budget_s, threads):
+    """Whole oracle steps (ray cast and direct-sum SMAD of every hypothesis in
+    hyp, TAM of the first n_tam in SMAD order) until budget_s has passed."""
+    import numpy as np
+    import oracle
+    steps, evals = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        _, z = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], w.resolution, w.range_max,
+                              threads=threads)
+        sm, _ = oracle.smad(z, pr, threads=threads)
+        order = np.lexsort((np.arange(len(sm)), sm))[:n_tam]
+        q = np.repeat(hyp[order], n_theta, axis=0)
+        kk = np.tile(np.arange(n_theta), n_tam)
+        oracle.tam(k, w.resolution, pr, q, kk, threads=threads)
+        steps += 1
+        evals += len(hyp) * pr["n_shifts"] + n_tam * n_theta
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            return steps, evals, dt
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, hyp, n_theta, batch_k, stages_gpu, budget_s):
     """The oracle as it stands on the host cores: whole steps of the same
     workload (ray cast and direct-sum SMAD of every hypothesis, TAM of the
-    stages the GPU ran), repeated until about budget_s has passed."""
-    import numpy as np
+    stages the GPU ran), repeated until about budget_s has passed; then the
+    same steps on one thread over the first 1/16 of the hypotheses (at
+    least 64), TAM of the same share of the evaluated ones, for about
+    budget_s / 3."""
     import oracle
     pr = oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
                      range_min=w.range_min, range_max=w.range_max, n_theta=n_theta)
     k = oracle.edt(w.occ)
     threads = oracle.num_threads()
     n_tam = min(len(hyp), stages_gpu * batch_k)
-    steps, evals = 0, 0
-    t0 = time.perf_counter()
-    while True:
-        _, z = oracle.raycast(w.occ, hyp, pr["Ns"], pr["Ng"], w.resolution, w.range_max)
-        sm, _ = oracle.smad(z, pr)
-        order = np.lexsort((np.arange(len(sm)), sm))[:n_tam]
-        q = np.repeat(hyp[order], n_theta, axis=0)
-        kk = np.tile(np.arange(n_theta), n_tam)
-        oracle.tam(k, w.resolution, pr, q, kk)
-        steps += 1
-        evals += len(hyp) * pr["n_shifts"] + n_tam * n_theta
-        dt = time.perf_counter() - t0
-        if dt >= budget_s:
-            break
+    steps, evals, dt = _oracle_steps(w, hyp, pr, k, n_tam, n_theta, budget_s, 0)
+    sub = hyp[:max(64, len(hyp) // 16)]
+    n_sub = max(1, min(len(sub), round(n_tam * len(sub) / len(hyp))))
+    s1, e1, d1 = _oracle_steps(w, sub, pr, k, n_sub, n_theta, budget_s / 3, 1)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": "%d whole steps: ray cast + direct-sum SMAD of all %d hypotheses, "
                       "TAM of the first %d in SMAD order x %d orientations; %.1f s"
-                      % (steps, len(hyp), n_tam, n_theta, dt)}
+                      % (steps, len(hyp), n_tam, n_theta, dt),
+            "single_thread": {"value": e1 / d1, "unit": "evals/s", "cores": 1,
+                              "sample": "%d steps over the first %d hypotheses, TAM of %d "
+                                        "x %d orientations; %.1f s"
+                                        % (s1, len(sub), n_sub, n_theta, d1)},
+            "host": {"cpu_model": _cpu_model(), "cpu_count": os.cpu_count(),
+                     "affinity": affinity}}
+
+
+def accuracy(pose, truth, st):
+    """Error of the best pose against the true pose, with the success
+    criterion of Sec. IV-C (position error below 0.5 m and heading error
+    below 30 deg), and the run's ambiguity statistics (Remark 1)."""
+    d = math.hypot(pose["x"] - truth[0], pose["y"] - truth[1])
+    phi = abs((pose["theta"] - truth[2] + math.pi) % (2 * math.pi) - math.pi)
+    deg = math.degrees(phi)
+    return {"d_err_m": d, "phi_err_deg": deg, "success": bool(d < 0.5 and deg < 30.0),
+            "best_margin": st["best_margin"], "ambiguous": st["ambiguous"]}
 
 
 def _load_multi(ctx, w):
@@ -316,6 +362,7 @@ def bench_stress(args):
                      "tam_lookups": st["tam_lookups"]},
         "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
         "true_pose": list(w.pose),
+        "accuracy": accuracy(poses[0], w.pose, st),
         "autotune": {"variant": tv, "chunk": tc, "ms": tms},
     }
     ctx.release(rid)
@@ -610,10 +657,12 @@ def main():
                      "smad_ms": float(np.mean(smad_ms)),
                      "tam_ms": float(np.mean(tam_ms)), "rays": st["rays"],
                      "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"],
+                     "tam_lookups_per_s": st["tam_lookups"] / (float(np.mean(tam_ms)) * 1e-3),
                      "refined": st["refined"], "refine_points": st["refine_points"]},
         "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k", "g",
                                                "refined")},
         "true_pose": list(w.pose),
+        "accuracy": accuracy(poses[0], w.pose, st),
         "roofline": roofline,
         "autotune": tuned,
         "rrt": rrt,
@@ -635,6 +684,17 @@ def main():
                                   "frac": ops / t_c / FP64_ADD_PEAK, "terms": terms,
                                   "avg_ms": t_c * 1e3}
     ctx.release(rid)
+    if tau is not None:
+        # untimed: the same search without early termination, so the line
+        # shows what the stop test at tau gave up (Sec. IV-C criterion)
+        rid_f = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
+                            w.range_max, n_theta=n_theta, batch_k=batch_k, tau=None, k_out=10,
+                            refine_k=args.refine_k, refine_cells=args.refine_cells,
+                            coarse_metric=COARSE[args.coarse], fine_metric=FINE[args.fine])
+        pf, sf = ctx.run(rid_f)
+        ctx.release(rid_f)
+        out["accuracy"]["full_search"] = dict(accuracy(pf[0], w.pose, sf), tam=pf[0]["tam"],
+                                              rank=pf[0]["rank"], ms=sf["ms_total"])
     if not args.no_cpu:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, hyp, n_theta, batch_k, st["stages"],

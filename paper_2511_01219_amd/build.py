@@ -26,7 +26,8 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-    # packed FP32 instructions are disabled on purpose
+    # no packed FP32 instructions: some of their forms gave silently wrong
+    # results on this hardware now and then
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INC}", f"-I{CSRC}", "-Wall", "-Wno-unused-result",
 ]

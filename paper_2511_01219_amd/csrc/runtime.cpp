@@ -657,11 +657,16 @@ int32_t enqueue_stages(reloc_ctx* c, Request& R, int r0, int ns, int nb, int sta
   return RELOC_OK;
 }
 
+// Pinned words the margin kernel writes (best distinct, stop fragility,
+// top-1 word).
+static uint64_t* head_margin_words(reloc_ctx* c) { return (uint64_t*)((char*)c->pinned + 2048); }
+
 // The device work of a run up to its first stop-flag read, the same on
 // every run of the request: ray cast, coarse metric, order, the first ns0
 // stages (nb0 ranks) and, when that is one stage, its ranking with the rows
 // copied to the pinned hrows (the result is ready at the first
-// synchronisation when the search stops there). When timed, events 0, 5,
+// synchronisation when the search stops there), followed by the ambiguity
+// statistics of that result. When timed, events 0, 5,
 // 1, 2 (and 3, 4 around the ranking) time the phases; a captured head is
 // not timed (event records inside a graph give no usable timestamps here).
 int32_t enqueue_head(reloc_ctx* c, Request& R, int ns0, int nb0, int32_t* hflag,
@@ -682,6 +687,10 @@ int32_t enqueue_head(reloc_ctx* c, Request& R, int ns0, int nb0, int32_t* hflag,
     HIP_TRY(mark(3));
     if (int32_t e = enqueue_rank(c, R, nb0, std::min(R.rows_cap, nb0), hrows)) return e;
     HIP_TRY(mark(4));
+    // the ambiguity statistics of that one-stage result, after the timed region
+    if (int32_t e = enqueue_margin(c, R, R.best, R.order, R.rows, nb0, R.stage, 1,
+                                   head_margin_words(c)))
+      return e;
   }
   return RELOC_OK;
 }
@@ -1250,8 +1259,9 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   }
   // ambiguity statistics, after the timed region (rows[0] is on the device);
   // the kernel writes its three words straight into pinned host memory
-  uint64_t* hmarg = (uint64_t*)((char*)c->pinned + 2048);
-  if (st && n_eval > 0)
+  // (a result ranked in the head has its statistics from the head too)
+  uint64_t* hmarg = head_margin_words(c);
+  if (st && n_eval > 0 && !ranked)
     if (int32_t e = enqueue_margin(c, R, R.best, R.order, R.rows, n_eval, R.stage, stages,
                                    hmarg))
       return e;
