@@ -36,6 +36,35 @@ constexpr int NW = TB / 64;
 constexpr int THETA_PER_BLOCK = 16;
 constexpr uint32_t NOKEY = 0xFFFFFFFFu;
 
+// The three gathered tables (squared EDT map, direction table, likelihood
+// LUT) are read through buffer resources with 32-bit byte offsets: no 64-bit
+// address arithmetic per gather. Every offset used is inside its table.
+struct TamTables {
+  __amdgpu_buffer_rsrc_t k, dir, lut;
+  __device__ __forceinline__ uint32_t kval(uint32_t idx) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(k, (int)(idx << 2), 0, 0);
+  }
+  __device__ __forceinline__ int2 direction(int i) const {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(dir, i << 3, 0, 0);
+    return int2{(int)v[0], (int)v[1]};
+  }
+  __device__ __forceinline__ int32_t ell(uint32_t key) const {
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
+  }
+};
+
+__device__ __forceinline__ TamTables tam_tables(const TamArgs& a) {
+  TamTables t;
+  // byte offsets are unsigned 32-bit: up to 2^30 cells (a 32768^2 map) fit,
+  // and the record count saturates at 2^32 - 1
+  const uint64_t kbytes = 4ull * (uint64_t)a.W * (uint64_t)a.H;
+  const uint32_t krec = kbytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)kbytes;
+  t.k = __builtin_amdgcn_make_buffer_rsrc((void*)a.kmap, (short)0, (int)krec, 0x00020000);
+  t.dir = __builtin_amdgcn_make_buffer_rsrc((void*)a.dirs, (short)0, 16 * a.Ng, 0x00020000);
+  t.lut = __builtin_amdgcn_make_buffer_rsrc((void*)a.lut, (short)0, 4 << a.keybits, 0x00020000);
+  return t;
+}
+
 __device__ __forceinline__ uint32_t sqrt_q16(uint32_t k) {
   return __float2uint_rn(__fsqrt_rn((float)k) * 65536.0f);
 }
@@ -158,8 +187,11 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   // every gather batch below reads whole 64 x SB slices of the padded table
   static_assert(64 * SB <= kTamBeamPad, "gather batch beyond the beam padding");
   const int nvp = tam_beams_padded(nv);
-  for (int v = tid; v < nvp; v += TB) sbz[v] = a.beams[v];
+  // padded entries get range -1: a slot is valid exactly when its range is
+  // non-negative (valid ranges are positive Q8 counts)
+  for (int v = tid; v < nvp; v += TB) sbz[v] = v < nv ? a.beams[v] : int2{0, -1};
   __syncthreads();
+  const TamTables tb = tam_tables(a);
 
   // per-pose results parked in lane g
   int64_t p_sl = 0;
@@ -186,7 +218,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
           // padded beams and a doubled direction table: no clamp, no wrap
           const int2 bz = sbz[lane + 64 * (i0 + s2)];
           zq[s2] = bz.y;
-          U[s2] = a.dirs[bz.x + ok];
+          U[s2] = tb.direction(bz.x + ok);
         }
         uint32_t kk[SB];
         bool in[SB];
@@ -197,24 +229,20 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
           const int ex = (int)((X20 + (int64_t)zq[s2] * U[s2].x) >> 28);
           const int ey = (int)((Y20 + (int64_t)zq[s2] * U[s2].y) >> 28);
           in[s2] = (uint32_t)ex < (uint32_t)a.W && (uint32_t)ey < (uint32_t)a.H;
-          const uint32_t idx = in[s2] ? (uint32_t)ey * (uint32_t)a.W + (uint32_t)ex : 0u;
-          kk[s2] = a.kmap[idx];
+          const uint32_t idx = in[s2] ? __umul24((uint32_t)ey, (uint32_t)a.W) + (uint32_t)ex : 0u;
+          kk[s2] = tb.kval(idx);
         }
+        // branch-free: keys and sums by selects
 #pragma unroll
         for (int s2 = 0; s2 < SB; ++s2) {
-          const bool valid = lane + 64 * (i0 + s2) < nv;
-          uint32_t key = NOKEY;
-          if (valid) {
-            if (in[s2]) {
-              key = 2u * min(kk[s2], (uint32_t)a.kcap);
-              sumk += kk[s2];
-              sumsq += sqrt_q16(kk[s2]);
-            } else {
-              key = (uint32_t)a.key_off;
-              ++noff;
-            }
-          }
-          keys[i0 + s2] = key;
+          const bool valid = zq[s2] >= 0;
+          const bool hit = valid && in[s2];
+          const uint32_t kv = kk[s2];
+          keys[i0 + s2] = hit ? 2u * min(kv, (uint32_t)a.kcap)
+                              : (valid ? (uint32_t)a.key_off : NOKEY);
+          sumk += hit ? kv : 0u;
+          sumsq += hit ? sqrt_q16(kv) : 0u;
+          noff += (valid && !in[s2]) ? 1 : 0;
         }
       } else {
 #pragma unroll
@@ -245,14 +273,14 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
           int32_t lv[SB];
 #pragma unroll
           for (int s2 = 0; s2 < SB; ++s2)
-            lv[s2] = a.lut[keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u];
+            lv[s2] = tb.ell(keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u);
 #pragma unroll
           for (int s2 = 0; s2 < SB; ++s2)
             if (keys[i0 + s2] < tkey) sl += lv[s2];
         }
       }
       sl = wave_sum(sl);
-      sl += (int64_t)(a.kmid - below) * (int64_t)a.lut[tkey];
+      sl += (int64_t)(a.kmid - below) * (int64_t)tb.ell(tkey);
     } else {
       // baseline and LF: the sum of l over every valid beam (eq. 32)
 #pragma unroll
@@ -261,7 +289,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
           int32_t lv[SB];
 #pragma unroll
           for (int s2 = 0; s2 < SB; ++s2)
-            lv[s2] = a.lut[keys[i0 + s2] != NOKEY ? keys[i0 + s2] : 0u];
+            lv[s2] = tb.ell(keys[i0 + s2] != NOKEY ? keys[i0 + s2] : 0u);
 #pragma unroll
           for (int s2 = 0; s2 < SB; ++s2)
             if (keys[i0 + s2] != NOKEY) sl += lv[s2];
