@@ -254,19 +254,27 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       // TAM and T_mean: the top-k_mid sum of eq. 24-27. The k_mid-th
       // smallest key: bitwise search for the largest t with fewer than
       // k_mid keys below it; counts from wavefront ballots
+      // (whole gather chunks are tested: their padded slots hold NOKEY,
+      // which is below no candidate)
       uint32_t tkey = 0;
       for (int bit = KB - 1; bit >= 0; --bit) {
         const uint32_t cand = tkey | (1u << bit);
         int cnt = 0;
 #pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (64 * q < nv) cnt += __popcll(__ballot(keys[q] < cand));
+        for (int i0 = 0; i0 < R; i0 += SB)
+          if (64 * i0 < nv) {
+#pragma unroll
+            for (int s2 = 0; s2 < SB; ++s2) cnt += __popcll(__ballot(keys[i0 + s2] < cand));
+          }
         if (cnt < a.kmid) tkey = cand;
       }
       int below = 0;
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (64 * q < nv) below += __popcll(__ballot(keys[q] < tkey));
+      for (int i0 = 0; i0 < R; i0 += SB)
+        if (64 * i0 < nv) {
+#pragma unroll
+          for (int s2 = 0; s2 < SB; ++s2) below += __popcll(__ballot(keys[i0 + s2] < tkey));
+        }
 #pragma unroll
       for (int i0 = 0; i0 < R; i0 += SB) {
         if (64 * i0 < nv) {
