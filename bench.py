@@ -492,6 +492,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tau", default="0.95")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-full-search", action="store_true",
+                    help="skip the untimed search without early termination that the "
+                         "accuracy report of a tau run adds (profiler runs that count "
+                         "the timed launches only)")
     ap.add_argument("--variant", type=int, default=0,
                     help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
     ap.add_argument("--no-cpu", action="store_true")
@@ -684,7 +688,7 @@ def main():
                                   "frac": ops / t_c / FP64_ADD_PEAK, "terms": terms,
                                   "avg_ms": t_c * 1e3}
     ctx.release(rid)
-    if tau is not None:
+    if tau is not None and not args.no_full_search:
         # untimed: the same search without early termination, so the line
         # shows what the stop test at tau gave up (Sec. IV-C criterion)
         rid_f = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,

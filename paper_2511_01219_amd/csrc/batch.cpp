@@ -4,13 +4,15 @@
 // A batch runs in three phases on the context's stream:
 //   front : one ray-cast launch and one SMAD launch over the hypotheses of
 //           every request (per-request descriptors in device memory), then
-//           one segmented stable sort for all SMAD orders;
+//           one segmented stable sort for all SMAD orders (for small groups
+//           one small sort per request);
 //   ticks : each tick is one TAM launch per kernel class over a rank range
 //           of every unfinished request plus one stage-control launch that
 //           reduces every stage of the tick on the device; the host reads
 //           one flag per stage. A request's range covers `spec` consecutive
-//           stages (1 for its first two ticks, then 2, 4, ... up to
-//           kMaxSpec), granted oldest request first out of a per-tick budget
+//           stages (in its first two ticks as many as the plain path's first
+//           launch, then twice as many each tick up to kMaxSpec), granted
+//           oldest request first out of a per-tick budget
 //           of TAM workgroups, at least one stage each; stages after the
 //           first one whose best T exceeds tau are discarded, so the
 //           evaluated set and every result equal those of the
@@ -30,6 +32,7 @@ namespace reloc {
 namespace {
 
 constexpr int kMaxSpec = kMaxTickStages;
+constexpr int kSmallSortGroup = 8;      // front groups up to this size sort per request
 constexpr int64_t kTickBlocks = 65536;  // TAM workgroups one tick may grant beyond one stage each
 
 // Contiguous buffers of one front-phase group: SMAD sort keys / values, the
@@ -90,12 +93,33 @@ struct Blob {
 
 }  // namespace
 
-struct ServeState {
-  // staging of descriptor tables: pinned host and device buffers
-  void* hbuf = nullptr;
+// One staging slot for descriptor tables: a pinned host buffer, its device
+// copy, and an event recorded after the copy out of the host buffer.
+struct Staging {
+  void* h = nullptr;
   size_t hcap = 0;
-  uint8_t* dbuf = nullptr;
+  uint8_t* d = nullptr;
   size_t dcap = 0;
+  hipEvent_t ev = nullptr;
+  bool armed = false;   // ev marks a copy that may still be reading h
+};
+constexpr int kStagingRing = 4;
+
+struct ServeState {
+  // staging of descriptor tables: a ring of slots, so a commit waits only
+  // for the copy made kStagingRing commits earlier, not for the stream
+  Staging ring[kStagingRing];
+  int ring_next = 0;
+  // ranking scratch, grown on demand and kept between calls
+  uint64_t* rk1 = nullptr;
+  uint64_t* rk2 = nullptr;
+  size_t rk_cap = 0;
+  PoseRow* rrows = nullptr;
+  size_t rrows_cap = 0;
+  uint64_t* rmarg = nullptr;
+  size_t rmarg_cap = 0;
+  uint8_t* rtmp = nullptr;
+  size_t rtmp_cap = 0;
   // per-tick stage outputs
   uint64_t* dstage = nullptr;
   int32_t* dflag = nullptr;
@@ -121,31 +145,60 @@ namespace {
 
 ServeState* state(reloc_ctx* c) { return c->serve; }
 
-// Copies the blob to device memory (after the stream has drained, so the
-// pinned buffer is free); *dev receives the device address of offset 0.
+// Copies the blob to device memory through the next staging slot;
+// *dev receives the device address of offset 0. The slot's host buffer is
+// rewritten only after the copy that last read it has completed; its device
+// buffer is rewritten by a copy queued behind every kernel that read it.
 int32_t commit(reloc_ctx* c, ServeState& S, const Blob& bl, uint8_t** dev) {
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  Staging& g = S.ring[S.ring_next];
+  S.ring_next = (S.ring_next + 1) % kStagingRing;
+  if (g.armed) {
+    HIP_TRY(hipEventSynchronize(g.ev));
+    g.armed = false;
+  }
   const size_t need = std::max<size_t>(bl.b.size(), 256);
-  if (need > S.hcap) {
-    if (S.hbuf) (void)hipHostFree(S.hbuf);
-    S.hbuf = nullptr;
-    S.hcap = 0;
-    const size_t cap = std::max(need, S.hcap * 2);
-    HIP_TRY(hipHostMalloc(&S.hbuf, cap, hipHostMallocDefault));
-    S.hcap = cap;
+  if (need > g.hcap) {
+    if (g.h) (void)hipHostFree(g.h);
+    g.h = nullptr;
+    const size_t cap = std::max(need, g.hcap * 2);
+    g.hcap = 0;
+    HIP_TRY(hipHostMalloc(&g.h, cap, hipHostMallocDefault));
+    g.hcap = cap;
   }
-  if (need > S.dcap) {
-    c->dfree(S.dbuf);
-    S.dbuf = nullptr;
-    S.dcap = 0;
+  if (need > g.dcap) {
+    // kernels queued earlier may still read the old device buffer
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->dfree(g.d);
+    g.d = nullptr;
+    g.dcap = 0;
     const size_t cap = std::max(need, (size_t)1 << 16);
-    S.dbuf = (uint8_t*)c->dalloc(cap);
-    if (!S.dbuf) return RELOC_E_NOMEM;
-    S.dcap = cap;
+    g.d = (uint8_t*)c->dalloc(cap);
+    if (!g.d) return RELOC_E_NOMEM;
+    g.dcap = cap;
   }
-  std::memcpy(S.hbuf, bl.b.data(), bl.b.size());
-  HIP_TRY(hipMemcpyAsync(S.dbuf, S.hbuf, bl.b.size(), hipMemcpyHostToDevice, c->stream));
-  *dev = S.dbuf;
+  if (!g.ev) HIP_TRY(hipEventCreateWithFlags(&g.ev, hipEventDisableTiming));
+  std::memcpy(g.h, bl.b.data(), bl.b.size());
+  HIP_TRY(hipMemcpyAsync(g.d, g.h, bl.b.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(g.ev, c->stream));
+  g.armed = true;
+  *dev = g.d;
+  return RELOC_OK;
+}
+
+// Grow-only device scratch of n elements (at least); the stream is drained
+// before a buffer that earlier work may still use is replaced.
+template <typename T>
+int32_t grow_scratch(reloc_ctx* c, T*& p, size_t& cap, size_t n) {
+  n = std::max<size_t>(n, 1);
+  if (p && n <= cap) return RELOC_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t nc = std::max(n, cap * 2);
+  c->dfree(p);
+  p = nullptr;
+  cap = 0;
+  p = (T*)c->dalloc(nc * sizeof(T));
+  if (!p) return RELOC_E_NOMEM;
+  cap = nc;
   return RELOC_OK;
 }
 
@@ -212,11 +265,20 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   A->best = A->get<uint64_t>(N);
   A->vals = A->get<int32_t>(N);
   A->order = A->get<int32_t>(N);
+  // a small group of sets within the small-sort limit is ordered by one
+  // two-kernel sort per request (the plain path's) rather than by the
+  // multi-pass segmented radix sort; both are stable, so the orders agree
+  bool per_request = n <= kSmallSortGroup;
+  for (int i = 0; i < n && per_request; ++i) per_request = hpre[i + 1] - hpre[i] <= kSmallSortMax;
   size_t tb = 0;
-  HIP_TRY(seg_sort_pairs_u64_i32(nullptr, &tb, A->keys, A->keys2, A->vals, A->order, N, n,
-                                 nullptr, c->stream));
-  void* tmp = A->get<uint8_t>(tb);
-  if (!A->keys || !A->keys2 || !A->best || !A->vals || !A->order || !tmp) return RELOC_E_NOMEM;
+  void* tmp = nullptr;
+  if (!per_request) {
+    HIP_TRY(seg_sort_pairs_u64_i32(nullptr, &tb, A->keys, A->keys2, A->vals, A->order, N, n,
+                                   nullptr, c->stream));
+    tmp = A->get<uint8_t>(tb);
+    if (!tmp) return RELOC_E_NOMEM;
+  }
+  if (!A->keys || !A->keys2 || !A->best || !A->vals || !A->order) return RELOC_E_NOMEM;
   std::vector<RayArgs> ra(n);
   for (int i = 0; i < n; ++i) {
     Request& R = c->reqs.at(F[i]->rid);
@@ -251,7 +313,17 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   for (int i = 0; i < n; ++i)
     if (ra[i].coarse != 0) HIP_TRY(launch_coarse(ra[i], s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
-  HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp, s));
+  if (per_request) {
+    for (int i = 0; i < n; ++i) {
+      const int64_t o = hpre[i];
+      // keys2 and vals serve as the tile-sort scratch
+      HIP_TRY(small_sort_pairs_u64(A->keys + o, A->keys2 + o, A->vals + o, nullptr, A->order + o,
+                                   (int)(hpre[i + 1] - o), s));
+    }
+  } else {
+    HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp,
+                                   s));
+  }
   HIP_TRY(hipEventRecord(c->ev[3], s));
   if (pt) {
     pt->raycast += elapsed(c->ev[0], c->ev[1]);
@@ -263,7 +335,8 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
     f.arena = A;
     f.off = hpre[i];
     f.next_rank = 0;
-    f.spec = 1;
+    // first ticks as large as the plain path's first launches
+    f.spec = std::min(kMaxSpec, plain_stages_per_launch(c->reqs.at(f.rid)));
     f.ticks = 0;
     f.stages = 0;
     f.n_eval = 0;
@@ -437,16 +510,33 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
     ra[i] = RankArgs{F[i]->arena->best + F[i]->off, F[i]->arena->order + F[i]->off, R.smad};
   }
   const int64_t NK = kpre[n], NR = rpre[n];
-  Arena T;
-  T.c = c;
-  uint64_t* k1 = T.get<uint64_t>(NK);
-  uint64_t* k2 = T.get<uint64_t>(NK);
-  PoseRow* dr = T.get<PoseRow>(NR);
-  uint64_t* dmarg = T.get<uint64_t>(3 * (size_t)n);
+  // a small group of short rankings: one single-launch ranking per request
+  // (the plain path's); otherwise one segmented sort for all. Both order by
+  // (T desc, rank asc) over distinct keys, so the rows agree.
+  bool per_request = n <= kSmallSortGroup;
+  for (int i = 0; i < n && per_request; ++i) per_request = F[i]->n_eval <= kRankSmallMax;
+  if (int32_t e = grow_scratch(c, S.rrows, S.rrows_cap, (size_t)NR)) return e;
+  if (int32_t e = grow_scratch(c, S.rmarg, S.rmarg_cap, 3 * (size_t)n)) return e;
+  PoseRow* dr = S.rrows;
+  uint64_t* dmarg = S.rmarg;
+  uint64_t* k1 = nullptr;
+  uint64_t* k2 = nullptr;
   size_t tb = 0;
-  HIP_TRY(seg_sort_keys_u64(nullptr, &tb, k1, k2, NK, n, nullptr, c->stream));
-  void* tmp = T.get<uint8_t>(tb);
-  if (!k1 || !k2 || !dr || !dmarg || !tmp) return RELOC_E_NOMEM;
+  void* tmp = nullptr;
+  if (!per_request) {
+    // both key buffers share one capacity
+    if (!S.rk1 || !S.rk2 || (size_t)NK > S.rk_cap) {
+      size_t c1 = S.rk_cap, c2 = S.rk_cap;
+      if (int32_t e = grow_scratch(c, S.rk1, c1, (size_t)NK)) return e;
+      if (int32_t e = grow_scratch(c, S.rk2, c2, c1)) return e;
+      S.rk_cap = std::min(c1, c2);
+    }
+    k1 = S.rk1;
+    k2 = S.rk2;
+    HIP_TRY(seg_sort_keys_u64(nullptr, &tb, k1, k2, NK, n, nullptr, c->stream));
+    if (int32_t e = grow_scratch(c, S.rtmp, S.rtmp_cap, tb)) return e;
+    tmp = S.rtmp;
+  }
   Blob bl;
   const size_t o_ra = bl.add(ra.data(), n);
   const size_t o_kp = bl.add(kpre.data(), n + 1);
@@ -459,9 +549,18 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   hipStream_t s = c->stream;
   std::vector<PoseRow> host(NR);
   HIP_TRY(hipEventRecord(c->ev[4], s));
-  HIP_TRY(launch_rank_keys_batch(d_ra, d_kp, n, NK, k1, s));
-  HIP_TRY(seg_sort_keys_u64(tmp, &tb, k1, k2, NK, n, d_kp, s));
-  HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k2, dr, s));
+  if (per_request) {
+    for (int i = 0; i < n; ++i) {
+      if (F[i]->n_eval <= 0) continue;
+      // at least row 0: the ambiguity statistics read it
+      HIP_TRY(launch_rank_small(ra[i].best, F[i]->n_eval, ra[i].order, ra[i].smad,
+                                std::max(1, nrow[i]), dr + rpre[i], s));
+    }
+  } else {
+    HIP_TRY(launch_rank_keys_batch(d_ra, d_kp, n, NK, k1, s));
+    HIP_TRY(seg_sort_keys_u64(tmp, &tb, k1, k2, NK, n, d_kp, s));
+    HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k2, dr, s));
+  }
   if (NR > 0)
     HIP_TRY(hipMemcpyAsync(host.data(), dr, NR * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
   std::vector<uint64_t> hm(3 * (size_t)n, 0);
@@ -693,10 +792,18 @@ void ctx_stop_serving(reloc_ctx* c) {
     f.arena.reset();
   }
   S->active.clear();
-  c->dfree(S->dbuf);
+  for (Staging& g : S->ring) {
+    c->dfree(g.d);
+    if (g.h) (void)hipHostFree(g.h);
+    if (g.ev) (void)hipEventDestroy(g.ev);
+  }
+  c->dfree(S->rk1);
+  c->dfree(S->rk2);
+  c->dfree(S->rrows);
+  c->dfree(S->rmarg);
+  c->dfree(S->rtmp);
   c->dfree(S->dstage);
   c->dfree(S->dflag);
-  if (S->hbuf) (void)hipHostFree(S->hbuf);
   if (S->hflag) (void)hipHostFree(S->hflag);
   if (S->hstage) (void)hipHostFree(S->hstage);
   S->dcv.notify_all();

@@ -919,6 +919,7 @@ void reloc_ctx_destroy(reloc_ctx* c) {
     c->reqs.clear();
     c->sets.clear();
     c->maps.clear();
+    c->flush_cache();
     for (auto& e : c->ev)
       if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);

@@ -143,38 +143,86 @@ struct reloc_ctx {
   void* prows = nullptr;          // pinned result rows
   size_t prows_cap = 0;
 
+  // Device blocks are handed out in size classes (powers of two up to
+  // 1 MiB, then multiples of 2 MiB). A freed block of at most
+  // kCacheBlockMax bytes is kept for a later allocation of its class
+  // instead of going back to the allocator: every use of device memory is
+  // queued on `stream`, so work that reuses a block runs after the last use
+  // of its previous owner. Live blocks (`used`) plus kept ones never exceed
+  // the budget: kept blocks go back to the allocator before an allocation
+  // would pass it, when the allocator fails, and at destruction.
+  std::multimap<size_t, void*> cache;
+  size_t cached = 0;
+  static constexpr size_t kCacheBlockMax = (size_t)256 << 20;
+  static constexpr size_t kCacheMax = (size_t)2 << 30;
+
+  static size_t size_class(size_t bytes) {
+    if (bytes <= ((size_t)1 << 20)) {
+      size_t c = 256;
+      while (c < bytes) c <<= 1;
+      return c;
+    }
+    const size_t m = (size_t)2 << 20;
+    return (bytes + m - 1) / m * m;
+  }
+  void* raw_alloc(size_t bytes) {
+    void* p = nullptr;
+    if (has_alloc) return alloc.alloc(bytes, alloc.user);
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
+  void raw_free(void* p) {
+    if (has_alloc)
+      alloc.free(p, alloc.user);
+    else
+      (void)hipFree(p);
+  }
+  void flush_cache() {
+    for (auto& kv : cache) raw_free(kv.second);
+    cache.clear();
+    cached = 0;
+  }
   void* dalloc(size_t bytes) {
-    if (bytes == 0) bytes = 1;
-    bytes = (bytes + 255) & ~(size_t)255;
-    if (used + bytes > budget) {
-      fail(RELOC_E_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu", used, bytes,
+    const size_t cls = size_class(bytes == 0 ? 1 : bytes);
+    if (used + cls > budget) {
+      fail(RELOC_E_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu", used, cls,
            budget);
       return nullptr;
     }
     void* p = nullptr;
-    if (has_alloc) {
-      p = alloc.alloc(bytes, alloc.user);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      p = nullptr;
+    auto it = cache.find(cls);
+    if (it != cache.end()) {
+      p = it->second;
+      cache.erase(it);
+      cached -= cls;
+    } else {
+      if (used + cached + cls > budget) flush_cache();
+      p = raw_alloc(cls);
+      if (!p && !cache.empty()) {
+        flush_cache();
+        p = raw_alloc(cls);
+      }
     }
     if (!p) {
-      fail(RELOC_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+      fail(RELOC_E_NOMEM, "device allocation of %zu bytes failed", cls);
       return nullptr;
     }
-    sizes[p] = bytes;
-    used += bytes;
+    sizes[p] = cls;
+    used += cls;
     return p;
   }
   void dfree(void* p) {
     if (!p) return;
     auto it = sizes.find(p);
     if (it == sizes.end()) return;
-    used -= it->second;
+    const size_t sz = it->second;
+    used -= sz;
     sizes.erase(it);
-    if (has_alloc)
-      alloc.free(p, alloc.user);
-    else
-      (void)hipFree(p);
+    if (sz <= kCacheBlockMax && cached + sz <= kCacheMax) {
+      cache.emplace(sz, p);
+      cached += sz;
+    } else {
+      raw_free(p);
+    }
   }
 };
 
