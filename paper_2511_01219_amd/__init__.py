@@ -147,7 +147,12 @@ class Context:
                     return None
 
             def _free(ptr, user, _t=torch):
-                _t.cuda.caching_allocator_delete(ptr)
+                try:
+                    _t.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    # a context left open until interpreter shutdown is torn
+                    # down after torch; the process is ending, nothing to free
+                    pass
 
             self._cb = (_abi.ALLOC_FN(_alloc), _abi.FREE_FN(_free))
             self._alloc_struct = _abi.reloc_allocator(self._cb[0], self._cb[1], None)

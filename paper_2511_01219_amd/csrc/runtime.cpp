@@ -321,15 +321,45 @@ int32_t sample_cells(const DevMap& m, const reloc_sample_params* p, std::vector<
   return RELOC_OK;
 }
 
+// Morton (Z-order) casting order of the cells xy[0, n), ties by index: the
+// rays in flight on one XCD then start in one compact region of the map.
+std::vector<int32_t> morton_order(const std::vector<int32_t>& xy, int n) {
+  auto spread = [](uint32_t v) {
+    v &= 0xFFFF;
+    v = (v | (v << 8)) & 0x00FF00FF;
+    v = (v | (v << 4)) & 0x0F0F0F0F;
+    v = (v | (v << 2)) & 0x33333333;
+    v = (v | (v << 1)) & 0x55555555;
+    return v;
+  };
+  std::vector<std::pair<uint32_t, int32_t>> mc(n);
+  for (int h = 0; h < n; ++h)
+    mc[h] = {spread((uint32_t)xy[2 * h]) | (spread((uint32_t)xy[2 * h + 1]) << 1), h};
+  std::sort(mc.begin(), mc.end());
+  std::vector<int32_t> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = mc[i].second;
+  return perm;
+}
+
 int32_t new_set(reloc_ctx* c, int map_id, std::vector<int32_t>&& xy, int32_t* set_id) {
   HypSet hs;
   hs.map_id = map_id;
   hs.n = (int)(xy.size() / 2);
   hs.host = std::move(xy);
+  hs.morton = morton_order(hs.host, hs.n);
   hs.dev = (int32_t*)c->dalloc(std::max<size_t>(1, hs.host.size()) * sizeof(int32_t));
-  if (!hs.dev) return RELOC_E_NOMEM;
-  if (int32_t e = upload(c, hs.dev, hs.host.data(), hs.host.size())) {
+  hs.morton_dev = (int32_t*)c->dalloc(std::max<size_t>(1, hs.morton.size()) * sizeof(int32_t));
+  if (!hs.dev || !hs.morton_dev) {
     c->dfree(hs.dev);
+    c->dfree(hs.morton_dev);
+    return RELOC_E_NOMEM;
+  }
+  int32_t e = upload(c, hs.dev, hs.host.data(), hs.host.size());
+  if (e == RELOC_OK) e = upload(c, hs.morton_dev, hs.morton.data(), hs.morton.size());
+  if (e == RELOC_OK && hipStreamSynchronize(c->stream) != hipSuccess) e = RELOC_E_DEVICE;
+  if (e != RELOC_OK) {
+    c->dfree(hs.dev);
+    c->dfree(hs.morton_dev);
     return e;
   }
   const int id = c->next_id++;
@@ -339,6 +369,18 @@ int32_t new_set(reloc_ctx* c, int map_id, std::vector<int32_t>&& xy, int32_t* se
   *set_id = id;
   return RELOC_OK;
 }
+
+// Host image of several tables, each at a 256-byte aligned offset.
+struct TableBlob {
+  std::vector<uint8_t> b;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = (b.size() + 255) & ~(size_t)255;
+    b.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) std::memcpy(b.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
 
 // Builds the request's device tables and work buffers.
 int32_t build_request(reloc_ctx* c, Request& R) {
@@ -378,22 +420,45 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   std::vector<int32_t> base(R.prep.vj.size());
   for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
   const int n = R.n_hyp, nv = I.n_valid;
-  R.raydirs = req_alloc<int2>(c, R, Ns);
-  R.kap = req_alloc<float2>(c, R, Ns);
-  R.dir_i = req_alloc<int4>(c, R, Ns);
-  R.dir_f = req_alloc<float4>(c, R, Ns);
-  R.runs = req_alloc<int2>(c, R, R.prep.runs.size());
   const int nvp = tam_beams_padded(nv);
-  R.beams = req_alloc<int2>(c, R, nvp);
-  R.dirs = req_alloc<int2>(c, R, 2 * (size_t)Ng);
-  R.dlut = req_alloc<int32_t>(c, R, R.lut.q.size());
   const bool direct = R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2;
-  if (direct) {
-    R.fov_z = req_alloc<double>(c, R, R.prep.fz.size());
-    R.fov_j = req_alloc<int32_t>(c, R, R.prep.fj.size());
+  const HypSet& hs = c->sets[R.set_id];
+  // the read-only tables of the request in one device block, one copy
+  std::vector<int2> beams(nvp, int2{0, 0});
+  for (int v = 0; v < nv; ++v) beams[v] = int2{base[v], R.prep.vzq[v]};
+  std::vector<int2> U2(2 * (size_t)Ng);
+  std::copy(U.begin(), U.end(), U2.begin());
+  std::copy(U.begin(), U.end(), U2.begin() + Ng);
+  // a request over a prefix of the set casts in the set's order restricted
+  // to the prefix (the Morton order of the prefix)
+  std::vector<int32_t> perm;
+  if (n < hs.n) {
+    perm.reserve(n);
+    for (int32_t h : hs.morton)
+      if (h < n) perm.push_back(h);
   }
+  TableBlob tb;
+  const size_t o_rd = tb.add(rd), o_kp = tb.add(kp), o_di = tb.add(di), o_df = tb.add(df);
+  const size_t o_runs = tb.add(R.prep.runs), o_beams = tb.add(beams), o_dirs = tb.add(U2);
+  const size_t o_lut = tb.add(R.lut.q);
+  const size_t o_fz = direct ? tb.add(R.prep.fz) : 0, o_fj = direct ? tb.add(R.prep.fj) : 0;
+  const size_t o_perm = perm.empty() ? 0 : tb.add(perm);
+  uint8_t* tables = req_alloc<uint8_t>(c, R, tb.b.size());
+  if (!tables) return RELOC_E_NOMEM;
+  R.raydirs = (int2*)(tables + o_rd);
+  R.kap = (float2*)(tables + o_kp);
+  R.dir_i = (int4*)(tables + o_di);
+  R.dir_f = (float4*)(tables + o_df);
+  R.runs = (int2*)(tables + o_runs);
+  R.beams = (int2*)(tables + o_beams);
+  R.dirs = (int2*)(tables + o_dirs);
+  R.dlut = (int32_t*)(tables + o_lut);
+  if (direct) {
+    R.fov_z = (double*)(tables + o_fz);
+    R.fov_j = (int32_t*)(tables + o_fj);
+  }
+  R.perm = perm.empty() ? hs.morton_dev : (int32_t*)(tables + o_perm);
   R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
-  R.perm = req_alloc<int32_t>(c, R, n);
   R.smad = req_alloc<double>(c, R, n);
   R.argm = req_alloc<int32_t>(c, R, n);
   R.keys = req_alloc<uint64_t>(c, R, n);
@@ -420,43 +485,7 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.tmp_bytes = std::max<size_t>(16, std::max(t1, t2));
   R.tmp = req_alloc<uint8_t>(c, R, R.tmp_bytes);
   if (!R.tmp) return RELOC_E_NOMEM;
-  if (int32_t e = upload(c, R.raydirs, rd.data(), rd.size())) return e;
-  if (int32_t e = upload(c, R.kap, kp.data(), kp.size())) return e;
-  if (int32_t e = upload(c, R.dir_i, di.data(), di.size())) return e;
-  if (int32_t e = upload(c, R.dir_f, df.data(), df.size())) return e;
-  if (int32_t e = upload(c, R.runs, R.prep.runs.data(), R.prep.runs.size())) return e;
-  std::vector<int2> beams(nvp, int2{0, 0});
-  for (int v = 0; v < nv; ++v) beams[v] = int2{base[v], R.prep.vzq[v]};
-  if (int32_t e = upload(c, R.beams, beams.data(), beams.size())) return e;
-  std::vector<int2> U2(2 * (size_t)Ng);
-  std::copy(U.begin(), U.end(), U2.begin());
-  std::copy(U.begin(), U.end(), U2.begin() + Ng);
-  if (int32_t e = upload(c, R.dirs, U2.data(), U2.size())) return e;
-  if (int32_t e = upload(c, R.dlut, R.lut.q.data(), R.lut.q.size())) return e;
-  if (direct) {
-    if (int32_t e = upload(c, R.fov_z, R.prep.fz.data(), R.prep.fz.size())) return e;
-    if (int32_t e = upload(c, R.fov_j, R.prep.fj.data(), R.prep.fj.size())) return e;
-  }
-  // casting order: Morton (Z-order) of the hypothesis cells, so that the rays
-  // in flight on one XCD start in one compact region of the map
-  std::vector<std::pair<uint32_t, int32_t>> mc(n);
-  {
-    const std::vector<int32_t>& xy = c->sets[R.set_id].host;
-    auto spread = [](uint32_t v) {
-      v &= 0xFFFF;
-      v = (v | (v << 8)) & 0x00FF00FF;
-      v = (v | (v << 4)) & 0x0F0F0F0F;
-      v = (v | (v << 2)) & 0x33333333;
-      v = (v | (v << 1)) & 0x55555555;
-      return v;
-    };
-    for (int h = 0; h < n; ++h)
-      mc[h] = {spread((uint32_t)xy[2 * h]) | (spread((uint32_t)xy[2 * h + 1]) << 1), h};
-    std::sort(mc.begin(), mc.end());
-  }
-  std::vector<int32_t> perm(n);
-  for (int i = 0; i < n; ++i) perm[i] = mc[i].second;
-  if (int32_t e = upload(c, R.perm, perm.data(), perm.size())) return e;
+  if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
   return RELOC_OK;
 }
@@ -910,7 +939,10 @@ void reloc_ctx_destroy(reloc_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->reqs) release_request(c, kv.second);
-    for (auto& kv : c->sets) c->dfree(kv.second.dev);
+    for (auto& kv : c->sets) {
+      c->dfree(kv.second.dev);
+      c->dfree(kv.second.morton_dev);
+    }
     for (auto& kv : c->maps) {
       c->dfree(kv.second.bits);
       c->dfree(kv.second.walk);
@@ -1096,6 +1128,7 @@ int32_t reloc_free_hypotheses(reloc_ctx* c, int32_t set_id) {
   if (serve_holds_set(c, set_id)) return fail(RELOC_E_BUSY, "set %d used by a queued request", set_id);
   (void)hipStreamSynchronize(c->stream);
   c->dfree(it->second.dev);
+  c->dfree(it->second.morton_dev);
   c->maps[it->second.map_id].n_sets -= 1;
   c->sets.erase(it);
   return RELOC_OK;

@@ -76,6 +76,10 @@ struct HypSet {
   int n = 0;
   int32_t* dev = nullptr;         // [n][2]
   std::vector<int32_t> host;
+  // casting order: the hypotheses sorted by the Morton (Z-order) code of
+  // their cells, ties by index; on the host and on the device
+  std::vector<int32_t> morton;
+  int32_t* morton_dev = nullptr;  // [n]
 };
 
 struct Request {
