@@ -1,0 +1,81 @@
+"""The context's device block cache against its HBM budget.
+
+Freed blocks are kept by size class for later allocations. Memory the
+context holds through torch's caching allocator (live plus kept blocks)
+must stay within the budget while maps of different sizes are loaded and
+unloaded (a load whose classes miss the cache has to hand kept blocks back
+first), the accounting must return to its starting value, and closing the
+context must hand every block back. Results computed in reused blocks equal
+those of a fresh context.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2511_01219_amd as reloc
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+RES = 0.05
+
+
+def _case(msg):
+    print("[gpu case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _room(n):
+    occ = np.zeros((n, n), np.int8)
+    occ[:3, :] = occ[-3:, :] = occ[:, :3] = occ[:, -3:] = 100
+    occ[n // 3:n // 3 + 6, n // 4:3 * n // 4] = 100
+    return occ
+
+
+def test_cache_within_budget_and_released():
+    import torch
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated(0)
+    budget = 56 << 20
+    slack = 1 << 20          # torch rounds small blocks up to 512 B
+    ctx = reloc.Context(0, hbm_budget=budget)
+    try:
+        start = ctx.bytes
+        # a 1600^2 load misses the classes kept from 1400^2 and, with them
+        # kept, would pass the budget: the kept blocks are handed back first
+        for n in (1400, 1600, 1300, 1600):
+            _case("block cache: load and unload a %d^2 map in a 56 MB context" % n)
+            m = ctx.load_map(_room(n), RES)
+            assert torch.cuda.memory_allocated(0) - base <= budget + slack
+            ctx.unload_map(m)
+            assert ctx.bytes == start
+            assert torch.cuda.memory_allocated(0) - base <= budget + slack
+        _case("block cache: relocalization in reused blocks")
+        w = make_config(1)
+        kw = dict(n_theta=360, batch_k=10, tau=0.95, k_out=5)
+        scan = (w.ranges, w.angle_min, w.angle_increment, w.range_min, w.range_max)
+        m = ctx.load_map(w.occ, w.resolution, w.origin)
+        s = w.sample
+        sid, _ = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
+                                       seed=s["seed"])
+        got = [ctx.relocalize(m, sid, *scan, **kw) for _ in range(3)]
+        assert torch.cuda.memory_allocated(0) - base <= budget + slack
+        ctx.free_hypotheses(sid)
+        ctx.unload_map(m)
+    finally:
+        ctx.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated(0) == base
+    _case("block cache: a fresh context gives the same result")
+    fresh = reloc.Context(0)
+    try:
+        m = fresh.load_map(w.occ, w.resolution, w.origin)
+        sid, _ = fresh.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
+                                         seed=s["seed"])
+        ref = fresh.relocalize(m, sid, *scan, **kw)
+    finally:
+        fresh.close()
+    for p, st in got:
+        assert p == ref[0]
+        for k in ("stages", "n_eval", "early_stopped", "best_margin", "ambiguous"):
+            assert st[k] == ref[1][k]
