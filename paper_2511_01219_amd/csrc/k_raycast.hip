@@ -202,19 +202,13 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
     if (kr > 0 && r.Dm + (int)(((uint32_t)r.b & 0x1FFFFFu) * ((uint32_t)(kr - 1) & 0xFFu) << 8) >= 0)
       --kr;
   }
-  if (kr >= J) {
-    if (kr > 0) {
-      r.na += kr;
-      r.Dm += (int)(((uint32_t)r.b & 0x1FFFFFu) * ((uint32_t)kr & 0x1FFu) << 8);
-      r.off += __mul24(kr, r.om);
-      if (r.na > r.la) {
-        *z = 0.f;
-        *hit = -1;
-        return true;
-      }
-    }
-  } else {
-    const int na = r.na + J;
+  // one update for both jumps: a run jump ends in the same window as the
+  // radius jump (only major crossings on the way, nb unchanged), so the
+  // state after the farther one is computed the same way for either, and
+  // lanes that take different jumps share one instruction stream
+  const int Jt = max(kr, J);
+  if (Jt > 0) {
+    const int na = r.na + Jt;
     int nb = (int)floorf(((float)na - 0.5f) * r.r - 0.5f) + 1;
     int Dm = (int)(__umul24(128 + 256 * na, r.b) - __umul24(128 + 256 * nb, r.a));
     const int dB = r.a << 8;
