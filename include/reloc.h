@@ -26,7 +26,12 @@
  *     context and are named by integer ids. Pointers documented as "host"
  *     are host memory.
  *   - Device memory comes from the allocator given to reloc_ctx_create
- *     (hipMalloc when NULL). Work is issued on the stream given there (a
+ *     (hipMalloc when NULL). The context keeps blocks it no longer needs
+ *     (up to 256 MiB each, 2 GiB in all) for later allocations of the same
+ *     size class, and returns them to the allocator when an allocation
+ *     would pass the HBM budget, when the allocator fails, and at
+ *     destruction; live plus kept blocks never exceed the budget. Work is
+ *     issued on the stream given there (a
  *     hipStream_t passed as void*; a private default-priority stream when
  *     NULL). Calls on one context are serialized internally.
  *   - Results are deterministic: the same inputs give bit-identical outputs,
@@ -88,7 +93,9 @@ int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* str
 /* Waits for outstanding work and frees everything the context holds. */
 void reloc_ctx_destroy(reloc_ctx* ctx);
 
-/* Bytes of device memory the context currently holds. */
+/* Bytes of device memory in live use by the context's maps, sets,
+ * requests and scratch (size classes: powers of two up to 1 MiB, then
+ * multiples of 2 MiB); blocks kept for reuse are not counted. */
 size_t reloc_ctx_bytes(const reloc_ctx* ctx);
 
 /* ------------------------------------------------------------------------
