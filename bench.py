@@ -655,6 +655,8 @@ def main():
                    "coarse": args.coarse, "fine": args.fine, "sampler": args.sampler},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
+        "value_by_kind": {"smad_evals_per_s": args.steps * st["smad_evals"] / elapsed,
+                          "tam_evals_per_s": args.steps * st["tam_evals"] / elapsed},
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
                      "stages": st["stages"], "early_stopped": st["early_stopped"],
                      "device_ms": float(np.mean(tot_ms)), "raycast_ms": float(np.mean(ray_ms)),
