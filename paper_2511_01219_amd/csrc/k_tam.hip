@@ -173,9 +173,11 @@ struct PoseListSrc {
 //
 // Per pose the valid beams are spread over the lanes, SB per lane at a
 // time: all SB direction loads, then all SB EDT gathers, are issued before
-// any is used. The per-pose integer sums are parked in lane g; the FP64 tail
-// (eq. 27-31) then runs once for the four poses in lanes 0..3, and one
-// atomic max per wavefront publishes the best (T, tie).
+// any is used. The per-pose integer sums are parked in lane g, then moved
+// to LDS; the FP64 tail (eq. 27-31) runs once per workgroup, for the 16
+// poses in lanes 0..15 of wavefront 0, and one atomic max per workgroup
+// publishes the best (T, tie). The other wavefronts end there: every caller
+// ends with the tile.
 template <int R, int KB, bool FULL, class Src>
 __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32_t* smem) {
   constexpr int SB = R >= 32 ? 8 : 4;  // keys per lane in flight together
@@ -315,14 +317,30 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       p_noff = noff;
     }
   }
-  // FP64 tail for the parked poses, one per lane
-  const int j = wv + NW * lane;
-  const bool mine = lane < G && src.has(j);
+  // the tile's 16 poses go to LDS (pose wv + NW g from lane g of wavefront
+  // wv); wavefront 0 then runs the FP64 tail once, one pose per lane
+  __shared__ int64_t t_sl[THETA_PER_BLOCK];
+  __shared__ uint64_t t_sumk[THETA_PER_BLOCK], t_sumsq[THETA_PER_BLOCK];
+  __shared__ int t_noff[THETA_PER_BLOCK];
+  if (lane < G) {
+    const int jj = wv + NW * lane;
+    t_sl[jj] = p_sl;
+    t_sumk[jj] = p_sumk;
+    t_sumsq[jj] = p_sumsq;
+    t_noff[jj] = p_noff;
+  }
+  __syncthreads();
+  if (wv != 0) return;                  // the caller's work ends with the tile
+  const int j = lane;
+  const bool mine = lane < THETA_PER_BLOCK && src.has(j);
   uint64_t packed = 0;
   if (mine) {
+    const int64_t q_sl = t_sl[j];
+    const uint64_t q_sumk = t_sumk[j], q_sumsq = t_sumsq[j];
+    const int q_noff = t_noff[j];
     const double nvd = (double)nv;
-    const double sum_d = a.res * ((double)p_sumsq / 65536.0) + (double)p_noff * a.d_max;
-    const double sum_d2 = a.res * a.res * (double)p_sumk + (double)p_noff * a.d_max * a.d_max;
+    const double sum_d = a.res * ((double)q_sumsq / 65536.0) + (double)q_noff * a.d_max;
+    const double sum_d2 = a.res * a.res * (double)q_sumk + (double)q_noff * a.d_max * a.d_max;
     const double dbar = sum_d / nvd;
     double var = sum_d2 / nvd - dbar * dbar;
     if (var < 0.0) var = 0.0;
@@ -331,12 +349,12 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     const double sd = 1.0 - (dt - dmin) / (a.d_max - dmin);
     double v;
     if constexpr (!FULL) {
-      const double Lbar = (double)p_sl / (67108864.0 * (double)a.kmid);
+      const double Lbar = (double)q_sl / (67108864.0 * (double)a.kmid);
       const double Pl = exp(Lbar);
       const double c = exp(-0.5 * var);
       v = a.fine == 0 ? cbrt(Pl * sd * c) : (Pl + sd + c) / 3.0;   // eq. 31 / eq. 34
     } else {
-      const double lf = (double)p_sl / 67108864.0;                 // eq. 32
+      const double lf = (double)q_sl / 67108864.0;                 // eq. 32
       v = a.fine == 3 ? lf : sqrt(exp(lf / nvd) * sd);               // eq. 33
     }
     const float T = (float)v;
@@ -344,7 +362,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     packed = ((uint64_t)score_key(T) << 32) | (uint64_t)src.tie(j);
   }
   if constexpr (Src::kPublish) {
-    for (int off = G / 2; off > 0; off >>= 1) {
+    for (int off = THETA_PER_BLOCK / 2; off > 0; off >>= 1) {
       const uint64_t o = __shfl_xor(packed, off, 64);
       packed = o > packed ? o : packed;
     }
