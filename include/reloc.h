@@ -62,6 +62,10 @@ enum {
   RELOC_E_DEVICE = -9     /* HIP runtime / device error */
 };
 
+/* What every call returns: RELOC_OK or one of the RELOC_E_* codes above
+ * (the functions are declared with its underlying type, int32_t). */
+typedef int32_t reloc_status;
+
 typedef struct reloc_ctx reloc_ctx;
 
 /* Device allocator hook. alloc returns device memory of at least `bytes`
