@@ -3,8 +3,9 @@
 // for up to kSmallSortMax keys a two-kernel sort: every 2048-key tile is
 // sorted in LDS by a stable block radix sort, then every key finds its final
 // position as its position in its tile plus, for every other tile, the
-// number of keys there that precede it (binary search; keys of earlier
-// tiles that are equal precede it, since indices grow with the tile).
+// number of keys there that precede it (binary searches, one thread per
+// key and tile; keys of earlier tiles that are equal precede it, since
+// indices grow with the tile).
 #include <hipcub/hipcub.hpp>
 
 #include "reloc_internal.h"
@@ -53,21 +54,36 @@ __device__ __forceinline__ int count_before(const uint64_t* a, int len, uint64_t
   return lo;
 }
 
-__global__ void merge_rank_kernel(const uint64_t* __restrict__ kt, const int32_t* __restrict__ vt,
-                                  int n, uint64_t* __restrict__ kout, int32_t* __restrict__ vout) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int t = g / kTile, p = g - t * kTile;
-  const uint64_t x = kt[g];
-  const int nt = (n + kTile - 1) / kTile;
-  int rank = p;
-  for (int u = 0; u < nt; ++u) {
-    if (u == t) continue;
-    const int len = min(kTile, n - u * kTile);
-    rank += count_before(kt + (size_t)u * kTile, len, x, u < t);
+// Every key's final position: its position in its tile plus, for every
+// other tile, the number of keys there that precede it. One thread per
+// (key, tile) pair, so a key's binary searches run side by side rather than
+// one after another; the counts meet in LDS. nt <= 32 tiles (n <= 65 536),
+// 256 / nt keys per workgroup.
+__global__ __launch_bounds__(256) void merge_rank_kernel(const uint64_t* __restrict__ kt,
+                                                         const int32_t* __restrict__ vt, int n,
+                                                         int nt, uint64_t* __restrict__ kout,
+                                                         int32_t* __restrict__ vout) {
+  __shared__ int acc[256];
+  const int tid = threadIdx.x;
+  const int E = 256 / nt;                      // keys of this workgroup
+  const int e = tid / nt, u = tid - e * nt;    // key e, tile u
+  const int g = blockIdx.x * E + e;
+  if (tid < E) acc[tid] = 0;
+  __syncthreads();
+  if (e < E && g < n) {
+    const int t = g / kTile;
+    const int cnt = u == t ? g - t * kTile
+                           : count_before(kt + (size_t)u * kTile, min(kTile, n - u * kTile),
+                                          kt[g], u < t);
+    atomicAdd(&acc[e], cnt);
   }
-  if (kout) kout[rank] = x;
-  vout[rank] = vt[g];
+  __syncthreads();
+  const int gg = blockIdx.x * E + tid;
+  if (tid < E && gg < n) {
+    const int rank = acc[tid];
+    if (kout) kout[rank] = kt[gg];
+    vout[rank] = vt[gg];
+  }
 }
 
 // Ranking of n <= 2048 evaluated ranks in one workgroup: the keys
@@ -113,12 +129,14 @@ hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
 hipError_t small_sort_pairs_u64(const uint64_t* kin, uint64_t* ktmp, int32_t* vtmp,
                                 uint64_t* kout, int32_t* vout, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (n > kSmallSortMax) return hipErrorInvalidValue;
   const int nt = (n + kTile - 1) / kTile;
   hipLaunchKernelGGL(tile_sort_kernel, dim3(nt), dim3(kTileThreads), 0, s, kin, n, ktmp, vtmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(merge_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ktmp, vtmp, n,
-                     kout, vout);
+  const int per = 256 / nt;                    // nt <= 32 for n <= kSmallSortMax
+  hipLaunchKernelGGL(merge_rank_kernel, dim3((n + per - 1) / per), dim3(256), 0, s, ktmp, vtmp,
+                     n, nt, kout, vout);
   return hipGetLastError();
 }
 
