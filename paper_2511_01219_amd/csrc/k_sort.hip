@@ -1,6 +1,6 @@
 // Stable sorts for the SMAD order (ascending (SMAD, index)) and for the
 // final ranking of evaluated poses: hipCUB / rocPRIM device radix sorts, and
-// for up to kSmallSortMax keys a two-kernel sort: every 2048-key tile is
+// for up to kSmallSortMax keys a two-kernel sort: every 1024-key tile is
 // sorted in LDS by a stable block radix sort, then every key finds its final
 // position as its position in its tile plus, for every other tile, the
 // number of keys there that precede it (binary searches, one thread per
@@ -14,7 +14,7 @@ namespace reloc {
 
 namespace {
 
-constexpr int kTileThreads = 256, kTileItems = 8, kTile = kTileThreads * kTileItems;
+constexpr int kTileThreads = 256, kTileItems = 4, kTile = kTileThreads * kTileItems;
 
 // Stable sort of each tile of (key, index) pairs; indices are positions in
 // the input. Padding keys (~0) sort last and are not stored.
@@ -57,7 +57,7 @@ __device__ __forceinline__ int count_before(const uint64_t* a, int len, uint64_t
 // Every key's final position: its position in its tile plus, for every
 // other tile, the number of keys there that precede it. One thread per
 // (key, tile) pair, so a key's binary searches run side by side rather than
-// one after another; the counts meet in LDS. nt <= 32 tiles (n <= 65 536),
+// one after another; the counts meet in LDS. nt <= 64 tiles (n <= 65 536),
 // 256 / nt keys per workgroup.
 __global__ __launch_bounds__(256) void merge_rank_kernel(const uint64_t* __restrict__ kt,
                                                          const int32_t* __restrict__ vt, int n,
@@ -134,7 +134,7 @@ hipError_t small_sort_pairs_u64(const uint64_t* kin, uint64_t* ktmp, int32_t* vt
   hipLaunchKernelGGL(tile_sort_kernel, dim3(nt), dim3(kTileThreads), 0, s, kin, n, ktmp, vtmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int per = 256 / nt;                    // nt <= 32 for n <= kSmallSortMax
+  const int per = 256 / nt;                    // nt <= 64 for n <= kSmallSortMax
   hipLaunchKernelGGL(merge_rank_kernel, dim3((n + per - 1) / per), dim3(256), 0, s, ktmp, vtmp,
                      n, nt, kout, vout);
   return hipGetLastError();
