@@ -76,6 +76,34 @@ def test_coarse_map_all_free_cells(world):
     ctx.free_hypotheses(sid)
 
 
+@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 4097, 65536])
+def test_order_with_ties_across_tiles(world, n):
+    """The stable SMAD order at sizes around the 1024-key tile edges of the
+    small sort and at its 65 536-key limit, with many exact ties (37 cells
+    repeated, so equal scans give equal SMAD): the order is the stable one
+    (ties by index) of the returned scores; with no coarse metric (every key
+    zero) it is the identity."""
+    w, k, ctx, m = world
+    F = (w.occ >= 0) & (w.occ < 65) & (k >= 18)
+    ys, xs = np.nonzero(F)
+    rng = np.random.default_rng([n, 3])
+    few = rng.choice(len(xs), 37, replace=False)
+    pick = rng.choice(few, n)
+    cells = np.stack([xs[pick], ys[pick]], 1).astype(np.int32)
+    sid = ctx.set_hypotheses(m, cells)
+    for cm in (0, 3):
+        _case("order with ties: n %d, coarse metric %d" % (n, cm))
+        rid = ctx.prepare(m, sid, **_scan(w), n_theta=360, batch_k=10, coarse_metric=cm)
+        sc, sh, order, st = ctx.coarse_scores(rid, n)
+        assert (order == np.lexsort((np.arange(n), sc))).all()
+        if cm == 3:
+            assert (order == np.arange(n)).all()
+        else:
+            assert len(np.unique(sc)) <= 37
+        ctx.release(rid)
+    ctx.free_hypotheses(sid)
+
+
 def _fine_prep(w, Ng):
     return oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
                        range_min=w.range_min, range_max=w.range_max, n_theta=Ng)
