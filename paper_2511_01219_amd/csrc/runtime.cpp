@@ -474,7 +474,6 @@ int32_t build_request(reloc_ctx* c, Request& R) {
     R.rbest = req_alloc<uint64_t>(c, R, R.ref_slots);
   }
   R.stage = req_alloc<uint64_t>(c, R, max_stages);
-  R.flag = req_alloc<int32_t>(c, R, max_stages);
   R.rows_cap = std::max(1, std::min(n, R.prm.k_out));
   R.rows = req_alloc<PoseRow>(c, R, R.rows_cap);
   for (void* p : R.owned)
@@ -615,12 +614,19 @@ int32_t run_smad_order(reloc_ctx* c, Request& R) {
 
 // ranking of ranks [0, n_eval) (T desc, rank asc); the first nrow rows are
 // copied to host_rows (pinned) on the stream
-int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* host_rows) {
+// Ranking of the first n_eval ranks, nrow rows to the pinned host_rows;
+// *top receives where the kernels find row 0 (the ambiguity statistics read
+// it): host_rows itself when the single-launch ranking writes the rows there
+// directly, else the request's device rows.
+int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* host_rows,
+                     const PoseRow** top) {
   hipStream_t s = c->stream;
-  // the device always holds row 0 (the ambiguity statistics read it)
   const int ndev = std::min(n_eval, std::max(1, nrow));
   if (n_eval <= kRankSmallMax) {
-    HIP_TRY(launch_rank_small(R.best, n_eval, R.order, R.smad, ndev, R.rows, s));
+    // host_rows holds at least one row (pinned_rows allocates max(1, n))
+    HIP_TRY(launch_rank_small(R.best, n_eval, R.order, R.smad, ndev, host_rows, s));
+    *top = host_rows;
+    return RELOC_OK;
   } else {
     HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
     size_t tb = R.tmp_bytes;
@@ -629,6 +635,7 @@ int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* ho
   }
   if (nrow > 0)
     HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  *top = R.rows;
   return RELOC_OK;
 }
 
@@ -680,9 +687,9 @@ int32_t enqueue_stages(reloc_ctx* c, Request& R, int r0, int ns, int nb, int sta
     HIP_TRY(launch_refine(fa, s));
     HIP_TRY(launch_refine_commit(fa, s));
   }
-  StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stage, R.flag + stage};
+  // the stop flags go straight to the pinned words the host reads
+  StageArgs sa{R.best, r0, nb, R.prm.tau, R.stage + stage, hflag};
   HIP_TRY(launch_stage_reduce_multi(sa, K, ns, R.n_hyp, s));
-  HIP_TRY(hipMemcpyAsync(hflag, R.flag + stage, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   return RELOC_OK;
 }
 
@@ -714,10 +721,11 @@ int32_t enqueue_head(reloc_ctx* c, Request& R, int ns0, int nb0, int32_t* hflag,
   if (int32_t e = enqueue_stages(c, R, 0, ns0, nb0, 0, hflag)) return e;
   if (ns0 == 1) {
     HIP_TRY(mark(3));
-    if (int32_t e = enqueue_rank(c, R, nb0, std::min(R.rows_cap, nb0), hrows)) return e;
+    const PoseRow* top = nullptr;
+    if (int32_t e = enqueue_rank(c, R, nb0, std::min(R.rows_cap, nb0), hrows, &top)) return e;
     HIP_TRY(mark(4));
     // the ambiguity statistics of that one-stage result, after the timed region
-    if (int32_t e = enqueue_margin(c, R, R.best, R.order, R.rows, nb0, R.stage, 1,
+    if (int32_t e = enqueue_margin(c, R, R.best, R.order, top, nb0, R.stage, 1,
                                    head_margin_words(c)))
       return e;
   }
@@ -1286,17 +1294,18 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     }
   }
   nrow = std::min(ncap, n_eval);
+  const PoseRow* top = nullptr;   // where row 0 is for the ambiguity kernel
   if (!ranked) {
     HIP_TRY(hipEventRecord(c->ev[3], s));
-    if (int32_t e = enqueue_rank(c, R, n_eval, nrow, hrows)) return e;
+    if (int32_t e = enqueue_rank(c, R, n_eval, nrow, hrows, &top)) return e;
     HIP_TRY(hipEventRecord(c->ev[4], s));
   }
-  // ambiguity statistics, after the timed region (rows[0] is on the device);
-  // the kernel writes its three words straight into pinned host memory
-  // (a result ranked in the head has its statistics from the head too)
+  // ambiguity statistics, after the timed region (row 0 at `top`); the
+  // kernel writes its three words straight into pinned host memory (a
+  // result ranked in the head has its statistics from the head too)
   uint64_t* hmarg = head_margin_words(c);
   if (st && n_eval > 0 && !ranked)
-    if (int32_t e = enqueue_margin(c, R, R.best, R.order, R.rows, n_eval, R.stage, stages,
+    if (int32_t e = enqueue_margin(c, R, R.best, R.order, top, n_eval, R.stage, stages,
                                    hmarg))
       return e;
   HIP_TRY(hipStreamSynchronize(s));
