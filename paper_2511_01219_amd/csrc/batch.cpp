@@ -121,8 +121,8 @@ struct ServeState {
   uint8_t* rtmp = nullptr;
   size_t rtmp_cap = 0;
   // per-tick stage outputs
-  uint64_t* dstage = nullptr;
-  int32_t* dflag = nullptr;
+  // per-tick stage outputs, written by the stage kernel straight into
+  // pinned host memory
   int32_t* hflag = nullptr;
   uint64_t* hstage = nullptr;
   size_t stage_cap = 0;
@@ -205,19 +205,12 @@ int32_t grow_scratch(reloc_ctx* c, T*& p, size_t& cap, size_t n) {
 int32_t ensure_stage_cap(reloc_ctx* c, ServeState& S, size_t n) {
   if (n <= S.stage_cap) return RELOC_OK;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->dfree(S.dstage);
-  c->dfree(S.dflag);
   if (S.hflag) (void)hipHostFree(S.hflag);
   if (S.hstage) (void)hipHostFree(S.hstage);
-  S.dstage = nullptr;
-  S.dflag = nullptr;
   S.hflag = nullptr;
   S.hstage = nullptr;
   S.stage_cap = 0;
   const size_t cap = std::max<size_t>(n, 1024);
-  S.dstage = (uint64_t*)c->dalloc(cap * sizeof(uint64_t));
-  S.dflag = (int32_t*)c->dalloc(cap * sizeof(int32_t));
-  if (!S.dstage || !S.dflag) return RELOC_E_NOMEM;
   HIP_TRY(hipHostMalloc((void**)&S.hflag, cap * sizeof(int32_t), hipHostMallocDefault));
   HIP_TRY(hipHostMalloc((void**)&S.hstage, cap * sizeof(uint64_t), hipHostMallocDefault));
   S.stage_cap = cap;
@@ -395,8 +388,8 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     for (int b = 0; b < ns; ++b) {
       const int r0 = f->next_rank + b * K;
       const size_t e = st.size();
-      st.push_back(StageArgs{a.best, r0, std::min(K, R.n_hyp - r0), R.prm.tau, S.dstage + e,
-                             S.dflag + e});
+      st.push_back(StageArgs{a.best, r0, std::min(K, R.n_hyp - r0), R.prm.tau, S.hstage + e,
+                             S.hflag + e});
     }
   }
   Blob bl;
@@ -442,9 +435,6 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     HIP_TRY(launch_refine_commit(fa, s));
   }
   HIP_TRY(launch_stage_reduce_batch((const StageArgs*)(d + o_st), (int)st.size(), s));
-  HIP_TRY(hipMemcpyAsync(S.hflag, S.dflag, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(S.hstage, S.dstage, st.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                         s));
   HIP_TRY(hipEventRecord(c->ev[4], s));
   HIP_TRY(hipStreamSynchronize(s));
   if (pt) pt->tam += elapsed(c->ev[3], c->ev[4]);
@@ -802,8 +792,6 @@ void ctx_stop_serving(reloc_ctx* c) {
   c->dfree(S->rrows);
   c->dfree(S->rmarg);
   c->dfree(S->rtmp);
-  c->dfree(S->dstage);
-  c->dfree(S->dflag);
   if (S->hflag) (void)hipHostFree(S->hflag);
   if (S->hstage) (void)hipHostFree(S->hstage);
   S->dcv.notify_all();
