@@ -399,6 +399,37 @@ def test_relocalize_c1_end_to_end(ctx, c1, tau, K):
     ctx.unload_map(m)
 
 
+def test_relocalize_c2_large_ranking(ctx, c2):
+    """A plain-path search that evaluates more than 2048 ranks (the first
+    3000 hypotheses of the warehouse, no early termination) ranks them with
+    the multi-kernel ranking: the oracle's stage loop gives the same
+    evaluated set and top pose, every returned row carries its rank's T, in
+    non-increasing order, and the batched form of the same request returns
+    the same rows bit for bit."""
+    w, k, hyp = c2
+    sub = hyp[:3000]
+    _case("relocalize c2 3000 hypotheses, tau none (large ranking)")
+    m = ctx.load_map(w.occ, 0.05)
+    sid = ctx.set_hypotheses(m, sub)
+    kw = dict(n_theta=720, batch_k=64, tau=None, k_out=20)
+    poses, st = ctx.relocalize(m, sid, **_scan(w), **kw)
+    assert st["n_eval"] == len(sub) > 2048
+    ref = _oracle_run(w, k, sub, 720, 64, None)
+    _compare_runs(poses, st, ref, None, 64)
+    assert len(poses) == 20
+    ts = [p["tam"] for p in poses]
+    assert all(a >= b for a, b in zip(ts, ts[1:]))
+    for p in poses:
+        t = ref["tstar"][p["rank"]]
+        assert abs(p["tam"] - t) <= T_RTOL * t + T_ATOL
+    rid = ctx.prepare(m, sid, **_scan(w), **kw)
+    batched = ctx.run_batch([rid], cap=20)
+    ctx.release(rid)
+    assert batched[0][0] == poses
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
 @pytest.mark.parametrize("tau", [None, 0.95])
 def test_relocalize_tied_smad(ctx, c1, tau):
     """Every hypothesis three times: every SMAD value is tied three ways, so
