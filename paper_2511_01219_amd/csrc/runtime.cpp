@@ -42,6 +42,7 @@ int32_t fail(int32_t code, const char* fmt, ...) {
 
 constexpr int kMaxNs = 4096;
 constexpr int64_t kPlainFillBlocks = 4096;   // TAM workgroups one plain-path launch aims at
+constexpr int64_t kPlainFirstFillBlocks = 1024;  // ... and its first launch
 constexpr int kPlainMaxStages = 64;          // stages of a later plain-path launch, at most
 constexpr int kMaxDim = 32768;
 constexpr int kMaxNg = 1 << 20;
@@ -587,12 +588,20 @@ int plain_max_stages_per_launch(const Request& R) {
   return std::max(plain_stages_per_launch(R), kPlainMaxStages);
 }
 
-int plain_stages_per_launch(const Request& R) {
+// stages of a launch that aims at `fill` TAM workgroups (at least one)
+static int stages_for_fill(const Request& R, int64_t fill) {
   const int64_t K = R.prm.batch_k;
   const int64_t bps = K * ((R.prep.info.Ntheta + 15) / 16);
   const int64_t stages = (R.n_hyp + K - 1) / K;
-  return (int)std::max<int64_t>(
-      1, std::min<int64_t>(stages, std::min<int64_t>(512, kPlainFillBlocks / bps)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(stages, std::min<int64_t>(512, fill / bps)));
+}
+
+int plain_stages_per_launch(const Request& R) { return stages_for_fill(R, kPlainFillBlocks); }
+
+// The first launch aims lower: a search that stops in it discards fewer
+// speculative stages (when one stage alone fills the device both are one).
+static int plain_first_stages_per_launch(const Request& R) {
+  return stages_for_fill(R, kPlainFirstFillBlocks);
 }
 
 // stable SMAD order of the request (after the SMAD kernel)
@@ -1209,13 +1218,15 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   if (int32_t e = pinned_rows(c, (size_t)R.rows_cap, &hrows)) return e;
   bool ranked = false;   // rows of the final n_eval already on the host
   int nrow = 0;
-  // the first two launches hold enough stages to fill the device; when the
-  // search goes on, each later launch holds twice as many as the one before,
-  // up to plain_max_stages_per_launch (fewer stop-flag round trips on long
-  // searches, no wasted stage when the search stops in its second launch).
-  // Stages after the first one that stops are discarded, so the result is
-  // that of one stage at a time.
-  int per = plain_stages_per_launch(R);
+  // the first launch holds enough stages for a quarter of the device, the
+  // second enough to fill it; when the search goes on, each later launch
+  // holds twice as many as the one before, up to plain_max_stages_per_launch
+  // (few speculative stages when the search stops early, few stop-flag round
+  // trips on long searches, and when one stage fills the device no wasted
+  // stage when the search stops in its second launch). Stages after the
+  // first one that stops are discarded, so the result is that of one stage
+  // at a time.
+  int per = plain_first_stages_per_launch(R);
   const int per_max = plain_max_stages_per_launch(R);
   int launches = 0;
   const int kr = R.prm.refine_k;
@@ -1284,7 +1295,10 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
       ranked = spec;
       break;
     }
-    if (++launches >= 2) per = std::min(per_max, 2 * per);
+    if (++launches >= 2)
+      per = std::min(per_max, 2 * per);
+    else
+      per = plain_stages_per_launch(R);
     if (R.prm.deadline_s > 0) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
       if (el > R.prm.deadline_s && n_eval < R.n_hyp) {
