@@ -69,10 +69,56 @@ __device__ __forceinline__ uint32_t sqrt_q16(uint32_t k) {
   return __float2uint_rn(__fsqrt_rn((float)k) * 65536.0f);
 }
 
+// Sum over the 64 lanes of a wavefront (every lane active), returned to
+// every lane. Quad permutes and row rotations leave each lane of a 16-lane
+// row with the row's sum; two row broadcasts then carry rows 0-2 into lane
+// 63, which is read back. The moves are DPP operands of VALU instructions:
+// no LDS round trips. Integer sums, so the order of the additions does not
+// change the result. In the 32-bit sum a lane with no source lane (rows 0-1
+// under the broadcasts) reads 0, the identity of the sum, which lets the
+// move fold into the add; the 64-bit sum moves each half on its own and
+// leaves such lanes unspecified, which lane 63 never reads from.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32_or0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+  v += dpp64<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp64<0x124>(v);   // row_ror:4
+  v += dpp64<0x128>(v);   // row_ror:8
+  v += dpp64<0x142>(v);   // row_bcast:15
+  v += dpp64<0x143>(v);   // row_bcast:31
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+  v += dpp32_or0<0xb1>(v);
+  v += dpp32_or0<0x4e>(v);
+  v += dpp32_or0<0x124>(v);
+  v += dpp32_or0<0x128>(v);
+  v += dpp32_or0<0x142>(v);
+  v += dpp32_or0<0x143>(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+  if constexpr (sizeof(T) == 8)
+    return (T)wave_sum64((uint64_t)v);
+  else
+    return (T)wave_sum32((uint32_t)v);
 }
 
 // The 16 poses of one workgroup come from a pose source: has(j) tells
