@@ -94,7 +94,10 @@ const char* reloc_last_error(void);
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
                          size_t hbm_budget, reloc_ctx** out);
 
-/* Waits for outstanding work and frees everything the context holds. */
+/* Waits for outstanding work and frees everything the context holds. A
+ * reloc_poll blocked on the context returns first (RELOC_E_PENDING for an
+ * unfinished ticket); no call may start on the context once destroy has
+ * begun. */
 void reloc_ctx_destroy(reloc_ctx* ctx);
 
 /* Bytes of device memory in live use by the context's maps, sets,
@@ -513,7 +516,8 @@ int32_t reloc_debug_smad(reloc_ctx* ctx, int32_t request_id, double* smad,
 
 /* TAM of every orientation for n ranks starting at rank r0 of the SMAD order:
  * T: host float[n*N_theta] (rank-major, may be NULL), tstar / kstar: host
- * float[n] / int32[n] (may be NULL). */
+ * float[n] / int32[n] (may be NULL). RELOC_E_INVALID, before any launch,
+ * unless 0 <= r0, 1 <= n and r0 + n <= the request's hypothesis count. */
 int32_t reloc_debug_tam(reloc_ctx* ctx, int32_t request_id, int32_t r0, int32_t n,
                         float* T, float* tstar, int32_t* kstar);
 

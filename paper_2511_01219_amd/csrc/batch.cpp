@@ -132,6 +132,7 @@ struct ServeState {
   std::mutex qmu;
   std::condition_variable qcv, dcv;
   bool stop = false;
+  int pollers = 0;                  // reloc_poll calls inside (under qmu)
   std::deque<Ticket*> pending;
   std::map<uint64_t, std::unique_ptr<Ticket>> tickets;
   uint64_t next_ticket = 1;
@@ -794,7 +795,12 @@ void ctx_stop_serving(reloc_ctx* c) {
   c->dfree(S->rtmp);
   if (S->hflag) (void)hipHostFree(S->hflag);
   if (S->hstage) (void)hipHostFree(S->hstage);
-  S->dcv.notify_all();
+  {
+    // polls still waiting see stop and return; the state outlives them
+    std::unique_lock<std::mutex> lk(S->qmu);
+    S->dcv.notify_all();
+    S->dcv.wait(lk, [&] { return S->pollers == 0; });
+  }
   delete S;
   c->serve = nullptr;
 }
@@ -845,7 +851,9 @@ int32_t reloc_run_batch(reloc_ctx* c, int32_t n, const int32_t* request_ids, rel
       std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < n; ++i) {
     const Request& R = c->reqs.at(request_ids[i]);
-    rows_to_poses(c, R, rows[i].data(), (int)rows[i].size(), out + (size_t)i * cap);
+    // rows exist only when cap > 0, and then out is a buffer of n * cap poses
+    if (!rows[i].empty())
+      rows_to_poses(c, R, rows[i].data(), (int)rows[i].size(), out + (size_t)i * (size_t)cap);
     n_out[i] = (int32_t)rows[i].size();
     status[i] = fl[i].status;
     if (stats) fill_stats(R, fl[i], pt, total, &stats[i]);
@@ -899,6 +907,16 @@ int32_t reloc_poll(reloc_ctx* c, uint64_t ticket, int32_t wait_ms, reloc_pose* o
   if (!c || !n_out || (!out && cap > 0)) return fail(RELOC_E_INVALID, "null argument");
   ServeState* S = c->serve;
   std::unique_lock<std::mutex> lk(S->qmu);
+  // counted while inside, so that destroying the context waits for a
+  // blocked poll to leave before the state goes (released under qmu)
+  ++S->pollers;
+  struct Leave {
+    ServeState* S;
+    ~Leave() {
+      --S->pollers;
+      S->dcv.notify_all();
+    }
+  } leave{S};
   auto it = S->tickets.find(ticket);
   if (it == S->tickets.end())
     return fail(RELOC_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);

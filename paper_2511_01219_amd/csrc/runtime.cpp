@@ -1567,7 +1567,9 @@ int32_t reloc_debug_tam(reloc_ctx* c, int32_t request_id, int32_t r0, int32_t n,
   auto it = c->reqs.find(request_id);
   if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
   Request& R = it->second;
-  if (r0 < 0 || n < 1 || r0 + n > R.n_hyp) return fail(RELOC_E_INVALID, "rank range out of bounds");
+  // n > n_hyp - r0 rather than r0 + n > n_hyp: the sum can wrap in 32 bits
+  if (r0 < 0 || r0 >= R.n_hyp || n < 1 || n > R.n_hyp - r0)
+    return fail(RELOC_E_INVALID, "rank range [%d, %d + %d) outside [0, %d)", r0, r0, n, R.n_hyp);
   if (int32_t e = set_device(c)) return e;
   if (int32_t e = run_smad_order(c, R)) return e;
   const int Nt = R.prep.info.Ntheta;

@@ -6,7 +6,9 @@ returns exactly what it returned before the failures.
   2000^2 map (EDT 16 MB + walk words 32 MB + tiles) does not (E_NOMEM);
 * a malformed scan (E_BEAMGRID), an unknown request (E_NOTFOUND), a second
   release (E_NOTFOUND), unloading a map whose set is alive (E_BUSY), bad
-  search parameters (E_INVALID), a scan with no valid beam (E_EMPTY).
+  search parameters (E_INVALID), a scan with no valid beam (E_EMPTY), rank
+  ranges of the debug TAM call outside the request, including one whose end
+  wraps in 32 bits (E_INVALID, refused before any launch).
 """
 import math
 import sys
@@ -64,6 +66,13 @@ def test_failures_leave_context_usable():
         _case("failures: unknown and released requests, busy map")
         refused(reloc.E_NOTFOUND, ctx.run, 12345)
         rid = ctx.prepare(m, sid, **_scan(w1), **kw)
+        _case("failures: debug TAM rank ranges outside the request (C ABI, no outputs)")
+        nh = len(hyp)
+        with_req = ctx.bytes
+        for r0, n in ((1, 2**31 - 1), (2**31 - 1, 1), (-1, 5), (0, 0), (nh, 1), (0, nh + 1)):
+            rc = ctx._lib.reloc_debug_tam(ctx._h, rid, r0, n, None, None, None)
+            assert rc == reloc.E_INVALID, (r0, n, rc)
+            assert ctx.bytes == with_req
         ctx.release(rid)
         assert ctx.bytes == held
         refused(reloc.E_NOTFOUND, ctx.release, rid)
