@@ -241,6 +241,9 @@ int32_t reloc_sample_rrt(reloc_ctx* c, int32_t map_id, const reloc_rrt_params* p
   if (info) std::memset(info, 0, sizeof *info);
   if (!c || !p || !set_id || !n_out) return fail(RELOC_E_INVALID, "null argument");
   if ((nodes_xy || parent) && nodes_cap < 0) return fail(RELOC_E_INVALID, "negative nodes_cap");
+  if (!std::isfinite(p->p0_x) || !std::isfinite(p->p0_y) || !std::isfinite(p->rho) ||
+      !std::isfinite(p->eta_max))
+    return fail(RELOC_E_INVALID, "p0, rho and eta_max must be finite");
   if (!(p->rho > 0) || !(p->robot_radius > 0) || !(p->eta_max >= p->robot_radius))
     return fail(RELOC_E_INVALID, "need rho > 0, robot_radius > 0, eta_max >= robot_radius");
   if (p->eps_gain < 0 || p->max_rounds < 1 || p->max_nodes < 1)

@@ -126,3 +126,30 @@ def test_rrt_set_relocalizes(ctx):
     assert d < 0.5
     ctx.free_hypotheses(sid)
     ctx.unload_map(m)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(p0=(float("nan"), 0.0)),
+    dict(p0=(0.0, float("inf"))),
+    dict(rho=float("nan")),
+    dict(rho=float("inf")),
+    dict(eta_max=float("inf")),
+    dict(rho=0.0),
+    dict(eta_max=0.1),          # below the robot radius
+    dict(eps_gain=-1),
+    dict(max_rounds=0),
+])
+def test_rrt_refuses_bad_parameters(ctx, bad):
+    w = make_config(1)
+    m = ctx.load_map(w.occ, w.resolution, w.origin)
+    try:
+        _case("RRT refuses %r" % (bad,))
+        kw = dict(p0=w.pose[:2], rho=0.3, seed=1)
+        kw.update(bad)
+        before = ctx.bytes
+        with pytest.raises(reloc.RelocError) as ei:
+            ctx.sample_rrt(m, **kw)
+        assert ei.value.code == reloc.E_INVALID, str(ei.value)
+        assert ctx.bytes == before
+    finally:
+        ctx.unload_map(m)
