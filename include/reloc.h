@@ -182,13 +182,15 @@ int32_t reloc_sample_hypotheses(reloc_ctx* ctx, int32_t map_id,
  * Rounds stop when gain <= eps_gain, after max_rounds, or at max_nodes
  * nodes. The set holds the representatives' cells in node order, without
  * repeats. p0 (the tree root, Algorithm 1's map origin) must be traversable
- * (RELOC_E_EMPTY otherwise).
+ * (RELOC_E_EMPTY otherwise). A host allocation that fails returns
+ * RELOC_E_NOMEM.
  *   info     : counts of the run (may be NULL);
  *   nodes_xy : optional host double[2 * nodes_cap], the tree nodes (world);
  *   parent   : optional host int32[nodes_cap], each node's parent (-1 root). */
 typedef struct {
   double p0_x, p0_y;        /* tree root, world */
-  double rho;               /* sampling spacing (voxel side), metres (0.3) */
+  double rho;               /* sampling spacing (voxel side), metres (0.3);
+                               at least the map resolution, else RELOC_E_INVALID */
   double robot_radius;      /* r_robot, metres (0.21) */
   double eta_max;           /* maximum expansion distance, metres (0.6) */
   int32_t eps_gain;         /* gain threshold (2) */
@@ -254,7 +256,9 @@ typedef struct {
   double z_hit, sigma_hit, z_rand; /* likelihood field, eq. 23 (1, 0.2, 0) */
   double d_max;           /* eq. 29 clamp and off-map distance (2.0 m) */
   int32_t alpha_mid_pm[2];/* alpha_mid at lambda = 0 and 1, per mille (900, 700) */
-  int32_t alpha_low_pm[2];/* alpha_low at lambda = 0 and 1, per mille (700, 500) */
+  int32_t alpha_low_pm[2];/* alpha_low at lambda = 0 and 1, per mille (700, 500);
+                             eq. 25 orders them: alpha_low_pm[i] <= alpha_mid_pm[i]
+                             for i = 0, 1, else RELOC_E_INVALID */
   double deadline_s;      /* plain path: stop with RELOC_E_TIMEOUT after this (0: none) */
   int32_t variant;        /* ray-cast kernel: 0 default; 1 bit tiles; 2, 3, 4, 5
                              distance skipping with wavefront ray refill once 1, 8,
@@ -477,6 +481,8 @@ typedef struct {
   int64_t submitted, completed, failed, ticks;  /* ticks = scheduler rounds */
   int32_t queued, inflight;
   double busy_s;                                /* wall time spent in rounds */
+  int32_t pollers;                              /* reloc_poll calls inside the library */
+  int32_t reserved;
 } reloc_serve_stats;
 
 int32_t reloc_serve_stats_get(reloc_ctx* ctx, reloc_serve_stats* out);

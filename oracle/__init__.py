@@ -80,8 +80,16 @@ def _declare(L):
     L.orc_sample.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, i32,
                              f64, f64, u64, i32, vp, vp]
     L.orc_num_threads.argtypes = []
+    L.orc_mix64.argtypes = [u64]
+    L.orc_mix64.restype = u64
     L.orc_rrt.argtypes = [i32, i32, vp, i32, vp, f64, f64, f64, f64, f64, f64, f64, f64,
                           i32, u64, i32, i32, vp, vp, vp, vp]
+
+
+def mix64(x: int) -> int:
+    """splitmix64's output function applied to x + 0x9E3779B97F4A7C15: the
+    sampler's visiting priority of cell c under seed s is mix64(s + c)."""
+    return int(lib().orc_mix64(ctypes.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
 
 
 def num_threads() -> int:

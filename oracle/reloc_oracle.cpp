@@ -54,6 +54,9 @@ i64 gcd64(i64 a, i64 b) { while (b) { i64 t = a % b; a = b; b = t; } return a; }
 
 extern "C" {
 
+// The sampler's priority function on its own (known-answer tests).
+u64 orc_mix64(u64 x) { return mix64(x); }
+
 // ---------------------------------------------------------------------------
 // Euclidean distance transform (Sec. III-A, MinDistToObstacle: a
 // precomputed EDT lookup table). Definition: k[c] = min over occupied cells o
@@ -409,6 +412,8 @@ int orc_prep(int n_beams, const float* ranges, double angle_min, double angle_in
   if (nfov == 0 || nvalid == 0) return info[0] = -5;
   const i64 a0 = alpha_mid_pm[0], a1 = alpha_mid_pm[1];
   const i64 b0 = alpha_low_pm[0], b1 = alpha_low_pm[1];
+  // eq. 25: alpha_low < alpha_mid (< alpha_full = 1) at every lambda
+  if (b0 > a0 || b1 > a1) return info[0] = -1;
   const i64 kmid = (nvalid * (a0 * Ns + (a1 - a0) * nfov)) / (1000 * Ns);
   const i64 klow = (nvalid * (b0 * Ns + (b1 - b0) * nfov)) / (1000 * Ns);
   info[1] = Ns; info[2] = Nt; info[3] = Ng; info[4] = nfov; info[5] = nvalid;

@@ -91,7 +91,7 @@ class reloc_serve_config(C.Structure):
 class reloc_serve_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("ticks", C.c_int64), ("queued", C.c_int32), ("inflight", C.c_int32),
-                ("busy_s", C.c_double)]
+                ("busy_s", C.c_double), ("pollers", C.c_int32), ("reserved", C.c_int32)]
 
 
 class reloc_rrt_params(C.Structure):

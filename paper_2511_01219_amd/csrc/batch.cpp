@@ -947,6 +947,7 @@ int32_t reloc_serve_stats_get(reloc_ctx* c, reloc_serve_stats* out) {
   ServeState* S = c->serve;
   std::lock_guard<std::mutex> lk(S->qmu);
   *out = S->stats;
+  out->pollers = S->pollers;
   return RELOC_OK;
 }
 

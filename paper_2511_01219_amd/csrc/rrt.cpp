@@ -252,6 +252,12 @@ int32_t reloc_sample_rrt(reloc_ctx* c, int32_t map_id, const reloc_rrt_params* p
   auto it = c->maps.find(map_id);
   if (it == c->maps.end()) return fail(RELOC_E_NOTFOUND, "unknown map %d", map_id);
   DevMap& m = it->second;
+  // representatives end up de-duplicated per cell, so a voxel finer than a
+  // cell adds nothing but attempts (Remark 4: N grows as 1 / rho^2) and
+  // voxel flags (one byte per rho^2)
+  if (!(p->rho >= m.res))
+    return fail(RELOC_E_INVALID, "rho = %g m is below the map resolution %g m", p->rho, m.res);
+  RELOC_GUARD_BEGIN
   if (int32_t e = ensure_khost(c, m)) return e;
   std::vector<int32_t> cells;
   std::vector<double> nodes;
@@ -271,6 +277,7 @@ int32_t reloc_sample_rrt(reloc_ctx* c, int32_t map_id, const reloc_rrt_params* p
   if (int32_t e = new_set(c, map_id, std::move(cells), set_id)) return e;
   *n_out = n;
   return RELOC_OK;
+  RELOC_GUARD_END
 }
 
 }  // extern "C"

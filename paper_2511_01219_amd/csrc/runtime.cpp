@@ -148,6 +148,12 @@ int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double re
   const int64_t c0 = p->alpha_low_pm[0], c1 = p->alpha_low_pm[1];
   if (a0 < 1 || a0 > 1000 || a1 < 1 || a1 > 1000 || c0 < 1 || c0 > 1000 || c1 < 1 || c1 > 1000)
     return fail(RELOC_E_INVALID, "alpha per-mille values must be in [1, 1000]");
+  // eq. 25 orders the fractions alpha_low < alpha_mid at every lambda; with
+  // alpha_low <= alpha_mid at both ends, k_low <= k_mid for every FoV, which
+  // is what makes the median of eq. 27 the top-k_mid mean
+  if (c0 > a0 || c1 > a1)
+    return fail(RELOC_E_INVALID, "alpha_low (%lld, %lld) must not exceed alpha_mid (%lld, %lld)",
+                (long long)c0, (long long)c1, (long long)a0, (long long)a1);
   const int64_t kmid = (nvalid * (a0 * Ns + (a1 - a0) * nfov)) / (1000 * Ns);
   const int64_t klow = (nvalid * (c0 * Ns + (c1 - c0) * nfov)) / (1000 * Ns);
   if (kmid < 1 || klow < 1) return fail(RELOC_E_EMPTY, "too few valid beams for TAM");

@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -30,6 +31,19 @@ int32_t fail(int32_t code, const char* fmt, ...);
     if (e_ != hipSuccess)                                                              \
       return fail(RELOC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
   } while (0)
+
+// Body guard of an extern "C" entry point: a host allocation that fails
+// (std::bad_alloc) becomes RELOC_E_NOMEM and any other exception
+// RELOC_E_DEVICE, so nothing propagates across the ABI.
+#define RELOC_GUARD_BEGIN try {
+#define RELOC_GUARD_END                                                                \
+  }                                                                                    \
+  catch (const std::bad_alloc&) {                                                      \
+    return fail(RELOC_E_NOMEM, "host allocation failed");                              \
+  }                                                                                    \
+  catch (...) {                                                                        \
+    return fail(RELOC_E_DEVICE, "unexpected host exception");                          \
+  }
 
 // ---- scan preprocessing (eq. 11-16, 25-26) ---------------------------------
 struct Prep {

@@ -147,6 +147,25 @@ def test_scan_info_errors_match_oracle_codes():
     assert ei.value.code == reloc.E_INVALID        # Ns above the 4096 limit
 
 
+def test_alpha_order_refused_on_both_sides():
+    """Eq. 25 orders alpha_low < alpha_mid. The library's top-k_mid mean is
+    the median of eq. 27 only when k_low <= k_mid, so misordered alphas are
+    refused before any work, by the library and by the oracle; equal alphas
+    (k_low == k_mid) and the defaults are accepted."""
+    z = np.full(360, 2.0, np.float32)
+    inc = 2 * math.pi / 360
+    for mid, low in (((900, 700), (700, 500)), ((800, 600), (800, 600)), ((900, 700), (100, 100))):
+        a, b = _both(z, -math.pi, inc, alpha_mid_pm=mid, alpha_low_pm=low)
+        assert b["status"] == 0 and a["k_low"] == b["k_low"] <= a["k_mid"] == b["k_mid"]
+    for mid, low in (((900, 700), (901, 500)), ((900, 700), (700, 701)),
+                     ((500, 500), (900, 100))):
+        with pytest.raises(reloc.RelocError) as ei:
+            reloc.scan_info(z, -math.pi, inc, 0.05, alpha_mid_pm=mid, alpha_low_pm=low)
+        assert ei.value.code == reloc.E_INVALID, (mid, low)
+        b = oracle.prep(z, -math.pi, inc, 0.05, alpha_mid_pm=mid, alpha_low_pm=low)
+        assert b["status"] == oracle.E_INVALID, (mid, low)
+
+
 def test_search_param_defaults():
     p = reloc.search_params()
     assert (p.batch_k, p.k_out, p.tau, p.z_hit, p.sigma_hit, p.z_rand, p.d_max) == \

@@ -135,6 +135,8 @@ def test_rrt_set_relocalizes(ctx):
     dict(rho=float("inf")),
     dict(eta_max=float("inf")),
     dict(rho=0.0),
+    dict(rho=1e-4),             # finite but below the 0.05 m cell: ~1e12 attempts per round
+    dict(rho=0.0499),
     dict(eta_max=0.1),          # below the robot radius
     dict(eps_gain=-1),
     dict(max_rounds=0),

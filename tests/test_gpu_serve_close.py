@@ -48,7 +48,15 @@ def test_close_ends_a_blocked_poll():
 
         th = threading.Thread(target=waiter)
         th.start()
-        time.sleep(0.15)           # the waiter is inside reloc_poll by now
+        # the waiter is counted inside reloc_poll (under the serving lock)
+        # before it waits; close only once it is there
+        t_end = time.monotonic() + 30.0
+        while ctx.serve_stats()["pollers"] < 1:
+            assert time.monotonic() < t_end, "the poll never entered the library"
+            assert th.is_alive() or "r" in got or "e" in got
+            if not th.is_alive():
+                break
+            time.sleep(0.001)
         _case("serve close: closing the context while a poll waits")
         ctx.close()
         closed = True

@@ -181,3 +181,16 @@ def test_config1_relocalizes_within_paper_criterion():
     d = math.hypot(b["x"] - w.pose[0], b["y"] - w.pose[1])
     dth = abs((b["theta"] - w.pose[2] + math.pi) % (2 * math.pi) - math.pi)
     assert d < 0.5 and dth < math.radians(30)      # success criterion, Sec. IV-C
+
+
+def test_splitmix64_known_answers():
+    """The sampler's visiting priority is splitmix64's output function
+    (Alg. 1 replaced by a seeded deterministic order): its seed-0 sequence
+    must match the published test vector, so a wrong constant, shift or
+    gamma fails here and not only through sampler invariants."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    want = [int(l, 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    gamma = 0x9E3779B97F4A7C15
+    got = [oracle.mix64((n * gamma) & 0xFFFFFFFFFFFFFFFF) for n in range(len(want))]
+    assert got == want, [hex(g) for g in got]
