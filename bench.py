@@ -6,14 +6,17 @@ Metric: hypothesis x orientation evaluations per second, SMAD + TAM
 the turn; TAM evals = hypotheses evaluated by TAM x N_theta), plus p50/p99
 latency of one relocalization.
 
-One step = one relocalization of the plain-large workload (2000 x 2000
-warehouse at 0.05 m, 20 000 hypotheses, 270 deg / 720-beam scan with
-clutter, 0.5 deg TAM orientations, 64 hypotheses per stage, tau = 0.95):
-ray cast + SMAD for every hypothesis, SMAD order, TAM stages with early
-termination, ranking. Map, hypotheses and the scan's tables are resident in
-HBM before timing starts (reloc_prepare); each step is one reloc_run.
+Default workload (stress): 8000 x 8000 mixed warehouse and rooms map at
+0.05 m, 200 000 hypotheses, panoramic 1440-beam scan taken in a perturbed
+copy of the map with 15 % short-return clutter, 1440 TAM orientations
+(0.25 deg), 256 hypotheses per stage, tau = 0.95. Each timed step is one
+whole relocalization through reloc_relocalize, from the host scan to the
+host poses: scan preprocessing and table upload, fused ray cast + SMAD of
+every hypothesis, SMAD order, TAM stages with early termination, ranking,
+release. Map and hypothesis set are resident before timing starts; the
+ray-cast launch shape is tuned once for the map, outside the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload ...]
 """
 from __future__ import annotations
 
@@ -28,54 +31,67 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: CUs x SIMDs x lanes x clock
-DDA_OPS_PER_STEP = 10                      # compare, 2 selects, D update, 2 bounds, 3 address, 1 bit test
 FP64_ADD_PEAK = 256 * 4 * 16 * 2.4e9       # FP64 adds/s (lane-ops; FP64 runs at the FP32 rate)
+# Algorithmic work of one iteration of the jump traversal (one free-space
+# jump test, one exact crossing, one walk-word test): int32 VALU operations
+# of that path in the compiled loop of the fused kernel.
+OPS_PER_ITER = 50
 COARSE = {"smad": 0, "smad-direct": 1, "caer": 2, "none": 3}
 FINE = {"tam": 0, "tam-mean": 1, "baseline": 2, "lf": 3}
 RAYCAST_SOURCES = ("paper_2511_01219_amd/csrc/k_raycast.hip",
                    "paper_2511_01219_amd/csrc/reloc_internal.h")
-TRAFFIC_FILE = "profiles/raycast_skip_kernel_plain-large_traffic.txt"
+# counter summaries of the dominant kernel on the default workload
+TRAFFIC_FILE = "profiles/raycast_smad_kernel_stress_traffic.txt"
+COUNTERS_FILE = "profiles/raycast_smad_kernel_stress_counters.txt"
+WORKLOADS = {   # config number, TAM orientations, hypotheses per stage
+    "plain-small": (1, 360, 10),
+    "plain-large": (2, 720, 64),
+    "stress": (5, 1440, 256),
+}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def exact_crossings(hit, hyp, Ns, W, H, rcells):
+def exact_crossings(hit, hyp, Ns, W, H, rcells, chunk=4096):
     """Cell crossings of the plain step-by-step traversal of every ray: for a
     hit |dx| + |dy| to the hit cell; for a miss the crossings done when the
-    ray first passes the map edge or the cut-off (continuous geometry)."""
+    ray first passes the map edge or the cut-off (continuous geometry).
+    Hypotheses are taken chunk by chunk to bound host memory."""
     import numpy as np
     n = len(hyp)
     hit = hit.reshape(n, Ns)
-    ix0 = hyp[:, 0:1].astype(np.int64)
-    iy0 = hyp[:, 1:2].astype(np.int64)
-    h = hit.astype(np.int64)
-    hx, hy = h % W, h // W
-    steps = np.where(h >= 0, np.abs(hx - ix0) + np.abs(hy - iy0), 0)
     ang = 2.0 * np.pi * np.arange(Ns) / Ns
     ux, uy = np.cos(ang)[None, :], np.sin(ang)[None, :]
     ux = np.where(np.abs(ux) < 1e-12, 0.0, ux)
     uy = np.where(np.abs(uy) < 1e-12, 0.0, uy)
-    lx = np.minimum(rcells, np.where(ux > 0, W - 1 - ix0, np.where(ux < 0, ix0, rcells)))
-    ly = np.minimum(rcells, np.where(uy > 0, H - 1 - iy0, np.where(uy < 0, iy0, rcells)))
     ax, ay = np.abs(ux), np.abs(uy)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        tx = np.where(ax > 0, (0.5 + lx) / ax, np.inf)
-        ty = np.where(ay > 0, (0.5 + ly) / ay, np.inf)
-        te = np.minimum(tx, ty)
-        cx = np.where(ax > 0, np.floor(te * ax - 0.5) + 1, 0)
-        cy = np.where(ay > 0, np.floor(te * ay - 0.5) + 1, 0)
-    miss = cx + cy
-    return int(np.where(h >= 0, steps, miss).sum())
+    total = 0
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        ix0 = hyp[a:b, 0:1].astype(np.int64)
+        iy0 = hyp[a:b, 1:2].astype(np.int64)
+        h = hit[a:b].astype(np.int64)
+        hx, hy = h % W, h // W
+        steps = np.where(h >= 0, np.abs(hx - ix0) + np.abs(hy - iy0), 0)
+        lx = np.minimum(rcells, np.where(ux > 0, W - 1 - ix0, np.where(ux < 0, ix0, rcells)))
+        ly = np.minimum(rcells, np.where(uy > 0, H - 1 - iy0, np.where(uy < 0, iy0, rcells)))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tx = np.where(ax > 0, (0.5 + lx) / ax, np.inf)
+            ty = np.where(ay > 0, (0.5 + ly) / ay, np.inf)
+            te = np.minimum(tx, ty)
+            cx = np.where(ax > 0, np.floor(te * ax - 0.5) + 1, 0)
+            cy = np.where(ay > 0, np.floor(te * ay - 0.5) + 1, 0)
+        total += int(np.where(h >= 0, steps, cx + cy).sum())
+    return total
 
 
-def measured_traffic():
-    """HBM bytes per launch of the ray-cast kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
+def _summary(path):
+    """key: value lines of a committed counter summary, or None when the file
+    is missing or the ray-cast sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -88,8 +104,28 @@ def measured_traffic():
         hs.update(open(os.path.join(ROOT, f), "rb").read())
     if kv.get("source_sha256") != hs.hexdigest():
         return None
+    return kv
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused ray-cast kernel on the default
+    workload from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
+    the kernel sources changed since it was taken."""
+    kv = _summary(TRAFFIC_FILE)
     try:
-        return float(kv["bytes_per_launch"])
+        return float(kv["bytes_per_launch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_counters():
+    """Executed VALU wave-instructions and L2 read requests per launch of the
+    fused ray-cast kernel on the default workload (committed counter summary,
+    same pass as its duration), or None when stale."""
+    kv = _summary(COUNTERS_FILE)
+    try:
+        return {k: float(kv[k]) for k in ("valu_insts_per_launch", "tcp_tcc_read_req_per_launch",
+                                          "duration_ns")} if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -308,87 +344,266 @@ def bench_sweep(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_stress(args):
-    """Stress: 8000 x 8000 mixed map, 200 000 hypotheses, panoramic 1440-beam
-    scan (perturbed environment, 15 % clutter), 1440 orientations, top-256
-    per stage, tau 0.95; one relocalization per step."""
+def cpu_baseline_sampled(w, hyp, n_theta, n_eval, budget_s):
+    """The oracle on seeded 1 % subsamples of the workload (ray cast and
+    direct-sum SMAD of 1 % of the hypotheses, TAM of 1 % of the evaluated
+    ones over every orientation), one subsample after another until about
+    budget_s has passed; the x100 extrapolation of one subsample's time is
+    reported as such."""
+    import numpy as np
+    import oracle
+    pr = oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                     range_min=w.range_min, range_max=w.range_max, n_theta=n_theta)
+    k = oracle.edt(w.occ)
+    n = len(hyp)
+    n_sub = max(1, n // 100)
+    n_tam = max(1, n_eval // 100)
+    t0 = time.perf_counter()
+    samples, evals = 0, 0
+    while True:
+        sub = np.sort(np.random.default_rng([5, 6, samples]).choice(n, n_sub, replace=False))
+        _, z = oracle.raycast(w.occ, hyp[sub], pr["Ns"], pr["Ng"], w.resolution, w.range_max)
+        oracle.smad(z, pr)
+        q = np.repeat(hyp[sub[:n_tam]], n_theta, axis=0)
+        oracle.tam(k, w.resolution, pr, q, np.tile(np.arange(n_theta), n_tam))
+        samples += 1
+        evals += n_sub * pr["n_shifts"] + n_tam * n_theta
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d seeded 1 %% subsamples, each: ray cast + direct-sum SMAD of %d "
+                      "hypotheses, TAM of %d x %d orientations; %.1f s in all; x100 "
+                      "extrapolation of one relocalization: %.1f s"
+                      % (samples, n_sub, n_tam, n_theta, dt, 100 * dt / samples),
+            "extrapolated_step_s": 100 * dt / samples,
+            "host": {"cpu_model": _cpu_model(), "cpu_count": os.cpu_count(),
+                     "affinity": affinity}}
+
+
+def bench_single(args):
+    """One relocalization per step on a single map: plain-small, plain-large
+    or stress (the default)."""
     import numpy as np
     import torch
     import paper_2511_01219_amd as reloc
     from synth import make_config
-    log("generating the stress workload")
-    w = make_config(5)
+
+    cid, n_theta, batch_k = WORKLOADS[args.workload]
+    tau = None if args.tau.lower() in ("none", "nan") else float(args.tau)
+    log("measuring device peaks")
+    peaks = reloc.measure_peaks(0)
+    log("peaks: int32 VALU %.1f T lane-ops/s, L2 gathers %.0f G/s, HBM read %.2f TB/s"
+        % (peaks["valu_i32_ops"] / 1e12, peaks["l2_gathers"] / 1e9, peaks["hbm_read"] / 1e12))
+    if args.calibrate_copy:
+        # one device-to-device copy (a plain copy kernel): reads and writes
+        # exactly this many bytes, the scale of the HBM byte counters
+        nbytes = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(nbytes, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calibrate_copy)
+        del src, dst
+    log("generating the %s workload" % args.workload)
+    w = make_config(cid)
     ctx = reloc.Context(0)
     m = ctx.load_map(w.occ, w.resolution, w.origin)
     s = w.sample
     sid, n_hyp = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
                                        seed=s["seed"])
     hyp = ctx.read_hypotheses(sid)
-    n_theta, batch_k = 1440, 256
-    rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
-                      w.range_max, n_theta=n_theta, batch_k=batch_k, tau=0.95, k_out=10)
-    tv, tc, tms = ctx.autotune(rid, reps=2)
-    log("map %dx%d, %d hypotheses; autotuned ray cast: variant %d, %d rays per chunk"
-        % (w.occ.shape[1], w.occ.shape[0], n_hyp, tv, tc))
+    rrt = None
+    if args.sampler == "rrt":
+        # Algorithm 1 from the first cell of the deterministic set as the
+        # tree root, spacing rho of the workload; the set replaces the grid one
+        p0 = ((hyp[0, 0] + 0.5) * w.resolution + w.origin[0],
+              (hyp[0, 1] + 0.5) * w.resolution + w.origin[1])
+        ctx.free_hypotheses(sid)
+        t0 = time.perf_counter()
+        sid, n_hyp, info = ctx.sample_rrt(m, p0, rho=s["min_spacing"],
+                                          robot_radius=s["robot_radius"], seed=s["seed"])
+        rrt = dict(info, seconds=time.perf_counter() - t0, n_hyp=n_hyp)
+        log("RRT: %d hypotheses from %d nodes in %d rounds, %.2f s" % (
+            n_hyp, info["nodes"], info["rounds"], rrt["seconds"]))
+        hyp = ctx.read_hypotheses(sid)
+    scan = (w.ranges, w.angle_min, w.angle_increment, w.range_min, w.range_max)
+    search = dict(n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10, variant=args.variant,
+                  refine_k=args.refine_k, refine_cells=args.refine_cells,
+                  coarse_metric=COARSE[args.coarse], fine_metric=FINE[args.fine])
+    tuned = None
+    if args.variant == 0 and args.tune:
+        # the ray-cast launch shape is picked once for the map (every shape
+        # gives bit-identical results), outside the timed region; later
+        # requests of the map with the same beam grid start from it
+        rid = ctx.prepare(m, sid, *scan, **search)
+        tv, tc, tms = ctx.autotune(rid, reps=2)
+        ctx.release(rid)
+        tuned = {"variant": tv, "shape": tc, "ms": tms}
+        log("ray-cast shape tuned for the map: variant %d, shape %d, %.3f ms" % (tv, tc, tms))
+    log("map %dx%d, %d hypotheses, warmup %d" % (w.occ.shape[1], w.occ.shape[0], n_hyp,
+                                               args.warmup))
     for _ in range(args.warmup):
-        ctx.run(rid)
+        ctx.relocalize(m, sid, *scan, **search)
     torch.cuda.synchronize()
-    lat, evals, ray_ms, tam_ms = [], 0, [], []
+    lat, evals, ray_ms, smad_ms, tam_ms, tot_ms = [], 0, [], [], [], []
+    last = None
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         ts = time.perf_counter()
-        poses, st = ctx.run(rid)
+        poses, st = ctx.relocalize(m, sid, *scan, **search)
         lat.append(time.perf_counter() - ts)
         evals += st["smad_evals"] + st["tam_evals"]
         ray_ms.append(st["ms_raycast"])
+        smad_ms.append(st["ms_smad"])
         tam_ms.append(st["ms_tam"])
+        tot_ms.append(st["ms_total"])
+        last = (poses, st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    poses, st = last
+    log("timed %d steps in %.3f s; stages %d, early stop %d" % (args.steps, elapsed,
+                                                              st["stages"], st["early_stopped"]))
+
+    # roofline of the dominant kernel, the fused ray cast + SMAD (its mean
+    # launch time from the hipEvents the library records around it on its
+    # own stream in every timed step)
+    info = reloc.scan_info(w.ranges, w.angle_min, w.angle_increment, w.resolution,
+                           w.range_min, w.range_max, n_theta=n_theta)
+    Ns, pano = info["Ns"], info["n_shifts"] == 1
+    iterations = crossings = 0
+    if not args.no_roofline:
+        rid = ctx.prepare(m, sid, *scan, **search)
+        hit, _, iters = ctx.debug_raycast(rid, n_hyp, Ns, steps=True)
+        ctx.release(rid)
+        rcells = int(math.ceil(w.range_max / w.resolution)) + 2
+        crossings = exact_crossings(hit, hyp[:n_hyp], Ns, w.occ.shape[1], w.occ.shape[0],
+                                    rcells)
+        del hit
+        iterations = int(iters.astype(np.int64).sum())
+        del iters
+    t_ray = float(np.mean(ray_ms)) * 1e-3
+    shape = tuned["shape"] if tuned else None
+    refill = {3: 8, 4: 16, 5: 32}.get(tuned["variant"]) if tuned else None
+    kname = ("raycast_smad_kernel<%s,%s,%s>" % (shape or "default", refill or 16,
+                                                "pano" if pano else "shifts")
+             if args.variant == 0 and COARSE[args.coarse] == 0 else "split ray cast")
+    alg_ops = iterations * OPS_PER_ITER / t_ray
+    cnt = measured_counters() if args.workload == "stress" else None
+    traffic = measured_traffic() if args.workload == "stress" else None
+    roofline = {"kernel": kname, "bound": "alu", "unit": "TOP/s (int32 lane-ops)",
+                "peak": peaks["valu_i32_ops"] / 1e12, "traffic": traffic,
+                "avg_ms": t_ray * 1e3}
+    if cnt:
+        # executed VALU lane-ops per launch (counters of the same kernel,
+        # workload and sources) over this run's mean launch time
+        ex = cnt["valu_insts_per_launch"] * 64.0
+        roofline.update(achieved=ex / t_ray / 1e12, frac=ex / t_ray / peaks["valu_i32_ops"],
+                        basis="executed VALU lane-ops (committed counters) / live launch time")
+        roofline["gather"] = {
+            "l2_requests_per_s": cnt["tcp_tcc_read_req_per_launch"] / t_ray,
+            "peak_l2_random_gathers_per_s": peaks["l2_gathers"],
+            "frac": cnt["tcp_tcc_read_req_per_launch"] / t_ray / peaks["l2_gathers"]}
+    else:
+        roofline.update(achieved=alg_ops / 1e12, frac=alg_ops / peaks["valu_i32_ops"],
+                        basis="algorithmic: traversal iterations x %d ops / live launch time"
+                              % OPS_PER_ITER)
+    roofline["algorithmic"] = {"unit": "traversal iteration (jump test + crossing)",
+                               "iterations_per_launch": iterations,
+                               "ops_per_iteration": OPS_PER_ITER,
+                               "achieved": alg_ops / 1e12,
+                               "frac": alg_ops / peaks["valu_i32_ops"]}
+    roofline["dda_crossing_rate"] = {
+        "note": "cells a step-by-step traversal visits; the jump traversal skips most of them",
+        "crossings_per_launch": crossings, "crossings_per_s": crossings / t_ray}
     out = {
         "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
-        "value": evals / elapsed, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32+f32+f64", "data": "synthetic",
-        "config": {"workload": "stress: mixed 8000x8000 @0.05 m, 200000 hypotheses, 360 deg "
-                               "1440 beams (perturbed map, 15 % clutter), 0.25 deg TAM, "
-                               "top-256 per stage, tau 0.95", "n_hyp": n_hyp},
+        "value": evals / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f32+f64",
+        "data": "synthetic",
+        "config": {"workload": {
+            "plain-small": "plain-small: rooms 200x200 @0.05 m, 300 hypotheses, 270 deg 360 "
+                           "beams, 1 deg TAM, top-10 per stage",
+            "plain-large": "plain-large: warehouse 2000x2000 @0.05 m, 20000 hypotheses, 270 deg "
+                           "720 beams, 0.5 deg TAM, top-64 per stage",
+            "stress": "stress: mixed 8000x8000 @0.05 m, 200000 hypotheses, 360 deg 1440 beams "
+                      "(perturbed map, 15 % clutter), 0.25 deg TAM, top-256 per stage"}[
+                          args.workload],
+                   "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k,
+                   "refine_k": args.refine_k,
+                   "refine_cells": args.refine_cells if args.refine_k else None,
+                   "coarse": args.coarse, "fine": args.fine, "sampler": args.sampler,
+                   "timed_step": "reloc_relocalize: prepare + run + release"},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "what": "submit to poses on the host, whole relocalization"},
+        "value_by_kind": {"smad_evals_per_s": args.steps * st["smad_evals"] / elapsed,
+                          "tam_evals_per_s": args.steps * st["tam_evals"] / elapsed},
         "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
                      "stages": st["stages"], "early_stopped": st["early_stopped"],
-                     "rays": st["rays"], "raycast_ms": float(np.mean(ray_ms)),
-                     "smad_ms": st["ms_smad"], "tam_ms": float(np.mean(tam_ms)),
-                     "tam_lookups": st["tam_lookups"]},
-        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k")},
+                     "device_ms": float(np.mean(tot_ms)), "raycast_ms": float(np.mean(ray_ms)),
+                     "smad_ms": float(np.mean(smad_ms)),
+                     "tam_ms": float(np.mean(tam_ms)), "rays": st["rays"],
+                     "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"],
+                     "tam_lookups_per_s": st["tam_lookups"] / max(1e-9, float(np.mean(tam_ms))
+                                                                  * 1e-3),
+                     "refined": st["refined"], "refine_points": st["refine_points"]},
+        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k", "g",
+                                               "refined")},
         "true_pose": list(w.pose),
         "accuracy": accuracy(poses[0], w.pose, st),
-        "autotune": {"variant": tv, "chunk": tc, "ms": tms},
+        "peaks": peaks,
+        "roofline": roofline,
+        "autotune": tuned,
+        "rrt": rrt,
     }
-    ctx.release(rid)
-    if not args.no_cpu:
-        # the oracle on a seeded 1 % subsample: ray cast + SMAD of 1 % of the
-        # hypotheses and TAM of 1 % of the evaluated (hypothesis, orientation) set
-        import oracle
-        pr = oracle.prep(w.ranges, w.angle_min, w.angle_increment, w.resolution,
-                         range_min=w.range_min, range_max=w.range_max, n_theta=n_theta)
-        k = oracle.edt(w.occ)
-        sub = np.sort(np.random.default_rng([5, 6]).choice(n_hyp, n_hyp // 100, replace=False))
-        n_tam = max(1, st["n_eval"] // 100)
-        t1 = time.perf_counter()
-        _, z = oracle.raycast(w.occ, hyp[sub], pr["Ns"], pr["Ng"], w.resolution, w.range_max)
-        oracle.smad(z, pr)
-        q = np.repeat(hyp[sub[:n_tam]], n_theta, axis=0)
-        oracle.tam(k, w.resolution, pr, q, np.tile(np.arange(n_theta), n_tam))
-        dt = time.perf_counter() - t1
-        ev = len(sub) * pr["n_shifts"] + n_tam * n_theta
-        out["cpu_baseline"] = {"value": ev / dt, "unit": "evals/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": "1 %% subsample: ray cast + SMAD of %d hypotheses, "
-                                         "TAM of %d x %d; %.1f s (x100 extrapolation of the "
-                                         "step: %.1f s)" % (len(sub), n_tam, n_theta, dt,
-                                                            100 * dt)}
+    if COARSE[args.coarse] in (1, 2):
+        # the direct coarse kernel: one FP64 subtract and one FP64 add (of an
+        # absolute value) per (hypothesis, shift, FoV beam) term for CAER, one
+        # add for direct-sum SMAD; FP64 add peak = 256 CUs x 64 lanes x 2.4 GHz
+        caer = COARSE[args.coarse] == 2
+        nsh = info["Ns"] if caer else info["n_shifts"]
+        terms = n_hyp * nsh * info["n_fov"]
+        t_c = float(np.mean(smad_ms)) * 1e-3
+        ops = terms * (2 if caer else 1)
+        out["coarse_roofline"] = {"kernel": "coarse_direct_kernel", "bound": "alu",
+                                  "achieved": ops / t_c / 1e12, "peak": FP64_ADD_PEAK / 1e12,
+                                  "unit": "TOP/s (fp64 lane-ops)",
+                                  "frac": ops / t_c / FP64_ADD_PEAK, "terms": terms,
+                                  "avg_ms": t_c * 1e3}
+    if tau is not None and not args.no_full_search and args.workload != "stress":
+        # untimed: the same search without early termination, so the line
+        # shows what the stop test at tau gave up (Sec. IV-C criterion)
+        pf, sf = ctx.relocalize(m, sid, *scan, **dict(search, tau=None))
+        out["accuracy"]["full_search"] = dict(accuracy(pf[0], w.pose, sf), tam=pf[0]["tam"],
+                                              rank=pf[0]["rank"], ms=sf["ms_total"])
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
     ctx.close()
+    if args.no_cpu:
+        out["cpu_baseline"] = None
+    elif args.workload == "stress":
+        log("cpu baseline (oracle, 1 %% subsamples) ~%.0f s" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_sampled(w, hyp[:n_hyp], n_theta, st["n_eval"],
+                                                   args.cpu_seconds)
+    else:
+        log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, hyp, n_theta, batch_k, st["stages"],
+                                           args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -485,6 +700,13 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_peaks(args):
+    """The device's measured peaks alone (reloc_measure_peaks)."""
+    import paper_2511_01219_amd as reloc
+    p = reloc.measure_peaks(0)
+    print(json.dumps({"metric": "measured peaks", "peaks": p, "n_gpus": 1}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,12 +718,18 @@ def main():
                     help="skip the untimed search without early termination that the "
                          "accuracy report of a tau run adds (profiler runs that count "
                          "the timed launches only)")
+    ap.add_argument("--no-roofline", action="store_true",
+                    help="skip the untimed debug ray cast behind the roofline fields "
+                         "(profiler runs that count the timed launches only)")
+    ap.add_argument("--tune", action="store_true",
+                    help="tune the ray-cast launch shape once for the map (untimed) instead "
+                         "of the default shape")
     ap.add_argument("--variant", type=int, default=0,
-                    help="ray-cast kernel: 0 tuned default, 1 bit tiles, 2 distance skipping")
+                    help="ray-cast kernel: 0 fused default, 1 bit tiles, 2-5 split skipping")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="plain-large",
-                    choices=("plain-large", "plain-small", "batched", "serving", "stress",
-                             "sweep"))
+    ap.add_argument("--workload", default="stress",
+                    choices=("stress", "plain-large", "plain-small", "batched", "serving",
+                             "sweep", "peaks"))
     ap.add_argument("--rates", default="50,100,200,500", help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per rate")
     ap.add_argument("--max-inflight", type=int, default=64)
@@ -527,188 +755,11 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
-    if args.workload == "stress":
-        return bench_stress(args)
     if args.workload == "sweep":
         return bench_sweep(args)
-
-    import numpy as np
-    import torch
-    import paper_2511_01219_amd as reloc
-    from synth import make_config
-
-    if args.calibrate_copy:
-        # one device-to-device copy (a plain copy kernel): reads and writes
-        # exactly this many bytes, the scale of the HBM byte counters
-        n = args.calibrate_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy of %d MiB done" % args.calibrate_copy)
-        del src, dst
-    tau = None if args.tau.lower() in ("none", "nan") else float(args.tau)
-    small = args.workload == "plain-small"
-    n_theta, batch_k = (360, 10) if small else (720, 64)
-    log("generating the %s workload" % args.workload)
-    w = make_config(1 if small else 2)
-    ctx = reloc.Context(0)
-    m = ctx.load_map(w.occ, w.resolution, w.origin)
-    s = w.sample
-    sid, n_hyp = ctx.sample_hypotheses(m, s["n_target"], s["min_spacing"], s["robot_radius"],
-                                       seed=s["seed"])
-    hyp = ctx.read_hypotheses(sid)
-    rrt = None
-    if args.sampler == "rrt":
-        # Algorithm 1 from the first cell of the deterministic set as the
-        # tree root, spacing rho of the workload; the set replaces the grid one
-        p0 = ((hyp[0, 0] + 0.5) * w.resolution + w.origin[0],
-              (hyp[0, 1] + 0.5) * w.resolution + w.origin[1])
-        ctx.free_hypotheses(sid)
-        t0 = time.perf_counter()
-        sid, n_hyp, info = ctx.sample_rrt(m, p0, rho=s["min_spacing"],
-                                          robot_radius=s["robot_radius"], seed=s["seed"])
-        rrt = dict(info, seconds=time.perf_counter() - t0, n_hyp=n_hyp)
-        log("RRT: %d hypotheses from %d nodes in %d rounds, %.2f s" % (
-            n_hyp, info["nodes"], info["rounds"], rrt["seconds"]))
-        hyp = ctx.read_hypotheses(sid)
-    rid = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
-                      w.range_max, n_theta=n_theta, batch_k=batch_k, tau=tau, k_out=10,
-                      variant=args.variant, refine_k=args.refine_k,
-                      refine_cells=args.refine_cells, coarse_metric=COARSE[args.coarse],
-                      fine_metric=FINE[args.fine])
-    tuned = None
-    if args.variant == 0:
-        # the ray-cast launch shape is picked on this GPU for this request
-        # (every shape gives bit-identical results), outside the timed region
-        tv, tc, tms = ctx.autotune(rid, reps=3)
-        tuned = {"variant": tv, "chunk": tc, "ms": tms}
-        log("autotuned ray cast: variant %d, %d rays per chunk, %.3f ms" % (tv, tc, tms))
-    log("map %dx%d, %d hypotheses, warmup %d" % (w.occ.shape[1], w.occ.shape[0], n_hyp,
-                                               args.warmup))
-    for _ in range(args.warmup):
-        ctx.run(rid)
-    torch.cuda.synchronize()
-    lat, evals, ray_ms, smad_ms, tam_ms, tot_ms = [], 0, [], [], [], []
-    last = None
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        poses, st = ctx.run(rid)
-        lat.append(time.perf_counter() - ts)
-        evals += st["smad_evals"] + st["tam_evals"]
-        ray_ms.append(st["ms_raycast"])
-        smad_ms.append(st["ms_smad"])
-        tam_ms.append(st["ms_tam"])
-        tot_ms.append(st["ms_total"])
-        last = (poses, st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    poses, st = last
-    log("timed %d steps in %.3f s; stages %d, early stop %d" % (args.steps, elapsed,
-                                                              st["stages"], st["early_stopped"]))
-
-    # roofline of the dominant kernel (the ray cast): algorithmic work = the
-    # cell crossings of the plain step-by-step traversal x DDA_OPS_PER_STEP
-    # integer lane-ops, over the kernel's mean duration from the hipEvents
-    # recorded around it on the library's stream in every timed step
-    Ns = reloc.scan_info(w.ranges, w.angle_min, w.angle_increment, w.resolution,
-                         w.range_min, w.range_max, n_theta=n_theta)["Ns"]
-    hit, _, iters = ctx.debug_raycast(rid, n_hyp, Ns, steps=True)
-    rcells = int(math.ceil(w.range_max / w.resolution)) + 2
-    crossings = exact_crossings(hit, hyp[:n_hyp], Ns, w.occ.shape[1], w.occ.shape[0], rcells)
-    iterations = int(iters.astype(np.int64).sum())
-    t_ray = float(np.mean(ray_ms)) * 1e-3
-    achieved = crossings * DDA_OPS_PER_STEP / t_ray
-    traffic = measured_traffic()
-    kname = {1: "raycast_bits_kernel", 2: "raycast_skip_kernel<1>", 3: "raycast_skip_kernel<8>",
-             4: "raycast_skip_kernel<16>", 5: "raycast_skip_kernel<32>"}.get(
-                 tuned["variant"] if tuned else (args.variant or 4))
-    roofline = {"kernel": kname, "bound": "alu",
-                "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "TOP/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-                "traffic": traffic, "dda_crossings": crossings,
-                "loop_iterations": iterations, "avg_ms": t_ray * 1e3,
-                "crossings_per_s": crossings / t_ray}
-    out = {
-        "metric": "hypothesis x orientation evals/s (SMAD+TAM)",
-        "value": evals / elapsed,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32+f32+f64",
-        "data": "synthetic",
-        "config": {"workload": ("plain-small: rooms 200x200 @0.05 m, 300 hypotheses, 270 deg "
-                                "360 beams, 1 deg TAM, top-10 per stage") if small else
-                               ("plain-large: warehouse 2000x2000 @0.05 m, 20000 hypotheses, "
-                                "270 deg 720 beams, 0.5 deg TAM, top-64 per stage"),
-                   "tau": tau, "n_hyp": n_hyp, "n_theta": n_theta, "batch_k": batch_k,
-                   "refine_k": args.refine_k,
-                   "refine_cells": args.refine_cells if args.refine_k else None,
-                   "coarse": args.coarse, "fine": args.fine, "sampler": args.sampler},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
-        "value_by_kind": {"smad_evals_per_s": args.steps * st["smad_evals"] / elapsed,
-                          "tam_evals_per_s": args.steps * st["tam_evals"] / elapsed},
-        "per_step": {"smad_evals": st["smad_evals"], "tam_evals": st["tam_evals"],
-                     "stages": st["stages"], "early_stopped": st["early_stopped"],
-                     "device_ms": float(np.mean(tot_ms)), "raycast_ms": float(np.mean(ray_ms)),
-                     "smad_ms": float(np.mean(smad_ms)),
-                     "tam_ms": float(np.mean(tam_ms)), "rays": st["rays"],
-                     "rays_per_s": st["rays"] / t_ray, "tam_lookups": st["tam_lookups"],
-                     "tam_lookups_per_s": st["tam_lookups"] / (float(np.mean(tam_ms)) * 1e-3),
-                     "refined": st["refined"], "refine_points": st["refine_points"]},
-        "best_pose": {k: poses[0][k] for k in ("x", "y", "theta", "tam", "hyp", "k", "g",
-                                               "refined")},
-        "true_pose": list(w.pose),
-        "accuracy": accuracy(poses[0], w.pose, st),
-        "roofline": roofline,
-        "autotune": tuned,
-        "rrt": rrt,
-    }
-    if COARSE[args.coarse] in (1, 2):
-        # the direct coarse kernel: one FP64 subtract and one FP64 add (of an
-        # absolute value) per (hypothesis, shift, FoV beam) term for CAER, one
-        # add for direct-sum SMAD; FP64 add peak = 256 CUs x 64 lanes x 2.4 GHz
-        info = reloc.scan_info(w.ranges, w.angle_min, w.angle_increment, w.resolution,
-                               w.range_min, w.range_max, n_theta=n_theta)
-        caer = COARSE[args.coarse] == 2
-        nsh = info["Ns"] if caer else info["n_shifts"]
-        terms = n_hyp * nsh * info["n_fov"]
-        t_c = float(np.mean(smad_ms)) * 1e-3
-        ops = terms * (2 if caer else 1)
-        out["coarse_roofline"] = {"kernel": "coarse_direct_kernel", "bound": "alu",
-                                  "achieved": ops / t_c / 1e12, "peak": FP64_ADD_PEAK / 1e12,
-                                  "unit": "TOP/s (fp64 lane-ops)",
-                                  "frac": ops / t_c / FP64_ADD_PEAK, "terms": terms,
-                                  "avg_ms": t_c * 1e3}
-    ctx.release(rid)
-    if tau is not None and not args.no_full_search:
-        # untimed: the same search without early termination, so the line
-        # shows what the stop test at tau gave up (Sec. IV-C criterion)
-        rid_f = ctx.prepare(m, sid, w.ranges, w.angle_min, w.angle_increment, w.range_min,
-                            w.range_max, n_theta=n_theta, batch_k=batch_k, tau=None, k_out=10,
-                            refine_k=args.refine_k, refine_cells=args.refine_cells,
-                            coarse_metric=COARSE[args.coarse], fine_metric=FINE[args.fine])
-        pf, sf = ctx.run(rid_f)
-        ctx.release(rid_f)
-        out["accuracy"]["full_search"] = dict(accuracy(pf[0], w.pose, sf), tam=pf[0]["tam"],
-                                              rank=pf[0]["rank"], ms=sf["ms_total"])
-    if not args.no_cpu:
-        log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(w, hyp, n_theta, batch_k, st["stages"],
-                                           args.cpu_seconds)
-    else:
-        out["cpu_baseline"] = None
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    if args.workload == "peaks":
+        return bench_peaks(args)
+    return bench_single(args)
 
 
 if __name__ == "__main__":

@@ -302,6 +302,13 @@ typedef struct {
    * microseconds of launch overhead per run (about 3 % on a 300-hypothesis
    * search): for serving loops that repeat one request. */
   int32_t use_graph;
+  /* Launch shape of the fused ray cast + SMAD kernel (the default path:
+   * coarse_metric 0, variant 0, a map with walk words): wavefronts per
+   * hypothesis workgroup (1, 2 or 4) and lane refill threshold (8, 16 or 32
+   * idle lanes); 0 takes the map's tuned shape or the default rule. Every
+   * shape gives bit-identical results. */
+  int32_t ray_waves;
+  int32_t ray_refill;
 } reloc_search_params;
 
 /* Fills the defaults listed above. */
@@ -489,18 +496,47 @@ int32_t reloc_serve_stats_get(reloc_ctx* ctx, reloc_serve_stats* out);
 
 /* ------------------------------------------------------------------------
  * Autotuning. Times the ray-cast kernel of a prepared request over a grid
- * of launch shapes (lane-refill threshold 8 / 16 / 32 idle lanes x 256,
- * 384, 512, 768, 1024 rays per chunk; every shape gives bit-identical
- * ranges), each warmed once and then launched reps times, and keeps the
- * fastest for the request's later runs (reloc_run, reloc_run_batch).
- * variant_out: the chosen public variant (3, 4, 5); chunk_out: rays per
- * chunk; ms_out: its mean kernel time. Any of them may be NULL. Requests on
- * maps without walk words (above 2^28 cells) keep the bit-tile kernel and
- * report their current settings. Errors: RELOC_E_INVALID (reps < 1),
- * RELOC_E_NOTFOUND, RELOC_E_DEVICE.
+ * of launch shapes, each warmed once and then launched reps times, and
+ * keeps the fastest for the request's later runs (reloc_run,
+ * reloc_run_batch); every shape gives bit-identical results.
+ *   - Requests on the default path (coarse_metric 0, variant 0, a map with
+ *     walk words) run the fused ray cast + SMAD kernel: the grid is 1, 2 or
+ *     4 wavefronts per hypothesis workgroup x lane refill at 8, 16 or 32
+ *     idle lanes. variant_out = 3, 4, 5 for refill 8, 16, 32; chunk_out =
+ *     the wavefronts per workgroup. The choice is also kept on the map, and
+ *     later requests of the map with the same beam grid (Ns) start from it.
+ *   - Other requests on maps with walk words run the split ray cast: refill
+ *     threshold 8 / 16 / 32 x 256, 384, 512, 768, 1024 rays per chunk;
+ *     variant_out = the public variant (3, 4, 5), chunk_out = rays per
+ *     chunk.
+ *   - Requests on maps without walk words (above 2^28 cells) keep the
+ *     bit-tile kernel and report their current settings.
+ * ms_out: the chosen shape's mean kernel time. Any out pointer may be NULL.
+ * Errors: RELOC_E_INVALID (reps < 1), RELOC_E_NOTFOUND, RELOC_E_DEVICE.
  * ---------------------------------------------------------------------- */
 int32_t reloc_autotune(reloc_ctx* ctx, int32_t request_id, int32_t reps, int32_t* variant_out,
                        int32_t* chunk_out, float* ms_out);
+
+/* ------------------------------------------------------------------------
+ * Measured peaks of the device (the denominators of roofline fractions).
+ * Runs short microbenchmarks on `device` with buffers of its own (about
+ * 2.2 GiB, allocated with hipMalloc and freed before returning), each timed
+ * as the best of five launches after a warm-up:
+ *   valu_i32_ops : int32 lane-operations per second (adds and xors, eight
+ *                  independent chains per lane, eight wavefronts per SIMD);
+ *   l2_gathers   : 4-byte lane loads per second at pseudo-random offsets of
+ *                  a 2 MiB table (resident in one XCD's L2);
+ *   mall_gathers : the same over a 128 MiB table (beyond L2, within MALL);
+ *   hbm_read     : bytes per second of a streaming read of 1 GiB;
+ *   hbm_copy     : bytes read plus written per second copying 1 GiB.
+ * Errors: RELOC_E_INVALID (null out), RELOC_E_DEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double valu_i32_ops, l2_gathers, mall_gathers, hbm_read, hbm_copy;
+  int32_t compute_units, clock_khz;
+} reloc_peaks;
+
+int32_t reloc_measure_peaks(int32_t device, reloc_peaks* out);
 
 /* ------------------------------------------------------------------------
  * Parity / inspection entry points (same kernels as reloc_run).

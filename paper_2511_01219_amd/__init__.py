@@ -117,6 +117,15 @@ def scan_info(ranges, angle_min, angle_increment, resolution, range_min=0.02,
     return d
 
 
+def measure_peaks(device: int = 0) -> Dict:
+    """Measured sustainable peaks of the device (reloc_measure_peaks): int32
+    VALU lane-ops/s, L2- and MALL-resident 4-byte gathers/s, HBM streaming
+    read and copy bytes/s."""
+    out = _abi.reloc_peaks()
+    _check(lib().reloc_measure_peaks(int(device), C.byref(out)))
+    return {f: getattr(out, f) for f, _ in out._fields_}
+
+
 class Context:
     """A reloc_ctx on one GPU, with torch's caching allocator and stream."""
 
@@ -283,13 +292,17 @@ class Context:
     def relocalize(self, map_id: int, set_id: int, ranges, angle_min: float,
                    angle_increment: float, range_min: float = 0.02, range_max: float = 30.0,
                    fov: Optional[Sequence] = None, cap: int = 64, **search):
-        """relocalize(scan, fov, beam angles) -> (ranked poses, stats)."""
-        rid = self.prepare(map_id, set_id, ranges, angle_min, angle_increment, range_min,
-                           range_max, fov, **search)
-        try:
-            return self.run(rid, cap)
-        finally:
-            self.release(rid)
+        """relocalize(scan, fov, beam angles) -> (ranked poses, stats): one
+        reloc_relocalize call (prepare + run + release in the library)."""
+        sc = _Scan(ranges, angle_min, angle_increment, range_min, range_max, fov)
+        p = search_params(**search)
+        out = (_abi.reloc_pose * max(1, cap))()
+        n = C.c_int32()
+        st = _abi.reloc_stats()
+        code = _check(self._lib.reloc_relocalize(self._h, int(map_id), int(set_id),
+                                                 C.byref(sc.s), C.byref(p), out, int(cap),
+                                                 C.byref(n), C.byref(st)))
+        return _poses(out, n.value), _stats(st, code)
 
     def coarse_scores(self, request_id: int, n_hyp: int):
         """Coarse metric of the n_hyp hypotheses of the request: (score FP64,
@@ -318,7 +331,9 @@ class Context:
 
     def autotune(self, request_id: int, reps: int = 3):
         """Picks the fastest ray-cast launch shape for the request; returns
-        (variant, rays per chunk, mean kernel ms)."""
+        (variant, shape, mean kernel ms): shape = wavefronts per hypothesis
+        workgroup for the fused kernel (the default path), else rays per
+        chunk of the split ray cast."""
         v, ch, ms = C.c_int32(), C.c_int32(), C.c_float()
         _check(self._lib.reloc_autotune(self._h, int(request_id), int(reps), C.byref(v),
                                         C.byref(ch), C.byref(ms)))
@@ -381,12 +396,17 @@ class Context:
         return {f: getattr(s, f) for f, _ in s._fields_}
 
     # -- parity / inspection ----------------------------------------------------
-    def debug_raycast(self, request_id: int, n_hyp: int, Ns: int, steps: bool = False):
-        hit = np.empty((n_hyp, Ns), dtype=np.int32)
-        rng = np.empty((n_hyp, Ns), dtype=np.float32)
-        stp = np.empty((n_hyp, Ns), dtype=np.int32) if steps else None
+    def debug_raycast(self, request_id: int, n_hyp: int, Ns: int, steps: bool = False,
+                      steps_only: bool = False):
+        """Hit cells and ranges of every ray (and, with steps, the traversal
+        iterations per ray); steps_only returns the iterations alone."""
+        hit = None if steps_only else np.empty((n_hyp, Ns), dtype=np.int32)
+        rng = None if steps_only else np.empty((n_hyp, Ns), dtype=np.float32)
+        stp = np.empty((n_hyp, Ns), dtype=np.int32) if (steps or steps_only) else None
         _check(self._lib.reloc_debug_raycast(self._h, int(request_id), _ptr(hit), _ptr(rng),
                                              _ptr(stp)))
+        if steps_only:
+            return stp
         return (hit, rng, stp) if steps else (hit, rng)
 
     def debug_smad(self, request_id: int, n_hyp: int):

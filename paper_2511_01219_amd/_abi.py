@@ -54,7 +54,8 @@ class reloc_search_params(C.Structure):
                 ("deadline_s", C.c_double), ("variant", C.c_int32),
                 ("refine_k", C.c_int32), ("refine_cells", C.c_int32),
                 ("refine_dirs", C.c_int32), ("coarse_metric", C.c_int32),
-                ("fine_metric", C.c_int32), ("use_graph", C.c_int32)]
+                ("fine_metric", C.c_int32), ("use_graph", C.c_int32),
+                ("ray_waves", C.c_int32), ("ray_refill", C.c_int32)]
 
 
 class reloc_scan_info(C.Structure):
@@ -104,6 +105,12 @@ class reloc_rrt_params(C.Structure):
 class reloc_rrt_info(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("attempts", C.c_int64), ("nodes", C.c_int64),
                 ("n_sampling", C.c_int64)]
+
+
+class reloc_peaks(C.Structure):
+    _fields_ = [("valu_i32_ops", C.c_double), ("l2_gathers", C.c_double),
+                ("mall_gathers", C.c_double), ("hbm_read", C.c_double), ("hbm_copy", C.c_double),
+                ("compute_units", C.c_int32), ("clock_khz", C.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -158,6 +165,7 @@ PROTOS = {
                                         C.c_void_p, C.c_void_p, C.POINTER(reloc_stats)]),
     "reloc_score_poses": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.POINTER(C.c_float)]),
+    "reloc_measure_peaks": (C.c_int32, [C.c_int32, C.POINTER(reloc_peaks)]),
     "reloc_debug_raycast": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "reloc_debug_smad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,

@@ -236,22 +236,8 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   if (n == 0) return RELOC_OK;
   auto A = std::make_shared<Arena>();
   A->c = c;
-  std::vector<int64_t> hpre(n + 1, 0), bpre(n + 1, 0), spre(n + 1, 0);
-  int max_ns = 1;
-  bool all_pano = true;
-  for (int i = 0; i < n; ++i) {
-    const Request& R = c->reqs.at(F[i]->rid);
-    hpre[i + 1] = hpre[i] + R.n_hyp;
-    max_ns = std::max(max_ns, R.prep.info.Ns);
-    all_pano &= R.prep.info.n_shifts == 1;
-  }
-  int wpb;
-  size_t smad_lds;
-  smad_layout(max_ns, all_pano, &wpb, &smad_lds);
-  for (int i = 0; i < n; ++i) {
-    const int nh = (int)(hpre[i + 1] - hpre[i]);
-    spre[i + 1] = spre[i] + (wpb ? (nh + wpb - 1) / wpb : nh);
-  }
+  std::vector<int64_t> hpre(n + 1, 0);
+  for (int i = 0; i < n; ++i) hpre[i + 1] = hpre[i] + c->reqs.at(F[i]->rid).n_hyp;
   const int64_t N = hpre[n];
   if (N > INT32_MAX) return fail(RELOC_E_INVALID, "batch holds more than 2^31 hypotheses");
   A->keys = A->get<uint64_t>(N);
@@ -273,39 +259,45 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
     if (!tmp) return RELOC_E_NOMEM;
   }
   if (!A->keys || !A->keys2 || !A->best || !A->vals || !A->order) return RELOC_E_NOMEM;
-  std::vector<RayArgs> ra(n);
+  // requests on the fused path share one launch (one workgroup per
+  // hypothesis); the others (ablation metrics, maps without walk words)
+  // cast into their range buffers and run their coarse kernel one by one
+  std::vector<RayArgs> ra(n), fra;
+  std::vector<int64_t> fpre(1, 0);
+  int max_ns = 0;                     // largest Ns of a non-panoramic fused request
   for (int i = 0; i < n; ++i) {
     Request& R = c->reqs.at(F[i]->rid);
     RayArgs a = ray_args(c, R, nullptr, nullptr);
     a.keys = A->keys + hpre[i];
     a.vals = A->vals + hpre[i];
-    a.best0 = A->best + hpre[i];      // the SMAD kernel clears the per-rank best
-    const int64_t rays = (int64_t)R.n_hyp * a.Ns;
-    const int64_t blocks = a.walk ? (rays + a.chunk - 1) / a.chunk : 0;
-    bpre[i + 1] = bpre[i] + blocks;
+    a.best0 = A->best + hpre[i];      // the coarse kernel clears the per-rank best
     ra[i] = a;
+    if (R.fused) {
+      fra.push_back(a);
+      fpre.push_back(fpre.back() + R.n_hyp);
+      if (a.n_shifts != 1) max_ns = std::max(max_ns, a.Ns);
+    }
   }
+  const int nf = (int)fra.size();
+  const int nw = fused_default_nw(fpre.back());
+  const size_t lds = max_ns ? fused_lds_bytes(max_ns, nw) : 0;
   Blob bl;
-  const size_t o_ra = bl.add(ra.data(), n);
-  const size_t o_bp = bl.add(bpre.data(), n + 1);
+  const size_t o_ra = bl.add(fra.data(), std::max(nf, 1));
+  const size_t o_fp = bl.add(fpre.data(), nf + 1);
   const size_t o_hp = bl.add(hpre.data(), n + 1);
-  const size_t o_sp = bl.add(spre.data(), n + 1);
   uint8_t* d = nullptr;
   if (int32_t e = commit(c, S, bl, &d)) return e;
   const RayArgs* d_ra = (const RayArgs*)(d + o_ra);
-  const int64_t* d_bp = (const int64_t*)(d + o_bp);
+  const int64_t* d_fp = (const int64_t*)(d + o_fp);
   const int64_t* d_hp = (const int64_t*)(d + o_hp);
-  const int64_t* d_sp = (const int64_t*)(d + o_sp);
   hipStream_t s = c->stream;
   HIP_TRY(hipEventRecord(c->ev[0], s));
+  if (nf > 0) HIP_TRY(launch_raycast_smad_fused_batch(d_ra, d_fp, nf, fpre.back(), nw, lds, s));
   for (int i = 0; i < n; ++i)
-    if (!ra[i].walk) HIP_TRY(launch_raycast(ra[i], s));   // maps without walk words
-  HIP_TRY(launch_raycast_batch(d_ra, d_bp, n, bpre[n], s));
+    if (!c->reqs.at(F[i]->rid).fused && ra[i].coarse != 3) HIP_TRY(launch_raycast(ra[i], s));
   HIP_TRY(hipEventRecord(c->ev[1], s));
-  HIP_TRY(launch_smad_batch(d_ra, d_sp, n, spre[n], wpb, smad_lds, s));
-  // requests with another coarse metric overwrite their keys (ablations)
   for (int i = 0; i < n; ++i)
-    if (ra[i].coarse != 0) HIP_TRY(launch_coarse(ra[i], s));
+    if (!c->reqs.at(F[i]->rid).fused) HIP_TRY(launch_coarse(ra[i], s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
   if (per_request) {
     for (int i = 0; i < n; ++i) {

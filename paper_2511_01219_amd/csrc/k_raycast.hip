@@ -1,11 +1,15 @@
 // Panoramic ray cast (eq. 13-14) and SMAD scoring (eq. 16-20).
 //
-// The ray cast writes one range per (hypothesis, direction) to a range
-// buffer; the SMAD kernel (one workgroup per positional hypothesis) loads a
-// hypothesis' Ns ranges into LDS, forms the cyclic prefix sums of eq. 17 in
-// FP64 (every partial sum is an exact multiple of 2^-29 below 2^18 for
-// ranges in [2^-6, 2^6) m, so the summation order cannot change a bit),
-// scores every circular shift with eq. 18-19 and reduces to the eq. 20
+// Default path: one fused kernel casts the Ns rays of a hypothesis with one
+// workgroup, keeps the ranges on chip and forms the hypothesis' SMAD there;
+// no range reaches memory. The split path (the bit-tile variant for maps
+// without walk words, explicit variants, and the ablation coarse metrics
+// that read every range) writes one range per (hypothesis, direction) to a
+// range buffer, and a SMAD kernel loads a hypothesis' Ns ranges into LDS.
+// Either way the cyclic prefix sums of eq. 17 are FP64 sums whose every
+// partial value is an exact multiple of 2^-29 below 2^18 (ranges lie in
+// [2^-6, 2^6) m), so the summation order cannot change a bit; every
+// circular shift is scored with eq. 18-19 and reduced to the eq. 20
 // minimum.
 //
 // Traversal. The ray leaves the centre of cell (ix0, iy0), X = 256 ix0 + 128
@@ -29,9 +33,10 @@
 //    touched cell's centre is within 0.7072 of the segment, the segment starts
 //    within 0.7072 of this centre). The traversal jumps over such free space
 //    and recomputes the exact crossing state at the landing point, so hits,
-//    ranges and tie rules are those of the step-by-step traversal. The rays
-//    of all hypotheses form one index space split into chunks, one
-//    single-wavefront workgroup per chunk, with lanes refilled as rays end.
+//    ranges and tie rules are those of the step-by-step traversal. Lanes
+//    are refilled with the next rays as rays end (the fused kernel: the
+//    rays of one hypothesis per workgroup; the split kernel: the rays of
+//    all hypotheses as one index space cut into single-wavefront chunks).
 #include <climits>
 #include <cmath>
 
@@ -380,17 +385,6 @@ __device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_
   return lo;
 }
 
-// Ray casts of several requests in one launch: request r owns the blocks
-// [prefix[r], prefix[r + 1]), each one chunk of that request's rays.
-template <int REFILL>
-__global__ __launch_bounds__(64) void raycast_skip_batch_kernel(const RayArgs* __restrict__ reqs,
-                                                                const int64_t* __restrict__ prefix,
-                                                                int n) {
-  const int t = xcd_slice(blockIdx.x, gridDim.x);
-  const int r = find_segment(prefix, n, t);
-  raycast_skip_run<REFILL>(reqs[r], (int)(t - prefix[r]));
-}
-
 // Bit-tile ray cast: one workgroup per hypothesis, rays from a shared counter.
 __global__ __launch_bounds__(RT) void raycast_bits_kernel(RayArgs a) {
   __shared__ int next_ray;
@@ -411,6 +405,273 @@ __global__ __launch_bounds__(RT) void raycast_bits_kernel(RayArgs a) {
     if (a.dbg_hit) a.dbg_hit[o] = hit;
     if (a.dbg_steps) a.dbg_steps[o] = steps;
   }
+}
+
+// ------------------------------------------- fused ray cast + SMAD (default)
+// One workgroup of NW wavefronts per hypothesis: its Ns rays come from a
+// counter shared by the wavefronts (lanes are refilled once REFILL of a
+// wavefront's lanes are idle), the ranges stay on chip, and the same
+// workgroup then forms SMAD (eq. 16-20), so no range ever goes to memory.
+//
+//  * Panoramic scans (one shift, eq. 20): a lane adds each of its finished
+//    rays that lies in the FoV to an FP64 accumulator; the workgroup sum of
+//    the accumulators is the interval sum of m = 0.
+//  * Otherwise the ranges go to LDS (Z[Ns], FP32). Each thread sums one
+//    contiguous block of Z, an exclusive scan of the block sums gives
+//    prefix values Pb, so S(x) = sum of Z[0, x) = Pb[x / cb] plus at most
+//    cb - 1 terms. Each thread scores a contiguous range of shifts: the
+//    first from S (eq. 17-18), each next one (shift stride 1) by adding the
+//    range that enters each FoV run and subtracting the one that leaves.
+// Every partial sum is a multiple of 2^-29 below 2^18 (see the file
+// header), so every FP64 addition and subtraction here is exact and the
+// result equals the prefix-sum form bit for bit, whatever the order.
+__device__ __forceinline__ bool in_fov(const RayArgs& a, int j) {
+  for (int r = 0; r < a.n_runs; ++r) {
+    const int2 rr = a.runs[r];
+    int d = j - rr.x;
+    if (d < 0) d += a.Ns;
+    if (d < rr.y) return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void smad_store(const RayArgs& a, int h, double v, int m) {
+  a.smad[h] = v;
+  a.argm[h] = m;
+  a.keys[h] = (uint64_t)__double_as_longlong(v);
+  a.vals[h] = h;
+  if (a.best0) a.best0[h] = 0;
+}
+
+template <int NW, int REFILL, bool PANO>
+__device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint8_t* dyn) {
+  constexpr int NT = NW * 64;
+  __shared__ int s_next;
+  __shared__ double s_wsum[NW];
+  __shared__ double s_bv[NW];
+  __shared__ int s_bm[NW];
+  __shared__ uint32_t s_fov[4096 / 32];   // panoramic: FoV membership bit per direction
+  float* Z = (float*)dyn;
+  double* Pb = (double*)(dyn + (((size_t)a.Ns * 4 + 7) & ~(size_t)7));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int Ns = a.Ns, W = a.W, H = a.H;
+  const int h = a.perm ? a.perm[pos] : pos;
+  const int ix0 = a.hyp_xy[2 * h], iy0 = a.hyp_xy[2 * h + 1];
+  const int off0 = (int)__umul24(iy0, W) + ix0;
+  const WalkMap sm = make_walkmap(a);
+  const uint32_t plane_bytes = a.walk_bytes >> 2;
+  // panoramic scans: whether each direction lies in the FoV, taken when a
+  // ray starts (a full turn needs no test); the bits are built once per
+  // workgroup so the loop never waits on the FoV table
+  const bool all_in = a.nfov == Ns;
+  if constexpr (PANO) {
+    if (!all_in) {
+      for (int wd = tid; wd < (Ns + 31) / 32; wd += NT) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; ++b)
+          if (wd * 32 + b < Ns && in_fov(a, wd * 32 + b)) bits |= 1u << b;
+        s_fov[wd] = bits;
+      }
+      if constexpr (NW == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  if constexpr (NW > 1) {
+    if (tid == 0) s_next = NT;
+    __syncthreads();
+  }
+  int nxt = NT;            // NW == 1: the wavefront's own (uniform) counter
+  int q = tid;             // direction of the lane's ray
+  bool busy = q < Ns;
+  bool dry = NT >= Ns;
+  double acc = 0.0;        // panoramic: FoV sum of the lane's finished rays
+  bool fov = true;         // panoramic: the lane's ray lies in the FoV
+  auto fov_of = [&](int j) { return all_in || ((s_fov[j >> 5] >> (j & 31)) & 1u) != 0; };
+  SkipRay r;
+  if (busy) {
+    skip_init(r, a.dir_i[q], a.dir_f[q], ix0, iy0, W, H, a.rcells, plane_bytes, sm);
+    if constexpr (PANO) fov = fov_of(q);
+  }
+  for (;;) {
+    if (busy) {
+      float z;
+      int hit;
+      if (skip_iter(r, sm, off0, &z, &hit)) {
+        if (z > a.rmax) {
+          z = 0.f;
+          hit = -1;
+        }
+        if constexpr (PANO) {
+          acc += fov ? (double)z : 0.0;
+        } else {
+          Z[q] = z;
+        }
+        const size_t o = (size_t)h * Ns + q;
+        if (a.zbuf) a.zbuf[o] = z;
+        if (a.dbg_hit) a.dbg_hit[o] = hit;
+        if (a.dbg_steps) a.dbg_steps[o] = r.it;
+        busy = false;
+      }
+    }
+    const unsigned long long idle = __ballot(!busy);
+    const int cnt = __popcll(idle);
+    if (dry && cnt == 64) break;
+    if (!dry && cnt >= REFILL) {
+      int base;
+      if constexpr (NW == 1) {
+        base = nxt;
+        nxt += cnt;
+      } else {
+        int b = 0;
+        if (lane == 0) b = atomicAdd(&s_next, cnt);
+        base = __builtin_amdgcn_readfirstlane(b);
+      }
+      dry = base + cnt >= Ns;
+      const int qn = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+      if (!busy && qn < Ns) {
+        q = qn;
+        skip_init(r, a.dir_i[q], a.dir_f[q], ix0, iy0, W, H, a.rcells, plane_bytes, sm);
+        if constexpr (PANO) fov = fov_of(q);
+        busy = true;
+      }
+    }
+  }
+
+  if constexpr (PANO) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if constexpr (NW > 1) {
+      if (lane == 0) s_wsum[wv] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        acc = 0.0;
+        for (int w = 0; w < NW; ++w) acc += s_wsum[w];
+      }
+    }
+    if (tid == 0) smad_store(a, h, fabs(a.zbar - acc / (double)a.nfov), 0);
+    return;
+  }
+
+  // every range of the hypothesis is in Z
+  if constexpr (NW > 1) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  const int cb = (Ns + NT - 1) / NT;
+  const int b0 = min(Ns, tid * cb), b1 = min(Ns, b0 + cb);
+  double local = 0.0;
+  for (int i = b0; i < b1; ++i) local += (double)Z[i];
+  double incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const double v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  double excl = incl - local, total;
+  if constexpr (NW > 1) {
+    if (lane == 63) s_wsum[wv] = incl;
+    __syncthreads();
+    total = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      if (w < wv) excl += s_wsum[w];
+      total += s_wsum[w];
+    }
+  } else {
+    total = __shfl(incl, 63, 64);
+  }
+  Pb[tid] = excl;
+  if constexpr (NW > 1) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  // S(x) = sum of Z[0, x) for 0 <= x < Ns; C(x) the cyclic form for x < 3 Ns
+  auto S = [&](int x) -> double {
+    const int b = x / cb;
+    double s = Pb[b];
+    for (int i = b * cb; i < x; ++i) s += (double)Z[i];
+    return s;
+  };
+  auto C = [&](int x) -> double {
+    const int qq = x >= 2 * Ns ? 2 : (x >= Ns ? 1 : 0);
+    return (double)qq * total + S(x - qq * Ns);
+  };
+  auto wrap = [&](int x) { return x >= 2 * Ns ? x - 2 * Ns : (x >= Ns ? x - Ns : x); };
+  const int nsh = a.n_shifts, ne = a.n_enum;
+  const int cs = (nsh + NT - 1) / NT;
+  const int s0 = tid * cs, s1 = min(nsh, s0 + cs);
+  double bv = INFINITY;
+  int bm = INT_MAX;
+  double tot = 0.0;
+  for (int sh = s0; sh < s1; ++sh) {
+    const int m = sh * ne;
+    if (sh == s0 || ne != 1) {
+      tot = 0.0;
+      for (int rr = 0; rr < a.n_runs; ++rr) {
+        const int2 ru = a.runs[rr];
+        tot += C(ru.x + m + ru.y) - C(ru.x + m);
+      }
+    } else {
+      // shift m - 1 -> m: each run gains Z[u + m - 1 + L] and loses Z[u + m - 1]
+      for (int rr = 0; rr < a.n_runs; ++rr) {
+        const int2 ru = a.runs[rr];
+        tot += (double)Z[wrap(ru.x + m - 1 + ru.y)] - (double)Z[wrap(ru.x + m - 1)];
+      }
+    }
+    const double v = fabs(a.zbar - tot / (double)a.nfov);
+    if (v < bv) {
+      bv = v;
+      bm = m;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int om = __shfl_xor(bm, off, 64);
+    if (ov < bv || (ov == bv && om < bm)) {
+      bv = ov;
+      bm = om;
+    }
+  }
+  if constexpr (NW > 1) {
+    if (lane == 0) {
+      s_bv[wv] = bv;
+      s_bm[wv] = bm;
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int w = 1; w < NW; ++w)
+        if (s_bv[w] < bv || (s_bv[w] == bv && s_bm[w] < bm)) {
+          bv = s_bv[w];
+          bm = s_bm[w];
+        }
+  }
+  if (tid == 0) smad_store(a, h, bv, bm);
+}
+
+template <int NW, int REFILL, bool PANO>
+__global__ __launch_bounds__(NW * 64) void raycast_smad_kernel(RayArgs a) {
+  extern __shared__ __align__(8) uint8_t fused_dyn[];
+  raycast_smad_run<NW, REFILL, PANO>(a, xcd_slice(blockIdx.x, gridDim.x), fused_dyn);
+}
+
+// Several requests, one workgroup per hypothesis: request r owns workgroups
+// [prefix[r], prefix[r + 1]) (its hypotheses in casting order).
+template <int NW, int REFILL>
+__global__ __launch_bounds__(NW * 64) void raycast_smad_batch_kernel(
+    const RayArgs* __restrict__ reqs, const int64_t* __restrict__ prefix, int n) {
+  extern __shared__ __align__(8) uint8_t fused_dyn[];
+  const int t = xcd_slice(blockIdx.x, gridDim.x);
+  const int r = find_segment(prefix, n, t);
+  const RayArgs& a = reqs[r];
+  const int pos = (int)(t - prefix[r]);
+  if (a.n_shifts == 1)                         // workgroup-uniform
+    raycast_smad_run<NW, REFILL, true>(a, pos, fused_dyn);
+  else
+    raycast_smad_run<NW, REFILL, false>(a, pos, fused_dyn);
 }
 
 // ------------------------------------------------------------------- SMAD
@@ -610,16 +871,6 @@ __global__ __launch_bounds__(RT) void smad_kernel(RayArgs a, int wpb) {
   smad_dispatch(a, blockIdx.x, wpb, S);
 }
 
-// SMAD of several requests: request r owns blocks [prefix[r], prefix[r + 1]),
-// wpb hypotheses each.
-__global__ __launch_bounds__(RT) void smad_batch_kernel(const RayArgs* __restrict__ reqs,
-                                                        const int64_t* __restrict__ prefix, int n,
-                                                        int wpb) {
-  extern __shared__ double S[];
-  const int r = find_segment(prefix, n, blockIdx.x);
-  smad_dispatch(reqs[r], (int)(blockIdx.x - prefix[r]), wpb, S);
-}
-
 // ------------------------------------------------- direct coarse metrics
 // SMAD by direct sums (eq. 16-20 without the prefix sums of eq. 17-18) or
 // CAER (eq. 21) of hypothesis blockIdx.x by one workgroup. The synthetic
@@ -796,19 +1047,54 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
-                                int64_t blocks, hipStream_t s) {
-  if (n <= 0 || blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(raycast_skip_batch_kernel<16>, dim3((unsigned)blocks), dim3(64), 0, s, reqs,
-                     prefix, n);
+namespace {
+template <int NW, bool PANO>
+hipError_t launch_fused_nw(const RayArgs& a, int refill, size_t lds, hipStream_t s) {
+  const dim3 g((unsigned)a.n_hyp), w(NW * 64);
+  switch (refill) {
+    case 8: hipLaunchKernelGGL((raycast_smad_kernel<NW, 8, PANO>), g, w, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((raycast_smad_kernel<NW, 32, PANO>), g, w, lds, s, a); break;
+    default: hipLaunchKernelGGL((raycast_smad_kernel<NW, 16, PANO>), g, w, lds, s, a); break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
-                             int wpb, size_t lds, hipStream_t s) {
+template <bool PANO>
+hipError_t launch_fused_pano(const RayArgs& a, int nw, int refill, hipStream_t s) {
+  const size_t lds = PANO ? 0 : fused_lds_bytes(a.Ns, nw);
+  switch (nw) {
+    case 1: return launch_fused_nw<1, PANO>(a, refill, lds, s);
+    case 2: return launch_fused_nw<2, PANO>(a, refill, lds, s);
+    default: return launch_fused_nw<4, PANO>(a, refill, lds, s);
+  }
+}
+}  // namespace
+
+hipError_t launch_raycast_smad_fused(const RayArgs& a, int nw, int refill, hipStream_t s) {
+  if (a.n_hyp <= 0) return hipSuccess;
+  if (!a.walk || (nw != 1 && nw != 2 && nw != 4) || (refill != 8 && refill != 16 && refill != 32))
+    return hipErrorInvalidValue;
+  return a.n_shifts == 1 ? launch_fused_pano<true>(a, nw, refill, s)
+                         : launch_fused_pano<false>(a, nw, refill, s);
+}
+
+hipError_t launch_raycast_smad_fused_batch(const RayArgs* reqs, const int64_t* prefix, int n,
+                                           int64_t blocks, int nw, size_t lds, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(smad_batch_kernel, dim3((unsigned)blocks), dim3(RT), lds, s, reqs, prefix, n,
-                     wpb);
+  const dim3 g((unsigned)blocks);
+  switch (nw) {
+    case 1:
+      hipLaunchKernelGGL((raycast_smad_batch_kernel<1, 16>), g, dim3(64), lds, s, reqs, prefix, n);
+      break;
+    case 2:
+      hipLaunchKernelGGL((raycast_smad_batch_kernel<2, 16>), g, dim3(128), lds, s, reqs, prefix, n);
+      break;
+    case 4:
+      hipLaunchKernelGGL((raycast_smad_batch_kernel<4, 16>), g, dim3(256), lds, s, reqs, prefix, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -833,14 +1119,6 @@ hipError_t launch_coarse(const RayArgs& a, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s) {
-  if (a.coarse != 3) {
-    const hipError_t e = launch_raycast(a, s);
-    if (e != hipSuccess) return e;
-  }
-  return launch_coarse(a, s);
 }
 
 // Walk words from the squared EDT. The radius byte is 1 + s with

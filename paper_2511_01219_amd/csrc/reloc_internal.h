@@ -62,20 +62,22 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s);      // zbuf -> smad, a
 // The coarse metric a.coarse (prefix-sum SMAD, direct-sum SMAD, CAER or
 // none) into smad, argm, keys, vals (and best0 cleared); none needs no ranges.
 hipError_t launch_coarse(const RayArgs& a, hipStream_t s);
-hipError_t launch_raycast_smad(const RayArgs& a, hipStream_t s);
-// Several requests in one launch each. reqs: device RayArgs[n]; prefix:
-// device int64[n + 1] block offsets (ray cast: chunks of a.chunk rays with the
-// walk-word traversal, refill at 16 idle lanes; SMAD: wpb hypotheses per
-// block, or one when wpb == 0). Every request of a ray-cast batch needs walk
-// words.
-// SMAD kernel layout for scans of up to max_ns beams: wpb hypotheses per
-// 256-thread workgroup (one wavefront each), or 0 for one workgroup per
-// hypothesis; lds = dynamic LDS bytes.
-void smad_layout(int max_ns, bool all_pano, int* wpb, size_t* lds);
-hipError_t launch_raycast_batch(const RayArgs* reqs, const int64_t* prefix, int n,
-                                int64_t blocks, hipStream_t s);
-hipError_t launch_smad_batch(const RayArgs* reqs, const int64_t* prefix, int n, int64_t blocks,
-                             int wpb, size_t lds, hipStream_t s);
+// Fused ray cast + SMAD (coarse metric 0, maps with walk words): one
+// workgroup of nw wavefronts (1, 2 or 4) per hypothesis casts its Ns rays
+// (lanes refilled once `refill` of a wavefront's lanes, 8, 16 or 32, are
+// idle) and forms its SMAD on chip: smad, argm, keys, vals (and best0
+// cleared); zbuf / dbg_hit / dbg_steps are written only when non-null.
+// Dynamic LDS of a non-panoramic scan: Z[Ns] FP32 (padded to 8 bytes) and
+// nw * 64 FP64 block prefixes; a panoramic scan needs none.
+__host__ __device__ inline size_t fused_lds_bytes(int Ns, int nw) {
+  return (((size_t)Ns * 4 + 7) & ~(size_t)7) + (size_t)nw * 64 * 8;
+}
+hipError_t launch_raycast_smad_fused(const RayArgs& a, int nw, int refill, hipStream_t s);
+// Several requests: request r owns workgroups [prefix[r], prefix[r + 1]),
+// one per hypothesis, refill 16; lds = fused_lds_bytes of the largest Ns
+// among the non-panoramic requests (0 when all are panoramic).
+hipError_t launch_raycast_smad_fused_batch(const RayArgs* reqs, const int64_t* prefix, int n,
+                                           int64_t blocks, int nw, size_t lds, hipStream_t s);
 // Walk words from the squared EDT: four row-major planes, one per major
 // direction of travel (+x, -x, +y, -y). A word is 0 for an occupied cell,
 // else s | run << 8 with s = 1 + free-space radius byte and run = free

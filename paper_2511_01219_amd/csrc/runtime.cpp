@@ -465,7 +465,10 @@ int32_t build_request(reloc_ctx* c, Request& R) {
     R.fov_j = (int32_t*)(tables + o_fj);
   }
   R.perm = perm.empty() ? hs.morton_dev : (int32_t*)(tables + o_perm);
-  R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns);
+  // the range buffer only for the split ray cast (the fused kernel keeps
+  // every range on chip)
+  const bool split = !fused_path(c, R);
+  if (split && !(R.zbuf = req_alloc<float>(c, R, (size_t)n * Ns))) return RELOC_E_NOMEM;
   R.smad = req_alloc<double>(c, R, n);
   R.argm = req_alloc<int32_t>(c, R, n);
   R.keys = req_alloc<uint64_t>(c, R, n);
@@ -473,18 +476,20 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.vals = req_alloc<int32_t>(c, R, n);
   R.order = req_alloc<int32_t>(c, R, n);
   R.best = req_alloc<uint64_t>(c, R, n);
+  if (!R.smad || !R.argm || !R.keys || !R.keys2 || !R.vals || !R.order || !R.best)
+    return RELOC_E_NOMEM;
   const int max_stages = (n + R.prm.batch_k - 1) / R.prm.batch_k;
   if (R.prm.refine_k > 0) {
     // slots for one launch of the plain path or one tick of the batched one
     R.ref_slots = std::max(plain_max_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k;
     R.rsel = req_alloc<int32_t>(c, R, R.ref_slots);
     R.rbest = req_alloc<uint64_t>(c, R, R.ref_slots);
+    if (!R.rsel || !R.rbest) return RELOC_E_NOMEM;
   }
   R.stage = req_alloc<uint64_t>(c, R, max_stages);
   R.rows_cap = std::max(1, std::min(n, R.prm.k_out));
   R.rows = req_alloc<PoseRow>(c, R, R.rows_cap);
-  for (void* p : R.owned)
-    if (!p) return RELOC_E_NOMEM;
+  if (!R.stage || !R.rows) return RELOC_E_NOMEM;
   size_t t1 = 0, t2 = 0;
   HIP_TRY(sort_pairs_u64_i32(nullptr, &t1, R.keys, R.keys2, R.vals, R.order, n, c->stream));
   HIP_TRY(sort_keys_u64(nullptr, &t2, R.keys, R.keys2, n, c->stream));
@@ -493,6 +498,37 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   if (!R.tmp) return RELOC_E_NOMEM;
   if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  return RELOC_OK;
+}
+
+bool fused_path(const reloc_ctx*, const Request& R) { return R.fused; }
+
+// Wavefronts per hypothesis workgroup of the fused kernel. Few hypotheses
+// cannot fill the device with one wavefront each, so a hypothesis' rays are
+// spread over four (256 lanes); many hypotheses are best served by one
+// wavefront each (no workgroup barrier, the tail of one hypothesis' rays
+// overlaps other wavefronts' work). Measured on MI355X: 300 hypotheses
+// 0.038 / 0.050 / 0.075 ms for 4 / 2 / 1; 20 000: 0.68 / 0.63 / 0.63 ms;
+// 200 000: 8.5 / 7.9 / 7.6 ms.
+int fused_default_nw(int64_t n_hyp) { return n_hyp < 4096 ? 4 : (n_hyp < 32768 ? 2 : 1); }
+
+void fused_shape(const Request& R, int* nw, int* refill) {
+  *nw = R.fuse_nw > 0 ? R.fuse_nw : fused_default_nw(R.n_hyp);
+  *refill = R.fuse_refill > 0 ? R.fuse_refill : 16;
+}
+
+int32_t enqueue_front(reloc_ctx* c, Request& R, const RayArgs& ra, hipEvent_t mid) {
+  hipStream_t s = c->stream;
+  if (fused_path(c, R)) {
+    int nw, rf;
+    fused_shape(R, &nw, &rf);
+    HIP_TRY(launch_raycast_smad_fused(ra, nw, rf, s));
+    if (mid) HIP_TRY(hipEventRecord(mid, s));
+    return RELOC_OK;
+  }
+  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));   // none needs no ranges
+  if (mid) HIP_TRY(hipEventRecord(mid, s));
+  HIP_TRY(launch_coarse(ra, s));
   return RELOC_OK;
 }
 
@@ -623,7 +659,7 @@ int32_t smad_order(reloc_ctx* c, Request& R) {
 
 // ray cast + SMAD for all hypotheses, then the stable SMAD order
 int32_t run_smad_order(reloc_ctx* c, Request& R) {
-  HIP_TRY(launch_raycast_smad(ray_args(c, R, nullptr, nullptr), c->stream));
+  if (int32_t e = enqueue_front(c, R, ray_args(c, R, nullptr, nullptr), nullptr)) return e;
   return smad_order(c, R);
 }
 
@@ -727,9 +763,7 @@ int32_t enqueue_head(reloc_ctx* c, Request& R, int ns0, int nb0, int32_t* hflag,
   RayArgs ra = ray_args(c, R, nullptr, nullptr);
   ra.best0 = R.best;                 // the coarse kernel clears the per-rank best
   HIP_TRY(mark(0));
-  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));   // none needs no ranges
-  HIP_TRY(mark(5));
-  HIP_TRY(launch_coarse(ra, s));
+  if (int32_t e = enqueue_front(c, R, ra, timed ? c->ev[5] : nullptr)) return e;
   HIP_TRY(mark(1));
   if (int32_t e = smad_order(c, R)) return e;
   HIP_TRY(mark(2));
@@ -778,6 +812,10 @@ int32_t validate_search(const reloc_search_params* p) {
     return fail(RELOC_E_INVALID, "coarse_metric must be in 0..3");
   if (p->fine_metric < 0 || p->fine_metric > 3)
     return fail(RELOC_E_INVALID, "fine_metric must be in 0..3");
+  if (p->ray_waves != 0 && p->ray_waves != 1 && p->ray_waves != 2 && p->ray_waves != 4)
+    return fail(RELOC_E_INVALID, "ray_waves must be 0, 1, 2 or 4");
+  if (p->ray_refill != 0 && p->ray_refill != 8 && p->ray_refill != 16 && p->ray_refill != 32)
+    return fail(RELOC_E_INVALID, "ray_refill must be 0, 8, 16 or 32");
   return RELOC_OK;
 }
 
@@ -821,6 +859,15 @@ int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
   if (int32_t e = build_lut(params, mi->second.res, &R->lut)) return e;
   R->rmax = scan->range_max;
   R->rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
+  R->fused = params->coarse_metric == 0 && params->variant == 0 && mi->second.walk != nullptr;
+  // a map's tuned fused shape carries over to its later requests of the
+  // same beam grid (a tuning done once per map)
+  if (R->fused && mi->second.fuse_ns == R->prep.info.Ns) {
+    R->fuse_nw = mi->second.fuse_nw;
+    R->fuse_refill = mi->second.fuse_refill;
+  }
+  if (params->ray_waves > 0) R->fuse_nw = params->ray_waves;
+  if (params->ray_refill > 0) R->fuse_refill = params->ray_refill;
   if (params->refine_k > 0)
     if (int32_t e = refine_lattice(params, R->prep.info, &R->ref_h, &R->ref_s, &R->ref_L))
       return e;
@@ -831,7 +878,8 @@ size_t request_bytes(const Request& R) {
   const reloc_scan_info& I = R.prep.info;
   const size_t n = (size_t)std::max(1, R.n_hyp), Ns = (size_t)I.Ns;
   const size_t stages = (n + (size_t)R.prm.batch_k - 1) / (size_t)R.prm.batch_k;
-  size_t b = n * (4 * Ns + 8 + 4 + 8 + 8 + 4 + 4 + 8);        // ranges, work buffers
+  size_t b = n * (8 + 4 + 8 + 8 + 4 + 4 + 8);                  // work buffers
+  if (!R.fused) b += n * 4 * Ns;                                // range buffer
   b += Ns * (8 + 8 + 16 + 16) + (size_t)I.Ng * 8 + R.prep.runs.size() * 8;
   b += R.prep.vj.size() * 8 + R.lut.q.size() * 4 + stages * 12;
   b += (size_t)std::min<size_t>(n, (size_t)R.prm.k_out) * sizeof(PoseRow);
@@ -919,6 +967,8 @@ void reloc_search_defaults(reloc_search_params* p) {
   p->coarse_metric = 0;
   p->fine_metric = 0;
   p->use_graph = 0;
+  p->ray_waves = 0;
+  p->ray_refill = 0;
 }
 
 int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* stream,
@@ -1395,6 +1445,46 @@ int32_t reloc_autotune(reloc_ctx* c, int32_t request_id, int32_t reps, int32_t* 
   hipStream_t s = c->stream;
   float best_ms = -1.f;
   int best_v = R.prm.variant, best_c = R.tuned_chunk;
+  auto time_launch = [&](auto launch, float* ms) -> int32_t {
+    HIP_TRY(launch());   // warm-up
+    HIP_TRY(hipEventRecord(c->ev[0], s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(launch());
+    HIP_TRY(hipEventRecord(c->ev[5], s));
+    HIP_TRY(hipEventSynchronize(c->ev[5]));
+    HIP_TRY(hipEventElapsedTime(ms, c->ev[0], c->ev[5]));
+    *ms /= (float)reps;
+    return RELOC_OK;
+  };
+  if (R.fused) {
+    // fused kernel: wavefronts per hypothesis workgroup x lane-refill
+    // threshold; every shape gives bit-identical SMAD values
+    static const int nws[3] = {1, 2, 4};
+    static const int refills[3] = {8, 16, 32};
+    const RayArgs a = ray_args(c, R, nullptr, nullptr);
+    int bnw = 0, brf = 0;
+    for (int nw : nws)
+      for (int rf : refills) {
+        float ms = 0.f;
+        if (int32_t e = time_launch([&] { return launch_raycast_smad_fused(a, nw, rf, s); }, &ms))
+          return e;
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          bnw = nw;
+          brf = rf;
+        }
+      }
+    R.fuse_nw = bnw;
+    R.fuse_refill = brf;
+    DevMap& m = c->maps.at(R.map_id);
+    m.fuse_ns = R.prep.info.Ns;
+    m.fuse_nw = bnw;
+    m.fuse_refill = brf;
+    drop_head(R);
+    if (variant_out) *variant_out = brf == 8 ? 3 : (brf == 16 ? 4 : 5);
+    if (chunk_out) *chunk_out = bnw;
+    if (ms_out) *ms_out = best_ms;
+    return RELOC_OK;
+  }
   if (c->maps.at(R.map_id).walk) {
     // lane-refill threshold (public variants 3, 4, 5: 8, 16, 32 idle lanes)
     // x rays per chunk; every shape gives bit-identical ranges
@@ -1405,14 +1495,8 @@ int32_t reloc_autotune(reloc_ctx* c, int32_t request_id, int32_t reps, int32_t* 
         R.prm.variant = v;
         R.tuned_chunk = ch;
         const RayArgs a = ray_args(c, R, nullptr, nullptr);
-        HIP_TRY(launch_raycast(a, s));   // warm-up
-        HIP_TRY(hipEventRecord(c->ev[0], s));
-        for (int r = 0; r < reps; ++r) HIP_TRY(launch_raycast(a, s));
-        HIP_TRY(hipEventRecord(c->ev[5], s));
-        HIP_TRY(hipEventSynchronize(c->ev[5]));
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[5]));
-        ms /= (float)reps;
+        if (int32_t e = time_launch([&] { return launch_raycast(a, s); }, &ms)) return e;
         if (best_ms < 0.f || ms < best_ms) {
           best_ms = ms;
           best_v = v;
@@ -1438,23 +1522,34 @@ int32_t reloc_debug_raycast(reloc_ctx* c, int32_t request_id, int32_t* hit_cell,
   if (int32_t e = set_device(c)) return e;
   Request& R = it->second;
   const size_t n = (size_t)R.n_hyp * R.prep.info.Ns;
-  int32_t* dh = (int32_t*)c->dalloc(n * sizeof(int32_t));
+  // the fused kernel writes ranges only into a buffer it is given
+  const bool fz = R.fused;
+  int32_t* dh = hit_cell ? (int32_t*)c->dalloc(n * sizeof(int32_t)) : nullptr;
   int32_t* ds = steps ? (int32_t*)c->dalloc(n * sizeof(int32_t)) : nullptr;
-  if (!dh || (steps && !ds)) {
+  float* dz = fz && range ? (float*)c->dalloc(n * sizeof(float)) : nullptr;
+  if ((hit_cell && !dh) || (steps && !ds) || (fz && range && !dz)) {
     c->dfree(dh);
     c->dfree(ds);
+    c->dfree(dz);
     return RELOC_E_NOMEM;
   }
-  hipError_t e = launch_raycast_smad(ray_args(c, R, dh, ds), c->stream);
+  RayArgs ra = ray_args(c, R, dh, ds);
+  if (fz) ra.zbuf = dz;
+  const int32_t ef = enqueue_front(c, R, ra, nullptr);
+  hipError_t e = ef == RELOC_OK ? hipSuccess : hipErrorLaunchFailure;
   if (e == hipSuccess && hit_cell)
     e = hipMemcpyAsync(hit_cell, dh, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && range)
-    e = hipMemcpyAsync(range, R.zbuf, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(range, fz ? dz : R.zbuf, n * sizeof(float), hipMemcpyDeviceToHost,
+                       c->stream);
   if (e == hipSuccess && steps)
     e = hipMemcpyAsync(steps, ds, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  const hipError_t es = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = es;
   c->dfree(dh);
   c->dfree(ds);
+  c->dfree(dz);
+  if (ef != RELOC_OK) return ef;
   if (e != hipSuccess) return fail(RELOC_E_DEVICE, "debug ray cast failed: %s", hipGetErrorString(e));
   return RELOC_OK;
 }
@@ -1474,9 +1569,7 @@ int32_t reloc_coarse_scores(reloc_ctx* c, int32_t request_id, int32_t cap, doubl
   hipStream_t s = c->stream;
   const RayArgs ra = ray_args(c, R, nullptr, nullptr);
   HIP_TRY(hipEventRecord(c->ev[0], s));
-  if (R.prm.coarse_metric != 3) HIP_TRY(launch_raycast(ra, s));
-  HIP_TRY(hipEventRecord(c->ev[1], s));
-  HIP_TRY(launch_coarse(ra, s));
+  if (int32_t e = enqueue_front(c, R, ra, c->ev[1])) return e;
   HIP_TRY(hipEventRecord(c->ev[2], s));
   if (int32_t e = smad_order(c, R)) return e;
   HIP_TRY(hipEventRecord(c->ev[3], s));

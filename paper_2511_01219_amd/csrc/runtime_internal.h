@@ -75,6 +75,9 @@ using reloc::PoseRow;
 using reloc::Prep;
 
 struct DevMap {
+  // fused ray-cast shape last chosen by reloc_autotune for requests of this
+  // map with fuse_ns directions (0: none); later requests start from it
+  int fuse_ns = 0, fuse_nw = 0, fuse_refill = 0;
   int W = 0, H = 0, thr = 65, tpr = 0, tph = 0;
   double res = 0.05, ox = 0, oy = 0;
   uint64_t* bits = nullptr;
@@ -103,6 +106,10 @@ struct Request {
   float rmax = 0.f;
   int rcells = 0;
   int tuned_chunk = 0;            // rays per ray-cast chunk chosen by reloc_autotune (0: rule)
+  // fused ray cast + SMAD: wavefronts per hypothesis workgroup and lane
+  // refill threshold chosen by reloc_autotune (0: the default rule)
+  int fuse_nw = 0, fuse_refill = 0;
+  bool fused = false;             // set by init_request: see fused_path
   Lut lut;
   // device tables
   int2* raydirs = nullptr;
@@ -264,6 +271,17 @@ int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
                      const reloc_search_params* params, Request* R);
 int32_t build_request(reloc_ctx* c, Request& R);
 RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps);
+// Whether the request's ray cast and SMAD run as the fused kernel (coarse
+// metric 0, default variant, a map with walk words): no range buffer then.
+bool fused_path(const reloc_ctx* c, const Request& R);
+// Workgroup shape of the fused kernel for R: tuned, else the default rule.
+void fused_shape(const Request& R, int* nw, int* refill);
+int fused_default_nw(int64_t n_hyp);
+// Ray cast and coarse metric of every hypothesis of R (smad, argm, keys,
+// vals; ra.best0 cleared when set): the fused kernel, or the ray cast into
+// the range buffer and the coarse kernel. `mid`, when not null, is recorded
+// between the two launches (after the fused kernel).
+int32_t enqueue_front(reloc_ctx* c, Request& R, const RayArgs& ra, hipEvent_t mid);
 TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out);
 RefineArgs refine_args(reloc_ctx* c, Request& R, int n_slots);
 // Stages per TAM launch of the plain path (several when a stage alone

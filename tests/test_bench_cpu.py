@@ -60,3 +60,21 @@ def test_traffic_summary_is_current():
     # scaled fetch + write add up to the reported total
     assert abs(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
                - got) <= 2.0
+
+
+def test_counter_summary_is_current():
+    """The executed-instruction summary the roofline divides by its live
+    launch time belongs to the committed ray-cast sources, its per-launch
+    figures are the medians of its per-dispatch rows, and the executed VALU
+    fraction it records is at most 1."""
+    import statistics
+    cnt = bench.measured_counters()
+    assert cnt is not None, "ray-cast sources changed since the counters were taken"
+    kv = {}
+    for line in open(os.path.join(ROOT, bench.COUNTERS_FILE)):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    per = [float(x) for x in kv["valu_insts_per_dispatch"].split(",")]
+    assert cnt["valu_insts_per_launch"] == statistics.median(per)
+    assert 0.0 < float(kv["executed_valu_frac_of_measured_peak"]) <= 1.0

@@ -42,7 +42,7 @@ def test_struct_layouts_match_c(tmp_path):
     structs = ["reloc_allocator", "reloc_map_desc", "reloc_sample_params",
                "reloc_interval", "reloc_scan", "reloc_search_params", "reloc_scan_info",
                "reloc_pose", "reloc_stats", "reloc_serve_config", "reloc_serve_stats",
-               "reloc_rrt_params", "reloc_rrt_info"]
+               "reloc_rrt_params", "reloc_rrt_info", "reloc_peaks"]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "reloc.h"',
              'int main(void) {']
     for st in structs:
