@@ -396,6 +396,25 @@ int32_t reloc_relocalize(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
                          const reloc_scan* scan, const reloc_search_params* params,
                          reloc_pose* out, int32_t cap, int32_t* n_out, reloc_stats* stats);
 
+/* reloc_relocalize for callers that cannot allocate device memory: code
+ * under HIP stream capture, tight serving loops, hosts that forbid
+ * allocation once running. It calls no hipMalloc, hipFree, hipHostMalloc,
+ * hipHostFree or allocator hook: every device buffer of the request comes
+ * from one 64 MiB scratch region that the library holds on each GPU it runs
+ * on until the process ends (set up when a context is created on the
+ * device); the host-side scan preprocessing uses ordinary host memory.
+ * Arguments and results are those of reloc_relocalize, bit for bit. A
+ * request whose device buffers exceed the region (about 60 bytes per
+ * hypothesis plus the scan's tables; the ablation coarse metrics add a
+ * 4 Ns-byte range buffer per hypothesis) fails with RELOC_E_NOMEM before any
+ * device work. All calls on one GPU share its region: calls on one context
+ * are serialized, calls that overlap on one GPU from different contexts
+ * race. The head graph (use_graph) is not used. */
+int32_t reloc_relocalize_noalloc(reloc_ctx* ctx, int32_t map_id, int32_t set_id,
+                                 const reloc_scan* scan, const reloc_search_params* params,
+                                 reloc_pose* out, int32_t cap, int32_t* n_out,
+                                 reloc_stats* stats);
+
 /* ------------------------------------------------------------------------
  * Dense sweeps (Sec. IV Case 1: Fig. 7's SMAD map over positions, Fig. 8's
  * metrics over a translation x rotation lattice).

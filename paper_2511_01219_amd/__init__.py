@@ -304,6 +304,22 @@ class Context:
                                                  C.byref(n), C.byref(st)))
         return _poses(out, n.value), _stats(st, code)
 
+    def relocalize_noalloc(self, map_id: int, set_id: int, ranges, angle_min: float,
+                           angle_increment: float, range_min: float = 0.02,
+                           range_max: float = 30.0, fov: Optional[Sequence] = None,
+                           cap: int = 64, **search):
+        """relocalize through reloc_relocalize_noalloc: no device allocation,
+        the library's per-GPU scratch region instead."""
+        sc = _Scan(ranges, angle_min, angle_increment, range_min, range_max, fov)
+        p = search_params(**search)
+        out = (_abi.reloc_pose * max(1, cap))()
+        n = C.c_int32()
+        st = _abi.reloc_stats()
+        code = _check(self._lib.reloc_relocalize_noalloc(self._h, int(map_id), int(set_id),
+                                                         C.byref(sc.s), C.byref(p), out,
+                                                         int(cap), C.byref(n), C.byref(st)))
+        return _poses(out, n.value), _stats(st, code)
+
     def coarse_scores(self, request_id: int, n_hyp: int):
         """Coarse metric of the n_hyp hypotheses of the request: (score FP64,
         argmin shift, stable order, stats)."""

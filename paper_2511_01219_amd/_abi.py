@@ -150,6 +150,11 @@ PROTOS = {
                                      C.POINTER(reloc_search_params), C.POINTER(reloc_pose),
                                      C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(reloc_stats)]),
+    "reloc_relocalize_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32,
+                                             C.POINTER(reloc_scan),
+                                             C.POINTER(reloc_search_params),
+                                             C.POINTER(reloc_pose), C.c_int32,
+                                             C.POINTER(C.c_int32), C.POINTER(reloc_stats)]),
     "reloc_run_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(reloc_pose),
                                     C.c_int32, C.c_void_p, C.c_void_p,
                                     C.POINTER(reloc_stats)]),

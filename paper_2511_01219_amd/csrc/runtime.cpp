@@ -684,8 +684,8 @@ int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* ho
     HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
     HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, ndev, R.rows, s));
   }
-  if (nrow > 0)
-    HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
+  if (nrow > 0)   // pinned host rows, or device rows on the no-allocation path
+    HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDefault, s));
   *top = R.rows;
   return RELOC_OK;
 }
@@ -1000,6 +1000,7 @@ int32_t reloc_ctx_create(int32_t device, const reloc_allocator* alloc, void* str
   for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
   c->serve = serve_create();
   HIP_TRY(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
+  if (int32_t e = noalloc_setup(device)) return e;
   *out = c.release();
   return RELOC_OK;
 }
@@ -1260,7 +1261,15 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   auto it = c->reqs.find(request_id);
   if (it == c->reqs.end()) return fail(RELOC_E_NOTFOUND, "unknown request %d", request_id);
   if (int32_t e = set_device(c)) return e;
-  Request& R = it->second;
+  return run_request(c, it->second, out, cap, n_out, st, nullptr);
+}
+
+}  // extern "C"
+
+namespace reloc {
+
+int32_t run_request(reloc_ctx* c, Request& R, reloc_pose* out, int32_t cap, int32_t* n_out,
+                    reloc_stats* st, PoseRow* dev_rows) {
   const reloc_scan_info& I = R.prep.info;
   const DevMap& m = c->maps[R.map_id];
   const auto t_start = std::chrono::steady_clock::now();
@@ -1270,8 +1279,9 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   int32_t status = RELOC_OK;
   int32_t* hflag = (int32_t*)c->pinned;
   const int ncap = std::min(R.rows_cap, std::max(0, cap));
-  PoseRow* hrows = nullptr;
-  if (int32_t e = pinned_rows(c, (size_t)R.rows_cap, &hrows)) return e;
+  PoseRow* hrows = dev_rows;
+  if (!hrows)
+    if (int32_t e = pinned_rows(c, (size_t)R.rows_cap, &hrows)) return e;
   bool ranked = false;   // rows of the final n_eval already on the host
   int nrow = 0;
   // the first launch holds enough stages for a quarter of the device, the
@@ -1294,7 +1304,7 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     const int nb0 = std::min(ns0 * K, R.n_hyp);
     // captured on the request's second run (a one-shot relocalization would
     // pay the capture and gain nothing)
-    const bool graph = R.prm.use_graph && s != nullptr && R.n_hyp <= kSmallSortMax &&
+    const bool graph = R.prm.use_graph && !dev_rows && s != nullptr && R.n_hyp <= kSmallSortMax &&
                        (ns0 != 1 || nb0 <= kRankSmallMax) && (R.head || R.runs_done >= 1);
     if (graph && !R.head) {
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1378,9 +1388,15 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
     if (int32_t e = enqueue_margin(c, R, R.best, R.order, top, n_eval, R.stage, stages,
                                    hmarg))
       return e;
+  std::vector<PoseRow> copied;
+  if (dev_rows && nrow > 0) {
+    copied.resize(nrow);
+    HIP_TRY(hipMemcpyAsync(copied.data(), dev_rows, nrow * sizeof(PoseRow), hipMemcpyDeviceToHost,
+                           s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   ++R.runs_done;
-  rows_to_poses(c, R, hrows, nrow, out);
+  rows_to_poses(c, R, dev_rows ? copied.data() : hrows, nrow, out);
   *n_out = nrow;
   if (st) {
     std::memset(st, 0, sizeof *st);
@@ -1417,6 +1433,10 @@ int32_t reloc_run(reloc_ctx* c, int32_t request_id, reloc_pose* out, int32_t cap
   }
   return status;
 }
+
+}  // namespace reloc
+
+extern "C" {
 
 int32_t reloc_relocalize(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
                          const reloc_search_params* params, reloc_pose* out, int32_t cap,

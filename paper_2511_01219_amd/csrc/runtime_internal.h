@@ -145,6 +145,10 @@ struct Request {
   hipGraphExec_t head = nullptr;  // captured head of reloc_run, or null
   int runs_done = 0;              // completed runs (the head is captured on the second)
   std::vector<void*> owned;
+  // when set, req_alloc carves the request's device buffers out of this
+  // region (256-byte aligned) instead of allocating them; nothing is owned
+  uint8_t* carve_base = nullptr;
+  size_t carve_cap = 0, carve_used = 0;
 };
 
 struct reloc_ctx {
@@ -270,6 +274,15 @@ int32_t refine_lattice(const reloc_search_params* p, const reloc_scan_info& I, i
 int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
                      const reloc_search_params* params, Request* R);
 int32_t build_request(reloc_ctx* c, Request& R);
+// The whole device path of a built request (reloc_run's body). dev_rows:
+// null to stage result rows in the context's pinned buffer, else device
+// memory of at least R.rows_cap rows that receives them (copied to the host
+// before returning); no head graph then.
+int32_t run_request(reloc_ctx* c, Request& R, reloc_pose* out, int32_t cap, int32_t* n_out,
+                    reloc_stats* st, PoseRow* dev_rows);
+// Per-device scratch of the no-allocation entry point (noalloc.hip): looks
+// up the address of the device's copy once, with the device current.
+int32_t noalloc_setup(int device);
 RayArgs ray_args(reloc_ctx* c, Request& R, int32_t* dbg_hit, int32_t* dbg_steps);
 // Whether the request's ray cast and SMAD run as the fused kernel (coarse
 // metric 0, default variant, a map with walk words): no range buffer then.
@@ -321,6 +334,18 @@ bool serve_holds_set(reloc_ctx* c, int32_t set_id);
 
 template <typename T>
 T* req_alloc(reloc_ctx* c, Request& r, size_t count) {
+  if (r.carve_base) {
+    const size_t off = (r.carve_used + 255) & ~(size_t)255;
+    const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    if (off > r.carve_cap || bytes > r.carve_cap - off) {
+      fail(RELOC_E_NOMEM, "the request needs more than the %zu-byte no-allocation scratch "
+                          "(about %zu bytes by the admission estimate)",
+           r.carve_cap, request_bytes(r));
+      return nullptr;
+    }
+    r.carve_used = off + bytes;
+    return (T*)(r.carve_base + off);
+  }
   void* p = c->dalloc(count * sizeof(T));
   if (p) r.owned.push_back(p);
   return (T*)p;
