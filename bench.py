@@ -39,7 +39,7 @@ OPS_PER_ITER = 50
 COARSE = {"smad": 0, "smad-direct": 1, "caer": 2, "none": 3}
 FINE = {"tam": 0, "tam-mean": 1, "baseline": 2, "lf": 3}
 RAYCAST_SOURCES = ("paper_2511_01219_amd/csrc/k_raycast.hip",
-                   "paper_2511_01219_amd/csrc/reloc_internal.h")
+                   "paper_2511_01219_amd/csrc/raycast.h")
 # counter summaries of the dominant kernel on the default workload
 TRAFFIC_FILE = "profiles/raycast_smad_kernel_stress_traffic.txt"
 COUNTERS_FILE = "profiles/raycast_smad_kernel_stress_counters.txt"

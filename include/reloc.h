@@ -294,9 +294,10 @@ typedef struct {
    * cast, coarse metric, order, first TAM launch with refinement and stage
    * control, first ranking) kernel by kernel (0, the default), or replays
    * it as a HIP graph captured on the request's second run (1). Graphs are
-   * used when the order and the first ranking run in the library's own
-   * kernels (n_hyp <= 65536, first ranking <= 2048 ranks) and the context's
-   * stream is not the null stream; results are identical either way. A
+   * used when a first launch of one stage ranks at most 2048 poses (its
+   * ranking is then one kernel writing the rows to pinned memory) and the
+   * context's stream is not the null stream; results are identical either
+   * way. A
    * replayed run times only ms_total (hipEvents around the graph launch and
    * the later launches); its per-phase times read 0. The graph saves a few
    * microseconds of launch overhead per run (about 3 % on a 300-hypothesis

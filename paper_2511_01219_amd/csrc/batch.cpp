@@ -113,13 +113,13 @@ struct ServeState {
   // ranking scratch, grown on demand and kept between calls
   uint64_t* rk1 = nullptr;
   uint64_t* rk2 = nullptr;
+  int32_t* rp1 = nullptr;          // positions of the ranking sort
+  int32_t* rp2 = nullptr;
   size_t rk_cap = 0;
   PoseRow* rrows = nullptr;
   size_t rrows_cap = 0;
   uint64_t* rmarg = nullptr;
   size_t rmarg_cap = 0;
-  uint8_t* rtmp = nullptr;
-  size_t rtmp_cap = 0;
   // per-tick stage outputs
   // per-tick stage outputs, written by the stage kernel straight into
   // pinned host memory
@@ -245,20 +245,15 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   A->best = A->get<uint64_t>(N);
   A->vals = A->get<int32_t>(N);
   A->order = A->get<int32_t>(N);
-  // a small group of sets within the small-sort limit is ordered by one
-  // two-kernel sort per request (the plain path's) rather than by the
-  // multi-pass segmented radix sort; both are stable, so the orders agree
-  bool per_request = n <= kSmallSortGroup;
-  for (int i = 0; i < n && per_request; ++i) per_request = hpre[i + 1] - hpre[i] <= kSmallSortMax;
-  size_t tb = 0;
-  void* tmp = nullptr;
-  if (!per_request) {
-    HIP_TRY(seg_sort_pairs_u64_i32(nullptr, &tb, A->keys, A->keys2, A->vals, A->order, N, n,
-                                   nullptr, c->stream));
-    tmp = A->get<uint8_t>(tb);
-    if (!tmp) return RELOC_E_NOMEM;
-  }
   if (!A->keys || !A->keys2 || !A->best || !A->vals || !A->order) return RELOC_E_NOMEM;
+  // every request's SMAD order in one segmented sort (tiles of 1024 keys
+  // per request, then the merge levels of the largest request)
+  std::vector<int64_t> tpre(n + 1, 0);
+  int64_t max_n = 0;
+  for (int i = 0; i < n; ++i) {
+    tpre[i + 1] = tpre[i] + argsort_tiles(hpre[i + 1] - hpre[i]);
+    max_n = std::max(max_n, hpre[i + 1] - hpre[i]);
+  }
   // requests on the fused path share one launch (one workgroup per
   // hypothesis); the others (ablation metrics, maps without walk words)
   // cast into their range buffers and run their coarse kernel one by one
@@ -285,11 +280,13 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   const size_t o_ra = bl.add(fra.data(), std::max(nf, 1));
   const size_t o_fp = bl.add(fpre.data(), nf + 1);
   const size_t o_hp = bl.add(hpre.data(), n + 1);
+  const size_t o_tp = bl.add(tpre.data(), n + 1);
   uint8_t* d = nullptr;
   if (int32_t e = commit(c, S, bl, &d)) return e;
   const RayArgs* d_ra = (const RayArgs*)(d + o_ra);
   const int64_t* d_fp = (const int64_t*)(d + o_fp);
   const int64_t* d_hp = (const int64_t*)(d + o_hp);
+  const int64_t* d_tp = (const int64_t*)(d + o_tp);
   hipStream_t s = c->stream;
   HIP_TRY(hipEventRecord(c->ev[0], s));
   if (nf > 0) HIP_TRY(launch_raycast_smad_fused_batch(d_ra, d_fp, nf, fpre.back(), nw, lds, s));
@@ -299,17 +296,8 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   for (int i = 0; i < n; ++i)
     if (!c->reqs.at(F[i]->rid).fused) HIP_TRY(launch_coarse(ra[i], s));
   HIP_TRY(hipEventRecord(c->ev[2], s));
-  if (per_request) {
-    for (int i = 0; i < n; ++i) {
-      const int64_t o = hpre[i];
-      // keys2 and vals serve as the tile-sort scratch
-      HIP_TRY(small_sort_pairs_u64(A->keys + o, A->keys2 + o, A->vals + o, nullptr, A->order + o,
-                                   (int)(hpre[i + 1] - o), s));
-    }
-  } else {
-    HIP_TRY(seg_sort_pairs_u64_i32(tmp, &tb, A->keys, A->keys2, A->vals, A->order, N, n, d_hp,
-                                   s));
-  }
+  // keys2 and vals serve as the sort's scratch
+  HIP_TRY(argsort_u64(A->keys, A->keys2, A->vals, A->order, N, n, d_hp, d_tp, tpre[n], max_n, s));
   HIP_TRY(hipEventRecord(c->ev[3], s));
   if (pt) {
     pt->raycast += elapsed(c->ev[0], c->ev[1]);
@@ -504,31 +492,36 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   uint64_t* dmarg = S.rmarg;
   uint64_t* k1 = nullptr;
   uint64_t* k2 = nullptr;
-  size_t tb = 0;
-  void* tmp = nullptr;
+  std::vector<int64_t> tpre(n + 1, 0);
+  int64_t max_n = 0;
   if (!per_request) {
-    // both key buffers share one capacity
-    if (!S.rk1 || !S.rk2 || (size_t)NK > S.rk_cap) {
-      size_t c1 = S.rk_cap, c2 = S.rk_cap;
+    // both key buffers and both position buffers share one capacity
+    if (!S.rk1 || !S.rk2 || !S.rp1 || !S.rp2 || (size_t)NK > S.rk_cap) {
+      size_t c1 = S.rk_cap, c2 = S.rk_cap, c3 = S.rk_cap, c4 = S.rk_cap;
       if (int32_t e = grow_scratch(c, S.rk1, c1, (size_t)NK)) return e;
       if (int32_t e = grow_scratch(c, S.rk2, c2, c1)) return e;
-      S.rk_cap = std::min(c1, c2);
+      if (int32_t e = grow_scratch(c, S.rp1, c3, c1)) return e;
+      if (int32_t e = grow_scratch(c, S.rp2, c4, c1)) return e;
+      S.rk_cap = std::min(std::min(c1, c2), std::min(c3, c4));
     }
     k1 = S.rk1;
     k2 = S.rk2;
-    HIP_TRY(seg_sort_keys_u64(nullptr, &tb, k1, k2, NK, n, nullptr, c->stream));
-    if (int32_t e = grow_scratch(c, S.rtmp, S.rtmp_cap, tb)) return e;
-    tmp = S.rtmp;
+    for (int i = 0; i < n; ++i) {
+      tpre[i + 1] = tpre[i] + argsort_tiles(F[i]->n_eval);
+      max_n = std::max<int64_t>(max_n, F[i]->n_eval);
+    }
   }
   Blob bl;
   const size_t o_ra = bl.add(ra.data(), n);
   const size_t o_kp = bl.add(kpre.data(), n + 1);
   const size_t o_rp = bl.add(rpre.data(), n + 1);
+  const size_t o_tp = bl.add(tpre.data(), n + 1);
   uint8_t* d = nullptr;
   if (int32_t e = commit(c, S, bl, &d)) return e;
   const RankArgs* d_ra = (const RankArgs*)(d + o_ra);
   const int64_t* d_kp = (const int64_t*)(d + o_kp);
   const int64_t* d_rp = (const int64_t*)(d + o_rp);
+  const int64_t* d_tp = (const int64_t*)(d + o_tp);
   hipStream_t s = c->stream;
   std::vector<PoseRow> host(NR);
   HIP_TRY(hipEventRecord(c->ev[4], s));
@@ -541,8 +534,9 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
     }
   } else {
     HIP_TRY(launch_rank_keys_batch(d_ra, d_kp, n, NK, k1, s));
-    HIP_TRY(seg_sort_keys_u64(tmp, &tb, k1, k2, NK, n, d_kp, s));
-    HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k2, dr, s));
+    // the sorted keys end in k1
+    HIP_TRY(argsort_u64(k1, k2, S.rp2, S.rp1, NK, n, d_kp, d_tp, tpre[n], max_n, s));
+    HIP_TRY(launch_rank_gather_batch(d_ra, d_rp, d_kp, n, NR, k1, dr, s));
   }
   if (NR > 0)
     HIP_TRY(hipMemcpyAsync(host.data(), dr, NR * sizeof(PoseRow), hipMemcpyDeviceToHost, s));
@@ -784,7 +778,8 @@ void ctx_stop_serving(reloc_ctx* c) {
   c->dfree(S->rk2);
   c->dfree(S->rrows);
   c->dfree(S->rmarg);
-  c->dfree(S->rtmp);
+  c->dfree(S->rp1);
+  c->dfree(S->rp2);
   if (S->hflag) (void)hipHostFree(S->hflag);
   if (S->hstage) (void)hipHostFree(S->hstage);
   {

@@ -1,12 +1,24 @@
-// Stable sorts for the SMAD order (ascending (SMAD, index)) and for the
-// final ranking of evaluated poses: hipCUB / rocPRIM device radix sorts, and
-// for up to kSmallSortMax keys a two-kernel sort: every 1024-key tile is
-// sorted in LDS by a stable block radix sort, then every key finds its final
-// position as its position in its tile plus, for every other tile, the
-// number of keys there that precede it (binary searches, one thread per
-// key and tile; keys of earlier tiles that are equal precede it, since
-// indices grow with the tile).
-#include <hipcub/hipcub.hpp>
+// Stable orders of 64-bit keys: the SMAD order (ascending (SMAD, index),
+// Sec. III pipeline) and the final ranking of evaluated poses (ascending
+// ((~T bits) << 32 | rank), eq. 8-9), for one request or for the segments
+// of several requests at once.
+//
+// The order of a segment is an argsort of (key, position) pairs, which are
+// all distinct, so any correct sort of the pairs is the stable order of the
+// keys:
+//  1. every 1024-key tile of a segment is sorted in LDS by a bitonic network
+//     over (key, position) (one workgroup per tile, in place);
+//  2. merge levels: sorted runs of length L are merged G at a time into runs
+//     of length G L (G <= 64). A key's place in the merged run is its place
+//     in its own run plus, for every other run of its group, the number of
+//     keys there that precede it: keys of an earlier run that are equal
+//     precede it (smaller positions), those of a later run do not. The
+//     counts come from binary searches, one thread per (key, run) pair, and
+//     meet in LDS.
+// Runs of 1024, 65 536 and 4 194 304 keys: a 200 000-key segment takes the
+// tile sort and two merge levels. No kernel waits on another workgroup.
+#include <climits>
+#include <vector>
 
 #include "reloc_internal.h"
 
@@ -14,75 +26,130 @@ namespace reloc {
 
 namespace {
 
-constexpr int kTileThreads = 256, kTileItems = 4, kTile = kTileThreads * kTileItems;
+constexpr int kTileThreads = 256, kTile = 1024;
 
-// Stable sort of each tile of (key, index) pairs; indices are positions in
-// the input. Padding keys (~0) sort last and are not stored.
-__global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(const uint64_t* __restrict__ kin,
-                                                                 int n, uint64_t* __restrict__ kout,
-                                                                 int32_t* __restrict__ vout) {
-  using BRS = hipcub::BlockRadixSort<uint64_t, kTileThreads, kTileItems, int32_t>;
-  __shared__ typename BRS::TempStorage tmp;
-  const int base = blockIdx.x * kTile;
-  uint64_t k[kTileItems];
-  int32_t v[kTileItems];
-#pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    const int idx = base + threadIdx.x * kTileItems + i;
-    k[i] = idx < n ? kin[idx] : ~0ull;
-    v[i] = idx;
+// Index of the segment holding item t: prefix[s] <= t < prefix[s + 1].
+__device__ __forceinline__ int find_seg(const int64_t* prefix, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
   }
-  BRS(tmp).Sort(k, v);
+  return lo;
+}
+
+// Segment bounds of a launch: one segment [0, n) when off is null.
+struct Segs {
+  const int64_t* off;    // [nseg + 1] key offsets, or null
+  const int64_t* tpre;   // [nseg + 1] tile prefix (tiles of 1024 keys per segment), or null
+  int nseg;
+  int64_t n;             // total keys
+};
+
+__device__ __forceinline__ bool pair_less(uint64_t ka, int32_t pa, uint64_t kb, int32_t pb) {
+  return ka < kb || (ka == kb && pa < pb);
+}
+
+// Bitonic sort of one tile of (key, position) pairs: kin[base + t0 + i]
+// for i < cnt, sorted into kout / pos at the same places (kout may be kin:
+// the tile is read whole before it is written); positions are positions in
+// the segment. Padding pairs (~0, INT_MAX) sort last and are not stored.
+__global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(const uint64_t* kin, Segs sg,
+                                                                 uint64_t* kout,
+                                                                 int32_t* __restrict__ pos) {
+  __shared__ uint64_t sk[kTile];
+  __shared__ int32_t sp[kTile];
+  int64_t base = 0, n_s = sg.n, t = blockIdx.x;
+  if (sg.off) {
+    const int s = find_seg(sg.tpre, sg.nseg, t);
+    t -= sg.tpre[s];
+    base = sg.off[s];
+    n_s = sg.off[s + 1] - base;
+  }
+  const int64_t t0 = t * kTile;
+  const int cnt = (int)min((int64_t)kTile, n_s - t0);
+  for (int i = threadIdx.x; i < kTile; i += kTileThreads) {
+    const bool in = i < cnt;
+    sk[i] = in ? kin[base + t0 + i] : ~0ull;
+    sp[i] = in ? (int32_t)(t0 + i) : INT_MAX;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kTile; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    const int idx = base + threadIdx.x * kTileItems + i;
-    if (idx < n) {
-      kout[idx] = k[i];
-      vout[idx] = v[i];
+      for (int r = 0; r < kTile / 2 / kTileThreads; ++r) {
+        const int q = threadIdx.x + r * kTileThreads;   // pair index
+        const int i = 2 * j * (q / j) + (q % j), l = i + j;
+        const bool asc = (i & k) == 0;
+        const uint64_t ki = sk[i], kl = sk[l];
+        const int32_t pi = sp[i], pl = sp[l];
+        const bool swap = asc ? pair_less(kl, pl, ki, pi) : pair_less(ki, pi, kl, pl);
+        if (swap) {
+          sk[i] = kl;
+          sk[l] = ki;
+          sp[i] = pl;
+          sp[l] = pi;
+        }
+      }
+      __syncthreads();
     }
+  }
+  for (int i = threadIdx.x; i < cnt; i += kTileThreads) {
+    kout[base + t0 + i] = sk[i];
+    pos[base + t0 + i] = sp[i];
   }
 }
 
 // number of keys in a[0, len) that are < x (strict) or <= x
-__device__ __forceinline__ int count_before(const uint64_t* a, int len, uint64_t x, bool le) {
-  int lo = 0, hi = len;
+__device__ __forceinline__ int64_t count_before(const uint64_t* a, int64_t len, uint64_t x,
+                                                bool le) {
+  int64_t lo = 0, hi = len;
   while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
+    const int64_t mid = (lo + hi) >> 1;
     const uint64_t v = a[mid];
     if (v < x || (le && v == x)) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
 
-// Every key's final position: its position in its tile plus, for every
-// other tile, the number of keys there that precede it. One thread per
-// (key, tile) pair, so a key's binary searches run side by side rather than
-// one after another; the counts meet in LDS. nt <= 64 tiles (n <= 65 536),
-// 256 / nt keys per workgroup.
-__global__ __launch_bounds__(256) void merge_rank_kernel(const uint64_t* __restrict__ kt,
-                                                         const int32_t* __restrict__ vt, int n,
-                                                         int nt, uint64_t* __restrict__ kout,
-                                                         int32_t* __restrict__ vout) {
-  __shared__ int acc[256];
+// One merge level: runs of L keys of every segment merged G at a time.
+// Workgroup: 256 / G keys, one thread per (key, run of its group).
+__global__ __launch_bounds__(256) void merge_level_kernel(const uint64_t* __restrict__ kin,
+                                                          const int32_t* __restrict__ pin,
+                                                          Segs sg, int64_t L, int G,
+                                                          uint64_t* __restrict__ kout,
+                                                          int32_t* __restrict__ pout) {
+  __shared__ int64_t acc[256];
   const int tid = threadIdx.x;
-  const int E = 256 / nt;                      // keys of this workgroup
-  const int e = tid / nt, u = tid - e * nt;    // key e, tile u
-  const int g = blockIdx.x * E + e;
+  const int E = 256 / G;
+  const int e = tid / G, u = tid - e * G;
+  const int64_t g = (int64_t)blockIdx.x * E + e;
   if (tid < E) acc[tid] = 0;
   __syncthreads();
-  if (e < E && g < n) {
-    const int t = g / kTile;
-    const int cnt = u == t ? g - t * kTile
-                           : count_before(kt + (size_t)u * kTile, min(kTile, n - u * kTile),
-                                          kt[g], u < t);
-    atomicAdd(&acc[e], cnt);
+  if (e < E && g < sg.n) {
+    int64_t base = 0, n_s = sg.n;
+    if (sg.off) {
+      const int s = find_seg(sg.off, sg.nseg, g);
+      base = sg.off[s];
+      n_s = sg.off[s + 1] - base;
+    }
+    const int64_t i = g - base, r = i / L, r0 = r / G * G, ru = r0 + u;
+    if (ru * L < n_s) {
+      const int64_t c = ru == r ? i - r * L
+                                : count_before(kin + base + ru * L, min(L, n_s - ru * L), kin[g],
+                                               ru < r);
+      atomicAdd((unsigned long long*)&acc[e], (unsigned long long)c);
+    }
   }
   __syncthreads();
-  const int gg = blockIdx.x * E + tid;
-  if (tid < E && gg < n) {
-    const int rank = acc[tid];
-    if (kout) kout[rank] = kt[gg];
-    vout[rank] = vt[gg];
+  const int64_t gg = (int64_t)blockIdx.x * E + tid;
+  if (tid < E && gg < sg.n) {
+    int64_t base = 0;
+    if (sg.off) base = sg.off[find_seg(sg.off, sg.nseg, gg)];
+    const int64_t r0 = (gg - base) / L / G * G;
+    const int64_t d = base + r0 * L + acc[tid];
+    kout[d] = kin[gg];
+    pout[d] = pin[gg];
   }
 }
 
@@ -115,7 +182,59 @@ __global__ __launch_bounds__(1024) void rank_small_kernel(const uint64_t* __rest
   }
 }
 
+// Group size of a level: runs of L keys of the largest segment, merged at
+// most 64 at a time (a power of two, so 256 / G keys fill a workgroup).
+int level_group(int64_t max_n, int64_t L) {
+  const int64_t runs = (max_n + L - 1) / L;
+  int G = 2;
+  while (G < 64 && G < runs) G <<= 1;
+  return G;
+}
+
 }  // namespace
+
+int argsort_levels(int64_t max_n) {
+  int m = 0;
+  for (int64_t L = kTile; L < max_n; L *= level_group(max_n, L)) ++m;
+  return m;
+}
+
+hipError_t argsort_u64(uint64_t* keys, uint64_t* tmp_k, int32_t* tmp_p, int32_t* pos,
+                       int64_t n, int nseg, const int64_t* off, const int64_t* tpre,
+                       int64_t tiles, int64_t max_n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nseg < 1 || (nseg > 1 && (!off || !tpre))) return hipErrorInvalidValue;
+  Segs sg{nseg > 1 ? off : nullptr, nseg > 1 ? tpre : nullptr, nseg, n};
+  if (nseg == 1) {
+    tiles = (n + kTile - 1) / kTile;
+    max_n = n;
+  }
+  const int m = argsort_levels(max_n);
+  // the levels alternate between (tmp_k, tmp_p) and (keys, pos) and must
+  // end in (keys, pos): the tile sort (in place) writes the buffer pair the
+  // parity of the level count calls for
+  uint64_t* ka = (m % 2 == 0) ? keys : tmp_k;
+  int32_t* pa = (m % 2 == 0) ? pos : tmp_p;
+  hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles), dim3(kTileThreads), 0, s, keys, sg,
+                     ka, pa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint64_t* kb = ka == keys ? tmp_k : keys;
+  int32_t* pb = pa == pos ? tmp_p : pos;
+  for (int64_t L = kTile; L < max_n;) {
+    const int G = level_group(max_n, L);
+    const int E = 256 / G;
+    hipLaunchKernelGGL(merge_level_kernel, dim3((unsigned)((n + E - 1) / E)), dim3(256), 0, s,
+                       ka, pa, sg, L, G, kb, pb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(ka, kb);
+    std::swap(pa, pb);
+    L *= G;
+  }
+  return hipSuccess;
+}
+
+int64_t argsort_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
 hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
                              const double* smad, int nrow, PoseRow* rows, hipStream_t s) {
@@ -124,46 +243,6 @@ hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
   hipLaunchKernelGGL(rank_small_kernel, dim3(1), dim3(threads), 0, s, best, n, order, smad, nrow,
                      rows);
   return hipGetLastError();
-}
-
-hipError_t small_sort_pairs_u64(const uint64_t* kin, uint64_t* ktmp, int32_t* vtmp,
-                                uint64_t* kout, int32_t* vout, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (n > kSmallSortMax) return hipErrorInvalidValue;
-  const int nt = (n + kTile - 1) / kTile;
-  hipLaunchKernelGGL(tile_sort_kernel, dim3(nt), dim3(kTileThreads), 0, s, kin, n, ktmp, vtmp);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int per = 256 / nt;                    // nt <= 64 for n <= kSmallSortMax
-  hipLaunchKernelGGL(merge_rank_kernel, dim3((n + per - 1) / per), dim3(256), 0, s, ktmp, vtmp,
-                     n, nt, kout, vout);
-  return hipGetLastError();
-}
-
-hipError_t sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
-                              uint64_t* kout, const int32_t* vin, int32_t* vout, int n,
-                              hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kin, kout, vin, vout, n, 0, 64,
-                                            s);
-}
-
-hipError_t sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
-                         int n, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortKeys(tmp, *tmp_bytes, kin, kout, n, 0, 64, s);
-}
-
-hipError_t seg_sort_pairs_u64_i32(void* tmp, size_t* tmp_bytes, const uint64_t* kin,
-                                  uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t n,
-                                  int nseg, const int64_t* offsets, hipStream_t s) {
-  return hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, *tmp_bytes, kin, kout, vin, vout,
-                                                     (int)n, nseg, offsets, offsets + 1, 0, 64,
-                                                     s);
-}
-
-hipError_t seg_sort_keys_u64(void* tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout,
-                             int64_t n, int nseg, const int64_t* offsets, hipStream_t s) {
-  return hipcub::DeviceSegmentedRadixSort::SortKeys(tmp, *tmp_bytes, kin, kout, (int)n, nseg,
-                                                    offsets, offsets + 1, 0, 64, s);
 }
 
 }  // namespace reloc

@@ -490,12 +490,10 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.rows_cap = std::max(1, std::min(n, R.prm.k_out));
   R.rows = req_alloc<PoseRow>(c, R, R.rows_cap);
   if (!R.stage || !R.rows) return RELOC_E_NOMEM;
-  size_t t1 = 0, t2 = 0;
-  HIP_TRY(sort_pairs_u64_i32(nullptr, &t1, R.keys, R.keys2, R.vals, R.order, n, c->stream));
-  HIP_TRY(sort_keys_u64(nullptr, &t2, R.keys, R.keys2, n, c->stream));
-  R.tmp_bytes = std::max<size_t>(16, std::max(t1, t2));
-  R.tmp = req_alloc<uint8_t>(c, R, R.tmp_bytes);
-  if (!R.tmp) return RELOC_E_NOMEM;
+  // second position buffer of the ranking sort (the SMAD order in R.order
+  // must survive it)
+  R.pos2 = req_alloc<int32_t>(c, R, n);
+  if (!R.pos2) return RELOC_E_NOMEM;
   if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
   return RELOC_OK;
@@ -648,12 +646,8 @@ static int plain_first_stages_per_launch(const Request& R) {
 
 // stable SMAD order of the request (after the SMAD kernel)
 int32_t smad_order(reloc_ctx* c, Request& R) {
-  if (R.n_hyp <= kSmallSortMax) {
-    HIP_TRY(small_sort_pairs_u64(R.keys, R.keys2, R.vals, nullptr, R.order, R.n_hyp, c->stream));
-  } else {
-    size_t tb = R.tmp_bytes;
-    HIP_TRY(sort_pairs_u64_i32(R.tmp, &tb, R.keys, R.keys2, R.vals, R.order, R.n_hyp, c->stream));
-  }
+  HIP_TRY(argsort_u64(R.keys, R.keys2, R.vals, R.order, R.n_hyp, 1, nullptr, nullptr, 0, 0,
+                      c->stream));
   return RELOC_OK;
 }
 
@@ -679,10 +673,10 @@ int32_t enqueue_rank(reloc_ctx* c, Request& R, int n_eval, int nrow, PoseRow* ho
     *top = host_rows;
     return RELOC_OK;
   } else {
+    // the SMAD keys are no longer needed: the rank keys take their buffer
     HIP_TRY(launch_rank_keys(R.best, n_eval, R.keys, s));
-    size_t tb = R.tmp_bytes;
-    HIP_TRY(sort_keys_u64(R.tmp, &tb, R.keys, R.keys2, n_eval, s));
-    HIP_TRY(launch_rank_gather(R.keys2, R.best, R.order, R.smad, ndev, R.rows, s));
+    HIP_TRY(argsort_u64(R.keys, R.keys2, R.vals, R.pos2, n_eval, 1, nullptr, nullptr, 0, 0, s));
+    HIP_TRY(launch_rank_gather(R.keys, R.best, R.order, R.smad, ndev, R.rows, s));
   }
   if (nrow > 0)   // pinned host rows, or device rows on the no-allocation path
     HIP_TRY(hipMemcpyAsync(host_rows, R.rows, nrow * sizeof(PoseRow), hipMemcpyDefault, s));
@@ -886,7 +880,7 @@ size_t request_bytes(const Request& R) {
   if (R.prm.refine_k > 0)
     b += (size_t)std::max(plain_max_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
   if (R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2) b += (size_t)I.n_fov * 12;
-  b += 2 * n * 12 + (1 << 20);                                  // sort scratch
+  b += n * 4;                                                   // ranking sort positions
   b += 32 * 256;                                                // allocation rounding
   return b;
 }
@@ -1304,7 +1298,7 @@ int32_t run_request(reloc_ctx* c, Request& R, reloc_pose* out, int32_t cap, int3
     const int nb0 = std::min(ns0 * K, R.n_hyp);
     // captured on the request's second run (a one-shot relocalization would
     // pay the capture and gain nothing)
-    const bool graph = R.prm.use_graph && !dev_rows && s != nullptr && R.n_hyp <= kSmallSortMax &&
+    const bool graph = R.prm.use_graph && !dev_rows && s != nullptr &&
                        (ns0 != 1 || nb0 <= kRankSmallMax) && (R.head || R.runs_done >= 1);
     if (graph && !R.head) {
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));

@@ -131,8 +131,7 @@ struct Request {
   uint64_t* keys2 = nullptr;
   int32_t* vals = nullptr;
   int32_t* order = nullptr;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0;
+  int32_t* pos2 = nullptr;        // [n] scratch of the ranking sort
   uint64_t* best = nullptr;
   // local refinement: lattice half-widths and size, slots per launch
   int ref_h = 0, ref_s = 0, ref_L = 0, ref_slots = 0;

@@ -211,9 +211,41 @@ def test_serve_admission_limits(ctx, multi, loaded):
         ctx.serve_configure()
 
 
+def _check_oracle(poses, st, occ, k, hyp, q, res, K=64, tau=0.95):
+    """A result against the full oracle path (ray cast, direct-sum SMAD,
+    order, stage loop): stop stage and evaluated count identical unless the
+    deciding batch best lies within 1e-4 of tau; best pose identical up to
+    the tie rule, T within 1e-4; every pose the oracle's hypothesis at its
+    rank with bit-identical FP32 SMAD."""
+    pr = oracle.prep(q.ranges, q.angle_min, q.angle_increment, res, range_min=q.range_min,
+                     range_max=q.range_max, n_theta=360)
+    _, zhat = oracle.raycast(occ, hyp, pr["Ns"], pr["Ng"], res, q.range_max, threads=16)
+    sm, _ = oracle.smad(zhat, pr, threads=16)
+    ref = oracle.stages(k, res, pr, hyp, sm, K, tau, all_T=True, threads=16)
+    for p in poses:
+        assert int(ref["order"][p["rank"]]) == p["hyp"]
+        assert np.float32(p["smad"]) == np.float32(sm[p["hyp"]])
+    if ref["early_stopped"] != bool(st["early_stopped"]) or ref["stages"] != st["stages"]:
+        s = min(ref["stages"], st["stages"]) - 1
+        tb = ref["tstar"][s * K:(s + 1) * K].max()
+        assert tau is not None and abs(tb - tau) <= 1e-4, (ref["stages"], st["stages"])
+        return
+    assert st["n_eval"] == ref["n_eval"]
+    ro = np.lexsort((np.arange(ref["n_eval"]), -ref["tstar"]))
+    best = ro[0]
+    tied = [r for r in ro[:5] if ref["tstar"][r] >= ref["tstar"][best] * (1 - 2e-4)]
+    b = poses[0]
+    assert b["rank"] in tied
+    assert abs(b["tam"] - ref["tstar"][b["rank"]]) <= T_RTOL * ref["tstar"][b["rank"]] + T_ATOL
+    if b["rank"] == best:
+        assert b["k"] == ref["kstar"][best] or \
+            abs(ref["all_T"][best][b["k"]] - ref["tstar"][best]) <= 2e-4 * ref["tstar"][best]
+
+
 def test_serve_poisson_trace_small(ctx):
     """A short Poisson trace on its own maps: every served result equals the
-    plain path's."""
+    plain path's and meets the oracle's bars (the full oracle path run for
+    each request)."""
     w = make_serving(200.0, 10, sizes=(200,), per_size=2, n_range=(100, 2000))
     mids, sids = [], []
     for m, occ in enumerate(w.maps):
@@ -226,10 +258,15 @@ def test_serve_poisson_trace_small(ctx):
     tickets = [ctx.submit(mids[q.map_index], sids[q.map_index], **_args(q), **_search(q))
                for q in w.queries]
     got = [ctx.poll(t, wait_ms=60000) for t in tickets]
-    for q, g in zip(w.queries, got):
+    kmaps = [oracle.edt(occ) for occ in w.maps]
+    for i, (q, g) in enumerate(zip(w.queries, got)):
         r = ctx.prepare(mids[q.map_index], sids[q.map_index], **_args(q), **_search(q))
         _same(g, ctx.run(r))
         ctx.release(r)
+        _case("serve poisson: request %d against the oracle" % i)
+        hyp = ctx.read_hypotheses(sids[q.map_index])[:q.n_hyp]
+        _check_oracle(g[0], g[1], w.maps[q.map_index], kmaps[q.map_index], hyp, q,
+                      w.resolution)
     for mid, sid in zip(mids, sids):
         ctx.free_hypotheses(sid)
         ctx.unload_map(mid)

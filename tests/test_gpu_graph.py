@@ -83,9 +83,10 @@ def test_graph_replays_equal_eager(ctx, which, kw):
     ctx.unload_map(m)
 
 
-def test_graph_limit_falls_back(ctx):
-    """A set of more than 65 536 hypotheses runs its head kernel by kernel
-    (the order then uses the library's radix sort) with the same results."""
+def test_graph_large_set(ctx):
+    """A set of more than 65 536 hypotheses (the SMAD order then takes two
+    merge levels after its tile sort) gives the same results with its head
+    captured and replayed as without."""
     w = make_config(2)
     k = oracle.edt(w.occ)
     ys, xs = np.nonzero((w.occ >= 0) & (w.occ < 65) & (k >= 18))
@@ -93,7 +94,7 @@ def test_graph_limit_falls_back(ctx):
     hyp = np.stack([xs[pick], ys[pick]], 1).astype(np.int32)
     m = ctx.load_map(w.occ, w.resolution, w.origin)
     sid = ctx.set_hypotheses(m, hyp)
-    _case("graph limit, 70000 hypotheses")
+    _case("graph, 70000 hypotheses")
     kw = dict(n_theta=720, batch_k=64, tau=0.95, k_out=10)
     rid_e = ctx.prepare(m, sid, *_scan(w), use_graph=0, **kw)
     rid_g = ctx.prepare(m, sid, *_scan(w), use_graph=1, **kw)
