@@ -113,7 +113,7 @@ size_t reloc_ctx_bytes(const reloc_ctx* ctx);
  * (dx^2 + dy^2) in cells (uint32). Both stay resident until unload.
  * ---------------------------------------------------------------------- */
 typedef struct {
-  int32_t width, height;    /* cells, 1 .. 32768 each */
+  int32_t width, height;    /* cells, 1 .. 32767 each */
   double resolution;        /* metres per cell, >= 1/32 */
   double origin_x, origin_y;/* world position of the lower-left map corner */
   int32_t occ_threshold;    /* occupied iff value >= threshold (65) */

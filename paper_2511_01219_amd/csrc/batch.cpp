@@ -385,7 +385,7 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     std::vector<int64_t> pre(m + 1, 0);
     for (int i = 0; i < m; ++i) {
       const TamArgs& a = items[k][i];
-      pre[i + 1] = pre[i] + (int64_t)a.nb * ((a.Nt + 15) / 16);
+      pre[i + 1] = pre[i] + (int64_t)a.nb * tam_tiles_per_rank(a);
       lds[k] = std::max(lds[k], tam_lds_bytes(a));
     }
     blocks[k] = pre[m];

@@ -83,7 +83,29 @@ __global__ void edt_rows_kernel(const int32_t* __restrict__ g, int W, int H,
   k[(size_t)y * W + x] = best == INT64_MAX ? 0xFFFFFFFFu : (uint32_t)best;
 }
 
+// TAM plane: 2 k per cell in 8 x 4 tiles, the sentinel 2^32 - 1 in column
+// W and row H (and the unused padding of the last tiles).
+__global__ void tam_plane_kernel(const uint32_t* __restrict__ k, int W, int H,
+                                 uint32_t* __restrict__ plane) {
+  const uint32_t tx = tam_plane_tx(W);
+  const size_t tw = (size_t)tx * 8;                 // plane columns, padding included
+  const size_t n = tam_plane_entries(W, H);
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t y = (uint32_t)(i / tw), x = (uint32_t)(i - (size_t)y * tw);
+  uint32_t v = 0xFFFFFFFFu;
+  if (x < (uint32_t)W && y < (uint32_t)H) v = 2u * k[(size_t)y * W + x];
+  plane[tam_plane_index(x, y, tx)] = v;
+}
+
 }  // namespace
+
+hipError_t launch_tam_plane(const uint32_t* k, int W, int H, uint32_t* plane, hipStream_t s) {
+  const size_t n = tam_plane_entries(W, H);
+  hipLaunchKernelGGL(tam_plane_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, W, H,
+                     plane);
+  return hipGetLastError();
+}
 
 hipError_t launch_bitpack(const int8_t* occ, int W, int H, int thr, uint64_t* bits, int tpr,
                           int tph, hipStream_t s) {

@@ -3,19 +3,31 @@
 //
 // Work layout: one workgroup (4 wavefronts) per (hypothesis, tile of 16
 // orientations); each wavefront evaluates one (p, theta_k) at a time with the
-// valid beams spread over its 64 lanes.
+// valid beams spread over its 64 lanes, R per lane.
 //
-// Per beam the endpoint cell is computed exactly in 64-bit integers,
-// e = floor((X * 2^20 + zq * U) / 2^28), and the squared EDT distance k of
-// that cell is gathered. The likelihood l(k) of eq. 23 is monotone
-// non-increasing in k, so the top-k_mid selection of eq. 24-27 is a
-// selection of the k_mid smallest integer keys: key = 2 * min(k, kcap) for
-// in-map endpoints and a host-chosen odd key for off-map ones (d = d_max).
-// kcap is where l(k) has converged to within 1e-10 of its limit. The
-// threshold key comes from a bitwise search whose counts are wavefront
-// ballots; sums are exact integers (l in Q26 fixed point from a host table,
-// sqrt(k) in Q16, k itself), so the result does not depend on lane order or
-// co-scheduling.
+// A hypothesis sits at its cell centre, so the endpoint cell of beam v at
+// heading g is the hypothesis cell plus an offset that depends on (g, v)
+// only: e = (ix, iy) + (dx, dy), dx = floor((2^27 + zq U_x) / 2^28) (eq. 22's
+// projection in exact fixed point). The request's offset table holds every
+// (g, v) offset, so a lookup is one coalesced offset load (four beams per
+// lane at a time), two clamps and one 4-byte gather from the map's TAM
+// plane: 2 k per cell in 8 x 4 tiles (an endpoint run along a wall in any
+// direction stays within few 128-byte lines), with a sentinel column and
+// row 2^32 - 1 that endpoints off the map (and padded beam slots) are
+// clamped onto, so no lookup needs a mask; sqrt(k) in Q16 is computed.
+// The likelihood l(k) of eq. 23 is monotone non-increasing in k, so the
+// top-k_mid selection of eq. 24-27 is a selection of the k_mid smallest
+// integer keys: key = 2 * min(k, kcap) for in-map endpoints and a
+// host-chosen odd key for off-map ones (d = d_max). kcap is where l(k) has
+// converged to within 1e-10 of its limit. The sentinel holds 2^32 - 1 in
+// place of 2 k, so every off-map or padded slot first takes the key
+// 2 kcap; the wavefront's sentinel count (from the sq sums) then moves the
+// off-map ones to key_off and drops the padded ones, in closed form, in
+// every count and sum. The threshold key comes from a bitwise search whose
+// counts are wavefront ballots; sums are exact integers
+// (l - lmin in Q26 fixed point from a host table, sqrt(k) in Q16, k itself,
+// lmin the table's smallest value added back per selected beam), so the
+// result does not depend on lane order or co-scheduling.
 // The median of eq. 27 is always the top-k_mid mean (top-k means are
 // non-increasing in k and k_low <= k_mid <= k_full).
 //
@@ -36,37 +48,11 @@ constexpr int NW = TB / 64;
 constexpr int THETA_PER_BLOCK = 16;
 constexpr uint32_t NOKEY = 0xFFFFFFFFu;
 
-// The three gathered tables (squared EDT map, direction table, likelihood
-// LUT) are read through buffer resources with 32-bit byte offsets: no 64-bit
-// address arithmetic per gather. Every offset used is inside its table.
-struct TamTables {
-  __amdgpu_buffer_rsrc_t k, dir, lut;
-  __device__ __forceinline__ uint32_t kval(uint32_t idx) const {
-    return __builtin_amdgcn_raw_buffer_load_b32(k, (int)(idx << 2), 0, 0);
-  }
-  __device__ __forceinline__ int2 direction(int i) const {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(dir, i << 3, 0, 0);
-    return int2{(int)v[0], (int)v[1]};
-  }
-  __device__ __forceinline__ int32_t ell(uint32_t key) const {
-    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
-  }
-};
-
-__device__ __forceinline__ TamTables tam_tables(const TamArgs& a) {
-  TamTables t;
-  // byte offsets are unsigned 32-bit: up to 2^30 cells (a 32768^2 map) fit,
-  // and the record count saturates at 2^32 - 1
-  const uint64_t kbytes = 4ull * (uint64_t)a.W * (uint64_t)a.H;
-  const uint32_t krec = kbytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)kbytes;
-  t.k = __builtin_amdgcn_make_buffer_rsrc((void*)a.kmap, (short)0, (int)krec, 0x00020000);
-  t.dir = __builtin_amdgcn_make_buffer_rsrc((void*)a.dirs, (short)0, 16 * a.Ng, 0x00020000);
-  t.lut = __builtin_amdgcn_make_buffer_rsrc((void*)a.lut, (short)0, 4 << a.keybits, 0x00020000);
-  return t;
-}
-
-__device__ __forceinline__ uint32_t sqrt_q16(uint32_t k) {
-  return __float2uint_rn(__fsqrt_rn((float)k) * 65536.0f);
+// The likelihood table (2^keybits entries and a zero slot) through a
+// buffer resource, for the 16-bit key class that does not keep it in LDS.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lut_rsrc(const TamArgs& a) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)a.lut, (short)0, 4 * ((1 << a.keybits) + 1),
+                                           0x00020000);
 }
 
 // Sum over the 64 lanes of a wavefront (every lane active), returned to
@@ -74,15 +60,9 @@ __device__ __forceinline__ uint32_t sqrt_q16(uint32_t k) {
 // row with the row's sum; two row broadcasts then carry rows 0-2 into lane
 // 63, which is read back. The moves are DPP operands of VALU instructions:
 // no LDS round trips. Integer sums, so the order of the additions does not
-// change the result. In the 32-bit sum a lane with no source lane (rows 0-1
-// under the broadcasts) reads 0, the identity of the sum, which lets the
-// move fold into the add; the 64-bit sum moves each half on its own and
-// leaves such lanes unspecified, which lane 63 never reads from.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp32_or0(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
-}
-
+// change the result. The 64-bit sum moves each half on its own and leaves
+// lanes with no source lane (rows 0-1 under the broadcasts) unspecified,
+// which lane 63 never reads from.
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
@@ -102,47 +82,28 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-  v += dpp32_or0<0xb1>(v);
-  v += dpp32_or0<0x4e>(v);
-  v += dpp32_or0<0x124>(v);
-  v += dpp32_or0<0x128>(v);
-  v += dpp32_or0<0x142>(v);
-  v += dpp32_or0<0x143>(v);
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
-  if constexpr (sizeof(T) == 8)
-    return (T)wave_sum64((uint64_t)v);
-  else
-    return (T)wave_sum32((uint32_t)v);
-}
-
 // The 16 poses of one workgroup come from a pose source: has(j) tells
-// whether pose j of the tile is evaluated, pose(j) gives its Q20 origin and
-// heading direction index (false when it is not evaluated), tie(j) the low
-// word that orders equal T in
-// the atomic max (larger wins), record(j, T) an optional per-pose output,
-// and dst the packed (T bits, tie) word the tile's best is folded into.
+// whether pose j of the tile is evaluated, pose(j) gives its cell and
+// heading index g on the Ng grid (false when it is not evaluated), tie(j)
+// the low word that orders equal T in the atomic max (larger wins),
+// record(j, T) an optional per-pose output, and dst the packed (T bits,
+// tie) word the tile's best is folded into.
 //
-// Orientation tile: hypothesis cell (X20, Y20), orientations [k0, k0 + 16)
-// of eq. 22, heading index o k on the Ng grid; ties go to the smaller k.
+// Orientation tile: hypothesis cell (ix, iy), orientations [k0, k0 + 16) of
+// eq. 22, heading index o k on the Ng grid; ties go to the smaller k.
 struct ThetaSrc {
   static constexpr bool kPrefix = true;   // the evaluated poses are a prefix
   static constexpr bool kPublish = true;  // fold the tile's best into *dst
-  int64_t X20, Y20;
+  int ix, iy;
   int k0, Nt, o, Ng;
   float* T_row;           // optional [Nt]
   uint64_t* dst;
-  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+  __device__ __forceinline__ bool pose(int j, int& x, int& y, int& g) const {
     const int k = k0 + j;
     if (k >= Nt) return false;
-    x = X20;
-    y = Y20;
-    ok = (int)(((int64_t)o * k) % Ng);
+    x = ix;
+    y = iy;
+    g = (int)(((int64_t)o * k) % Ng);
     return true;
   }
   __device__ __forceinline__ bool has(int j) const { return k0 + j < Nt; }
@@ -173,15 +134,14 @@ struct LatticeSrc {
     if ((uint32_t)cx >= (uint32_t)W || (uint32_t)cy >= (uint32_t)H) return false;
     return kmap[(size_t)cy * (size_t)W + (size_t)cx] != 0u;
   }
-  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+  __device__ __forceinline__ bool pose(int j, int& x, int& y, int& g) const {
     if (!has(j)) return false;
     const int q = q0 + j, t = q / w;
     const int dx = q - t * w - h, dy = t % w - h, dg = t / w - s;
-    const int cx = ix + dx, cy = iy + dy;
-    x = (int64_t)(256 * cx + 128) * (int64_t)(1 << 20);
-    y = (int64_t)(256 * cy + 128) * (int64_t)(1 << 20);
-    int g = (g0 + dg) % Ng;
-    ok = g < 0 ? g + Ng : g;
+    x = ix + dx;
+    y = iy + dy;
+    const int gg = (g0 + dg) % Ng;
+    g = gg < 0 ? gg + Ng : gg;
     return true;
   }
   __device__ __forceinline__ uint32_t tie(int j) const {
@@ -202,44 +162,64 @@ struct PoseListSrc {
   float* out;
   uint64_t* dst;
   __device__ __forceinline__ bool has(int j) const { return q0 + j < n; }
-  __device__ __forceinline__ bool pose(int j, int64_t& x, int64_t& y, int& ok) const {
+  __device__ __forceinline__ bool pose(int j, int& x, int& y, int& gg) const {
     const int q = q0 + j;
     if (q >= n) return false;
-    x = (int64_t)(256 * xy[2 * q] + 128) * (int64_t)(1 << 20);
-    y = (int64_t)(256 * xy[2 * q + 1] + 128) * (int64_t)(1 << 20);
-    ok = g[q];
+    x = xy[2 * q];
+    y = xy[2 * q + 1];
+    gg = g[q];
     return true;
   }
   __device__ __forceinline__ uint32_t tie(int) const { return 0u; }
   __device__ __forceinline__ void record(int j, float T) const { out[q0 + j] = T; }
 };
 
+// LDS of a tile: the likelihood table (2^12 keys and a zero slot) for the
+// 12-bit key class; the 16-bit class reads it from memory.
+__host__ __device__ constexpr size_t tam_lut_lds(int kb) {
+  return kb <= 12 ? (size_t)((1 << 12) + 1) * 4 : 0;
+}
+
 // One workgroup's work: the 16 poses of a tile; wavefront w takes poses
 // w + 4 g, g = 0..3.
 //
-// Per pose the valid beams are spread over the lanes, SB per lane at a
-// time: all SB direction loads, then all SB EDT gathers, are issued before
-// any is used. The per-pose integer sums are parked in lane g, then moved
-// to LDS; the FP64 tail (eq. 27-31) runs once per workgroup, for the 16
-// poses in lanes 0..15 of wavefront 0, and one atomic max per workgroup
-// publishes the best (T, tie). The other wavefronts end there: every caller
-// ends with the tile.
+// Per pose the R beam slots of a lane come SB at a time: one 16-byte load
+// of four offsets per four slots, then SB plane gathers, all in flight
+// before any is used. The per-pose integer sums are parked in lane g, then
+// moved to LDS; the FP64 tail (eq. 27-31) runs once per workgroup, for the
+// 16 poses in lanes 0..15 of wavefront 0, and one atomic max per workgroup
+// publishes the best (T, tie). The other wavefronts end there: every
+// caller ends with the tile.
 template <int R, int KB, bool FULL, class Src>
 __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32_t* smem) {
-  constexpr int SB = R >= 32 ? 8 : 4;  // keys per lane in flight together
+  // beam slots per lane in flight together: every slot up to 12 keys per
+  // lane, then batches of 8 (register pressure)
+  constexpr int SB = R <= 12 ? R : 8;
   constexpr int G = THETA_PER_BLOCK / NW;
-  int2* sbz = (int2*)smem;            // [nvp] (direction base, Q8 range)
+  constexpr bool kLdsLut = KB <= 12;
+  constexpr uint32_t ZERO = 1u << KB;   // the likelihood table's zero slot
+  static_assert(R % SB == 0, "whole gather batches");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = a.nv;
-
-  // every gather batch below reads whole 64 x SB slices of the padded table
-  static_assert(64 * SB <= kTamBeamPad, "gather batch beyond the beam padding");
-  const int nvp = tam_beams_padded(nv);
-  // padded entries get range -1: a slot is valid exactly when its range is
-  // non-negative (valid ranges are positive Q8 counts)
-  for (int v = tid; v < nvp; v += TB) sbz[v] = v < nv ? a.beams[v] : int2{0, -1};
-  __syncthreads();
-  const TamTables tb = tam_tables(a);
+  const __amdgpu_buffer_rsrc_t lut = lut_rsrc(a);
+  if constexpr (kLdsLut) {
+    for (int i = tid; i <= (int)ZERO; i += TB)
+      smem[i] = i < (1 << a.keybits)
+                    ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, i << 2, 0, 0) : 0;
+    __syncthreads();
+  }
+  auto ell = [&](uint32_t key) -> int32_t {
+    if constexpr (kLdsLut) return smem[key];
+    else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
+  };
+  const char* __restrict__ plane = reinterpret_cast<const char*>(a.plane);
+  const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, tx = tam_plane_tx(a.W);
+  const uint32_t kcap2 = 2u * (uint32_t)a.kcap, key_off = (uint32_t)a.key_off;
+  // the sentinel's share of a sq sum, by the same instructions as a slot's
+  // (the empty asm keeps the compiler from folding it with other rounding)
+  uint32_t s_half = 0x7FFFFFFFu;
+  asm volatile("" : "+v"(s_half));
+  const uint32_t sq_sent = __float2uint_rn(__fsqrt_rn((float)s_half) * 65536.0f);
 
   // per-pose results parked in lane g
   int64_t p_sl = 0;
@@ -247,124 +227,119 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   int p_noff = 0;
 
   for (int g = 0; g < G; ++g) {
-    int64_t X20, Y20;
-    int ok;
-    if (!src.pose(wv + NW * g, X20, Y20, ok)) {         // wavefront-uniform
+    int px, py, pg;
+    if (!src.pose(wv + NW * g, px, py, pg)) {           // wavefront-uniform
       if (Src::kPrefix) break;
       continue;
     }
+    const uint4* __restrict__ orow =
+        reinterpret_cast<const uint4*>(a.off + (size_t)pg * (size_t)a.off_stride) + lane;
+    // raw keys: min(2 k, 2 kcap) for every slot, the sentinel's 2^32 - 1
+    // included (so off-map and padded slots hold 2 kcap here; the counts
+    // and sums below move them to key_off or drop them)
     uint32_t keys[R];
-    uint64_t sumk = 0, sumsq = 0;
-    int noff = 0;
+    uint64_t sumk = 0, sums = 0;
+    uint32_t n_sent = 0;
 #pragma unroll
-    for (int i0 = 0; i0 < R; i0 += SB) {
-      if (64 * i0 < nv) {                       // wavefront-uniform
-        int2 U[SB];
-        int zq[SB];
+    for (int b = 0; b < R / SB; ++b) {
+      uint32_t o[SB];
 #pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2) {
-          // padded beams and a doubled direction table: no clamp, no wrap
-          const int2 bz = sbz[lane + 64 * (i0 + s2)];
-          zq[s2] = bz.y;
-          U[s2] = tb.direction(bz.x + ok);
-        }
-        uint32_t kk[SB];
-        bool in[SB];
-#pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2) {
-          // the shifted endpoint is a cell index within a few thousand of
-          // the map, so its low 32 bits are the whole value
-          const int ex = (int)((X20 + (int64_t)zq[s2] * U[s2].x) >> 28);
-          const int ey = (int)((Y20 + (int64_t)zq[s2] * U[s2].y) >> 28);
-          in[s2] = (uint32_t)ex < (uint32_t)a.W && (uint32_t)ey < (uint32_t)a.H;
-          const uint32_t idx = in[s2] ? __umul24((uint32_t)ey, (uint32_t)a.W) + (uint32_t)ex : 0u;
-          kk[s2] = tb.kval(idx);
-        }
-        // branch-free: keys and sums by selects
-#pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2) {
-          const bool valid = zq[s2] >= 0;
-          const bool hit = valid && in[s2];
-          const uint32_t kv = kk[s2];
-          keys[i0 + s2] = hit ? 2u * min(kv, (uint32_t)a.kcap)
-                              : (valid ? (uint32_t)a.key_off : NOKEY);
-          sumk += hit ? kv : 0u;
-          sumsq += hit ? sqrt_q16(kv) : 0u;
-          noff += (valid && !in[s2]) ? 1 : 0;
-        }
-      } else {
-#pragma unroll
-        for (int s2 = 0; s2 < SB; ++s2) keys[i0 + s2] = NOKEY;
+      for (int q = 0; q < SB / 4; ++q) {
+        const uint4 o4 = orow[64 * (b * (SB / 4) + q)];
+        o[4 * q] = o4.x;
+        o[4 * q + 1] = o4.y;
+        o[4 * q + 2] = o4.z;
+        o[4 * q + 3] = o4.w;
       }
+      uint32_t idx[SB];
+#pragma unroll
+      for (int s2 = 0; s2 < SB; ++s2) {
+        // off the map (either side) clamps onto the sentinel column / row
+        const uint32_t ex = (uint32_t)px + (uint32_t)(int32_t)(int16_t)(o[s2] & 0xFFFFu);
+        const uint32_t ey = (uint32_t)py + (uint32_t)((int32_t)o[s2] >> 16);
+        idx[s2] = tam_plane_index(min(ex, Wc), min(ey, Hc), tx);
+      }
+      // 32-bit byte offsets from the plane base (at most 2^32 - 4)
+      uint32_t v[SB];
+#pragma unroll
+      for (int s2 = 0; s2 < SB; ++s2)
+        v[s2] = *reinterpret_cast<const uint32_t*>(plane + (idx[s2] << 2));
+#pragma unroll
+      for (int s2 = 0; s2 < SB; ++s2) {
+        const uint32_t k2 = v[s2];
+        // round(sqrt(k) 2^16), the distance in Q16 cells, for every slot
+        // (the sentinel's share is taken back out below): no branch
+        const uint32_t sq = __float2uint_rn(__fsqrt_rn((float)(k2 >> 1)) * 65536.0f);
+        keys[SB * b + s2] = min(k2, kcap2);
+        sumk += k2;
+        sums += sq;
+        n_sent += k2 & 1u;                             // the sentinel is the one odd entry
+      }
+      // one gather batch at a time: without this the scheduler issues every
+      // batch's loads together and holds them all
+      __builtin_amdgcn_sched_barrier(0);
     }
+    // wavefront totals first: the selection needs the off-map count
+    sums += (uint64_t)n_sent << 48;     // sq sums stay below 2^44
+    sumk = wave_sum64(sumk);
+    sums = wave_sum64(sums);
+    const int nsent = (int)(sums >> 48);   // sentinel slots: off-map beams and padding
+    const int nin = 64 * R - nsent;
+    const int noff = nv - nin;
+    sumk -= (uint64_t)nsent * 0xFFFFFFFFull;
+    // the selection over the true keys (in-map keys, noff copies of key_off):
+    // a count or sum over raw keys below c, less the sentinel slots when
+    // 2 kcap < c, plus the off-map beams when key_off < c
     int64_t sl = 0;
     if constexpr (!FULL) {
       // TAM and T_mean: the top-k_mid sum of eq. 24-27. The k_mid-th
       // smallest key: bitwise search for the largest t with fewer than
       // k_mid keys below it; counts from wavefront ballots
-      // (whole gather chunks are tested: their padded slots hold NOKEY,
-      // which is below no candidate)
+      auto corr = [&](uint32_t c) -> int {
+        return (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
+      };
       uint32_t tkey = 0;
       for (int bit = KB - 1; bit >= 0; --bit) {
         const uint32_t cand = tkey | (1u << bit);
-        int cnt = 0;
+        int cnt = corr(cand);
 #pragma unroll
-        for (int i0 = 0; i0 < R; i0 += SB)
-          if (64 * i0 < nv) {
-#pragma unroll
-            for (int s2 = 0; s2 < SB; ++s2) cnt += __popcll(__ballot(keys[i0 + s2] < cand));
-          }
+        for (int i = 0; i < R; ++i) cnt += __popcll(__ballot(keys[i] < cand));
         if (cnt < a.kmid) tkey = cand;
       }
-      int below = 0;
+      int below = corr(tkey);
 #pragma unroll
-      for (int i0 = 0; i0 < R; i0 += SB)
-        if (64 * i0 < nv) {
+      for (int i = 0; i < R; ++i) below += __popcll(__ballot(keys[i] < tkey));
+      // table entries are l - lmin >= 0, below 2^31: pairs add in 32 bits
 #pragma unroll
-          for (int s2 = 0; s2 < SB; ++s2) below += __popcll(__ballot(keys[i0 + s2] < tkey));
-        }
-#pragma unroll
-      for (int i0 = 0; i0 < R; i0 += SB) {
-        if (64 * i0 < nv) {
-          int32_t lv[SB];
-#pragma unroll
-          for (int s2 = 0; s2 < SB; ++s2)
-            lv[s2] = tb.ell(keys[i0 + s2] < tkey ? keys[i0 + s2] : 0u);
-#pragma unroll
-          for (int s2 = 0; s2 < SB; ++s2)
-            if (keys[i0 + s2] < tkey) sl += lv[s2];
-        }
+      for (int i = 0; i < R; i += 2) {
+        const uint32_t l0 = (uint32_t)ell(keys[i] < tkey ? keys[i] : ZERO);
+        const uint32_t l1 = (uint32_t)ell(keys[i + 1] < tkey ? keys[i + 1] : ZERO);
+        sl += (int64_t)(uint64_t)(l0 + l1);
       }
-      sl = wave_sum(sl);
-      sl += (int64_t)(a.kmid - below) * (int64_t)tb.ell(tkey);
+      sl = (int64_t)wave_sum64((uint64_t)sl);
+      if (kcap2 < tkey) sl -= (int64_t)nsent * (int64_t)ell(kcap2);
+      if (key_off < tkey) sl += (int64_t)noff * (int64_t)ell(key_off);
+      sl += (int64_t)(a.kmid - below) * (int64_t)ell(tkey);
+      sl += (int64_t)a.kmid * (int64_t)a.lmin;
     } else {
       // baseline and LF: the sum of l over every valid beam (eq. 32)
 #pragma unroll
-      for (int i0 = 0; i0 < R; i0 += SB) {
-        if (64 * i0 < nv) {
-          int32_t lv[SB];
-#pragma unroll
-          for (int s2 = 0; s2 < SB; ++s2)
-            lv[s2] = tb.ell(keys[i0 + s2] != NOKEY ? keys[i0 + s2] : 0u);
-#pragma unroll
-          for (int s2 = 0; s2 < SB; ++s2)
-            if (keys[i0 + s2] != NOKEY) sl += lv[s2];
-        }
-      }
-      sl = wave_sum(sl);
+      for (int i = 0; i < R; i += 2)
+        sl += (int64_t)(uint64_t)((uint32_t)ell(keys[i]) + (uint32_t)ell(keys[i + 1]));
+      sl = (int64_t)wave_sum64((uint64_t)sl);
+      sl += (int64_t)noff * (int64_t)ell(key_off) - (int64_t)nsent * (int64_t)ell(kcap2);
+      sl += (int64_t)nv * (int64_t)a.lmin;
     }
-    sumk = wave_sum(sumk);
-    sumsq = wave_sum(sumsq);
-    noff = wave_sum(noff);
     if (lane == g) {
       p_sl = sl;
-      p_sumk = sumk;
-      p_sumsq = sumsq;
+      p_sumk = sumk >> 1;               // the plane holds 2 k
+      // in Q16 cells, less the sentinel slots' share
+      p_sumsq = (sums & ((1ull << 48) - 1)) - (uint64_t)nsent * (uint64_t)sq_sent;
       p_noff = noff;
     }
   }
-  // the tile's 16 poses go to LDS (pose wv + NW g from lane g of wavefront
-  // wv); wavefront 0 then runs the FP64 tail once, one pose per lane
+  // the tile's poses go to LDS (pose wv + NW g from lane g of wavefront wv);
+  // wavefront 0 then runs the FP64 tail once, one pose per lane
   __shared__ int64_t t_sl[THETA_PER_BLOCK];
   __shared__ uint64_t t_sumk[THETA_PER_BLOCK], t_sumsq[THETA_PER_BLOCK];
   __shared__ int t_noff[THETA_PER_BLOCK];
@@ -422,8 +397,8 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   const int r = a.r0 + i;
   const int hyp = a.order[r];
   ThetaSrc src;
-  src.X20 = (int64_t)(256 * a.hyp_xy[2 * hyp] + 128) * (int64_t)(1 << 20);
-  src.Y20 = (int64_t)(256 * a.hyp_xy[2 * hyp + 1] + 128) * (int64_t)(1 << 20);
+  src.ix = a.hyp_xy[2 * hyp];
+  src.iy = a.hyp_xy[2 * hyp + 1];
   src.k0 = kb * THETA_PER_BLOCK;
   src.Nt = a.Nt;
   src.o = a.o;
@@ -446,7 +421,7 @@ __device__ __forceinline__ int xcd_slice(int b, int n) {
 template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
   extern __shared__ int32_t smem[];
-  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  const int ntb = tam_tiles_per_rank(a);
   const int L = xcd_slice(blockIdx.x, gridDim.x);
   tam_block<R, KB, FULL>(a, L / ntb, L % ntb, smem);
 }
@@ -544,22 +519,30 @@ __global__ void refine_commit_kernel(RefineArgs a) {
 
 template <int R, int KB, bool FULL>
 hipError_t launch_refine_t(const RefineArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)tam_beams_padded(a.t.nv) * sizeof(int2);
   const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  hipLaunchKernelGGL((refine_kernel<R, KB, FULL>), dim3(tiles * a.n_slots), dim3(TB), lds, s,
-                     a);
+  hipLaunchKernelGGL((refine_kernel<R, KB, FULL>), dim3(tiles * a.n_slots), dim3(TB),
+                     tam_lut_lds(KB), s, a);
   return hipGetLastError();
 }
 
+// Kernel class dispatch on the keys per lane of the request's beams.
+#define RELOC_TAM_CLASSES(F, KB, FULL, ...)                                   \
+  switch (tam_keys_per_lane(nv)) {                                           \
+    case 4: return F<4, KB, FULL>(__VA_ARGS__);                              \
+    case 8: return F<8, KB, FULL>(__VA_ARGS__);                              \
+    case 12: return F<12, KB, FULL>(__VA_ARGS__);                            \
+    case 16: return F<16, KB, FULL>(__VA_ARGS__);                            \
+    case 24: return F<24, KB, FULL>(__VA_ARGS__);                            \
+    case 32: return F<32, KB, FULL>(__VA_ARGS__);                            \
+    case 48: return F<48, KB, FULL>(__VA_ARGS__);                            \
+    case 64: return F<64, KB, FULL>(__VA_ARGS__);                            \
+    default: return hipErrorInvalidValue;                                    \
+  }
+
 template <int KB, bool FULL>
 hipError_t launch_refine_kb(const RefineArgs& a, hipStream_t s) {
-  const int R = (a.t.nv + 63) / 64;
-  if (R <= 4) return launch_refine_t<4, KB, FULL>(a, s);
-  if (R <= 8) return launch_refine_t<8, KB, FULL>(a, s);
-  if (R <= 16) return launch_refine_t<16, KB, FULL>(a, s);
-  if (R <= 32) return launch_refine_t<32, KB, FULL>(a, s);
-  if (R <= 64) return launch_refine_t<64, KB, FULL>(a, s);
-  return hipErrorInvalidValue;
+  const int nv = a.t.nv;
+  RELOC_TAM_CLASSES(launch_refine_t, KB, FULL, a, s)
 }
 
 // Scores of an explicit pose list, 16 poses per workgroup.
@@ -578,21 +561,15 @@ __global__ __launch_bounds__(TB) void pose_kernel(PoseArgs a) {
 
 template <int R, int KB, bool FULL>
 hipError_t launch_poses_t(const PoseArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)tam_beams_padded(a.t.nv) * sizeof(int2);
   const int blocks = (a.n + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  hipLaunchKernelGGL((pose_kernel<R, KB, FULL>), dim3(blocks), dim3(TB), lds, s, a);
+  hipLaunchKernelGGL((pose_kernel<R, KB, FULL>), dim3(blocks), dim3(TB), tam_lut_lds(KB), s, a);
   return hipGetLastError();
 }
 
 template <int KB, bool FULL>
 hipError_t launch_poses_kb(const PoseArgs& a, hipStream_t s) {
-  const int R = (a.t.nv + 63) / 64;
-  if (R <= 4) return launch_poses_t<4, KB, FULL>(a, s);
-  if (R <= 8) return launch_poses_t<8, KB, FULL>(a, s);
-  if (R <= 16) return launch_poses_t<16, KB, FULL>(a, s);
-  if (R <= 32) return launch_poses_t<32, KB, FULL>(a, s);
-  if (R <= 64) return launch_poses_t<64, KB, FULL>(a, s);
-  return hipErrorInvalidValue;
+  const int nv = a.t.nv;
+  RELOC_TAM_CLASSES(launch_poses_t, KB, FULL, a, s)
 }
 
 // Index of the segment holding item t: prefix[e] <= t < prefix[e + 1].
@@ -614,28 +591,50 @@ __global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict
   const int t = xcd_slice(blockIdx.x, gridDim.x);
   const int e = find_segment(prefix, n, t);
   const TamArgs& a = items[e];
-  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
+  const int ntb = tam_tiles_per_rank(a);
   const int local = (int)(t - prefix[e]);
   tam_block<R, KB, FULL>(a, local / ntb, local % ntb, smem);
 }
 
 template <int R, int KB, bool FULL>
 hipError_t launch_tam_t(const TamArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)tam_beams_padded(a.nv) * sizeof(int2);
-  const int ntb = (a.Nt + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
-  hipLaunchKernelGGL((tam_kernel<R, KB, FULL>), dim3(ntb * a.nb), dim3(TB), lds, s, a);
+  const int ntb = tam_tiles_per_rank(a);
+  hipLaunchKernelGGL((tam_kernel<R, KB, FULL>), dim3(ntb * a.nb), dim3(TB), tam_lut_lds(KB), s,
+                     a);
   return hipGetLastError();
 }
 
 template <int KB, bool FULL>
 hipError_t launch_tam_kb(const TamArgs& a, hipStream_t s) {
-  const int R = (a.nv + 63) / 64;
-  if (R <= 4) return launch_tam_t<4, KB, FULL>(a, s);
-  if (R <= 8) return launch_tam_t<8, KB, FULL>(a, s);
-  if (R <= 16) return launch_tam_t<16, KB, FULL>(a, s);
-  if (R <= 32) return launch_tam_t<32, KB, FULL>(a, s);
-  if (R <= 64) return launch_tam_t<64, KB, FULL>(a, s);
-  return hipErrorInvalidValue;
+  const int nv = a.nv;
+  RELOC_TAM_CLASSES(launch_tam_t, KB, FULL, a, s)
+}
+
+
+// Endpoint-offset table: one thread per (heading g, beam slot v).
+__global__ void tam_offsets_kernel(const int2* __restrict__ beams, int nv,
+                                   const int2* __restrict__ dirs, int Ng, int stride,
+                                   uint32_t* __restrict__ off) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Ng * stride) return;
+  const int g = (int)(t / stride);
+  // slot p = 4 (64 b + l) + q holds beam 256 b + 64 q + l
+  const int p = (int)(t - (int64_t)g * stride);
+  const int v = (p & ~255) + 64 * (p & 3) + ((p & 255) >> 2);
+  if (v >= nv) {
+    off[t] = 0x80000000u;                      // dy = -32768: never inside a map
+    return;
+  }
+  const int2 bz = beams[v];
+  const int2 U = dirs[bz.x + g];               // the table is stored twice: no wrap
+  const int64_t half = (int64_t)1 << 27;
+  // maps are at most 32767 cells a side, so an offset of 32767 or more
+  // leaves the map from any cell: clamping keeps it off the map
+  const int64_t dx = (half + (int64_t)bz.y * U.x) >> 28;
+  const int64_t dy = (half + (int64_t)bz.y * U.y) >> 28;
+  const int cx = (int)(dx < -32767 ? -32767 : (dx > 32767 ? 32767 : dx));
+  const int cy = (int)(dy < -32767 ? -32767 : (dy > 32767 ? 32767 : dy));
+  off[t] = (uint32_t)(uint16_t)(int16_t)cx | ((uint32_t)(uint16_t)(int16_t)cy << 16);
 }
 
 __device__ __forceinline__ void stage_reduce_run(const StageArgs& a) {
@@ -817,15 +816,13 @@ hipError_t launch_tam_batch_t(const TamArgs* items, const int64_t* prefix, int n
   return hipGetLastError();
 }
 
+constexpr int kTamR[8] = {4, 8, 12, 16, 24, 32, 48, 64};
+
 template <int KB, bool FULL>
 hipError_t launch_tam_batch_kb(int R, const TamArgs* items, const int64_t* prefix, int n,
                                int64_t blocks, size_t lds, hipStream_t s) {
-  if (R <= 4) return launch_tam_batch_t<4, KB, FULL>(items, prefix, n, blocks, lds, s);
-  if (R <= 8) return launch_tam_batch_t<8, KB, FULL>(items, prefix, n, blocks, lds, s);
-  if (R <= 16) return launch_tam_batch_t<16, KB, FULL>(items, prefix, n, blocks, lds, s);
-  if (R <= 32) return launch_tam_batch_t<32, KB, FULL>(items, prefix, n, blocks, lds, s);
-  if (R <= 64) return launch_tam_batch_t<64, KB, FULL>(items, prefix, n, blocks, lds, s);
-  return hipErrorInvalidValue;
+  const int nv = 64 * R;
+  RELOC_TAM_CLASSES(launch_tam_batch_t, KB, FULL, items, prefix, n, blocks, lds, s)
 }
 
 }  // namespace
@@ -879,22 +876,32 @@ hipError_t launch_refine_commit(const RefineArgs& a, hipStream_t s) {
 }
 
 int tam_class(const TamArgs& a) {
-  const int R = (a.nv + 63) / 64;
-  const int rc = R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : R <= 32 ? 3 : R <= 64 ? 4 : -1;
+  const int R = tam_keys_per_lane(a.nv);
+  int rc = -1;
+  for (int i = 0; i < 8; ++i)
+    if (kTamR[i] == R) rc = i;
   const int kc = a.keybits <= 12 ? 0 : a.keybits <= 16 ? 1 : -1;
   if (rc < 0 || kc < 0 || a.fine < 0 || a.fine > 3) return -1;
-  return (a.fine >= 2 ? 10 : 0) + kc * 5 + rc;
+  return (a.fine >= 2 ? 16 : 0) + kc * 8 + rc;
 }
 
-size_t tam_lds_bytes(const TamArgs& a) { return (size_t)tam_beams_padded(a.nv) * sizeof(int2); }
+size_t tam_lds_bytes(const TamArgs& a) { return tam_lut_lds(a.keybits <= 12 ? 12 : 16); }
+
+hipError_t launch_tam_offsets(const int2* beams, int nv, const int2* dirs, int Ng, int stride,
+                              uint32_t* off, hipStream_t s) {
+  const int64_t n = (int64_t)Ng * stride;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tam_offsets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     beams, nv, dirs, Ng, stride, off);
+  return hipGetLastError();
+}
 
 hipError_t launch_tam_batch(int cls, const TamArgs* items, const int64_t* prefix, int n,
                             int64_t blocks, size_t lds, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return hipSuccess;
-  static const int Rs[5] = {4, 8, 16, 32, 64};
   if (cls < 0 || cls >= kTamClasses) return hipErrorInvalidValue;
-  const int R = Rs[cls % 5];
-  switch (cls / 5) {
+  const int R = kTamR[cls % 8];
+  switch (cls / 8) {
     case 0: return launch_tam_batch_kb<12, false>(R, items, prefix, n, blocks, lds, s);
     case 1: return launch_tam_batch_kb<16, false>(R, items, prefix, n, blocks, lds, s);
     case 2: return launch_tam_batch_kb<12, true>(R, items, prefix, n, blocks, lds, s);

@@ -27,8 +27,25 @@ int64_t argsort_tiles(int64_t n);
 int argsort_levels(int64_t max_n);
 
 // ---- TAM -----------------------------------------------------------------
+// TAM plane of a W x H map from its squared EDT k: cell (x, y) holds 2 k
+// (below 2^32 for maps up to 32767 cells a side); column W and row H hold
+// the sentinel 2^32 - 1 (odd, so never 2 k). Layout: tiles of 8 x 4 cells
+// (one 128-byte line each), tiles row-major, tam_plane_tx(W) per tile row;
+// at most 2^30 entries, so a byte offset fits in 32 bits.
+__host__ __device__ inline uint32_t tam_plane_tx(int W) { return ((uint32_t)W + 8u) >> 3; }
+__host__ __device__ inline size_t tam_plane_entries(int W, int H) {
+  return (size_t)tam_plane_tx(W) * (((size_t)H + 4) >> 2) * 32;
+}
+__device__ __forceinline__ uint32_t tam_plane_index(uint32_t x, uint32_t y, uint32_t tx) {
+  return ((__umul24(y >> 2, tx) + (x >> 3)) << 5) | ((y & 3u) << 3) | (x & 7u);
+}
+hipError_t launch_tam_plane(const uint32_t* k, int W, int H, uint32_t* plane, hipStream_t s);
+
 struct TamArgs {
-  const uint32_t* kmap;
+  const uint32_t* kmap;      // [W H] squared EDT
+  const uint32_t* plane;     // TAM plane (launch_tam_plane)
+  const uint32_t* off;       // [Ng][off_stride] endpoint offsets (launch_tam_offsets)
+  int off_stride;            // 64 x keys per lane of the request's kernel class
   int W, H;
   const int32_t* hyp_xy;
   const int32_t* order;      // hypothesis index per SMAD rank
@@ -38,7 +55,8 @@ struct TamArgs {
   int nv;
   const int2* dirs;          // [2 Ng] direction table, stored twice
   int Ng, o, Nt;             // o = Ng / Nt
-  const int32_t* lut;        // [n_keys] likelihood per selection key, Q26
+  const int32_t* lut;        // [2^keybits + 1] l - lmin per selection key (Q26), 0 last
+  int lmin;                  // the smallest l of the table (Q26)
   int kcap, key_off, keybits;
   int kmid;
   double res, d_max;
@@ -48,12 +66,34 @@ struct TamArgs {
   uint64_t* best;            // [>= r0 + nb] packed (score_key(T), ~k) per rank
 };
 hipError_t launch_tam(const TamArgs& a, hipStream_t s);
-// Beam-table length the TAM kernels read: nv rounded up to 512, a whole
-// gather batch of every kernel class (64 lanes x up to 8 keys).
+// Workgroups per rank of the TAM kernels: 16 orientations each.
+__host__ __device__ inline int tam_tiles_per_rank(const TamArgs& a) { return (a.Nt + 15) / 16; }
+// Beam-table length: nv rounded up to 512 entries (padded with (0, 0)).
 constexpr int kTamBeamPad = 512;
 __host__ __device__ inline int tam_beams_padded(int nv) {
   return (nv + kTamBeamPad - 1) / kTamBeamPad * kTamBeamPad;
 }
+// Valid beams per lane of a TAM kernel class: nv beams spread over 64
+// lanes, rounded up to 4, 8, 12, 16, 24, 32, 48 or 64 (0: more than 4096).
+__host__ __device__ inline int tam_keys_per_lane(int nv) {
+  const int r = (nv + 63) / 64;
+  return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : r <= 16 ? 16 : r <= 24 ? 24
+       : r <= 32 ? 32 : r <= 48 ? 48 : r <= 64 ? 64 : 0;
+}
+// Endpoint-offset table of a request: for every heading g < Ng and beam slot
+// v < stride = 64 tam_keys_per_lane(nv), the endpoint cell of beam v at
+// heading g relative to the hypothesis cell,
+//   dx = floor((2^27 + zq U_x) / 2^28), dy likewise (exact in 64 bits; the
+//   hypothesis sits at its cell centre, X = 256 ix + 128 in Q8),
+// clamped to [-32767, 32767] and packed as (uint16)dx | (uint16)dy << 16;
+// slots of beams v >= nv hold dy = -32768 (never inside a map). Row g is
+// read in 16-byte groups, slot 4 (64 b + l) + q holding beam 256 b + 64 q
+// + l: lane l's q-th gather of batch b, so each gather instruction covers
+// 64 consecutive beams.
+// beams: [nv] (b j_v, zq_v); dirs: [2 Ng]; off: [Ng][stride], 16-byte aligned.
+hipError_t launch_tam_offsets(const int2* beams, int nv, const int2* dirs, int Ng, int stride,
+                              uint32_t* off, hipStream_t s);
+
 
 // Scores (the request's fine metric) of n explicit poses: cell xy[2q],
 // xy[2q + 1] (in the map) and heading index g[q] on the Ng grid (< Ng).
@@ -158,7 +198,7 @@ hipError_t launch_rank_small(const uint64_t* best, int n, const int32_t* order,
 // Kernel class of a TAM argument set (keys per lane x key bits x whether
 // the score needs the full l sum), -1 if unsupported; items of one launch
 // share a class.
-constexpr int kTamClasses = 20;
+constexpr int kTamClasses = 32;
 int tam_class(const TamArgs& a);
 size_t tam_lds_bytes(const TamArgs& a);
 // items: device TamArgs[n] (each a rank range of one request); prefix:

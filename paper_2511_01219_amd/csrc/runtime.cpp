@@ -44,7 +44,7 @@ constexpr int kMaxNs = 4096;
 constexpr int64_t kPlainFillBlocks = 4096;   // TAM workgroups one plain-path launch aims at
 constexpr int64_t kPlainFirstFillBlocks = 1024;  // ... and its first launch
 constexpr int kPlainMaxStages = 64;          // stages of a later plain-path launch, at most
-constexpr int kMaxDim = 32768;
+constexpr int kMaxDim = 32767;
 constexpr int kMaxNg = 1 << 20;
 
 // ---- direction table -------------------------------------------------------
@@ -191,7 +191,7 @@ int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
   L->kcap = kcap;
   L->keybits = (2 * kcap + 2 <= 4096) ? 12 : 16;
   const int nk = 1 << L->keybits;
-  L->q.assign(nk, 0);
+  L->q.assign(nk + 1, 0);   // and the zero slot q[nk] the TAM sums read for unselected keys
   for (int k = 0; k <= kcap; ++k) {
     const double v = ell(std::sqrt((double)k) * res);
     L->q[2 * k] = (int32_t)std::llrint(v * 67108864.0);
@@ -205,6 +205,12 @@ int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
     L->key_off = 2 * fk + 1;
     L->q[L->key_off] = (int32_t)std::llrint(ell(dm) * 67108864.0);
   }
+  // reachable keys are 0 .. 2 kcap (key_off among them); the TAM kernels
+  // add l - qmin (at most ln(1e12) in Q26, below 2^31) in 32 bits pairwise
+  int32_t qmin = L->q[0];
+  for (int k = 0; k <= 2 * kcap; ++k) qmin = std::min(qmin, L->q[k]);
+  for (int k = 0; k <= 2 * kcap; ++k) L->q[k] -= qmin;
+  L->qmin = qmin;
   return RELOC_OK;
 }
 
@@ -494,7 +500,12 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   // must survive it)
   R.pos2 = req_alloc<int32_t>(c, R, n);
   if (!R.pos2) return RELOC_E_NOMEM;
+  // TAM endpoint offsets, every heading x the beam slots of the kernel class
+  R.off_stride = 64 * tam_keys_per_lane(nv);
+  R.off = req_alloc<uint32_t>(c, R, (size_t)Ng * (size_t)R.off_stride);
+  if (!R.off) return RELOC_E_NOMEM;
   if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
+  HIP_TRY(launch_tam_offsets(R.beams, nv, R.dirs, Ng, R.off_stride, R.off, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
   return RELOC_OK;
 }
@@ -587,6 +598,9 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   const reloc_scan_info& I = R.prep.info;
   TamArgs a;
   a.kmap = m.kmap;
+  a.plane = m.plane;
+  a.off = R.off;
+  a.off_stride = R.off_stride;
   a.W = m.W;
   a.H = m.H;
   a.hyp_xy = c->sets[R.set_id].dev;
@@ -600,6 +614,7 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   a.o = I.Ng / I.Ntheta;
   a.Nt = I.Ntheta;
   a.lut = R.dlut;
+  a.lmin = R.lut.qmin;
   a.kcap = R.lut.kcap;
   a.key_off = R.lut.key_off;
   a.keybits = R.lut.keybits;
@@ -881,6 +896,7 @@ size_t request_bytes(const Request& R) {
     b += (size_t)std::max(plain_max_stages_per_launch(R), kMaxTickStages) * R.prm.refine_k * 12;
   if (R.prm.coarse_metric == 1 || R.prm.coarse_metric == 2) b += (size_t)I.n_fov * 12;
   b += n * 4;                                                   // ranking sort positions
+  b += (size_t)I.Ng * 64 * (size_t)tam_keys_per_lane(I.n_valid) * 4;   // TAM offsets
   b += 32 * 256;                                                // allocation rounding
   return b;
 }
@@ -1015,6 +1031,7 @@ void reloc_ctx_destroy(reloc_ctx* c) {
       c->dfree(kv.second.bits);
       c->dfree(kv.second.walk);
       c->dfree(kv.second.kmap);
+      c->dfree(kv.second.plane);
     }
     c->reqs.clear();
     c->sets.clear();
@@ -1062,27 +1079,31 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
   if (N <= kWalkMaxCells) m.walk = (uint16_t*)c->dalloc(4 * N * sizeof(uint16_t));
   m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
+  m.plane = (uint32_t*)c->dalloc(tam_plane_entries(m.W, m.H) * sizeof(uint32_t));
   auto cleanup = [&]() {
     c->dfree(docc);
     c->dfree(g);
   };
-  if (!docc || !g || !m.bits || (N <= kWalkMaxCells && !m.walk) || !m.kmap) {
+  if (!docc || !g || !m.bits || (N <= kWalkMaxCells && !m.walk) || !m.kmap || !m.plane) {
     cleanup();
     c->dfree(m.bits);
     c->dfree(m.walk);
     c->dfree(m.kmap);
+    c->dfree(m.plane);
     return RELOC_E_NOMEM;
   }
   hipError_t e = hipMemcpyAsync(docc, occ, N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_bitpack(docc, m.W, m.H, m.thr, m.bits, m.tpr, m.tph, c->stream);
   if (e == hipSuccess) e = launch_edt(docc, m.W, m.H, m.thr, g, m.kmap, c->stream);
   if (e == hipSuccess && m.walk) e = launch_walkmap(m.kmap, m.W, m.H, m.walk, c->stream);
+  if (e == hipSuccess) e = launch_tam_plane(m.kmap, m.W, m.H, m.plane, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {
     c->dfree(m.bits);
     c->dfree(m.walk);
     c->dfree(m.kmap);
+    c->dfree(m.plane);
     return fail(RELOC_E_DEVICE, "map upload failed: %s", hipGetErrorString(e));
   }
   const int id = c->next_id++;
@@ -1104,6 +1125,7 @@ int32_t reloc_unload_map(reloc_ctx* c, int32_t map_id) {
   c->dfree(it->second.bits);
   c->dfree(it->second.walk);
   c->dfree(it->second.kmap);
+  c->dfree(it->second.plane);
   std::lock_guard<std::mutex> rg(c->reg_mu);
   c->maps.erase(it);
   return RELOC_OK;

@@ -57,7 +57,10 @@ int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double re
 
 // ---- likelihood table for TAM (eq. 23) --------------------------------------
 struct Lut {
-  std::vector<int32_t> q;   // Q26 likelihood per selection key
+  // Q26 likelihood per selection key less qmin (>= 0); 2^keybits entries
+  // and a zero slot
+  std::vector<int32_t> q;
+  int32_t qmin = 0;         // the smallest likelihood of a reachable key
   int kcap = 1, key_off = 2, keybits = 12;
 };
 int32_t build_lut(const reloc_search_params* p, double res, Lut* L);
@@ -83,6 +86,7 @@ struct DevMap {
   uint64_t* bits = nullptr;
   uint16_t* walk = nullptr;       // null when the map exceeds kWalkMaxCells
   uint32_t* kmap = nullptr;
+  uint32_t* plane = nullptr;      // TAM plane (tam_plane_entries)
   std::vector<int8_t> occ;        // host copy for the sampler
   std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
   int n_sets = 0;
@@ -124,6 +128,8 @@ struct Request {
   int32_t* fov_j = nullptr;       // metrics only)
   int2* dirs = nullptr;
   int32_t* dlut = nullptr;
+  uint32_t* off = nullptr;        // TAM endpoint offsets [Ng][off_stride]
+  int off_stride = 0;
   // device work
   double* smad = nullptr;
   int32_t* argm = nullptr;
