@@ -294,21 +294,25 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     if constexpr (!FULL) {
       // TAM and T_mean: the top-k_mid sum of eq. 24-27. The k_mid-th
       // smallest key: bitwise search for the largest t with fewer than
-      // k_mid keys below it; counts from wavefront ballots
+      // k_mid keys below it; counts from wavefront ballots. Every key is
+      // at most 2 kcap, so the bits above its top bit stay clear, and the
+      // count below t is that of the last candidate taken (0 if none).
       auto corr = [&](uint32_t c) -> int {
         return (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
       };
+      const int top = 31 - __builtin_clz(kcap2);
       uint32_t tkey = 0;
-      for (int bit = KB - 1; bit >= 0; --bit) {
+      int below = 0;
+      for (int bit = top; bit >= 0; --bit) {
         const uint32_t cand = tkey | (1u << bit);
         int cnt = corr(cand);
 #pragma unroll
         for (int i = 0; i < R; ++i) cnt += __popcll(__ballot(keys[i] < cand));
-        if (cnt < a.kmid) tkey = cand;
+        if (cnt < a.kmid) {
+          tkey = cand;
+          below = cnt;
+        }
       }
-      int below = corr(tkey);
-#pragma unroll
-      for (int i = 0; i < R; ++i) below += __popcll(__ballot(keys[i] < tkey));
       // table entries are l - lmin >= 0, below 2^31: pairs add in 32 bits
 #pragma unroll
       for (int i = 0; i < R; i += 2) {
