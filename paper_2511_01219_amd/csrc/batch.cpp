@@ -18,12 +18,18 @@
 //           evaluated set and every result equal those of the
 //           one-stage-at-a-time path;
 //   rank  : one segmented sort and one gather for every finished request.
-// The scheduler repeats admission -> front of the admitted requests -> one
-// tick of everything in flight -> rank of the finished ones, so requests
-// that arrive while others run join at the next stage boundary.
+// The serving scheduler repeats: admission -> front of the admitted requests
+// on a second stream (same priority) -> one more tick of every request whose
+// front has finished, on the context's stream -> the stop flags of the tick
+// before it -> rank of the finished ones. Requests that arrive while others
+// run start at once on the front stream and join the ticks at the next
+// stage boundary after their front; two ticks are in flight, so the device
+// works on tick t + 1 while the host reads the flags of tick t (a request
+// that stopped in tick t has its share of tick t + 1 discarded).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
 
 #include "runtime_internal.h"
 
@@ -53,12 +59,28 @@ struct Arena {
   }
 };
 
+// The requests admitted together: their front phase's timing marks (the
+// last one ends the phase) and, once it has ended, its phase times.
+struct FrontGroup {
+  hipEvent_t ev[4] = {};
+  bool ready = false;
+  float raycast = 0, smad = 0, sort = 0;
+  ~FrontGroup() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // One request in batched execution.
 struct Flight {
   int rid = -1;                     // key in c->reqs
   std::shared_ptr<Arena> arena;
   int64_t off = 0;                  // first hypothesis of the request in the arena
   int next_rank = 0, spec = 1, stages = 0, n_eval = 0, ticks = 0;
+  int plan_rank = 0;                // first rank not yet in an enqueued tick
+  int pending = 0;                  // enqueued ticks not yet completed
+  float tam_ms = 0;                 // device time of the ticks it took part in
+  std::shared_ptr<FrontGroup> fg;   // its front phase
   bool done = false, stopped = false;
   int32_t status = RELOC_OK;
   std::chrono::steady_clock::time_point t_start;
@@ -105,11 +127,48 @@ struct Staging {
 };
 constexpr int kStagingRing = 4;
 
+// A ring of staging slots used by one stream: a slot's device buffer is
+// rewritten by a copy queued on that stream behind every kernel that read it.
+struct StagingRing {
+  Staging slot[kStagingRing];
+  int next = 0;
+};
+
+// One tick's share of a request: ranks [r0, r0 + nb), ns stages, whose
+// stop flags start at entry.
+struct TickItem {
+  Flight* f;
+  int r0, ns, nb, entry;
+};
+
+// One tick: its events (start, end), the pinned stop flags and stage words
+// its stage kernel writes, and the requests it covers.
+struct TickSlot {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int32_t* hflag = nullptr;
+  uint64_t* hstage = nullptr;
+  size_t cap = 0;
+  std::vector<TickItem> items;
+};
+
+// Ticks of one driver (a batch call or the serving worker), at most two in
+// flight, completed in order.
+struct TickPipe {
+  TickSlot slot[2];
+  std::deque<int> inflight;
+  int next = 0;
+};
+
 struct ServeState {
-  // staging of descriptor tables: a ring of slots, so a commit waits only
-  // for the copy made kStagingRing commits earlier, not for the stream
-  Staging ring[kStagingRing];
-  int ring_next = 0;
+  // staging of descriptor tables: a ring of slots per stream, so a commit
+  // waits only for the copy made kStagingRing commits earlier, not for the
+  // stream
+  StagingRing ring;                 // the context's stream
+  StagingRing fring;                // the serving front stream
+  StagingRing rring;                // the serving rank stream
+  hipStream_t sfront = nullptr;     // serving front phases (default priority)
+  hipStream_t srank = nullptr;      // serving rankings (default priority)
+  TickPipe pipe_batch, pipe_serve;
   // ranking scratch, grown on demand and kept between calls
   uint64_t* rk1 = nullptr;
   uint64_t* rk2 = nullptr;
@@ -120,12 +179,6 @@ struct ServeState {
   size_t rrows_cap = 0;
   uint64_t* rmarg = nullptr;
   size_t rmarg_cap = 0;
-  // per-tick stage outputs
-  // per-tick stage outputs, written by the stage kernel straight into
-  // pinned host memory
-  int32_t* hflag = nullptr;
-  uint64_t* hstage = nullptr;
-  size_t stage_cap = 0;
   // serving
   std::thread worker;
   bool running = false;
@@ -136,7 +189,7 @@ struct ServeState {
   std::deque<Ticket*> pending;
   std::map<uint64_t, std::unique_ptr<Ticket>> tickets;
   uint64_t next_ticket = 1;
-  std::vector<Flight> active;       // touched by the worker only
+  std::list<Flight> active;         // touched by the worker only (stable addresses)
   reloc_serve_config cfg{64, 0, 16};
   reloc_serve_stats stats{};
   int32_t worker_error = RELOC_OK;
@@ -146,13 +199,14 @@ namespace {
 
 ServeState* state(reloc_ctx* c) { return c->serve; }
 
-// Copies the blob to device memory through the next staging slot;
-// *dev receives the device address of offset 0. The slot's host buffer is
-// rewritten only after the copy that last read it has completed; its device
-// buffer is rewritten by a copy queued behind every kernel that read it.
-int32_t commit(reloc_ctx* c, ServeState& S, const Blob& bl, uint8_t** dev) {
-  Staging& g = S.ring[S.ring_next];
-  S.ring_next = (S.ring_next + 1) % kStagingRing;
+// Copies the blob to device memory through the next staging slot of the ring
+// of c->stream; *dev receives the device address of offset 0. The slot's
+// host buffer is rewritten only after the copy that last read it has
+// completed; its device buffer is rewritten by a copy queued behind every
+// kernel that read it.
+int32_t commit(reloc_ctx* c, StagingRing& ring, const Blob& bl, uint8_t** dev) {
+  Staging& g = ring.slot[ring.next];
+  ring.next = (ring.next + 1) % kStagingRing;
   if (g.armed) {
     HIP_TRY(hipEventSynchronize(g.ev));
     g.armed = false;
@@ -203,19 +257,41 @@ int32_t grow_scratch(reloc_ctx* c, T*& p, size_t& cap, size_t n) {
   return RELOC_OK;
 }
 
-int32_t ensure_stage_cap(reloc_ctx* c, ServeState& S, size_t n) {
-  if (n <= S.stage_cap) return RELOC_OK;
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (S.hflag) (void)hipHostFree(S.hflag);
-  if (S.hstage) (void)hipHostFree(S.hstage);
-  S.hflag = nullptr;
-  S.hstage = nullptr;
-  S.stage_cap = 0;
+// Stage outputs of a slot that no tick in flight uses.
+int32_t ensure_stage_cap(TickSlot& t, size_t n) {
+  if (!t.e0) HIP_TRY(hipEventCreate(&t.e0));
+  if (!t.e1) HIP_TRY(hipEventCreate(&t.e1));
+  if (n <= t.cap) return RELOC_OK;
+  if (t.hflag) (void)hipHostFree(t.hflag);
+  if (t.hstage) (void)hipHostFree(t.hstage);
+  t.hflag = nullptr;
+  t.hstage = nullptr;
+  t.cap = 0;
   const size_t cap = std::max<size_t>(n, 1024);
-  HIP_TRY(hipHostMalloc((void**)&S.hflag, cap * sizeof(int32_t), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc((void**)&S.hstage, cap * sizeof(uint64_t), hipHostMallocDefault));
-  S.stage_cap = cap;
+  HIP_TRY(hipHostMalloc((void**)&t.hflag, cap * sizeof(int32_t), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&t.hstage, cap * sizeof(uint64_t), hipHostMallocDefault));
+  t.cap = cap;
   return RELOC_OK;
+}
+
+void free_pipe(TickPipe& P) {
+  for (TickSlot& t : P.slot) {
+    if (t.hflag) (void)hipHostFree(t.hflag);
+    if (t.hstage) (void)hipHostFree(t.hstage);
+    if (t.e0) (void)hipEventDestroy(t.e0);
+    if (t.e1) (void)hipEventDestroy(t.e1);
+    t = TickSlot{};
+  }
+  P.inflight.clear();
+}
+
+void free_ring(reloc_ctx* c, StagingRing& r) {
+  for (Staging& g : r.slot) {
+    c->dfree(g.d);
+    if (g.h) (void)hipHostFree(g.h);
+    if (g.ev) (void)hipEventDestroy(g.ev);
+    g = Staging{};
+  }
 }
 
 struct PhaseTimes {
@@ -229,11 +305,15 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-// Ray cast, SMAD and SMAD order of the requests of F; F's flights get a
-// shared arena and start at stage 0.
-int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* pt) {
+// Ray cast, SMAD and SMAD order of the requests of F on c->stream, its
+// descriptors through `ring` (the ring of that stream); F's flights get a
+// shared arena, the group's events, and start at stage 0. Nothing waits
+// for the device.
+int32_t front(reloc_ctx* c, StagingRing& ring, std::vector<Flight*>& F) {
   const int n = (int)F.size();
   if (n == 0) return RELOC_OK;
+  auto G = std::make_shared<FrontGroup>();
+  for (hipEvent_t& e : G->ev) HIP_TRY(hipEventCreate(&e));
   auto A = std::make_shared<Arena>();
   A->c = c;
   std::vector<int64_t> hpre(n + 1, 0);
@@ -282,33 +362,31 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   const size_t o_hp = bl.add(hpre.data(), n + 1);
   const size_t o_tp = bl.add(tpre.data(), n + 1);
   uint8_t* d = nullptr;
-  if (int32_t e = commit(c, S, bl, &d)) return e;
+  if (int32_t e = commit(c, ring, bl, &d)) return e;
   const RayArgs* d_ra = (const RayArgs*)(d + o_ra);
   const int64_t* d_fp = (const int64_t*)(d + o_fp);
   const int64_t* d_hp = (const int64_t*)(d + o_hp);
   const int64_t* d_tp = (const int64_t*)(d + o_tp);
   hipStream_t s = c->stream;
-  HIP_TRY(hipEventRecord(c->ev[0], s));
+  HIP_TRY(hipEventRecord(G->ev[0], s));
   if (nf > 0) HIP_TRY(launch_raycast_smad_fused_batch(d_ra, d_fp, nf, fpre.back(), nw, lds, s));
   for (int i = 0; i < n; ++i)
     if (!c->reqs.at(F[i]->rid).fused && ra[i].coarse != 3) HIP_TRY(launch_raycast(ra[i], s));
-  HIP_TRY(hipEventRecord(c->ev[1], s));
+  HIP_TRY(hipEventRecord(G->ev[1], s));
   for (int i = 0; i < n; ++i)
     if (!c->reqs.at(F[i]->rid).fused) HIP_TRY(launch_coarse(ra[i], s));
-  HIP_TRY(hipEventRecord(c->ev[2], s));
+  HIP_TRY(hipEventRecord(G->ev[2], s));
   // keys2 and vals serve as the sort's scratch
   HIP_TRY(argsort_u64(A->keys, A->keys2, A->vals, A->order, N, n, d_hp, d_tp, tpre[n], max_n, s));
-  HIP_TRY(hipEventRecord(c->ev[3], s));
-  if (pt) {
-    pt->raycast += elapsed(c->ev[0], c->ev[1]);
-    pt->smad += elapsed(c->ev[1], c->ev[2]);
-    pt->sort += elapsed(c->ev[2], c->ev[3]);
-  }
+  HIP_TRY(hipEventRecord(G->ev[3], s));
   for (int i = 0; i < n; ++i) {
     Flight& f = *F[i];
+    f.fg = G;
     f.arena = A;
     f.off = hpre[i];
     f.next_rank = 0;
+    f.plan_rank = 0;
+    f.pending = 0;
     // first ticks as large as the plain path's first launches
     f.spec = std::min(kMaxSpec, plain_stages_per_launch(c->reqs.at(f.rid)));
     f.ticks = 0;
@@ -319,15 +397,37 @@ int32_t front(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* 
   return RELOC_OK;
 }
 
-// One tick over the unfinished flights of F.
-int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* pt) {
+// Whether the group's front phase has ended (its phase times taken then);
+// with wait, blocks until it has.
+bool front_done(FrontGroup& G, bool wait) {
+  if (G.ready) return true;
+  if (wait) {
+    if (hipEventSynchronize(G.ev[3]) != hipSuccess) return false;
+  } else if (hipEventQuery(G.ev[3]) != hipSuccess) {
+    return false;
+  }
+  G.raycast = elapsed(G.ev[0], G.ev[1]);
+  G.smad = elapsed(G.ev[1], G.ev[2]);
+  G.sort = elapsed(G.ev[2], G.ev[3]);
+  G.ready = true;
+  return true;
+}
+
+// Enqueues one tick over the flights of F that are not done and have
+// stages left (from their planned rank on), into the pipe's next slot, on
+// c->stream; *enq tells whether there was any. Nothing waits for the device.
+int32_t enqueue_tick(reloc_ctx* c, TickPipe& P, StagingRing& ring, std::vector<Flight*>& F,
+                     bool* enq) {
+  *enq = false;
   std::vector<TamArgs> items[kTamClasses];
-  std::vector<Flight*> owner[kTamClasses];
   std::vector<StageArgs> st;
   std::vector<Flight*> live;
   for (Flight* f : F)
-    if (!f->done) live.push_back(f);
+    if (!f->done && f->plan_rank < c->reqs.at(f->rid).n_hyp) live.push_back(f);
   if (live.empty()) return RELOC_OK;
+  if (P.inflight.size() >= 2) return fail(RELOC_E_INVALID, "two ticks already in flight");
+  const int si = P.next;
+  TickSlot& T = P.slot[si];
   // stages per request this tick: the speculation schedule, granted oldest
   // request first out of a budget of TAM workgroups, at least one stage each
   std::vector<size_t> by_age(live.size());
@@ -342,35 +442,33 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
     const Flight* f = live[j];
     const Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
-    const int left = (R.n_hyp - f->next_rank + K - 1) / K;
+    const int left = (R.n_hyp - f->plan_rank + K - 1) / K;
     const int64_t bps = (int64_t)K * ((R.prep.info.Ntheta + 15) / 16);
     const int64_t cap = std::max<int64_t>(1, budget / bps);
     nst[j] = (int)std::min<int64_t>(std::min(f->spec, left), cap);
     budget -= nst[j] * bps;
     n_entries += (size_t)nst[j];
   }
-  if (int32_t e = ensure_stage_cap(c, S, n_entries)) return e;
+  if (int32_t e = ensure_stage_cap(T, n_entries)) return e;
+  T.items.clear();
   for (size_t j = 0; j < live.size(); ++j) {
     Flight* f = live[j];
     Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
     const int ns = nst[j];
-    const int nb = std::min(ns * K, R.n_hyp - f->next_rank);
-    TamArgs a = tam_args(c, R, f->next_rank, nb, nullptr);
+    const int nb = std::min(ns * K, R.n_hyp - f->plan_rank);
+    TamArgs a = tam_args(c, R, f->plan_rank, nb, nullptr);
     a.order = f->arena->order + f->off;
     a.best = f->arena->best + f->off;
     const int cls = tam_class(a);
     if (cls < 0) return fail(RELOC_E_INVALID, "TAM configuration outside the kernel classes");
     items[cls].push_back(a);
-    owner[cls].push_back(f);
-    f->tentry = (int)st.size();
-    f->tstages = ns;
-    f->tnb = nb;
+    T.items.push_back(TickItem{f, f->plan_rank, ns, nb, (int)st.size()});
     for (int b = 0; b < ns; ++b) {
-      const int r0 = f->next_rank + b * K;
+      const int r0 = f->plan_rank + b * K;
       const size_t e = st.size();
-      st.push_back(StageArgs{a.best, r0, std::min(K, R.n_hyp - r0), R.prm.tau, S.hstage + e,
-                             S.hflag + e});
+      st.push_back(StageArgs{a.best, r0, std::min(K, R.n_hyp - r0), R.prm.tau, T.hstage + e,
+                             T.hflag + e});
     }
   }
   Blob bl;
@@ -394,76 +492,103 @@ int32_t tick(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, PhaseTimes* p
   }
   const size_t o_st = bl.add(st.data(), st.size());
   uint8_t* d = nullptr;
-  if (int32_t e = commit(c, S, bl, &d)) return e;
+  if (int32_t e = commit(c, ring, bl, &d)) return e;
   hipStream_t s = c->stream;
-  HIP_TRY(hipEventRecord(c->ev[3], s));
+  HIP_TRY(hipEventRecord(T.e0, s));
   for (int k = 0; k < kTamClasses; ++k) {
     if (!blocks[k]) continue;
     HIP_TRY(launch_tam_batch(k, (const TamArgs*)(d + o_items[k]), (const int64_t*)(d + o_pre[k]),
                              (int)items[k].size(), blocks[k], lds[k], s));
   }
   // local refinement of each stage's best poses, per refining request
-  for (Flight* f : live) {
+  for (const TickItem& it : T.items) {
+    Flight* f = it.f;
     Request& R = c->reqs.at(f->rid);
     const int kr = R.prm.refine_k;
     if (kr <= 0) continue;
-    RefineArgs fa = refine_args(c, R, f->tstages * kr);
+    RefineArgs fa = refine_args(c, R, it.ns * kr);
     fa.t.order = f->arena->order + f->off;
     fa.t.best = f->arena->best + f->off;
-    HIP_TRY(launch_refine_select(fa.t.best, f->next_rank, R.prm.batch_k, R.n_hyp, f->tstages,
-                                 kr, R.rsel, R.rbest, s));
+    HIP_TRY(launch_refine_select(fa.t.best, it.r0, R.prm.batch_k, R.n_hyp, it.ns, kr, R.rsel,
+                                 R.rbest, s));
     HIP_TRY(launch_refine(fa, s));
     HIP_TRY(launch_refine_commit(fa, s));
   }
   HIP_TRY(launch_stage_reduce_batch((const StageArgs*)(d + o_st), (int)st.size(), s));
-  HIP_TRY(hipEventRecord(c->ev[4], s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (pt) pt->tam += elapsed(c->ev[3], c->ev[4]);
+  HIP_TRY(hipEventRecord(T.e1, s));
+  for (const TickItem& it : T.items) {
+    Flight* f = it.f;
+    f->plan_rank += it.nb;
+    ++f->pending;
+    // the first two ticks as planned, then twice as many stages each tick
+    if (++f->ticks >= 2) f->spec = std::min(kMaxSpec, f->spec * 2);
+  }
+  P.inflight.push_back(si);
+  P.next ^= 1;
+  *enq = true;
+  return RELOC_OK;
+}
+
+// Waits for the oldest tick in flight and applies its stop flags: a request
+// stops at the first of its stages whose best T exceeds tau (its share of
+// later ticks is discarded), or advances by the tick's ranks.
+int32_t complete_tick(reloc_ctx* c, TickPipe& P, PhaseTimes* pt) {
+  if (P.inflight.empty()) return RELOC_OK;
+  TickSlot& T = P.slot[P.inflight.front()];
+  P.inflight.pop_front();
+  HIP_TRY(hipEventSynchronize(T.e1));
+  const float ms = elapsed(T.e0, T.e1);
+  if (pt) pt->tam += ms;
   const auto now = std::chrono::steady_clock::now();
-  for (Flight* f : live) {
+  for (const TickItem& it : T.items) {
+    Flight* f = it.f;
+    --f->pending;
+    f->tam_ms += ms;
+    if (f->done) continue;                  // stopped in an earlier tick
     const Request& R = c->reqs.at(f->rid);
     const int K = R.prm.batch_k;
     int hit = -1;
-    for (int b = 0; b < f->tstages; ++b)
-      if (S.hflag[f->tentry + b]) {
+    for (int b = 0; b < it.ns; ++b)
+      if (T.hflag[it.entry + b]) {
         hit = b;
         break;
       }
     if (!std::isnan(R.prm.tau)) {
-      const int used = hit >= 0 ? hit + 1 : f->tstages;
+      const int used = hit >= 0 ? hit + 1 : it.ns;
       for (int b = 0; b < used; ++b) {
-        const double T = (double)score_of_key((uint32_t)(S.hstage[f->tentry + b] >> 32));
-        if (T >= R.prm.tau - 1e-4 && T <= R.prm.tau + 1e-4) f->fragile = true;
+        const double Tb = (double)score_of_key((uint32_t)(T.hstage[it.entry + b] >> 32));
+        if (Tb >= R.prm.tau - 1e-4 && Tb <= R.prm.tau + 1e-4) f->fragile = true;
       }
     }
     if (hit >= 0) {
       f->stages += hit + 1;
-      f->n_eval = std::min(R.n_hyp, f->next_rank + (hit + 1) * K);
+      f->n_eval = std::min(R.n_hyp, it.r0 + (hit + 1) * K);
       f->done = true;
       f->stopped = true;
       continue;
     }
-    f->stages += f->tstages;
-    f->next_rank += f->tnb;
+    f->stages += it.ns;
+    f->next_rank = it.r0 + it.nb;
     f->n_eval = f->next_rank;
     if (f->next_rank >= R.n_hyp) {
       f->done = true;
       continue;
     }
-    if (++f->ticks >= 2) f->spec = std::min(kMaxSpec, f->spec * 2);
     if (R.prm.deadline_s > 0 &&
         std::chrono::duration<double>(now - f->t_start).count() > R.prm.deadline_s) {
       f->done = true;
       f->status = RELOC_E_TIMEOUT;
     }
   }
+  T.items.clear();
   return RELOC_OK;
 }
 
 // Ranked poses of finished flights: rows[i] receives min(cap[i], k_out,
 // n_eval) rows of flight F[i].
-int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::vector<int>& cap,
-             std::vector<std::vector<PoseRow>>* rows, PhaseTimes* pt) {
+int32_t rank(reloc_ctx* c, ServeState& S, StagingRing& ring, std::vector<Flight*>& F,
+             const std::vector<int>& cap, std::vector<std::vector<PoseRow>>* rows,
+             PhaseTimes* pt) {
   const int n = (int)F.size();
   rows->assign(n, {});
   if (n == 0) return RELOC_OK;
@@ -517,7 +642,7 @@ int32_t rank(reloc_ctx* c, ServeState& S, std::vector<Flight*>& F, const std::ve
   const size_t o_rp = bl.add(rpre.data(), n + 1);
   const size_t o_tp = bl.add(tpre.data(), n + 1);
   uint8_t* d = nullptr;
-  if (int32_t e = commit(c, S, bl, &d)) return e;
+  if (int32_t e = commit(c, ring, bl, &d)) return e;
   const RankArgs* d_ra = (const RankArgs*)(d + o_ra);
   const int64_t* d_kp = (const int64_t*)(d + o_kp);
   const int64_t* d_rp = (const int64_t*)(d + o_rp);
@@ -651,45 +776,106 @@ bool serve_round(reloc_ctx* c, ServeState& S) {
     }
     S.stats.queued = (int32_t)S.pending.size();
   }
-  std::vector<Flight*> fresh;
-  const size_t base = S.active.size();
-  for (Ticket* t : adm) {
-    Request R = t->R;   // host part; the ticket keeps its copy
-    int32_t e = build_request(c, R);
-    if (e != RELOC_OK) {
-      release_request(c, R);
-      finish_ticket(S, t, e);
-      continue;
+  int32_t err = RELOC_OK;
+  // the admitted requests' tables and front phase go to the front stream,
+  // beside the ticks in flight on the context's stream
+  if (!adm.empty()) {
+    if (!S.sfront && hipStreamCreateWithFlags(&S.sfront, hipStreamNonBlocking) != hipSuccess)
+      S.sfront = nullptr;               // then everything runs on the context's stream
+    const hipStream_t main = c->stream;
+    c->stream = S.sfront ? S.sfront : main;
+    StagingRing& fr = S.sfront ? S.fring : S.ring;
+    std::vector<Flight*> fresh;
+    for (Ticket* t : adm) {
+      Request R = t->R;   // host part; the ticket keeps its copy
+      int32_t e = build_request(c, R);
+      if (e != RELOC_OK) {
+        release_request(c, R);
+        finish_ticket(S, t, e);
+        continue;
+      }
+      const int id = c->next_id++;
+      c->reqs[id] = std::move(R);
+      S.active.emplace_back();
+      Flight& f = S.active.back();
+      f.rid = id;
+      f.ticket = t->id;
+      f.t_start = t->t_submit;
+      fresh.push_back(&f);
     }
-    const int id = c->next_id++;
-    c->reqs[id] = std::move(R);
-    Flight f;
-    f.rid = id;
-    f.ticket = t->id;
-    f.t_start = t->t_submit;
-    S.active.push_back(f);
+    const int32_t e = front(c, fr, fresh);
+    if (e != RELOC_OK) {
+      (void)hipStreamSynchronize(c->stream);   // what the front queued ends first
+      for (Flight* f : fresh) {
+        f->done = true;
+        f->status = e;
+      }
+    }
+    c->stream = main;
   }
-  for (size_t i = base; i < S.active.size(); ++i) fresh.push_back(&S.active[i]);
-  PhaseTimes pt;
-  int32_t err = front(c, S, fresh, &pt);
-  std::vector<Flight*> all;
-  for (Flight& f : S.active) all.push_back(&f);
-  if (err == RELOC_OK) err = tick(c, S, all, &pt);
+  // every request with its front queued joins the ticks: the context's
+  // stream waits (on the device) for the fronts still running, which run
+  // beside the tick in flight
+  std::vector<Flight*> ready;
+  std::vector<FrontGroup*> waits;
+  for (Flight& f : S.active) {
+    if (f.done || !f.fg) continue;
+    if (!front_done(*f.fg, false) &&
+        std::find(waits.begin(), waits.end(), f.fg.get()) == waits.end())
+      waits.push_back(f.fg.get());
+    ready.push_back(&f);
+  }
+  for (FrontGroup* g : waits)
+    if (err == RELOC_OK && hipStreamWaitEvent(c->stream, g->ev[3], 0) != hipSuccess)
+      err = fail(RELOC_E_DEVICE, "stream wait on a front phase failed");
+  TickPipe& P = S.pipe_serve;
+  bool enq = false;
+  if (err == RELOC_OK && P.inflight.size() < 2) err = enqueue_tick(c, P, S.ring, ready, &enq);
+  // the stop flags of the oldest tick, read once a newer one is queued
+  // behind it, when several requests are in flight (one alone reads its
+  // flags at once: nothing to overlap, and no speculative tick to wait for)
+  const size_t depth = ready.size() >= 2 ? 2 : 1;
+  if (err == RELOC_OK && !P.inflight.empty() && (P.inflight.size() >= depth || !enq))
+    err = complete_tick(c, P, nullptr);
+  else if (err == RELOC_OK && !enq && P.inflight.empty())
+    for (Flight& f : S.active)       // only front phases running: wait for one
+      if (!f.done && f.fg && !f.fg->ready) {
+        (void)front_done(*f.fg, true);
+        break;
+      }
   if (err != RELOC_OK) {
+    // the device work queued so far ends before anything is released
+    (void)hipStreamSynchronize(c->stream);
+    if (S.sfront) (void)hipStreamSynchronize(S.sfront);
+    if (S.srank) (void)hipStreamSynchronize(S.srank);
+    P.inflight.clear();
     for (Flight& f : S.active) {
       f.done = true;
-      f.status = err;
+      f.pending = 0;
+      if (f.status == RELOC_OK) f.status = err;
     }
   }
+  // finished requests that no tick in flight covers: rank, answer, release
   std::vector<Flight*> fin;
   std::vector<int> caps;
   for (Flight& f : S.active)
-    if (f.done) {
+    if (f.done && f.pending == 0) {
+      if (f.fg) (void)front_done(*f.fg, true);   // its front work has ended too
       fin.push_back(&f);
       caps.push_back(INT32_MAX);
     }
   std::vector<std::vector<PoseRow>> rows;
-  if (!fin.empty() && err == RELOC_OK) err = rank(c, S, fin, caps, &rows, &pt);
+  PhaseTimes rpt;
+  if (!fin.empty() && err == RELOC_OK) {
+    // on a stream of its own: the answer does not wait for the tick in
+    // flight (which no finished request takes part in)
+    if (!S.srank && hipStreamCreateWithFlags(&S.srank, hipStreamNonBlocking) != hipSuccess)
+      S.srank = nullptr;
+    const hipStream_t main = c->stream;
+    c->stream = S.srank ? S.srank : main;
+    err = rank(c, S, S.srank ? S.rring : S.ring, fin, caps, &rows, &rpt);
+    c->stream = main;
+  }
   for (size_t i = 0; i < fin.size(); ++i) {
     Flight& f = *fin[i];
     Ticket* t = ticket_of(S, f.ticket);
@@ -702,6 +888,13 @@ bool serve_round(reloc_ctx* c, ServeState& S) {
         const float total =
             std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                      t->t_submit).count();
+        PhaseTimes pt = rpt;
+        if (f.fg) {
+          pt.raycast = f.fg->raycast;
+          pt.smad = f.fg->smad;
+          pt.sort = f.fg->sort;
+        }
+        pt.tam = f.tam_ms;
         fill_stats(R, f, pt, total, &t->st);
       }
       finish_ticket(S, t, status);
@@ -709,10 +902,9 @@ bool serve_round(reloc_ctx* c, ServeState& S) {
     release_request(c, R);
     c->reqs.erase(f.rid);
     f.arena.reset();
+    f.fg.reset();
   }
-  S.active.erase(std::remove_if(S.active.begin(), S.active.end(),
-                                [](const Flight& f) { return f.done; }),
-                 S.active.end());
+  S.active.remove_if([](const Flight& f) { return f.done && f.pending == 0; });
   {
     std::lock_guard<std::mutex> lk(S.qmu);
     ++S.stats.ticks;
@@ -760,6 +952,12 @@ void ctx_stop_serving(reloc_ctx* c) {
   std::lock_guard<std::recursive_mutex> cl(c->mu);
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (hipStream_t* q : {&S->sfront, &S->srank})
+    if (*q) {
+      (void)hipStreamSynchronize(*q);
+      (void)hipStreamDestroy(*q);
+      *q = nullptr;
+    }
   for (Flight& f : S->active) {
     auto it = c->reqs.find(f.rid);
     if (it != c->reqs.end()) {
@@ -769,19 +967,17 @@ void ctx_stop_serving(reloc_ctx* c) {
     f.arena.reset();
   }
   S->active.clear();
-  for (Staging& g : S->ring) {
-    c->dfree(g.d);
-    if (g.h) (void)hipHostFree(g.h);
-    if (g.ev) (void)hipEventDestroy(g.ev);
-  }
+  free_ring(c, S->ring);
+  free_ring(c, S->fring);
+  free_ring(c, S->rring);
+  free_pipe(S->pipe_batch);
+  free_pipe(S->pipe_serve);
   c->dfree(S->rk1);
   c->dfree(S->rk2);
   c->dfree(S->rrows);
   c->dfree(S->rmarg);
   c->dfree(S->rp1);
   c->dfree(S->rp2);
-  if (S->hflag) (void)hipHostFree(S->hflag);
-  if (S->hstage) (void)hipHostFree(S->hstage);
   {
     // polls still waiting see stop and return; the state outlives them
     std::unique_lock<std::mutex> lk(S->qmu);
@@ -824,16 +1020,29 @@ int32_t reloc_run_batch(reloc_ctx* c, int32_t n, const int32_t* request_ids, rel
     F[i] = &fl[i];
   }
   PhaseTimes pt;
-  if (int32_t e = front(c, S, F, &pt)) return e;
+  // on an error, the device work queued so far ends before the flights'
+  // buffers go
+  auto bail = [&](int32_t e) {
+    (void)hipStreamSynchronize(c->stream);
+    S.pipe_batch.inflight.clear();
+    return e;
+  };
+  if (int32_t e = front(c, S.ring, F)) return bail(e);
+  if (!front_done(*F[0]->fg, true)) return bail(fail(RELOC_E_DEVICE, "front phase failed"));
+  pt.raycast = F[0]->fg->raycast;
+  pt.smad = F[0]->fg->smad;
+  pt.sort = F[0]->fg->sort;
+  // one tick at a time: a batch has no later arrivals to overlap with
+  TickPipe& P = S.pipe_batch;
   for (;;) {
-    bool any = false;
-    for (Flight* f : F) any |= !f->done;
-    if (!any) break;
-    if (int32_t e = tick(c, S, F, &pt)) return e;
+    bool enq = false;
+    if (int32_t e = enqueue_tick(c, P, S.ring, F, &enq)) return bail(e);
+    if (!enq) break;
+    if (int32_t e = complete_tick(c, P, &pt)) return bail(e);
   }
   std::vector<int> caps(n, std::max(0, cap));
   std::vector<std::vector<PoseRow>> rows;
-  if (int32_t e = rank(c, S, F, caps, &rows, &pt)) return e;
+  if (int32_t e = rank(c, S, S.ring, F, caps, &rows, &pt)) return bail(e);
   const float total =
       std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < n; ++i) {
