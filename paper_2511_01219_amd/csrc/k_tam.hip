@@ -632,8 +632,9 @@ __global__ void tam_offsets_kernel(const int2* __restrict__ beams, int nv,
   const int2 bz = beams[v];
   const int2 U = dirs[bz.x + g];               // the table is stored twice: no wrap
   const int64_t half = (int64_t)1 << 27;
-  // maps are at most 32767 cells a side, so an offset of 32767 or more
-  // leaves the map from any cell: clamping keeps it off the map
+  // ranges stay below 64 m at cells of at least 1/32 m, so an offset is at
+  // most 2048 cells and 16 bits hold it; the clamp only guards the packing
+  // (maps are at most 32767 cells a side, so 32767 leaves the map anyway)
   const int64_t dx = (half + (int64_t)bz.y * U.x) >> 28;
   const int64_t dy = (half + (int64_t)bz.y * U.y) >> 28;
   const int cx = (int)(dx < -32767 ? -32767 : (dx > 32767 ? 32767 : dx));

@@ -96,6 +96,10 @@ def test_load_map_rejects_empty_and_bad(ctx):
     with pytest.raises(reloc.RelocError) as ei:
         ctx.load_map(np.full((10, 10), 100, np.int8), resolution=0.01)
     assert ei.value.code == reloc.E_INVALID
+    # sides above 32767 cells are refused before any device work
+    with pytest.raises(reloc.RelocError) as ei:
+        ctx.load_map(np.full((2, 32768), 100, np.int8))
+    assert ei.value.code == reloc.E_INVALID
 
 
 # --------------------------------------------------------------------------- a1
@@ -372,6 +376,41 @@ def test_tam_off_map_endpoints(ctx):
     q = np.repeat(hyp[order[:30]], 90, axis=0)
     kk = np.tile(np.arange(90), 30)
     ref = oracle.tam(k, 0.05, pr, q, kk)[:, 0].reshape(30, 90)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
+def test_tam_widest_map_edges(ctx):
+    """A map 32767 cells wide (the largest side the library takes) and 40
+    tall: hypotheses at both ends, beams of 2.5 m and of 40 m leaving the
+    map across the left wall, the open right edge and the top and bottom
+    rows, so every endpoint class of the tiled plane (inside, the sentinel
+    column at x = W, the sentinel row at y = H, negative coordinates) meets
+    the widest tile row."""
+    W, H = 32767, 40
+    occ = np.zeros((H, W), np.int8)
+    occ[0, :W - 200] = 100
+    occ[H - 1, :W - 200] = 100
+    occ[:, 0] = 100
+    occ[12:16, 30:34] = 100
+    occ[20:26, W - 40:W - 36] = 100
+    rng = np.random.default_rng(11)
+    xs = np.concatenate([rng.integers(3, 60, 15), rng.integers(W - 60, W, 15)])
+    ys = rng.integers(3, H - 3, 30)
+    keep = occ[ys, xs] == 0
+    hyp = np.stack([xs[keep], ys[keep]], 1).astype(np.int32)
+    n = len(hyp)
+    z = np.full(360, 2.5, np.float32)
+    z[::3] = 40.0
+    inc = 2 * math.pi / 360
+    _case("tam widest map (%d x %d), %d hypotheses at both ends" % (W, H, n))
+    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, -math.pi, inc, 60.0, n_theta=90)
+    k = oracle.edt(occ)
+    _, _, order = ctx.debug_smad(rid, n)
+    T, ts, ks = ctx.debug_tam(rid, 0, n, 90)
+    q = np.repeat(hyp[order[:n]], 90, axis=0)
+    kk = np.tile(np.arange(90), n)
+    ref = oracle.tam(k, 0.05, pr, q, kk)[:, 0].reshape(n, 90)
     _check_tam(T, ts, ks, ref)
     _cleanup(ctx, m, sid, rid)
 
