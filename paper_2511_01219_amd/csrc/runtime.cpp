@@ -504,9 +504,42 @@ int32_t build_request(reloc_ctx* c, Request& R) {
   R.off_stride = 64 * tam_keys_per_lane(nv);
   R.off = req_alloc<uint32_t>(c, R, (size_t)Ng * (size_t)R.off_stride);
   if (!R.off) return RELOC_E_NOMEM;
-  if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
+  if (R.carve_base) {
+    // no allocation of any kind: a copy from the host vectors, drained
+    // before they go out of scope
+    if (int32_t e = upload(c, tables, tb.b.data(), tb.b.size())) return e;
+    HIP_TRY(launch_tam_offsets(R.beams, nv, R.dirs, Ng, R.off_stride, R.off, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RELOC_OK;
+  }
+  // through pinned staging: the request's kernels queue behind the copy and
+  // the host does not wait for it
+  if (int32_t e = upload_staged(c, tables, tb.b.data(), tb.b.size())) return e;
   HIP_TRY(launch_tam_offsets(R.beams, nv, R.dirs, Ng, R.off_stride, R.off, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  return RELOC_OK;
+}
+
+int32_t upload_staged(reloc_ctx* c, void* dst, const void* src, size_t n) {
+  if (n == 0) return RELOC_OK;
+  const int i = c->tstage_next;
+  c->tstage_next ^= 1;
+  if (c->tstage_armed[i]) {
+    HIP_TRY(hipEventSynchronize(c->tstage_ev[i]));
+    c->tstage_armed[i] = false;
+  }
+  if (n > c->tstage_cap[i]) {
+    if (c->tstage[i]) (void)hipHostFree(c->tstage[i]);
+    c->tstage[i] = nullptr;
+    c->tstage_cap[i] = 0;
+    const size_t cap = std::max(n, (size_t)1 << 16);
+    HIP_TRY(hipHostMalloc(&c->tstage[i], cap, hipHostMallocDefault));
+    c->tstage_cap[i] = cap;
+  }
+  if (!c->tstage_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c->tstage_ev[i], hipEventDisableTiming));
+  std::memcpy(c->tstage[i], src, n);
+  HIP_TRY(hipMemcpyAsync(dst, c->tstage[i], n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->tstage_ev[i], c->stream));
+  c->tstage_armed[i] = true;
   return RELOC_OK;
 }
 
@@ -1041,6 +1074,10 @@ void reloc_ctx_destroy(reloc_ctx* c) {
       if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->prows) (void)hipHostFree(c->prows);
+    for (int i = 0; i < 2; ++i) {
+      if (c->tstage[i]) (void)hipHostFree(c->tstage[i]);
+      if (c->tstage_ev[i]) (void)hipEventDestroy(c->tstage_ev[i]);
+    }
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;

@@ -176,6 +176,13 @@ struct reloc_ctx {
   void* pinned = nullptr;         // small pinned staging buffer
   void* prows = nullptr;          // pinned result rows
   size_t prows_cap = 0;
+  // two pinned staging buffers for request tables: a copy out of one is
+  // asynchronous, and the buffer is rewritten only after its event
+  void* tstage[2] = {};
+  size_t tstage_cap[2] = {};
+  hipEvent_t tstage_ev[2] = {};
+  bool tstage_armed[2] = {};
+  int tstage_next = 0;
 
   // Device blocks are handed out in size classes (powers of two up to
   // 1 MiB, then multiples of 2 MiB). A freed block of at most
@@ -362,6 +369,11 @@ int32_t upload(reloc_ctx* c, T* dst, const T* src, size_t count) {
   HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
   return RELOC_OK;
 }
+
+// Copies n bytes to the device through the context's next pinned staging
+// buffer, on c->stream; returns without waiting for the copy (the source
+// may go out of scope at once).
+int32_t upload_staged(reloc_ctx* c, void* dst, const void* src, size_t n);
 
 }  // namespace reloc
 
