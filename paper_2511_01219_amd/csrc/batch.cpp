@@ -25,7 +25,9 @@
 // run start at once on the front stream and join the ticks at the next
 // stage boundary after their front; two ticks are in flight, so the device
 // works on tick t + 1 while the host reads the flags of tick t (a request
-// that stopped in tick t has its share of tick t + 1 discarded).
+// that stopped in tick t has its share of tick t + 1 discarded). A small
+// request that finds the device idle and nobody else waiting runs the plain
+// path instead.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -40,6 +42,7 @@ namespace {
 constexpr int kMaxSpec = kMaxTickStages;
 constexpr int kSmallSortGroup = 8;      // front groups up to this size sort per request
 constexpr int64_t kTickBlocks = 65536;  // TAM workgroups one tick may grant beyond one stage each
+constexpr int kSoloMaxHyp = 8000;       // largest request served alone on the plain path
 
 // Contiguous buffers of one front-phase group: SMAD sort keys / values, the
 // SMAD order and the per-rank best of every request of the group.
@@ -777,6 +780,45 @@ bool serve_round(reloc_ctx* c, ServeState& S) {
     S.stats.queued = (int32_t)S.pending.size();
   }
   int32_t err = RELOC_OK;
+  // a small request on an idle device with nothing else waiting runs the
+  // plain path at once: nothing to batch with, no stream hand-offs, and
+  // (small) it cannot hold later arrivals back for long; a large one is
+  // run in ticks, which later arrivals join
+  bool alone = false;
+  if (adm.size() == 1 && S.active.empty() && S.pipe_serve.inflight.empty() &&
+      adm[0]->R.n_hyp <= kSoloMaxHyp) {
+    std::lock_guard<std::mutex> lk(S.qmu);
+    alone = S.pending.empty();
+  }
+  if (alone) {
+    Ticket* t = adm[0];
+    Request R = t->R;
+    int32_t e = build_request(c, R);
+    if (e == RELOC_OK) {
+      std::vector<reloc_pose> out((size_t)std::max(1, R.rows_cap));
+      int32_t n = 0;
+      reloc_stats st{};
+      e = run_request(c, R, out.data(), R.rows_cap, &n, &st, nullptr);
+      if (e == RELOC_OK || e == RELOC_E_TIMEOUT) {
+        out.resize((size_t)n);
+        t->poses = std::move(out);
+        st.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                               t->t_submit).count();
+        t->st = st;
+      }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    release_request(c, R);
+    finish_ticket(S, t, e);
+    {
+      std::lock_guard<std::mutex> lk(S.qmu);
+      ++S.stats.ticks;
+      S.stats.busy_s +=
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    S.dcv.notify_all();
+    return true;
+  }
   // the admitted requests' tables and front phase go to the front stream,
   // beside the ticks in flight on the context's stream
   if (!adm.empty()) {
