@@ -103,7 +103,7 @@ struct ThetaSrc {
     if (k >= Nt) return false;
     x = ix;
     y = iy;
-    g = (int)(((int64_t)o * k) % Ng);
+    g = o * k;            // o = floor(Ng / Nt) and k < Nt: below Ng, no reduction
     return true;
   }
   __device__ __forceinline__ bool has(int j) const { return k0 + j < Nt; }
