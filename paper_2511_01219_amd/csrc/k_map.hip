@@ -83,19 +83,20 @@ __global__ void edt_rows_kernel(const int32_t* __restrict__ g, int W, int H,
   k[(size_t)y * W + x] = best == INT64_MAX ? 0xFFFFFFFFu : (uint32_t)best;
 }
 
-// TAM plane: 2 k per cell in 8 x 4 tiles, the sentinel 2^32 - 1 in column
-// W and row H (and the unused padding of the last tiles).
+// TAM plane: 2 k per cell in strips of 8 columns, the sentinel 2^32 - 1 in
+// column W and row H (and the padding of the last strip and rows); one
+// entry per thread, written in plane order.
 __global__ void tam_plane_kernel(const uint32_t* __restrict__ k, int W, int H,
                                  uint32_t* __restrict__ plane) {
-  const uint32_t tx = tam_plane_tx(W);
-  const size_t tw = (size_t)tx * 8;                 // plane columns, padding included
+  const size_t per_strip = (size_t)8 * tam_plane_rows(H);
   const size_t n = tam_plane_entries(W, H);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t y = (uint32_t)(i / tw), x = (uint32_t)(i - (size_t)y * tw);
+  const size_t st = i / per_strip, r = i - st * per_strip;
+  const uint32_t y = (uint32_t)(r >> 3), x = (uint32_t)(st * 8 + (r & 7));
   uint32_t v = 0xFFFFFFFFu;
   if (x < (uint32_t)W && y < (uint32_t)H) v = 2u * k[(size_t)y * W + x];
-  plane[tam_plane_index(x, y, tx)] = v;
+  plane[i] = v;
 }
 
 }  // namespace

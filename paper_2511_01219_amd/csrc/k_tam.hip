@@ -11,8 +11,9 @@
 // projection in exact fixed point). The request's offset table holds every
 // (g, v) offset, so a lookup is one coalesced offset load (four beams per
 // lane at a time), two clamps and one 4-byte gather from the map's TAM
-// plane: 2 k per cell in 8 x 4 tiles (an endpoint run along a wall in any
-// direction stays within few 128-byte lines), with a sentinel column and
+// plane: 2 k per cell in strips of 8 columns, so a 128-byte line holds 8 x 4
+// cells (an endpoint run along a wall in any direction stays within few
+// lines) and the index is one multiply-add, with a sentinel column and
 // row 2^32 - 1 that endpoints off the map (and padded beam slots) are
 // clamped onto, so no lookup needs a mask; sqrt(k) in Q16 is computed.
 // The likelihood l(k) of eq. 23 is monotone non-increasing in k, so the
@@ -80,6 +81,26 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
   return ((uint64_t)hi << 32) | lo;
+}
+
+// A 64-bit running sum of 32-bit values kept as two words: an add with carry
+// out and an add of the carry, so no zeroed upper word is held beside each
+// value in flight.
+struct Sum64 {
+  uint32_t lo = 0, hi = 0;
+  __device__ __forceinline__ void add(uint32_t v) {
+    uint32_t c;
+    lo = __builtin_addc(lo, v, 0u, &c);
+    hi += c;
+  }
+  __device__ __forceinline__ uint64_t get() const { return ((uint64_t)hi << 32) | lo; }
+};
+
+// sqrt(k) 2^16 (the distance in Q16 cells) from a plane entry v = 2 k, as
+// sqrt(v) sqrt(2) 2^15 truncated: no shift and no separate rounding step.
+// FP32: a relative error of a few 2^-24 and at most one Q16 unit per beam.
+__device__ __forceinline__ uint32_t q16_sqrt_half(uint32_t v) {
+  return (uint32_t)(__fsqrt_rn((float)v) * 0x1.6a09e6p+15f);
 }
 
 // The 16 poses of one workgroup come from a pose source: has(j) tells
@@ -215,13 +236,13 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
   };
   const char* __restrict__ plane = reinterpret_cast<const char*>(a.plane);
-  const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, tx = tam_plane_tx(a.W);
+  const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, rows1 = tam_plane_rows(a.H) - 1u;
   const uint32_t kcap2 = 2u * (uint32_t)a.kcap, key_off = (uint32_t)a.key_off;
   // the sentinel's share of a sq sum, by the same instructions as a slot's
   // (the empty asm keeps the compiler from folding it with other rounding)
-  uint32_t s_half = 0x7FFFFFFFu;
-  asm volatile("" : "+v"(s_half));
-  const uint32_t sq_sent = __float2uint_rn(__fsqrt_rn((float)s_half) * 65536.0f);
+  uint32_t s_raw = 0xFFFFFFFFu;
+  asm volatile("" : "+v"(s_raw));
+  const uint32_t sq_sent = q16_sqrt_half(s_raw);
 
   // per-pose results parked in lane g
   int64_t p_sl = 0;
@@ -240,7 +261,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     // included (so off-map and padded slots hold 2 kcap here; the counts
     // and sums below move them to key_off or drop them)
     uint32_t keys[R];
-    uint64_t sumk = 0, sums = 0;
+    Sum64 sumk_a, sums_a;
     uint32_t n_sent = 0;
 #pragma unroll
     for (int b = 0; b < R / SB; ++b) {
@@ -259,7 +280,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
         // off the map (either side) clamps onto the sentinel column / row
         const uint32_t ex = (uint32_t)px + (uint32_t)(int32_t)(int16_t)(o[s2] & 0xFFFFu);
         const uint32_t ey = (uint32_t)py + (uint32_t)((int32_t)o[s2] >> 16);
-        idx[s2] = tam_plane_index(min(ex, Wc), min(ey, Hc), tx);
+        idx[s2] = tam_plane_index(min(ex, Wc), min(ey, Hc), rows1);
       }
       // 32-bit byte offsets from the plane base (at most 2^32 - 4)
       uint32_t v[SB];
@@ -269,12 +290,12 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
 #pragma unroll
       for (int s2 = 0; s2 < SB; ++s2) {
         const uint32_t k2 = v[s2];
-        // round(sqrt(k) 2^16), the distance in Q16 cells, for every slot
-        // (the sentinel's share is taken back out below): no branch
-        const uint32_t sq = __float2uint_rn(__fsqrt_rn((float)(k2 >> 1)) * 65536.0f);
+        // sqrt(k) in Q16 cells for every slot (the sentinel's share is
+        // taken back out below): no branch
+        const uint32_t sq = q16_sqrt_half(k2);
         keys[SB * b + s2] = min(k2, kcap2);
-        sumk += k2;
-        sums += sq;
+        sumk_a.add(k2);
+        sums_a.add(sq);
         n_sent += k2 & 1u;                             // the sentinel is the one odd entry
       }
       // one gather batch at a time: without this the scheduler issues every
@@ -282,6 +303,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       __builtin_amdgcn_sched_barrier(0);
     }
     // wavefront totals first: the selection needs the off-map count
+    uint64_t sumk = sumk_a.get(), sums = sums_a.get();
     sums += (uint64_t)n_sent << 48;     // sq sums stay below 2^44
     sumk = wave_sum64(sumk);
     sums = wave_sum64(sums);
@@ -303,9 +325,12 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
         return (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
       };
       const int top = 31 - __builtin_clz(kcap2);
+      // when key_off is even every key is: no odd candidate can then be the
+      // threshold, and the bit-0 round is skipped
+      const int low = (int)(key_off & 1u) ^ 1;
       uint32_t tkey = 0;
       int below = 0;
-      for (int bit = top; bit >= 0; --bit) {
+      for (int bit = top; bit >= low; --bit) {
         const uint32_t cand = tkey | (1u << bit);
         int cnt = corr(cand);
 #pragma unroll
@@ -414,6 +439,12 @@ __device__ __forceinline__ void tam_block(const TamArgs& a, int i, int kb, int32
   tam_tile<R, KB, FULL>(a, src, smem);
 }
 
+// Wavefronts per SIMD the register allocation of a TAM launch aims for:
+// 8 (at most 64 VGPRs) up to 24 keys per lane, which fit it without spills
+// (and schedule better for it: TAM at the stress workload 1.55 -> 1.49 ms);
+// no target above.
+constexpr int tam_waves(int R) { return R <= 24 ? 8 : 1; }
+
 // Workgroup b of an n-workgroup grid runs on XCD b % 8 (round-robin
 // dispatch); the returned index gives every XCD one contiguous slice of
 // [0, n), so the orientation tiles of one hypothesis (whose endpoints touch
@@ -425,7 +456,8 @@ __device__ __forceinline__ int xcd_slice(int b, int n) {
 }
 
 template <int R, int KB, bool FULL>
-__global__ __launch_bounds__(TB) void tam_kernel(TamArgs a) {
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(tam_waves(R))))
+void tam_kernel(TamArgs a) {
   extern __shared__ int32_t smem[];
   const int ntb = tam_tiles_per_rank(a);
   const int L = xcd_slice(blockIdx.x, gridDim.x);
@@ -591,8 +623,8 @@ __device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_
 // TAM over several rank ranges (of one or several requests) in one launch:
 // item e owns blocks [prefix[e], prefix[e + 1]) = nb x ceil(Nt / 16).
 template <int R, int KB, bool FULL>
-__global__ __launch_bounds__(TB) void tam_batch_kernel(const TamArgs* __restrict__ items,
-                                                       const int64_t* __restrict__ prefix, int n) {
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(tam_waves(R))))
+void tam_batch_kernel(const TamArgs* __restrict__ items, const int64_t* __restrict__ prefix, int n) {
   extern __shared__ int32_t smem[];
   const int t = xcd_slice(blockIdx.x, gridDim.x);
   const int e = find_segment(prefix, n, t);

@@ -29,15 +29,18 @@ int argsort_levels(int64_t max_n);
 // ---- TAM -----------------------------------------------------------------
 // TAM plane of a W x H map from its squared EDT k: cell (x, y) holds 2 k
 // (below 2^32 for maps up to 32767 cells a side); column W and row H hold
-// the sentinel 2^32 - 1 (odd, so never 2 k). Layout: tiles of 8 x 4 cells
-// (one 128-byte line each), tiles row-major, tam_plane_tx(W) per tile row;
-// at most 2^30 entries, so a byte offset fits in 32 bits.
-__host__ __device__ inline uint32_t tam_plane_tx(int W) { return ((uint32_t)W + 8u) >> 3; }
+// the sentinel 2^32 - 1 (odd, so never 2 k). Layout: strips of 8 columns
+// side by side, each tam_plane_rows(H) rows of 8 entries, so rows 4j..4j+3
+// of a strip are one 128-byte line (the lines of 8 x 4 tiles); at most 2^30
+// entries, so a byte offset fits in 32 bits.
+__host__ __device__ inline uint32_t tam_plane_rows(int H) { return (((uint32_t)H + 4u) >> 2) << 2; }
 __host__ __device__ inline size_t tam_plane_entries(int W, int H) {
-  return (size_t)tam_plane_tx(W) * (((size_t)H + 4) >> 2) * 32;
+  return (size_t)(((uint32_t)W + 8u) >> 3) * 8 * tam_plane_rows(H);
 }
-__device__ __forceinline__ uint32_t tam_plane_index(uint32_t x, uint32_t y, uint32_t tx) {
-  return ((__umul24(y >> 2, tx) + (x >> 3)) << 5) | ((y & 3u) << 3) | (x & 7u);
+// entry (x >> 3) 8 rows + 8 y + (x & 7), written as (x & ~7)(rows - 1) + 8 y + x
+// (one 24-bit multiply-add); rows1 = tam_plane_rows(H) - 1
+__device__ __forceinline__ uint32_t tam_plane_index(uint32_t x, uint32_t y, uint32_t rows1) {
+  return __umul24(x & ~7u, rows1) + ((y << 3) + x);
 }
 hipError_t launch_tam_plane(const uint32_t* k, int W, int H, uint32_t* plane, hipStream_t s);
 
