@@ -249,6 +249,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   uint64_t p_sumk = 0, p_sumsq = 0;
   int p_noff = 0;
 
+  uint32_t t_prev = kcap2;              // the selection's first guess
   for (int g = 0; g < G; ++g) {
     int px, py, pg;
     if (!src.pose(wv + NW * g, px, py, pg)) {           // wavefront-uniform
@@ -316,30 +317,54 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     // 2 kcap < c, plus the off-map beams when key_off < c
     int64_t sl = 0;
     if constexpr (!FULL) {
-      // TAM and T_mean: the top-k_mid sum of eq. 24-27. The k_mid-th
-      // smallest key: bitwise search for the largest t with fewer than
-      // k_mid keys below it; counts from wavefront ballots. Every key is
-      // at most 2 kcap, so the bits above its top bit stay clear, and the
+      // TAM and T_mean: the top-k_mid sum of eq. 24-27. The threshold t,
+      // the k_mid-th smallest key, is the largest t with fewer than k_mid
+      // keys below it; counts come from wavefront ballots over the raw keys,
+      // corrected as above. Candidates are multiples of 2^sh (when key_off
+      // is even every key is). The previous pose's t (2 kcap for the first)
+      // is tried first: nearby orientations and lattice poses often share
+      // t, and 2 kcap is where every far miss sits. One or two rounds settle
+      // it; otherwise a binary search runs on the side where t lies. The
       // count below t is that of the last candidate taken (0 if none).
-      auto corr = [&](uint32_t c) -> int {
-        return (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
-      };
-      const int top = 31 - __builtin_clz(kcap2);
-      // when key_off is even every key is: no odd candidate can then be the
-      // threshold, and the bit-0 round is skipped
-      const int low = (int)(key_off & 1u) ^ 1;
-      uint32_t tkey = 0;
-      int below = 0;
-      for (int bit = top; bit >= low; --bit) {
-        const uint32_t cand = tkey | (1u << bit);
-        int cnt = corr(cand);
+      auto cnt = [&](uint32_t c) -> int {
+        int n = (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
 #pragma unroll
-        for (int i = 0; i < R; ++i) cnt += __popcll(__ballot(keys[i] < cand));
-        if (cnt < a.kmid) {
-          tkey = cand;
-          below = cnt;
+        for (int i = 0; i < R; ++i) n += __popcll(__ballot(keys[i] < c));
+        return n;
+      };
+      const int sh = (int)(key_off & 1u) ^ 1;
+      const uint32_t umax = kcap2 >> sh;
+      const uint32_t ug = t_prev >> sh;
+      uint32_t lo = 0, hi = umax;
+      int below = 0;
+      const int cg = cnt(ug << sh);
+      if (cg >= a.kmid) {
+        hi = ug - 1;                         // count(< 0) = 0 < k_mid: ug >= 1
+      } else {
+        lo = ug;
+        below = cg;
+        if (ug < umax) {
+          const int c2 = cnt((ug + 1) << sh);
+          if (c2 >= a.kmid) {
+            hi = ug;
+          } else {
+            lo = ug + 1;
+            below = c2;
+          }
         }
       }
+      while (lo < hi) {                      // wavefront-uniform
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        const int c = cnt(mid << sh);
+        if (c < a.kmid) {
+          lo = mid;
+          below = c;
+        } else {
+          hi = mid - 1;
+        }
+      }
+      const uint32_t tkey = lo << sh;
+      t_prev = tkey;
       // table entries are l - lmin >= 0, below 2^31: pairs add in 32 bits
 #pragma unroll
       for (int i = 0; i < R; i += 2) {
