@@ -83,11 +83,12 @@ __global__ void edt_rows_kernel(const int32_t* __restrict__ g, int W, int H,
   k[(size_t)y * W + x] = best == INT64_MAX ? 0xFFFFFFFFu : (uint32_t)best;
 }
 
-// TAM plane: 2 k per cell in strips of 8 columns, the sentinel 2^32 - 1 in
-// column W and row H (and the padding of the last strip and rows); one
-// entry per thread, written in plane order.
+// TAM planes: 2 k per cell in strips of 8 columns, 32-bit and 16-bit (2 k
+// below 2^15, else the escape 0xFFFE), the sentinel in column W and row H
+// (and the padding of the last strip and rows); one entry of each per
+// thread, written in plane order.
 __global__ void tam_plane_kernel(const uint32_t* __restrict__ k, int W, int H,
-                                 uint32_t* __restrict__ plane) {
+                                 uint32_t* __restrict__ plane, uint16_t* __restrict__ plane16) {
   const size_t per_strip = (size_t)8 * tam_plane_rows(H);
   const size_t n = tam_plane_entries(W, H);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,8 +96,14 @@ __global__ void tam_plane_kernel(const uint32_t* __restrict__ k, int W, int H,
   const size_t st = i / per_strip, r = i - st * per_strip;
   const uint32_t y = (uint32_t)(r >> 3), x = (uint32_t)(st * 8 + (r & 7));
   uint32_t v = 0xFFFFFFFFu;
-  if (x < (uint32_t)W && y < (uint32_t)H) v = 2u * k[(size_t)y * W + x];
+  uint16_t h = 0xFFFFu;
+  if (x < (uint32_t)W && y < (uint32_t)H) {
+    const uint32_t kk = k[(size_t)y * W + x];
+    v = 2u * kk;
+    h = kk < (1u << 14) ? (uint16_t)v : (uint16_t)0xFFFEu;
+  }
   plane[i] = v;
+  plane16[i] = h;
 }
 
 }  // namespace
@@ -104,7 +111,7 @@ __global__ void tam_plane_kernel(const uint32_t* __restrict__ k, int W, int H,
 hipError_t launch_tam_plane(const uint32_t* k, int W, int H, uint32_t* plane, hipStream_t s) {
   const size_t n = tam_plane_entries(W, H);
   hipLaunchKernelGGL(tam_plane_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, W, H,
-                     plane);
+                     plane, reinterpret_cast<uint16_t*>(plane + n));
   return hipGetLastError();
 }
 

@@ -10,21 +10,23 @@
 // only: e = (ix, iy) + (dx, dy), dx = floor((2^27 + zq U_x) / 2^28) (eq. 22's
 // projection in exact fixed point). The request's offset table holds every
 // (g, v) offset, so a lookup is one coalesced offset load (four beams per
-// lane at a time), two clamps and one 4-byte gather from the map's TAM
-// plane: 2 k per cell in strips of 8 columns, so a 128-byte line holds 8 x 4
-// cells (an endpoint run along a wall in any direction stays within few
-// lines) and the index is one multiply-add, with a sentinel column and
-// row 2^32 - 1 that endpoints off the map (and padded beam slots) are
-// clamped onto, so no lookup needs a mask; sqrt(k) in Q16 is computed.
+// lane at a time), two clamps and one 2-byte gather from the map's 16-bit
+// TAM plane: 2 k per cell in strips of 8 columns, so a 128-byte line holds
+// 8 x 8 cells (an endpoint run along a wall in any direction stays within
+// few lines) and the index is one multiply-add, with a sentinel column and
+// row that endpoints off the map (and padded beam slots) are clamped onto,
+// so no lookup needs a mask; sqrt(k) in Q16 is computed. Cells 128 or more
+// cells from any obstacle hold an escape instead (2 k does not fit); a
+// wavefront that meets one reads those slots again from the 32-bit plane.
 // The likelihood l(k) of eq. 23 is monotone non-increasing in k, so the
 // top-k_mid selection of eq. 24-27 is a selection of the k_mid smallest
 // integer keys: key = 2 * min(k, kcap) for in-map endpoints and a
 // host-chosen odd key for off-map ones (d = d_max). kcap is where l(k) has
-// converged to within 1e-10 of its limit. The sentinel holds 2^32 - 1 in
-// place of 2 k, so every off-map or padded slot first takes the key
-// 2 kcap; the wavefront's sentinel count (from the sq sums) then moves the
-// off-map ones to key_off and drops the padded ones, in closed form, in
-// every count and sum. The threshold key comes from a bitwise search whose
+// converged to within 1e-10 of its limit. The sentinel reads 2^32 - 1 in
+// place of 2 k (sign-extended), so every off-map or padded slot first takes
+// the key 2 kcap; the wavefront's sentinel count (from the sq sums) then
+// moves the off-map ones to key_off and drops the padded ones, in closed
+// form, in every count and sum. The threshold key comes from a search whose
 // counts are wavefront ballots; sums are exact integers
 // (l - lmin in Q26 fixed point from a host table, sqrt(k) in Q16, k itself,
 // lmin the table's smallest value added back per selected beam), so the
@@ -206,8 +208,8 @@ __host__ __device__ constexpr size_t tam_lut_lds(int kb) {
 //
 // Per pose the R beam slots of a lane come SB at a time: one 16-byte load
 // of four offsets per four slots, then SB plane gathers, all in flight
-// before any is used. The per-pose integer sums are parked in lane g, then
-// moved to LDS; the FP64 tail (eq. 27-31) runs once per workgroup, for the
+// before any is used. The per-pose integer sums (wavefront-uniform) go to
+// LDS as each pose ends; the FP64 tail (eq. 27-31) runs once per workgroup, for the
 // 16 poses in lanes 0..15 of wavefront 0, and one atomic max per workgroup
 // publishes the best (T, tie). The other wavefronts end there: every
 // caller ends with the tile.
@@ -236,18 +238,30 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
   };
   const char* __restrict__ plane = reinterpret_cast<const char*>(a.plane);
+  const char* __restrict__ plane16 = reinterpret_cast<const char*>(a.plane16);
   const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, rows1 = tam_plane_rows(a.H) - 1u;
   const uint32_t kcap2 = 2u * (uint32_t)a.kcap, key_off = (uint32_t)a.key_off;
-  // the sentinel's share of a sq sum, by the same instructions as a slot's
-  // (the empty asm keeps the compiler from folding it with other rounding)
-  uint32_t s_raw = 0xFFFFFFFFu;
-  asm volatile("" : "+v"(s_raw));
-  const uint32_t sq_sent = q16_sqrt_half(s_raw);
+  // plane entry of the endpoint at offset word o (dx low, dy high) from the
+  // pose's cell; off the map (either side) clamps onto the sentinel column
+  // or row
+  auto entry_index = [&](uint32_t o, int px, int py) -> uint32_t {
+    const uint32_t ex = (uint32_t)px + (uint32_t)(int32_t)(int16_t)(o & 0xFFFFu);
+    const uint32_t ey = (uint32_t)py + (uint32_t)((int32_t)o >> 16);
+    return tam_plane_index(min(ex, Wc), min(ey, Hc), rows1);
+  };
+  // the shares of the sentinel (2^32 - 1 sign-extended from the 16-bit
+  // plane) and of the escape (2^32 - 2) in a sq sum, by the same
+  // instructions as a slot's (the empty asm keeps the compiler from folding
+  // them with other rounding)
+  uint32_t s_raw = 0xFFFFFFFFu, e_raw = 0xFFFFFFFEu;
+  asm volatile("" : "+v"(s_raw), "+v"(e_raw));
+  const uint32_t sq_sent = q16_sqrt_half(s_raw), sq_esc = q16_sqrt_half(e_raw);
 
-  // per-pose results parked in lane g
-  int64_t p_sl = 0;
-  uint64_t p_sumk = 0, p_sumsq = 0;
-  int p_noff = 0;
+  // per-pose results (wavefront-uniform) go to LDS as each pose ends, for
+  // the FP64 tail
+  __shared__ int64_t t_sl[THETA_PER_BLOCK];
+  __shared__ uint64_t t_sumk[THETA_PER_BLOCK], t_sumsq[THETA_PER_BLOCK];
+  __shared__ int t_noff[THETA_PER_BLOCK];
 
   uint32_t t_prev = kcap2;              // the selection's first guess
   for (int g = 0; g < G; ++g) {
@@ -258,9 +272,11 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     }
     const uint4* __restrict__ orow =
         reinterpret_cast<const uint4*>(a.off + (size_t)pg * (size_t)a.off_stride) + lane;
-    // raw keys: min(2 k, 2 kcap) for every slot, the sentinel's 2^32 - 1
-    // included (so off-map and padded slots hold 2 kcap here; the counts
-    // and sums below move them to key_off or drop them)
+    // raw keys: min(2 k, 2 kcap) for every slot, from the 16-bit plane
+    // sign-extended: the sentinel reads 2^32 - 1 and the escape 2^32 - 2,
+    // so off-map, padded and far slots hold 2 kcap here (the counts and sums
+    // below move the off-map ones to key_off and drop the padded ones; the
+    // rare far ones are fixed from the 32-bit plane)
     uint32_t keys[R];
     Sum64 sumk_a, sums_a;
     uint32_t n_sent = 0;
@@ -277,17 +293,12 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       }
       uint32_t idx[SB];
 #pragma unroll
-      for (int s2 = 0; s2 < SB; ++s2) {
-        // off the map (either side) clamps onto the sentinel column / row
-        const uint32_t ex = (uint32_t)px + (uint32_t)(int32_t)(int16_t)(o[s2] & 0xFFFFu);
-        const uint32_t ey = (uint32_t)py + (uint32_t)((int32_t)o[s2] >> 16);
-        idx[s2] = tam_plane_index(min(ex, Wc), min(ey, Hc), rows1);
-      }
-      // 32-bit byte offsets from the plane base (at most 2^32 - 4)
+      for (int s2 = 0; s2 < SB; ++s2) idx[s2] = entry_index(o[s2], px, py);
+      // 32-bit byte offsets from the plane base (below 2^31)
       uint32_t v[SB];
 #pragma unroll
       for (int s2 = 0; s2 < SB; ++s2)
-        v[s2] = *reinterpret_cast<const uint32_t*>(plane + (idx[s2] << 2));
+        v[s2] = (uint32_t)(int32_t)*reinterpret_cast<const int16_t*>(plane16 + (idx[s2] << 1));
 #pragma unroll
       for (int s2 = 0; s2 < SB; ++s2) {
         const uint32_t k2 = v[s2];
@@ -309,6 +320,32 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     sumk = wave_sum64(sumk);
     sums = wave_sum64(sums);
     const int nsent = (int)(sums >> 48);   // sentinel slots: off-map beams and padding
+    // sentinel and escape slots together: every other raw value is below
+    // 2^15, so the rounded top word of the raw sum counts them
+    const int nesc = (int)((sumk + 0x80000000ull) >> 32) - nsent;
+    if (nesc > 0) {                        // wavefront-uniform; rare
+      // cells 128 or more cells from any obstacle: their 2 k from the 32-bit
+      // plane (in-map entries of 2^15 or more; its sentinel is odd) gives
+      // their keys and their shares of the sums, in place of the escape's
+      Sum64 ek, es;
+#pragma unroll
+      for (int m = 0; m < R / 4; ++m) {
+        const uint4 o4 = orow[64 * m];
+        const uint32_t o[4] = {o4.x, o4.y, o4.z, o4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t w =
+              *reinterpret_cast<const uint32_t*>(plane + (entry_index(o[q], px, py) << 2));
+          const bool far = w >= (1u << 15) && !(w & 1u);
+          ek.add(far ? w : 0u);
+          es.add(far ? q16_sqrt_half(w) : 0u);
+          if (far) keys[4 * m + q] = min(w, kcap2);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // four gathers in flight at a time
+      }
+      sumk += wave_sum64(ek.get()) - (uint64_t)nesc * 0xFFFFFFFEull;
+      sums += wave_sum64(es.get()) - (uint64_t)nesc * (uint64_t)sq_esc;
+    }
     const int nin = 64 * R - nsent;
     const int noff = nv - nin;
     sumk -= (uint64_t)nsent * 0xFFFFFFFFull;
@@ -386,26 +423,16 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       sl += (int64_t)noff * (int64_t)ell(key_off) - (int64_t)nsent * (int64_t)ell(kcap2);
       sl += (int64_t)nv * (int64_t)a.lmin;
     }
-    if (lane == g) {
-      p_sl = sl;
-      p_sumk = sumk >> 1;               // the plane holds 2 k
+    if (lane == 0) {
+      const int jj = wv + NW * g;
+      t_sl[jj] = sl;
+      t_sumk[jj] = sumk >> 1;           // the plane holds 2 k
       // in Q16 cells, less the sentinel slots' share
-      p_sumsq = (sums & ((1ull << 48) - 1)) - (uint64_t)nsent * (uint64_t)sq_sent;
-      p_noff = noff;
+      t_sumsq[jj] = (sums & ((1ull << 48) - 1)) - (uint64_t)nsent * (uint64_t)sq_sent;
+      t_noff[jj] = noff;
     }
   }
-  // the tile's poses go to LDS (pose wv + NW g from lane g of wavefront wv);
   // wavefront 0 then runs the FP64 tail once, one pose per lane
-  __shared__ int64_t t_sl[THETA_PER_BLOCK];
-  __shared__ uint64_t t_sumk[THETA_PER_BLOCK], t_sumsq[THETA_PER_BLOCK];
-  __shared__ int t_noff[THETA_PER_BLOCK];
-  if (lane < G) {
-    const int jj = wv + NW * lane;
-    t_sl[jj] = p_sl;
-    t_sumk[jj] = p_sumk;
-    t_sumsq[jj] = p_sumsq;
-    t_noff[jj] = p_noff;
-  }
   __syncthreads();
   if (wv != 0) return;                  // the caller's work ends with the tile
   const int j = lane;

@@ -27,16 +27,21 @@ int64_t argsort_tiles(int64_t n);
 int argsort_levels(int64_t max_n);
 
 // ---- TAM -----------------------------------------------------------------
-// TAM plane of a W x H map from its squared EDT k: cell (x, y) holds 2 k
-// (below 2^32 for maps up to 32767 cells a side); column W and row H hold
-// the sentinel 2^32 - 1 (odd, so never 2 k). Layout: strips of 8 columns
-// side by side, each tam_plane_rows(H) rows of 8 entries, so rows 4j..4j+3
-// of a strip are one 128-byte line (the lines of 8 x 4 tiles); at most 2^30
+// TAM planes of a W x H map from its squared EDT k, one allocation of
+// tam_plane_bytes: first the 32-bit plane, cell (x, y) holding 2 k (below
+// 2^32 for maps up to 32767 cells a side), then the 16-bit plane the TAM
+// gathers read, holding 2 k for k < 2^14 (below 2^15) and the escape
+// 0xFFFE for farther cells (whose 2 k the 32-bit plane gives). Column W and
+// row H hold the sentinel, 2^32 - 1 and 0xFFFF (odd, so never 2 k). Both
+// in one layout: strips of 8 columns side by side, each tam_plane_rows(H)
+// rows of 8 entries, so a 128-byte line of the 16-bit plane is 8 x 8 cells
+// (4 rows of a strip: 8 x 4 cells in the 32-bit plane); at most 2^30
 // entries, so a byte offset fits in 32 bits.
 __host__ __device__ inline uint32_t tam_plane_rows(int H) { return (((uint32_t)H + 4u) >> 2) << 2; }
 __host__ __device__ inline size_t tam_plane_entries(int W, int H) {
   return (size_t)(((uint32_t)W + 8u) >> 3) * 8 * tam_plane_rows(H);
 }
+__host__ __device__ inline size_t tam_plane_bytes(int W, int H) { return tam_plane_entries(W, H) * 6; }
 // entry (x >> 3) 8 rows + 8 y + (x & 7), written as (x & ~7)(rows - 1) + 8 y + x
 // (one 24-bit multiply-add); rows1 = tam_plane_rows(H) - 1
 __device__ __forceinline__ uint32_t tam_plane_index(uint32_t x, uint32_t y, uint32_t rows1) {
@@ -46,7 +51,8 @@ hipError_t launch_tam_plane(const uint32_t* k, int W, int H, uint32_t* plane, hi
 
 struct TamArgs {
   const uint32_t* kmap;      // [W H] squared EDT
-  const uint32_t* plane;     // TAM plane (launch_tam_plane)
+  const uint32_t* plane;     // 32-bit TAM plane (launch_tam_plane)
+  const uint16_t* plane16;   // 16-bit TAM plane, after the 32-bit one
   const uint32_t* off;       // [Ng][off_stride] endpoint offsets (launch_tam_offsets)
   int off_stride;            // 64 x keys per lane of the request's kernel class
   int W, H;

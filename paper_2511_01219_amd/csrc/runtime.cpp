@@ -632,6 +632,7 @@ TamArgs tam_args(reloc_ctx* c, Request& R, int r0, int nb, float* T_out) {
   TamArgs a;
   a.kmap = m.kmap;
   a.plane = m.plane;
+  a.plane16 = reinterpret_cast<const uint16_t*>(m.plane + tam_plane_entries(m.W, m.H));
   a.off = R.off;
   a.off_stride = R.off_stride;
   a.W = m.W;
@@ -1116,7 +1117,7 @@ int32_t reloc_load_map(reloc_ctx* c, const reloc_map_desc* d, const int8_t* occ,
   m.bits = (uint64_t*)c->dalloc((size_t)m.tpr * m.tph * sizeof(uint64_t));
   if (N <= kWalkMaxCells) m.walk = (uint16_t*)c->dalloc(4 * N * sizeof(uint16_t));
   m.kmap = (uint32_t*)c->dalloc(N * sizeof(uint32_t));
-  m.plane = (uint32_t*)c->dalloc(tam_plane_entries(m.W, m.H) * sizeof(uint32_t));
+  m.plane = (uint32_t*)c->dalloc(tam_plane_bytes(m.W, m.H));
   auto cleanup = [&]() {
     c->dfree(docc);
     c->dfree(g);

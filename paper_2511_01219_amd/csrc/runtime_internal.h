@@ -86,7 +86,7 @@ struct DevMap {
   uint64_t* bits = nullptr;
   uint16_t* walk = nullptr;       // null when the map exceeds kWalkMaxCells
   uint32_t* kmap = nullptr;
-  uint32_t* plane = nullptr;      // TAM plane (tam_plane_entries)
+  uint32_t* plane = nullptr;      // TAM planes (tam_plane_bytes)
   std::vector<int8_t> occ;        // host copy for the sampler
   std::vector<uint32_t> khost;    // host copy of the EDT (filled on demand)
   int n_sets = 0;

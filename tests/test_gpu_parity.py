@@ -415,6 +415,42 @@ def test_tam_widest_map_edges(ctx):
     _cleanup(ctx, m, sid, rid)
 
 
+@pytest.mark.parametrize("params", [dict(), dict(sigma_hit=1.0)])
+def test_tam_far_cells(ctx, params):
+    """An open hall 1000 x 900 cells: most cells lie 128 or more cells from
+    any obstacle, beyond what the 16-bit TAM plane holds (k >= 2^14), so
+    most wavefronts take the escape path through the 32-bit plane; with
+    sigma_hit = 1 m, 2 kcap exceeds 2^15 and the far slots' keys change
+    too (the 16-bit key class, odd key_off)."""
+    W, H = 1000, 900
+    occ = np.zeros((H, W), np.int8)
+    occ[0, :] = occ[H - 1, :] = 100
+    occ[:, 0] = occ[:, W - 1] = 100
+    occ[400:430, 200:260] = 100
+    occ[700:705, 600:900] = 100
+    k = oracle.edt(occ)
+    assert (k >= (1 << 14)).mean() > 0.3
+    rng = np.random.default_rng(21)
+    xs = np.concatenate([rng.integers(300, 700, 24), rng.integers(3, 60, 8)])
+    ys = np.concatenate([rng.integers(250, 650, 24), rng.integers(3, 60, 8)])
+    keep = occ[ys, xs] == 0
+    hyp = np.stack([xs[keep], ys[keep]], 1).astype(np.int32)
+    n = len(hyp)
+    z = np.full(360, 3.0, np.float32)
+    z[::3] = 12.0
+    z[1::3] = 30.0
+    inc = 2 * math.pi / 360
+    _case("tam far cells (%d x %d), %d hypotheses, params %s" % (W, H, n, params))
+    m, sid, rid, pr = _raycast_case(ctx, occ, hyp, z, -math.pi, inc, 40.0, n_theta=90, **params)
+    _, _, order = ctx.debug_smad(rid, n)
+    T, ts, ks = ctx.debug_tam(rid, 0, n, 90)
+    q = np.repeat(hyp[order[:n]], 90, axis=0)
+    kk = np.tile(np.arange(90), n)
+    ref = oracle.tam(k, 0.05, pr, q, kk, **params)[:, 0].reshape(n, 90)
+    _check_tam(T, ts, ks, ref)
+    _cleanup(ctx, m, sid, rid)
+
+
 # ----------------------------------------------------------------------- a7 a8
 def _compare_runs(poses, st, ref, tau, K):
     assert st["n_hyp"] == len(ref["order"])
