@@ -227,10 +227,21 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = a.nv;
   const __amdgpu_buffer_rsrc_t lut = lut_rsrc(a);
+  const uint32_t kcap2 = 2u * (uint32_t)a.kcap, key_off = (uint32_t)a.key_off;
   if constexpr (kLdsLut) {
-    for (int i = tid; i <= (int)ZERO; i += TB)
-      smem[i] = i < (1 << a.keybits)
-                    ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, i << 2, 0, 0) : 0;
+    // the entries keys can reach, 0 .. 2 kcap (below 4096 here), four per
+    // 16-byte load: at most four loads per lane, all in flight before the
+    // first store; then the zero slot
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const int n4 = (int)(kcap2 >> 2) + 1;
+    u32x4 q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (tid + j * TB < n4) q[j] = __builtin_amdgcn_raw_buffer_load_b128(lut, (tid + j * TB) << 4, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (tid + j * TB < n4) reinterpret_cast<u32x4*>(smem)[tid + j * TB] = q[j];
+    if (tid == 0) smem[ZERO] = 0;
     __syncthreads();
   }
   auto ell = [&](uint32_t key) -> int32_t {
@@ -240,7 +251,6 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   const char* __restrict__ plane = reinterpret_cast<const char*>(a.plane);
   const char* __restrict__ plane16 = reinterpret_cast<const char*>(a.plane16);
   const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, rows1 = tam_plane_rows(a.H) - 1u;
-  const uint32_t kcap2 = 2u * (uint32_t)a.kcap, key_off = (uint32_t)a.key_off;
   // plane entry of the endpoint at offset word o (dx low, dy high) from the
   // pose's cell; off the map (either side) clamps onto the sentinel column
   // or row
@@ -510,7 +520,7 @@ __device__ __forceinline__ int xcd_slice(int b, int n) {
 template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(tam_waves(R))))
 void tam_kernel(TamArgs a) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   const int ntb = tam_tiles_per_rank(a);
   const int L = xcd_slice(blockIdx.x, gridDim.x);
   tam_block<R, KB, FULL>(a, L / ntb, L % ntb, smem);
@@ -521,7 +531,7 @@ void tam_kernel(TamArgs a) {
 // and heading o k*, k* read from the rank's packed TAM best).
 template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void refine_kernel(RefineArgs a) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   const int tiles = (a.L + THETA_PER_BLOCK - 1) / THETA_PER_BLOCK;
   const int b = xcd_slice(blockIdx.x, gridDim.x);
   const int slot = b / tiles, tile = b - slot * tiles;
@@ -638,7 +648,7 @@ hipError_t launch_refine_kb(const RefineArgs& a, hipStream_t s) {
 // Scores of an explicit pose list, 16 poses per workgroup.
 template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) void pose_kernel(PoseArgs a) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   PoseListSrc src;
   src.xy = a.xy;
   src.g = a.g;
@@ -677,7 +687,7 @@ __device__ __forceinline__ int find_segment(const int64_t* prefix, int n, int64_
 template <int R, int KB, bool FULL>
 __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(tam_waves(R))))
 void tam_batch_kernel(const TamArgs* __restrict__ items, const int64_t* __restrict__ prefix, int n) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   const int t = xcd_slice(blockIdx.x, gridDim.x);
   const int e = find_segment(prefix, n, t);
   const TamArgs& a = items[e];
