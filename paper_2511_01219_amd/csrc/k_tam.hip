@@ -49,12 +49,11 @@ namespace {
 constexpr int TB = 256;
 constexpr int NW = TB / 64;
 constexpr int THETA_PER_BLOCK = 16;
-constexpr uint32_t NOKEY = 0xFFFFFFFFu;
 
-// The likelihood table (2^keybits entries and a zero slot) through a
-// buffer resource, for the 16-bit key class that does not keep it in LDS.
+// The likelihood table (2^keybits entries) through a buffer resource, for
+// the 16-bit key class that does not keep it in LDS.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t lut_rsrc(const TamArgs& a) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)a.lut, (short)0, 4 * ((1 << a.keybits) + 1),
+  return __builtin_amdgcn_make_buffer_rsrc((void*)a.lut, (short)0, 4 * (1 << a.keybits),
                                            0x00020000);
 }
 
@@ -85,9 +84,37 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// The same over 32-bit values: each move is the DPP operand of the add.
+// Integer sums do not depend on the order of the additions; the FP32 sum
+// takes its additions in one fixed order, so it is the same on every run.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+  v += dpp32<0xb1>(v);
+  v += dpp32<0x4e>(v);
+  v += dpp32<0x124>(v);
+  v += dpp32<0x128>(v);
+  v += dpp32<0x142>(v);
+  v += dpp32<0x143>(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ float wave_sumf(float v) {
+  v += __uint_as_float(dpp32<0xb1>(__float_as_uint(v)));
+  v += __uint_as_float(dpp32<0x4e>(__float_as_uint(v)));
+  v += __uint_as_float(dpp32<0x124>(__float_as_uint(v)));
+  v += __uint_as_float(dpp32<0x128>(__float_as_uint(v)));
+  v += __uint_as_float(dpp32<0x142>(__float_as_uint(v)));
+  v += __uint_as_float(dpp32<0x143>(__float_as_uint(v)));
+  return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
+}
+
 // A 64-bit running sum of 32-bit values kept as two words: an add with carry
 // out and an add of the carry, so no zeroed upper word is held beside each
-// value in flight.
+// value.
 struct Sum64 {
   uint32_t lo = 0, hi = 0;
   __device__ __forceinline__ void add(uint32_t v) {
@@ -98,11 +125,12 @@ struct Sum64 {
   __device__ __forceinline__ uint64_t get() const { return ((uint64_t)hi << 32) | lo; }
 };
 
-// sqrt(k) 2^16 (the distance in Q16 cells) from a plane entry v = 2 k, as
-// sqrt(v) sqrt(2) 2^15 truncated: no shift and no separate rounding step.
-// FP32: a relative error of a few 2^-24 and at most one Q16 unit per beam.
-__device__ __forceinline__ uint32_t q16_sqrt_half(uint32_t v) {
-  return (uint32_t)(__fsqrt_rn((float)v) * 0x1.6a09e6p+15f);
+// sqrt(|v|) in FP32 for a plane entry read sign-extended: sqrt(2 k) for an
+// in-map cell, 1 for the sentinel (-1), sqrt 2 for the escape (-2). The
+// absolute value is a source modifier of the square root: one conversion
+// and one square root per slot.
+__device__ __forceinline__ float sqrt_abs(uint32_t v) {
+  return __fsqrt_rn(fabsf((float)(int32_t)v));
 }
 
 // The 16 poses of one workgroup come from a pose source: has(j) tells
@@ -197,10 +225,10 @@ struct PoseListSrc {
   __device__ __forceinline__ void record(int j, float T) const { out[q0 + j] = T; }
 };
 
-// LDS of a tile: the likelihood table (2^12 keys and a zero slot) for the
-// 12-bit key class; the 16-bit class reads it from memory.
+// LDS of a tile: the likelihood table (2^12 keys) for the 12-bit key class;
+// the 16-bit class reads it from memory.
 __host__ __device__ constexpr size_t tam_lut_lds(int kb) {
-  return kb <= 12 ? (size_t)((1 << 12) + 1) * 4 : 0;
+  return kb <= 12 ? (size_t)(1 << 12) * 4 : 0;
 }
 
 // One workgroup's work: the 16 poses of a tile; wavefront w takes poses
@@ -222,7 +250,6 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   constexpr int SB = R <= 12 ? R : (R % 12 == 0 ? 12 : 8);
   constexpr int G = THETA_PER_BLOCK / NW;
   constexpr bool kLdsLut = KB <= 12;
-  constexpr uint32_t ZERO = 1u << KB;   // the likelihood table's zero slot
   static_assert(R % SB == 0, "whole gather batches");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = a.nv;
@@ -231,7 +258,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   if constexpr (kLdsLut) {
     // the entries keys can reach, 0 .. 2 kcap (below 4096 here), four per
     // 16-byte load: at most four loads per lane, all in flight before the
-    // first store; then the zero slot
+    // first store
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const int n4 = (int)(kcap2 >> 2) + 1;
     u32x4 q[4];
@@ -241,7 +268,6 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (tid + j * TB < n4) reinterpret_cast<u32x4*>(smem)[tid + j * TB] = q[j];
-    if (tid == 0) smem[ZERO] = 0;
     __syncthreads();
   }
   auto ell = [&](uint32_t key) -> int32_t {
@@ -259,18 +285,18 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     const uint32_t ey = (uint32_t)py + (uint32_t)((int32_t)o >> 16);
     return tam_plane_index(min(ex, Wc), min(ey, Hc), rows1);
   };
-  // the shares of the sentinel (2^32 - 1 sign-extended from the 16-bit
-  // plane) and of the escape (2^32 - 2) in a sq sum, by the same
-  // instructions as a slot's (the empty asm keeps the compiler from folding
-  // them with other rounding)
-  uint32_t s_raw = 0xFFFFFFFFu, e_raw = 0xFFFFFFFEu;
-  asm volatile("" : "+v"(s_raw), "+v"(e_raw));
-  const uint32_t sq_sent = q16_sqrt_half(s_raw), sq_esc = q16_sqrt_half(e_raw);
+  // the escape's share of a square-root sum (the sentinel's is 1), by the
+  // same instructions as a slot's (the empty asm keeps the compiler from
+  // folding it)
+  uint32_t e_raw = 0xFFFFFFFEu;
+  asm volatile("" : "+v"(e_raw));
+  const float sq_esc = sqrt_abs(e_raw);
 
   // per-pose results (wavefront-uniform) go to LDS as each pose ends, for
   // the FP64 tail
   __shared__ int64_t t_sl[THETA_PER_BLOCK];
-  __shared__ uint64_t t_sumk[THETA_PER_BLOCK], t_sumsq[THETA_PER_BLOCK];
+  __shared__ uint64_t t_sumk[THETA_PER_BLOCK];
+  __shared__ double t_sq[THETA_PER_BLOCK];
   __shared__ int t_noff[THETA_PER_BLOCK];
 
   uint32_t t_prev = kcap2;              // the selection's first guess
@@ -288,8 +314,12 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     // below move the off-map ones to key_off and drop the padded ones; the
     // rare far ones are fixed from the 32-bit plane)
     uint32_t keys[R];
-    Sum64 sumk_a, sums_a;
-    uint32_t n_sent = 0;
+    // per lane: the sum of the raw values (in-map 2 k below 2^15, -1 per
+    // sentinel, -2 per escape: exact in 32 bits), the counts of sentinels
+    // (low half) and of sentinels and escapes (high half), and the FP32 sum
+    // of sqrt(|raw|)
+    uint32_t sk = 0, cnt = 0;
+    float sq = 0.0f;
 #pragma unroll
     for (int b = 0; b < R / SB; ++b) {
       uint32_t o[SB];
@@ -312,32 +342,31 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
 #pragma unroll
       for (int s2 = 0; s2 < SB; ++s2) {
         const uint32_t k2 = v[s2];
-        // sqrt(k) in Q16 cells for every slot (the sentinel's share is
-        // taken back out below): no branch
-        const uint32_t sq = q16_sqrt_half(k2);
         keys[SB * b + s2] = min(k2, kcap2);
-        sumk_a.add(k2);
-        sums_a.add(sq);
-        n_sent += k2 & 1u;                             // the sentinel is the one odd entry
+        sk += k2;
+        cnt += k2 & 0x10001u;          // -1: both bits; -2: bit 16; 2 k < 2^15: neither
+        sq += sqrt_abs(k2);            // no branch: the shares of -1 and -2 come out below
       }
       // one gather batch at a time: without this the scheduler issues every
       // batch's loads together and holds them all
       __builtin_amdgcn_sched_barrier(0);
     }
     // wavefront totals first: the selection needs the off-map count
-    uint64_t sumk = sumk_a.get(), sums = sums_a.get();
-    sums += (uint64_t)n_sent << 48;     // sq sums stay below 2^44
-    sumk = wave_sum64(sumk);
-    sums = wave_sum64(sums);
-    const int nsent = (int)(sums >> 48);   // sentinel slots: off-map beams and padding
-    // sentinel and escape slots together: every other raw value is below
-    // 2^15, so the rounded top word of the raw sum counts them
-    const int nesc = (int)((sumk + 0x80000000ull) >> 32) - nsent;
+    cnt = wave_sum32(cnt);
+    const int nsent = (int)(cnt & 0xFFFFu);        // sentinel slots: off-map beams and padding
+    const int nesc = (int)(cnt >> 16) - nsent;     // escape slots
+    // sum of 2 k over the in-map slots that are not escapes
+    uint64_t sumk = (uint64_t)((int64_t)(int32_t)wave_sum32(sk) + nsent + 2 * nesc);
+    // each lane's FP32 sum of sqrt(|raw|) (at most 64 x 182) in Q12, then
+    // an exact wavefront sum (below 2^32)
+    const uint32_t sq12 = wave_sum32((uint32_t)(sq * 4096.0f));
+    float sq_far = 0.0f;                   // sqrt(2 k) of the escape slots
     if (nesc > 0) {                        // wavefront-uniform; rare
       // cells 128 or more cells from any obstacle: their 2 k from the 32-bit
       // plane (in-map entries of 2^15 or more; its sentinel is odd) gives
-      // their keys and their shares of the sums, in place of the escape's
-      Sum64 ek, es;
+      // their keys and their shares of the sums
+      Sum64 ek;
+      float es = 0.0f;
 #pragma unroll
       for (int m = 0; m < R / 4; ++m) {
         const uint4 o4 = orow[64 * m];
@@ -348,17 +377,16 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
               *reinterpret_cast<const uint32_t*>(plane + (entry_index(o[q], px, py) << 2));
           const bool far = w >= (1u << 15) && !(w & 1u);
           ek.add(far ? w : 0u);
-          es.add(far ? q16_sqrt_half(w) : 0u);
+          es += far ? __fsqrt_rn((float)w) : 0.0f;
           if (far) keys[4 * m + q] = min(w, kcap2);
         }
         __builtin_amdgcn_sched_barrier(0);   // four gathers in flight at a time
       }
-      sumk += wave_sum64(ek.get()) - (uint64_t)nesc * 0xFFFFFFFEull;
-      sums += wave_sum64(es.get()) - (uint64_t)nesc * (uint64_t)sq_esc;
+      sumk += wave_sum64(ek.get());
+      sq_far = wave_sumf(es);
     }
     const int nin = 64 * R - nsent;
     const int noff = nv - nin;
-    sumk -= (uint64_t)nsent * 0xFFFFFFFFull;
     // the selection over the true keys (in-map keys, noff copies of key_off):
     // a count or sum over raw keys below c, less the sentinel slots when
     // 2 kcap < c, plus the off-map beams when key_off < c
@@ -412,17 +440,22 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       }
       const uint32_t tkey = lo << sh;
       t_prev = tkey;
-      // table entries are l - lmin >= 0, below 2^31: pairs add in 32 bits
+      // the sum of l over the raw keys below t, as the sum of l(min(key, t))
+      // over every raw key less l(t) once per raw key at or above t (one
+      // min per key, no compare and select); table entries are l - lmin >= 0,
+      // below 2^31: pairs add in 32 bits
 #pragma unroll
       for (int i = 0; i < R; i += 2) {
-        const uint32_t l0 = (uint32_t)ell(keys[i] < tkey ? keys[i] : ZERO);
-        const uint32_t l1 = (uint32_t)ell(keys[i + 1] < tkey ? keys[i + 1] : ZERO);
+        const uint32_t l0 = (uint32_t)ell(min(keys[i], tkey));
+        const uint32_t l1 = (uint32_t)ell(min(keys[i + 1], tkey));
         sl += (int64_t)(uint64_t)(l0 + l1);
       }
-      sl = (int64_t)wave_sum64((uint64_t)sl);
+      const int64_t lt = ell(tkey);
+      const int below_raw = below - (kcap2 < tkey ? -nsent : 0) - (key_off < tkey ? noff : 0);
+      sl = (int64_t)wave_sum64((uint64_t)sl) - (int64_t)(64 * R - below_raw) * lt;
       if (kcap2 < tkey) sl -= (int64_t)nsent * (int64_t)ell(kcap2);
       if (key_off < tkey) sl += (int64_t)noff * (int64_t)ell(key_off);
-      sl += (int64_t)(a.kmid - below) * (int64_t)ell(tkey);
+      sl += (int64_t)(a.kmid - below) * lt;
       sl += (int64_t)a.kmid * (int64_t)a.lmin;
     } else {
       // baseline and LF: the sum of l over every valid beam (eq. 32)
@@ -437,8 +470,10 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       const int jj = wv + NW * g;
       t_sl[jj] = sl;
       t_sumk[jj] = sumk >> 1;           // the plane holds 2 k
-      // in Q16 cells, less the sentinel slots' share
-      t_sumsq[jj] = (sums & ((1ull << 48) - 1)) - (uint64_t)nsent * (uint64_t)sq_sent;
+      // sum of sqrt(2 k) over the in-map slots: less 1 per sentinel and
+      // sqrt 2 per escape, plus the escapes' own
+      t_sq[jj] = (double)sq12 * (1.0 / 4096.0) - (double)nsent - (double)nesc * (double)sq_esc +
+                 (double)sq_far;
       t_noff[jj] = noff;
     }
   }
@@ -450,10 +485,11 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
   uint64_t packed = 0;
   if (mine) {
     const int64_t q_sl = t_sl[j];
-    const uint64_t q_sumk = t_sumk[j], q_sumsq = t_sumsq[j];
+    const uint64_t q_sumk = t_sumk[j];
+    const double q_sq = t_sq[j] * 0.70710678118654752;   // sum of sqrt(k)
     const int q_noff = t_noff[j];
     const double nvd = (double)nv;
-    const double sum_d = a.res * ((double)q_sumsq / 65536.0) + (double)q_noff * a.d_max;
+    const double sum_d = a.res * q_sq + (double)q_noff * a.d_max;
     const double sum_d2 = a.res * a.res * (double)q_sumk + (double)q_noff * a.d_max * a.d_max;
     const double dbar = sum_d / nvd;
     double var = sum_d2 / nvd - dbar * dbar;

@@ -191,7 +191,7 @@ int32_t build_lut(const reloc_search_params* p, double res, Lut* L) {
   L->kcap = kcap;
   L->keybits = (2 * kcap + 2 <= 4096) ? 12 : 16;
   const int nk = 1 << L->keybits;
-  L->q.assign(nk + 1, 0);   // and the zero slot q[nk] the TAM sums read for unselected keys
+  L->q.assign(nk, 0);
   for (int k = 0; k <= kcap; ++k) {
     const double v = ell(std::sqrt((double)k) * res);
     L->q[2 * k] = (int32_t)std::llrint(v * 67108864.0);

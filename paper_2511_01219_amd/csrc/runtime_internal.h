@@ -58,7 +58,6 @@ int32_t preprocess(const reloc_scan* sc, const reloc_search_params* p, double re
 // ---- likelihood table for TAM (eq. 23) --------------------------------------
 struct Lut {
   // Q26 likelihood per selection key less qmin (>= 0); 2^keybits entries
-  // and a zero slot
   std::vector<int32_t> q;
   int32_t qmin = 0;         // the smallest likelihood of a reachable key
   int kcap = 1, key_off = 2, keybits = 12;
