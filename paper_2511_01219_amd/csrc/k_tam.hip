@@ -22,15 +22,17 @@
 // top-k_mid selection of eq. 24-27 is a selection of the k_mid smallest
 // integer keys: key = 2 * min(k, kcap) for in-map endpoints and a
 // host-chosen odd key for off-map ones (d = d_max). kcap is where l(k) has
-// converged to within 1e-10 of its limit. The sentinel reads 2^32 - 1 in
-// place of 2 k (sign-extended), so every off-map or padded slot first takes
-// the key 2 kcap; the wavefront's sentinel count (from the sq sums) then
-// moves the off-map ones to key_off and drops the padded ones, in closed
-// form, in every count and sum. The threshold key comes from a search whose
-// counts are wavefront ballots; sums are exact integers
-// (l - lmin in Q26 fixed point from a host table, sqrt(k) in Q16, k itself,
-// lmin the table's smallest value added back per selected beam), so the
-// result does not depend on lane order or co-scheduling.
+// converged to within 1e-10 of its limit. A slot holds its raw plane value
+// (times 4, a table byte offset) as its key: every candidate threshold is at
+// most 2 kcap, so the cap needs no instruction, and the sentinel (2^32 - 1
+// sign-extended) lies above every candidate; the wavefront's sentinel count
+// then moves the off-map slots to key_off and drops the padded ones, in
+// closed form, in every count and sum. The threshold key comes from a
+// search whose counts are wavefront ballots; the likelihood sums are exact
+// integers (l - lmin in Q26 fixed point from a host table, lmin added back
+// per selected beam), k is summed exactly and sqrt(k) in FP32 within a lane
+// then exactly across lanes, so the result does not depend on lane order or
+// co-scheduling.
 // The median of eq. 27 is always the top-k_mid mean (top-k means are
 // non-increasing in k and k_low <= k_mid <= k_full).
 //
@@ -270,10 +272,13 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       if (tid + j * TB < n4) reinterpret_cast<u32x4*>(smem)[tid + j * TB] = q[j];
     __syncthreads();
   }
-  auto ell = [&](uint32_t key) -> int32_t {
-    if constexpr (kLdsLut) return smem[key];
-    else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)(key << 2), 0, 0);
+  // the table entry at byte offset k4 = 4 key (keys are held as 4 key, so a
+  // lookup needs no shift)
+  auto ell4 = [&](uint32_t k4) -> int32_t {
+    if constexpr (kLdsLut) return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(smem) + k4);
+    else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(lut, (int)k4, 0, 0);
   };
+  auto ell = [&](uint32_t key) -> int32_t { return ell4(key << 2); };
   const char* __restrict__ plane = reinterpret_cast<const char*>(a.plane);
   const char* __restrict__ plane16 = reinterpret_cast<const char*>(a.plane16);
   const uint32_t Wc = (uint32_t)a.W, Hc = (uint32_t)a.H, rows1 = tam_plane_rows(a.H) - 1u;
@@ -308,11 +313,11 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     }
     const uint4* __restrict__ orow =
         reinterpret_cast<const uint4*>(a.off + (size_t)pg * (size_t)a.off_stride) + lane;
-    // raw keys: min(2 k, 2 kcap) for every slot, from the 16-bit plane
-    // sign-extended: the sentinel reads 2^32 - 1 and the escape 2^32 - 2,
-    // so off-map, padded and far slots hold 2 kcap here (the counts and sums
-    // below move the off-map ones to key_off and drop the padded ones; the
-    // rare far ones are fixed from the 32-bit plane)
+    // raw keys: 4 x the 16-bit plane value read sign-extended, so the
+    // sentinel (2^32 - 1) and the escape (2^32 - 2) wrap to near 2^32,
+    // above every candidate (the counts and sums below move the off-map
+    // slots to key_off and drop the padded ones; the rare far ones are fixed
+    // from the 32-bit plane)
     uint32_t keys[R];
     // per lane: the sum of the raw values (in-map 2 k below 2^15, -1 per
     // sentinel, -2 per escape: exact in 32 bits), the counts of sentinels
@@ -342,7 +347,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
 #pragma unroll
       for (int s2 = 0; s2 < SB; ++s2) {
         const uint32_t k2 = v[s2];
-        keys[SB * b + s2] = min(k2, kcap2);
+        keys[SB * b + s2] = k2 << 2;    // the sentinel and the escape wrap far above 8 kcap
         sk += k2;
         cnt += k2 & 0x10001u;          // -1: both bits; -2: bit 16; 2 k < 2^15: neither
         sq += sqrt_abs(k2);            // no branch: the shares of -1 and -2 come out below
@@ -378,7 +383,7 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
           const bool far = w >= (1u << 15) && !(w & 1u);
           ek.add(far ? w : 0u);
           es += far ? __fsqrt_rn((float)w) : 0.0f;
-          if (far) keys[4 * m + q] = min(w, kcap2);
+          if (far) keys[4 * m + q] = min(w, kcap2) << 2;
         }
         __builtin_amdgcn_sched_barrier(0);   // four gathers in flight at a time
       }
@@ -388,8 +393,8 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
     const int nin = 64 * R - nsent;
     const int noff = nv - nin;
     // the selection over the true keys (in-map keys, noff copies of key_off):
-    // a count or sum over raw keys below c, less the sentinel slots when
-    // 2 kcap < c, plus the off-map beams when key_off < c
+    // a count or sum over raw keys below c, plus the off-map beams when
+    // key_off < c
     int64_t sl = 0;
     if constexpr (!FULL) {
       // TAM and T_mean: the top-k_mid sum of eq. 24-27. The threshold t,
@@ -401,10 +406,14 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       // t, and 2 kcap is where every far miss sits. One or two rounds settle
       // it; otherwise a binary search runs on the side where t lies. The
       // count below t is that of the last candidate taken (0 if none).
+      // Every candidate is at most 2 kcap, so raw keys (4 x the plane value,
+      // no cap) count as capped ones would and the sentinel slots (2^34 - 4
+      // wrapped) never count.
       auto cnt = [&](uint32_t c) -> int {
-        int n = (kcap2 < c ? -nsent : 0) + (key_off < c ? noff : 0);
+        int n = key_off < c ? noff : 0;
+        const uint32_t c4 = c << 2;
 #pragma unroll
-        for (int i = 0; i < R; ++i) n += __popcll(__ballot(keys[i] < c));
+        for (int i = 0; i < R; ++i) n += __popcll(__ballot(keys[i] < c4));
         return n;
       };
       const int sh = (int)(key_off & 1u) ^ 1;
@@ -446,14 +455,13 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       // below 2^31: pairs add in 32 bits
 #pragma unroll
       for (int i = 0; i < R; i += 2) {
-        const uint32_t l0 = (uint32_t)ell(min(keys[i], tkey));
-        const uint32_t l1 = (uint32_t)ell(min(keys[i + 1], tkey));
+        const uint32_t l0 = (uint32_t)ell4(min(keys[i], tkey << 2));
+        const uint32_t l1 = (uint32_t)ell4(min(keys[i + 1], tkey << 2));
         sl += (int64_t)(uint64_t)(l0 + l1);
       }
       const int64_t lt = ell(tkey);
-      const int below_raw = below - (kcap2 < tkey ? -nsent : 0) - (key_off < tkey ? noff : 0);
+      const int below_raw = below - (key_off < tkey ? noff : 0);
       sl = (int64_t)wave_sum64((uint64_t)sl) - (int64_t)(64 * R - below_raw) * lt;
-      if (kcap2 < tkey) sl -= (int64_t)nsent * (int64_t)ell(kcap2);
       if (key_off < tkey) sl += (int64_t)noff * (int64_t)ell(key_off);
       sl += (int64_t)(a.kmid - below) * lt;
       sl += (int64_t)a.kmid * (int64_t)a.lmin;
@@ -461,7 +469,8 @@ __device__ __forceinline__ void tam_tile(const TamArgs& a, const Src& src, int32
       // baseline and LF: the sum of l over every valid beam (eq. 32)
 #pragma unroll
       for (int i = 0; i < R; i += 2)
-        sl += (int64_t)(uint64_t)((uint32_t)ell(keys[i]) + (uint32_t)ell(keys[i + 1]));
+        sl += (int64_t)(uint64_t)((uint32_t)ell4(min(keys[i], kcap2 << 2)) +
+                                  (uint32_t)ell4(min(keys[i + 1], kcap2 << 2)));
       sl = (int64_t)wave_sum64((uint64_t)sl);
       sl += (int64_t)noff * (int64_t)ell(key_off) - (int64_t)nsent * (int64_t)ell(kcap2);
       sl += (int64_t)nv * (int64_t)a.lmin;
