@@ -238,8 +238,8 @@ __host__ __device__ constexpr size_t tam_lut_lds(int kb) {
 //
 // Per pose the R beam slots of a lane come SB at a time: one 16-byte load
 // of four offsets per four slots, then SB plane gathers, all in flight
-// before any is used. The per-pose integer sums (wavefront-uniform) go to
-// LDS as each pose ends; the FP64 tail (eq. 27-31) runs once per workgroup, for the
+// before any is used. The per-pose sums (wavefront-uniform) go to LDS as
+// each pose ends; the FP64 tail (eq. 27-31) runs once per workgroup, for the
 // 16 poses in lanes 0..15 of wavefront 0, and one atomic max per workgroup
 // publishes the best (T, tie). The other wavefronts end there: every
 // caller ends with the tile.
