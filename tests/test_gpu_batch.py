@@ -8,6 +8,7 @@ Bars:
   * against the FP64 oracle, the batched results meet the plain path's bars
     (ray-cast hit cells bit-exact, SMAD order identical, TAM within 1e-4).
 """
+import math
 import sys
 
 import numpy as np
@@ -315,3 +316,51 @@ def test_batch_and_serve_deadline(ctx, multi, loaded):
     poses, st = ctx.poll(t, wait_ms=60000)
     assert st["status"] == reloc.E_TIMEOUT
     assert 0 < st["n_eval"] < st["n_hyp"] and len(poses) > 0
+
+
+def test_batch_and_serve_far_cells(ctx):
+    """An open hall where most endpoints lie 128 or more cells from any
+    obstacle, so the TAM kernels take the escape path through the 32-bit
+    plane: batched and served results equal the plain path's (which the
+    parity tests hold to the oracle on such maps), with 2 kcap below and
+    above 2^15 and a full search."""
+    W, H = 700, 600
+    occ = np.zeros((H, W), np.int8)
+    occ[0, :] = occ[H - 1, :] = 100
+    occ[:, 0] = occ[:, W - 1] = 100
+    occ[280:300, 150:200] = 100
+    k = oracle.edt(occ)
+    assert (k >= (1 << 14)).mean() > 0.2
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.integers(250, 450, 150), rng.integers(3, 40, 30)])
+    ys = np.concatenate([rng.integers(200, 400, 150), rng.integers(3, 40, 30)])
+    keep = occ[ys, xs] == 0
+    hyp = np.unique(np.stack([xs[keep], ys[keep]], 1).astype(np.int32), axis=0)
+    m = ctx.load_map(occ, 0.05)
+    sid = ctx.set_hypotheses(m, hyp)
+    inc = 2 * math.pi / 360
+    cases = []
+    for i, params in enumerate([dict(), dict(sigma_hit=1.0), dict(tau=None)]):
+        z = np.full(360, 3.0 + i, np.float32)
+        z[::3] = 12.0
+        z[1::3] = 25.0
+        scan = dict(ranges=z, angle_min=-math.pi, angle_increment=inc, range_min=0.02,
+                    range_max=40.0)
+        search = dict(n_theta=90, batch_k=16, tau=0.95, k_out=8)
+        search.update(params)
+        cases.append((scan, search))
+    _case("far cells: %d hypotheses, plain and batched" % len(hyp))
+    rids = [ctx.prepare(m, sid, **sc, **se) for sc, se in cases]
+    plain = [ctx.run(r) for r in rids]
+    for a, b in zip(plain, ctx.run_batch(rids)):
+        _same(a, b)
+    _case("far cells: served")
+    tickets = [ctx.submit(m, sid, **sc, **se) for sc, se in cases]
+    for t, a in zip(tickets, plain):
+        got = ctx.poll(t, wait_ms=60000)
+        assert got is not None
+        _same(got, a)
+    for r in rids:
+        ctx.release(r)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
