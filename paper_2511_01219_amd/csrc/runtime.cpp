@@ -885,6 +885,26 @@ int32_t refine_lattice(const reloc_search_params* p, const reloc_scan_info& I, i
   return RELOC_OK;
 }
 
+// The likelihood table of a parameter set: from the context's recent ones
+// when the parameters match exactly, else built (and kept).
+int32_t cached_lut(reloc_ctx* c, const reloc_search_params* p, double res, Lut* L) {
+  const double key[5] = {p->z_hit, p->sigma_hit, p->z_rand, p->d_max, res};
+  {
+    std::lock_guard<std::mutex> lk(c->lut_mu);
+    for (auto it = c->luts.begin(); it != c->luts.end(); ++it)
+      if (std::memcmp(it->key, key, sizeof key) == 0) {
+        *L = it->lut;
+        if (it + 1 != c->luts.end()) std::rotate(it, it + 1, c->luts.end());
+        return RELOC_OK;
+      }
+  }
+  if (int32_t e = build_lut(p, res, L)) return e;
+  std::lock_guard<std::mutex> lk(c->lut_mu);
+  if (c->luts.size() >= reloc_ctx::kLutCache) c->luts.erase(c->luts.begin());
+  c->luts.push_back(reloc_ctx::LutEntry{{key[0], key[1], key[2], key[3], key[4]}, *L});
+  return RELOC_OK;
+}
+
 int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_scan* scan,
                      const reloc_search_params* params, Request* R) {
   if (int32_t e = validate_search(params)) return e;
@@ -899,7 +919,7 @@ int32_t init_request(reloc_ctx* c, int32_t map_id, int32_t set_id, const reloc_s
   R->prm = *params;
   R->n_hyp = params->n_hyp > 0 ? std::min(params->n_hyp, si->second.n) : si->second.n;
   if (int32_t e = preprocess(scan, params, mi->second.res, &R->prep)) return e;
-  if (int32_t e = build_lut(params, mi->second.res, &R->lut)) return e;
+  if (int32_t e = cached_lut(c, params, mi->second.res, &R->lut)) return e;
   R->rmax = scan->range_max;
   R->rcells = (int)std::ceil((double)scan->range_max / mi->second.res) + 2;
   R->fused = params->coarse_metric == 0 && params->variant == 0 && mi->second.walk != nullptr;
