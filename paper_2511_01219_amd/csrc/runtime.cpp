@@ -396,40 +396,71 @@ struct TableBlob {
 };
 
 // Builds the request's device tables and work buffers.
-int32_t build_request(reloc_ctx* c, Request& R) {
-  DevMap& m = c->maps[R.map_id];
-  const reloc_scan_info& I = R.prep.info;
-  const int Ns = I.Ns, Ng = I.Ng, b = Ng / Ns;
-  const std::vector<int2> U = direction_table(Ng);
-  std::vector<int2> rd(Ns);
-  std::vector<float2> kp(Ns);
-  for (int j = 0; j < Ns; ++j) {
-    rd[j] = U[(size_t)j * b];
-    kp[j].x = rd[j].x ? axis_scale(rd[j].x, rd[j].y, m.res) : 0.f;
-    kp[j].y = rd[j].y ? axis_scale(rd[j].y, rd[j].x, m.res) : 0.f;
+// The direction tables of a beam grid, from the context's recent ones or
+// built (and kept).
+std::shared_ptr<const DirTables> dir_tables(reloc_ctx* c, int Ng, int Ns, double res) {
+  {
+    std::lock_guard<std::mutex> lk(c->lut_mu);
+    for (auto it = c->dirs.begin(); it != c->dirs.end(); ++it)
+      if ((*it)->Ng == Ng && (*it)->Ns == Ns && std::memcmp(&(*it)->res, &res, sizeof res) == 0) {
+        std::shared_ptr<const DirTables> d = *it;
+        if (it + 1 != c->dirs.end()) std::rotate(it, it + 1, c->dirs.end());
+        return d;
+      }
   }
-  // per-direction constants of the skip traversal
-  std::vector<int4> di(Ns);
-  std::vector<float4> df(Ns);
+  auto D = std::make_shared<DirTables>();
+  D->Ng = Ng;
+  D->Ns = Ns;
+  D->res = res;
+  D->U = direction_table(Ng);
+  const int b = Ng / Ns;
+  D->rd.resize(Ns);
+  D->kp.resize(Ns);
+  D->di.resize(Ns);
+  D->df.resize(Ns);
   for (int j = 0; j < Ns; ++j) {
-    const int ax = std::abs(rd[j].x), ay = std::abs(rd[j].y);
+    const int2 u = D->U[(size_t)j * b];
+    D->rd[j] = u;
+    D->kp[j].x = u.x ? axis_scale(u.x, u.y, res) : 0.f;
+    D->kp[j].y = u.y ? axis_scale(u.y, u.x, res) : 0.f;
+    // per-direction constants of the skip traversal
+    const int ax = std::abs(u.x), ay = std::abs(u.y);
     const bool xmaj = ax >= ay;
     const int amaj = xmaj ? ax : ay, bmin = xmaj ? ay : ax;
     // (a, b, code, bits of 1/(256 b)) with a = |U_major|, b = |U_minor|;
     // code bit 0: x is the major axis, bit 1: U_major < 0, bit 2: U_minor < 0
-    const int umaj = xmaj ? rd[j].x : rd[j].y, umin = xmaj ? rd[j].y : rd[j].x;
-    di[j].x = amaj;
-    di[j].y = bmin;
-    di[j].z = (xmaj ? 1 : 0) | (umaj < 0 ? 2 : 0) | (umin < 0 ? 4 : 0);
+    const int umaj = xmaj ? u.x : u.y, umin = xmaj ? u.y : u.x;
+    int4& di = D->di[j];
+    di.x = amaj;
+    di.y = bmin;
+    di.z = (xmaj ? 1 : 0) | (umaj < 0 ? 2 : 0) | (umin < 0 ? 4 : 0);
     const float inv = bmin > 0 ? (float)(1.0 / (256.0 * bmin)) : INFINITY;
-    std::memcpy(&di[j].w, &inv, sizeof(float));
+    std::memcpy(&di.w, &inv, sizeof(float));
     const double nrm = std::sqrt((double)ax * ax + (double)ay * ay);
     // (f, r, kappa_major, kappa_minor)
-    df[j].x = (float)((double)amaj / nrm * 0.99999);   // rounds down a hair
-    df[j].y = (float)((double)bmin / (double)amaj);
-    df[j].z = xmaj ? kp[j].x : kp[j].y;
-    df[j].w = xmaj ? kp[j].y : kp[j].x;
+    float4& df = D->df[j];
+    df.x = (float)((double)amaj / nrm * 0.99999);   // rounds down a hair
+    df.y = (float)((double)bmin / (double)amaj);
+    df.z = xmaj ? D->kp[j].x : D->kp[j].y;
+    df.w = xmaj ? D->kp[j].y : D->kp[j].x;
   }
+  std::shared_ptr<const DirTables> d = D;
+  std::lock_guard<std::mutex> lk(c->lut_mu);
+  if (c->dirs.size() >= reloc_ctx::kLutCache) c->dirs.erase(c->dirs.begin());
+  c->dirs.push_back(d);
+  return d;
+}
+
+int32_t build_request(reloc_ctx* c, Request& R) {
+  DevMap& m = c->maps[R.map_id];
+  const reloc_scan_info& I = R.prep.info;
+  const int Ns = I.Ns, Ng = I.Ng, b = Ng / Ns;
+  const std::shared_ptr<const DirTables> D = dir_tables(c, Ng, Ns, m.res);
+  const std::vector<int2>& U = D->U;
+  const std::vector<int2>& rd = D->rd;
+  const std::vector<float2>& kp = D->kp;
+  const std::vector<int4>& di = D->di;
+  const std::vector<float4>& df = D->df;
   std::vector<int32_t> base(R.prep.vj.size());
   for (size_t v = 0; v < base.size(); ++v) base[v] = b * R.prep.vj[v];
   const int n = R.n_hyp, nv = I.n_valid;
