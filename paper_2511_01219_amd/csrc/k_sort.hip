@@ -28,6 +28,7 @@ namespace reloc {
 namespace {
 
 constexpr int kTileThreads = 256, kTile = 1024;
+constexpr int kRankMax = 2 * kTileThreads;   // tiles of at most this many keys are ranked
 
 // Index of the segment holding item t: prefix[s] <= t < prefix[s + 1].
 __device__ __forceinline__ int find_seg(const int64_t* prefix, int n, int64_t t) {
@@ -51,10 +52,12 @@ __device__ __forceinline__ bool pair_less(uint64_t ka, int32_t pa, uint64_t kb, 
   return ka < kb || (ka == kb && pa < pb);
 }
 
-// Bitonic sort of one tile of (key, position) pairs: kin[base + t0 + i]
-// for i < cnt, sorted into kout / pos at the same places (kout may be kin:
-// the tile is read whole before it is written); positions are positions in
-// the segment. Padding pairs (~0, INT_MAX) sort last and are not stored.
+// Sort of one tile of (key, position) pairs: kin[base + t0 + i] for
+// i < cnt, sorted into kout / pos at the same places (kout may be kin: the
+// tile is read whole before it is written); positions are positions in the
+// segment. A bitonic network in LDS, or for a tile of at most 512 keys a
+// rank count; padding pairs (~0, INT_MAX) of the network sort last and are
+// not stored.
 __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(const uint64_t* kin, Segs sg,
                                                                  uint64_t* kout,
                                                                  int32_t* __restrict__ pos) {
@@ -69,6 +72,43 @@ __global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(const uint64_t*
   }
   const int64_t t0 = t * kTile;
   const int cnt = (int)min((int64_t)kTile, n_s - t0);
+  if (cnt <= kRankMax) {                 // workgroup-uniform
+    // a small tile: every pair's place is the number of pairs that precede
+    // it (keys of smaller position that are equal or smaller, keys of larger
+    // position that are smaller; the pairs are distinct, so the places are
+    // a permutation), two pairs per thread against the tile in LDS, all lanes
+    // of a wavefront reading the same word at a time: no barrier between
+    // steps (the network below takes 55 barrier-separated steps, 28 us,
+    // whatever the count)
+    constexpr int PER = kRankMax / kTileThreads;
+    uint64_t mine[PER];
+    int rank[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = threadIdx.x + r * kTileThreads;
+      mine[r] = 0;
+      rank[r] = 0;
+      if (i < cnt) sk[i] = mine[r] = kin[base + t0 + i];
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const uint64_t kj = sk[j];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * kTileThreads;
+        rank[r] += (kj < mine[r] || (kj == mine[r] && j < i)) ? 1 : 0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = threadIdx.x + r * kTileThreads;
+      if (i < cnt) {
+        kout[base + t0 + rank[r]] = mine[r];
+        pos[base + t0 + rank[r]] = (int32_t)(t0 + i);
+      }
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < kTile; i += kTileThreads) {
     const bool in = i < cnt;
     sk[i] = in ? kin[base + t0 + i] : ~0ull;

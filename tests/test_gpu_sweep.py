@@ -76,11 +76,12 @@ def test_coarse_map_all_free_cells(world):
     ctx.free_hypotheses(sid)
 
 
-@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 4097, 65536, 65537, 200000, 262145])
+@pytest.mark.parametrize("n", [1, 300, 512, 513, 1023, 1024, 1025, 4097, 65536, 65537, 200000,
+                               262145])
 def test_order_with_ties_across_tiles(world, n):
-    """The stable SMAD order at sizes around the 1024-key tiles of the sort
-    and around the 65 536-key runs of its first merge level (up to two merge
-    levels), with many exact ties (37 cells repeated, so equal scans give
+    """The stable SMAD order at sizes around the 512-key limit of the
+    ranked small tiles and the 1024-key tiles of the sort, and around the
+    runs of its merge levels, with many exact ties (37 cells repeated, so equal scans give
     equal SMAD): the order is the stable one (ties by index) of the returned
     scores; with no coarse metric (every key zero) it is the identity."""
     w, k, ctx, m = world
