@@ -156,6 +156,40 @@ def test_random_poses(world, n, fine):
     ctx.free_hypotheses(sid)
 
 
+@pytest.mark.parametrize("fine", [0, 1, 2, 3])
+def test_random_poses_far_cells(world, fine):
+    """Every fine metric at random poses of an open hall, where most
+    endpoints lie 128 or more cells from any obstacle (the escape path of
+    the TAM planes, in the full-sum class too), against the oracle."""
+    _, _, ctx, _ = world
+    W, H = 700, 600
+    occ = np.zeros((H, W), np.int8)
+    occ[0, :] = occ[H - 1, :] = 100
+    occ[:, 0] = occ[:, W - 1] = 100
+    occ[280:300, 150:200] = 100
+    k = oracle.edt(occ)
+    m = ctx.load_map(occ, 0.05)
+    sid = ctx.set_hypotheses(m, np.array([[350, 300]], np.int32))
+    inc = 2 * math.pi / 360
+    z = np.full(360, 4.0, np.float32)
+    z[::3] = 12.0
+    z[1::3] = 25.0
+    rid = ctx.prepare(m, sid, z, -math.pi, inc, 0.02, 40.0, n_theta=360, batch_k=10,
+                      fine_metric=fine)
+    rng = np.random.default_rng([7, fine])
+    n = 200
+    xy = np.stack([rng.integers(1, W - 1, n), rng.integers(1, H - 1, n)], 1).astype(np.int32)
+    g = rng.integers(0, 360, n).astype(np.int32)
+    _case("score %d random poses in an open hall, fine %d" % (n, fine))
+    v, _ = ctx.score_poses(rid, xy, g)
+    pr = oracle.prep(z, -math.pi, inc, 0.05, range_min=0.02, range_max=40.0, n_theta=360)
+    ref = oracle.tam(k, 0.05, pr, xy, g)[:, oracle.FINE_COL[fine]]
+    assert (np.abs(v.astype(np.float64) - ref) <= V_RTOL * np.abs(ref) + V_ATOL).all()
+    ctx.release(rid)
+    ctx.free_hypotheses(sid)
+    ctx.unload_map(m)
+
+
 def test_pose_arguments_checked(world):
     w, k, ctx, m = world
     H, W = w.occ.shape
