@@ -139,8 +139,11 @@ struct SkipRay {
   int om, on;          // cell-offset change of a major / minor crossing
   int Dm, na, nb, off, it;
   int la, lb;          // last in-range major / minor crossing count
+  int b8, na8, dab8;   // Dm change of a major crossing (256 b), of a minor one
+                       // (-256 a), of a corner (256 (b - a))
   uint32_t pbase;      // byte offset of the ray's walk plane
   float f, r;          // major crossings per cell of path (rounded down), b / a
+  float c;             // -(r + 1) / 2: the landing estimate is na r + c
   float inv;           // 1 / (256 b), +inf for b = 0
   float kmaj, kmin;    // metres per Q8 unit along the major / minor axis
   uint32_t v;          // walk word of the current cell
@@ -169,6 +172,10 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.kmaj = df.z;
   r.kmin = df.w;
   r.Dm = (r.b - r.a) << 7;
+  r.b8 = r.b << 8;
+  r.na8 = -(r.a << 8);
+  r.dab8 = (r.b - r.a) << 8;
+  r.c = -0.5f * r.r - 0.5f;
   r.na = r.nb = r.it = 0;
   r.off = (int)__umul24(iy0, W) + ix0;
   r.v = sm.at(r.pbase, r.off);
@@ -204,8 +211,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   if (r.Dm < 0) {
     const float est = fminf((float)(-r.Dm) * r.inv, 256.f);
     kr = min((int)(r.v >> 8), (int)ceilf(est));
-    if (kr > 0 && r.Dm + (int)(((uint32_t)r.b & 0x1FFFFFu) * ((uint32_t)(kr - 1) & 0xFFu) << 8) >= 0)
-      --kr;
+    if (kr > 0 && r.Dm + (int)__umul24((uint32_t)r.b, (uint32_t)(kr - 1) << 8) >= 0) --kr;
   }
   // one update for both jumps: a run jump ends in the same window as the
   // radius jump (only major crossings on the way, nb unchanged), so the
@@ -214,11 +220,13 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   const int Jt = max(kr, J);
   if (Jt > 0) {
     const int na = r.na + Jt;
-    int nb = (int)floorf(((float)na - 0.5f) * r.r - 0.5f) + 1;
+    // nb = floor(x) + 1 with x = (na - 1/2) r - 1/2 >= -1/2; the float x
+    // truncated is within one of floor(x) (on [-1/2, 0) floor(x) = -1 and
+    // the truncation 0; elsewhere only rounding near an integer moves it)
+    int nb = (int)__builtin_fmaf((float)na, r.r, r.c) + 1;
     int Dm = (int)(__umul24(128 + 256 * na, r.b) - __umul24(128 + 256 * nb, r.a));
-    const int dB = r.a << 8;
-    if (Dm >= (r.b << 8)) { ++nb; Dm -= dB; }
-    if (Dm < ((r.b - r.a) << 8)) { --nb; Dm += dB; }
+    if (Dm >= r.b8) { ++nb; Dm += r.na8; }
+    if (Dm < r.dab8) { --nb; Dm -= r.na8; }
     r.na = na;
     r.nb = nb;
     r.Dm = Dm;
@@ -233,7 +241,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
     const bool maj = r.Dm < 0;
     r.na += maj ? 1 : 0;
     r.nb += maj ? 0 : 1;
-    r.Dm += maj ? (r.b << 8) : -(r.a << 8);
+    r.Dm += maj ? r.b8 : r.na8;
     r.off += maj ? r.om : r.on;
     const bool out = r.na > r.la || r.nb > r.lb;
     r.v = out ? 1u : sm.at(r.pbase, r.off);
@@ -259,7 +267,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   r.off = dg;
   ++r.na;
   ++r.nb;
-  r.Dm += (r.b - r.a) << 8;
+  r.Dm += r.dab8;
   r.v = vd;
   if (best >= 0 || !ind) {
     // the entry offset is measured along x at a corner
