@@ -137,14 +137,15 @@ struct WalkMap {
 struct SkipRay {
   int a, b;            // |U_major|, |U_minor|
   int om, on;          // cell-offset change of a major / minor crossing
-  int Dm, na, nb, off, it;
+  int Dm, na, nb, off;
+  int it;              // skip_iter calls so far (counted only where reported)
   int la, lb;          // last in-range major / minor crossing count
   int b8, na8, dab8;   // Dm change of a major crossing (256 b), of a minor one
                        // (-256 a), of a corner (256 (b - a))
   uint32_t pbase;      // byte offset of the ray's walk plane
   float f, r;          // major crossings per cell of path (rounded down), b / a
-  float c;             // -(r + 1) / 2: the landing estimate is na r + c
-  float inv;           // 1 / (256 b), +inf for b = 0
+  float c;             // (1 - r) / 2: the landing estimate is na r + c
+  float ninv;          // -1 / (256 b), -inf for b = 0
   float kmaj, kmin;    // metres per Q8 unit along the major / minor axis
   uint32_t v;          // walk word of the current cell
   bool xmaj;
@@ -166,7 +167,7 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.la = min(rcells, mneg ? pM : eM - 1 - pM);
   r.lb = r.b == 0 ? rcells : min(rcells, nneg ? pN : eN - 1 - pN);
   r.pbase = (uint32_t)((r.xmaj ? 0 : 2) + (mneg ? 1 : 0)) * plane_bytes;
-  r.inv = __int_as_float(di.w);
+  r.ninv = -__int_as_float(di.w);
   r.f = df.x;
   r.r = df.y;
   r.kmaj = df.z;
@@ -175,16 +176,18 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.b8 = r.b << 8;
   r.na8 = -(r.a << 8);
   r.dab8 = (r.b - r.a) << 8;
-  r.c = -0.5f * r.r - 0.5f;
+  r.c = 0.5f - 0.5f * r.r;
   r.na = r.nb = r.it = 0;
   r.off = (int)__umul24(iy0, W) + ix0;
   r.v = sm.at(r.pbase, r.off);
 }
 
 // One iteration: at most one exact free-space jump, then one exact crossing
-// with an occupancy test of the entered cell(s). Returns true when the ray
-// ends; *z / *hit then hold its range (0 / -1 for none). Counts beyond
-// la / lb mean the ray left the map or passed the cut-off: a miss.
+// with an occupancy test of the entered cell(s). Returns 0 while the ray
+// goes on, 1 when it ends without a hit, 2 / 3 when it ends in the occupied
+// cell r.off entered across a major / minor boundary (skip_range gives the
+// range). Counts beyond la / lb mean the ray left the map or passed the
+// cut-off: a miss.
 //
 // Two jumps are possible from the current cell, both landing just after a
 // major crossing on the exact crossing sequence; the one reaching further
@@ -202,14 +205,12 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 // Every product here has factors below 2^23 (counts below 2^12 for ranges
 // under 64 m at >= 1/32 m cells, |U| <= 2^20, strides <= 32768) and only its
 // low 32 bits are used, so the full-rate 24-bit multiplies are exact.
-__device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off0, float* z,
-                                          int* hit) {
-  ++r.it;
+__device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0) {
   const int s = (int)(r.v & 255u) - 1;
   const int J = s >= 2 ? (int)((float)s * r.f) : 0;
   int kr = 0;
   if (r.Dm < 0) {
-    const float est = fminf((float)(-r.Dm) * r.inv, 256.f);
+    const float est = fminf((float)r.Dm * r.ninv, 256.f);
     kr = min((int)(r.v >> 8), (int)ceilf(est));
     if (kr > 0 && r.Dm + (int)__umul24((uint32_t)r.b, (uint32_t)(kr - 1) << 8) >= 0) --kr;
   }
@@ -220,10 +221,9 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   const int Jt = max(kr, J);
   if (Jt > 0) {
     const int na = r.na + Jt;
-    // nb = floor(x) + 1 with x = (na - 1/2) r - 1/2 >= -1/2; the float x
-    // truncated is within one of floor(x) (on [-1/2, 0) floor(x) = -1 and
-    // the truncation 0; elsewhere only rounding near an integer moves it)
-    int nb = (int)__builtin_fmaf((float)na, r.r, r.c) + 1;
+    // nb = floor(x) with x = (na - 1/2) r + 1/2 >= 1/2, and the float x
+    // truncated is its floor up to rounding near an integer
+    int nb = (int)__builtin_fmaf((float)na, r.r, r.c);
     int Dm = (int)(__umul24(128 + 256 * na, r.b) - __umul24(128 + 256 * nb, r.a));
     if (Dm >= r.b8) { ++nb; Dm += r.na8; }
     if (Dm < r.dab8) { --nb; Dm -= r.na8; }
@@ -231,11 +231,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
     r.nb = nb;
     r.Dm = Dm;
     r.off = off0 + __mul24(na, r.om) + __mul24(nb, r.on);
-    if (na > r.la || nb > r.lb) {
-      *z = 0.f;
-      *hit = -1;
-      return true;
-    }
+    if (na > r.la || nb > r.lb) return 1;
   }
   if (r.Dm != 0) {
     const bool maj = r.Dm < 0;
@@ -246,13 +242,7 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
     const bool out = r.na > r.la || r.nb > r.lb;
     r.v = out ? 1u : sm.at(r.pbase, r.off);
     const bool occ = r.v == 0;
-    if (out || occ) {
-      const int n = maj ? r.na : r.nb;
-      *z = occ ? __fmul_rn((float)(128 + 256 * (n - 1)), maj ? r.kmaj : r.kmin) : 0.f;
-      *hit = occ ? r.off : -1;
-      return true;
-    }
-    return false;
+    return occ ? (maj ? 2 : 3) : (out ? 1 : 0);
   }
   // exact corner: both neighbours and the diagonal share the entry parameter
   const bool ina = r.na + 1 <= r.la, inb = r.nb + 1 <= r.lb;
@@ -269,14 +259,21 @@ __device__ __forceinline__ bool skip_iter(SkipRay& r, const WalkMap& sm, int off
   ++r.nb;
   r.Dm += r.dab8;
   r.v = vd;
-  if (best >= 0 || !ind) {
+  if (best >= 0) {
     // the entry offset is measured along x at a corner
-    const int n = r.xmaj ? r.na : r.nb;
-    *z = best >= 0 ? __fmul_rn((float)(128 + 256 * (n - 1)), r.xmaj ? r.kmaj : r.kmin) : 0.f;
-    *hit = best;
-    return true;
+    r.off = best;
+    return r.xmaj ? 2 : 3;
   }
-  return false;
+  return ind ? 0 : 1;
+}
+
+// Range of a ray that skip_iter ended with code e: the entry offset along the
+// crossing's axis (n crossings of that axis done) times that axis' metres per
+// Q8 unit; 0 for a miss.
+__device__ __forceinline__ float skip_range(const SkipRay& r, int e) {
+  const bool mj = e == 2;
+  const int n = mj ? r.na : r.nb;
+  return e >= 2 ? __fmul_rn((float)(128 + 256 * (n - 1)), mj ? r.kmaj : r.kmin) : 0.f;
 }
 
 __device__ __forceinline__ WalkMap make_walkmap(const RayArgs& a) {
@@ -333,9 +330,11 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
   if (busy) start(q);
   for (;;) {
     if (busy) {
-      float z;
-      int hit;
-      if (skip_iter(r, sm, off0, &z, &hit)) {
+      ++r.it;
+      const int e = skip_iter(r, sm, off0);
+      if (e != 0) {
+        float z = skip_range(r, e);
+        int hit = e >= 2 ? r.off : -1;
         if (z > a.rmax) {
           z = 0.f;
           hit = -1;
@@ -451,7 +450,9 @@ __device__ __forceinline__ void smad_store(const RayArgs& a, int h, double v, in
   if (a.best0) a.best0[h] = 0;
 }
 
-template <int NW, int REFILL, bool PANO>
+// DBG: the launch carries a range, hit or step buffer (reloc_debug_raycast)
+// and the kernel counts steps and writes them; the timed path does neither.
+template <int NW, int REFILL, bool PANO, bool DBG>
 __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint8_t* dyn) {
   constexpr int NT = NW * 64;
   __shared__ int s_next;
@@ -504,22 +505,23 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   }
   for (;;) {
     if (busy) {
-      float z;
-      int hit;
-      if (skip_iter(r, sm, off0, &z, &hit)) {
-        if (z > a.rmax) {
-          z = 0.f;
-          hit = -1;
-        }
+      if constexpr (DBG) ++r.it;
+      const int e = skip_iter(r, sm, off0);
+      if (e != 0) {
+        float z = skip_range(r, e);
+        const bool far = z > a.rmax;
+        if (far) z = 0.f;
         if constexpr (PANO) {
           acc += fov ? (double)z : 0.0;
         } else {
           Z[q] = z;
         }
-        const size_t o = (size_t)h * Ns + q;
-        if (a.zbuf) a.zbuf[o] = z;
-        if (a.dbg_hit) a.dbg_hit[o] = hit;
-        if (a.dbg_steps) a.dbg_steps[o] = r.it;
+        if constexpr (DBG) {
+          const size_t o = (size_t)h * Ns + q;
+          if (a.zbuf) a.zbuf[o] = z;
+          if (a.dbg_hit) a.dbg_hit[o] = e >= 2 && !far ? r.off : -1;
+          if (a.dbg_steps) a.dbg_steps[o] = r.it;
+        }
         busy = false;
       }
     }
@@ -660,10 +662,10 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   if (tid == 0) smad_store(a, h, bv, bm);
 }
 
-template <int NW, int REFILL, bool PANO>
+template <int NW, int REFILL, bool PANO, bool DBG>
 __global__ __launch_bounds__(NW * 64) void raycast_smad_kernel(RayArgs a) {
   extern __shared__ __align__(8) uint8_t fused_dyn[];
-  raycast_smad_run<NW, REFILL, PANO>(a, xcd_slice(blockIdx.x, gridDim.x), fused_dyn);
+  raycast_smad_run<NW, REFILL, PANO, DBG>(a, xcd_slice(blockIdx.x, gridDim.x), fused_dyn);
 }
 
 // Several requests, one workgroup per hypothesis: request r owns workgroups
@@ -677,9 +679,9 @@ __global__ __launch_bounds__(NW * 64) void raycast_smad_batch_kernel(
   const RayArgs& a = reqs[r];
   const int pos = (int)(t - prefix[r]);
   if (a.n_shifts == 1)                         // workgroup-uniform
-    raycast_smad_run<NW, REFILL, true>(a, pos, fused_dyn);
+    raycast_smad_run<NW, REFILL, true, false>(a, pos, fused_dyn);
   else
-    raycast_smad_run<NW, REFILL, false>(a, pos, fused_dyn);
+    raycast_smad_run<NW, REFILL, false, false>(a, pos, fused_dyn);
 }
 
 // ------------------------------------------------------------------- SMAD
@@ -1056,14 +1058,22 @@ hipError_t launch_smad(const RayArgs& a, hipStream_t s) {
 }
 
 namespace {
-template <int NW, bool PANO>
-hipError_t launch_fused_nw(const RayArgs& a, int refill, size_t lds, hipStream_t s) {
+template <int NW, bool PANO, bool DBG>
+void launch_fused_refill(const RayArgs& a, int refill, size_t lds, hipStream_t s) {
   const dim3 g((unsigned)a.n_hyp), w(NW * 64);
   switch (refill) {
-    case 8: hipLaunchKernelGGL((raycast_smad_kernel<NW, 8, PANO>), g, w, lds, s, a); break;
-    case 32: hipLaunchKernelGGL((raycast_smad_kernel<NW, 32, PANO>), g, w, lds, s, a); break;
-    default: hipLaunchKernelGGL((raycast_smad_kernel<NW, 16, PANO>), g, w, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((raycast_smad_kernel<NW, 8, PANO, DBG>), g, w, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((raycast_smad_kernel<NW, 32, PANO, DBG>), g, w, lds, s, a); break;
+    default: hipLaunchKernelGGL((raycast_smad_kernel<NW, 16, PANO, DBG>), g, w, lds, s, a); break;
   }
+}
+
+template <int NW, bool PANO>
+hipError_t launch_fused_nw(const RayArgs& a, int refill, size_t lds, hipStream_t s) {
+  if (a.zbuf || a.dbg_hit || a.dbg_steps)
+    launch_fused_refill<NW, PANO, true>(a, refill, lds, s);
+  else
+    launch_fused_refill<NW, PANO, false>(a, refill, lds, s);
   return hipGetLastError();
 }
 
