@@ -151,22 +151,43 @@ struct SkipRay {
   bool xmaj;
 };
 
-__device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix0, int iy0,
-                                          int W, int H, int rcells, uint32_t plane_bytes,
-                                          const WalkMap& sm) {
-  const int code = di.z;
-  r.xmaj = (code & 1) != 0;
-  const bool mneg = (code & 2) != 0, nneg = (code & 4) != 0;
+// What a ray's crossings depend on besides its direction, for one start
+// cell and one direction class (code bit 0: x is the major axis, bit 1: the
+// major step is negative, bit 2: the minor step is negative): cell-offset
+// change of a major / minor crossing, last in-range major / minor crossing
+// count (the minor one for b > 0), byte offset of the walk plane.
+struct RayClass {
+  int om, on, la, lb;
+  uint32_t pbase;
+};
+
+__device__ __forceinline__ RayClass ray_class(int code, int ix0, int iy0, int W, int H,
+                                              int rcells, uint32_t plane_bytes) {
+  const bool xmaj = (code & 1) != 0, mneg = (code & 2) != 0, nneg = (code & 4) != 0;
+  const int sM = xmaj ? 1 : W, sN = xmaj ? W : 1;
+  const int pM = xmaj ? ix0 : iy0, eM = xmaj ? W : H;
+  const int pN = xmaj ? iy0 : ix0, eN = xmaj ? H : W;
+  RayClass k;
+  k.om = mneg ? -sM : sM;
+  k.on = nneg ? -sN : sN;
+  k.la = min(rcells, mneg ? pM : eM - 1 - pM);
+  k.lb = min(rcells, nneg ? pN : eN - 1 - pN);
+  k.pbase = (uint32_t)((xmaj ? 0 : 2) + (mneg ? 1 : 0)) * plane_bytes;
+  return k;
+}
+
+// Starts the ray of direction (di, df) from the cell at offset off0, whose
+// class entry is k.
+__device__ __forceinline__ void skip_start(SkipRay& r, int4 di, float4 df, const RayClass& k,
+                                           int off0, int rcells, const WalkMap& sm) {
+  r.xmaj = (di.z & 1) != 0;
   r.a = di.x;
   r.b = di.y;
-  const int sM = r.xmaj ? 1 : W, sN = r.xmaj ? W : 1;
-  r.om = mneg ? -sM : sM;
-  r.on = nneg ? -sN : sN;
-  const int pM = r.xmaj ? ix0 : iy0, eM = r.xmaj ? W : H;
-  const int pN = r.xmaj ? iy0 : ix0, eN = r.xmaj ? H : W;
-  r.la = min(rcells, mneg ? pM : eM - 1 - pM);
-  r.lb = r.b == 0 ? rcells : min(rcells, nneg ? pN : eN - 1 - pN);
-  r.pbase = (uint32_t)((r.xmaj ? 0 : 2) + (mneg ? 1 : 0)) * plane_bytes;
+  r.om = k.om;
+  r.on = k.on;
+  r.la = k.la;
+  r.lb = r.b == 0 ? rcells : k.lb;
+  r.pbase = k.pbase;
   r.ninv = -__int_as_float(di.w);
   r.f = df.x;
   r.r = df.y;
@@ -178,8 +199,15 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
   r.dab8 = (r.b - r.a) << 8;
   r.c = 0.5f - 0.5f * r.r;
   r.na = r.nb = r.it = 0;
-  r.off = (int)__umul24(iy0, W) + ix0;
+  r.off = off0;
   r.v = sm.at(r.pbase, r.off);
+}
+
+__device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix0, int iy0,
+                                          int W, int H, int rcells, uint32_t plane_bytes,
+                                          const WalkMap& sm) {
+  skip_start(r, di, df, ray_class(di.z, ix0, iy0, W, H, rcells, plane_bytes),
+             (int)__umul24(iy0, W) + ix0, rcells, sm);
 }
 
 // One iteration: at most one exact free-space jump, then one exact crossing
@@ -460,6 +488,8 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   __shared__ double s_bv[NW];
   __shared__ int s_bm[NW];
   __shared__ uint32_t s_fov[4096 / 32];   // panoramic: FoV membership bit per direction
+  __shared__ int4 s_cls[8];                // the hypothesis' ray classes (om, on, la, lb)
+  __shared__ uint32_t s_clp[8];            // and their walk planes
   float* Z = (float*)dyn;
   double* Pb = (double*)(dyn + (((size_t)a.Ns * 4 + 7) & ~(size_t)7));
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -469,6 +499,13 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   const int off0 = (int)__umul24(iy0, W) + ix0;
   const WalkMap sm = make_walkmap(a);
   const uint32_t plane_bytes = a.walk_bytes >> 2;
+  // the eight ray classes of the hypothesis, so that starting a ray takes
+  // its class entry instead of deriving it
+  if (tid < 8) {
+    const RayClass k = ray_class(tid, ix0, iy0, W, H, a.rcells, plane_bytes);
+    s_cls[tid] = make_int4(k.om, k.on, k.la, k.lb);
+    s_clp[tid] = k.pbase;
+  }
   // panoramic scans: whether each direction lies in the FoV, taken when a
   // ray starts (a full turn needs no test); the bits are built once per
   // workgroup so the loop never waits on the FoV table
@@ -481,15 +518,14 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
           if (wd * 32 + b < Ns && in_fov(a, wd * 32 + b)) bits |= 1u << b;
         s_fov[wd] = bits;
       }
-      if constexpr (NW == 1) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
     }
   }
   if constexpr (NW > 1) {
     if (tid == 0) s_next = NT;
     __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   int nxt = NT;            // NW == 1: the wavefront's own (uniform) counter
   int q = tid;             // direction of the lane's ray
@@ -499,8 +535,15 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   bool fov = true;         // panoramic: the lane's ray lies in the FoV
   auto fov_of = [&](int j) { return all_in || ((s_fov[j >> 5] >> (j & 31)) & 1u) != 0; };
   SkipRay r;
+  auto start = [&](int j) {
+    const int4 di = a.dir_i[j];
+    const int c = di.z & 7;
+    const int4 e = s_cls[c];
+    const RayClass k{e.x, e.y, e.z, e.w, s_clp[c]};
+    skip_start(r, di, a.dir_f[j], k, off0, a.rcells, sm);
+  };
   if (busy) {
-    skip_init(r, a.dir_i[q], a.dir_f[q], ix0, iy0, W, H, a.rcells, plane_bytes, sm);
+    start(q);
     if constexpr (PANO) fov = fov_of(q);
   }
   for (;;) {
@@ -543,7 +586,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
                                 (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
       if (!busy && qn < Ns) {
         q = qn;
-        skip_init(r, a.dir_i[q], a.dir_f[q], ix0, iy0, W, H, a.rcells, plane_bytes, sm);
+        start(q);
         if constexpr (PANO) fov = fov_of(q);
         busy = true;
       }
