@@ -234,8 +234,9 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 // under 64 m at >= 1/32 m cells, |U| <= 2^20, strides <= 32768) and only its
 // low 32 bits are used, so the full-rate 24-bit multiplies are exact.
 __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0) {
+  // f < 1, so s <= 1 (s = -1 only for an occupied start cell) gives J = 0
   const int s = (int)(r.v & 255u) - 1;
-  const int J = s >= 2 ? (int)((float)s * r.f) : 0;
+  const int J = (int)((float)s * r.f);
   int kr = 0;
   if (r.Dm < 0) {
     const float est = fminf((float)r.Dm * r.ninv, 256.f);
@@ -532,7 +533,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   bool busy = q < Ns;
   bool dry = NT >= Ns;
   double acc = 0.0;        // panoramic: FoV sum of the lane's finished rays
-  bool fov = true;         // panoramic: the lane's ray lies in the FoV
+  float fov = 1.f;         // panoramic: 1 when the lane's ray lies in the FoV, else 0
   auto fov_of = [&](int j) { return all_in || ((s_fov[j >> 5] >> (j & 31)) & 1u) != 0; };
   SkipRay r;
   auto start = [&](int j) {
@@ -544,7 +545,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   };
   if (busy) {
     start(q);
-    if constexpr (PANO) fov = fov_of(q);
+    if constexpr (PANO) fov = fov_of(q) ? 1.f : 0.f;
   }
   for (;;) {
     if (busy) {
@@ -555,7 +556,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
         const bool far = z > a.rmax;
         if (far) z = 0.f;
         if constexpr (PANO) {
-          acc += fov ? (double)z : 0.0;
+          acc += (double)(z * fov);   // z is finite and >= 0: exact
         } else {
           Z[q] = z;
         }
@@ -587,7 +588,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
       if (!busy && qn < Ns) {
         q = qn;
         start(q);
-        if constexpr (PANO) fov = fov_of(q);
+        if constexpr (PANO) fov = fov_of(q) ? 1.f : 0.f;
         busy = true;
       }
     }
