@@ -530,7 +530,11 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
   }
   int nxt = NT;            // NW == 1: the wavefront's own (uniform) counter
   int q = tid;             // direction of the lane's ray
-  bool busy = q < Ns;
+  // lane state: 0 casting; 1-3 the ray ended with that skip_iter code and its
+  // range is not taken yet; 4 nothing to take. A lane's ended ray is taken
+  // when the lane is refilled or at the end (its state stays as it ended), so
+  // the loop does not form a range on every trip
+  int st = q < Ns ? 0 : 4;
   bool dry = NT >= Ns;
   double acc = 0.0;        // panoramic: FoV sum of the lane's finished rays
   float fov = 1.f;         // panoramic: 1 when the lane's ray lies in the FoV, else 0
@@ -543,33 +547,34 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
     const RayClass k{e.x, e.y, e.z, e.w, s_clp[c]};
     skip_start(r, di, a.dir_f[j], k, off0, a.rcells, sm);
   };
-  if (busy) {
+  // the range of the lane's ended ray (state e in 1-3) into the FoV sum or
+  // LDS, and into the debug buffers
+  auto take = [&](int e) {
+    float z = skip_range(r, e);
+    const bool far = z > a.rmax;
+    if (far) z = 0.f;
+    if constexpr (PANO) {
+      acc += (double)(z * fov);   // z is finite and >= 0: exact, in any order
+    } else {
+      Z[q] = z;
+    }
+    if constexpr (DBG) {
+      const size_t o = (size_t)h * Ns + q;
+      if (a.zbuf) a.zbuf[o] = z;
+      if (a.dbg_hit) a.dbg_hit[o] = e >= 2 && !far ? r.off : -1;
+      if (a.dbg_steps) a.dbg_steps[o] = r.it;
+    }
+  };
+  if (st == 0) {
     start(q);
     if constexpr (PANO) fov = fov_of(q) ? 1.f : 0.f;
   }
   for (;;) {
-    if (busy) {
+    if (st == 0) {
       if constexpr (DBG) ++r.it;
-      const int e = skip_iter(r, sm, off0);
-      if (e != 0) {
-        float z = skip_range(r, e);
-        const bool far = z > a.rmax;
-        if (far) z = 0.f;
-        if constexpr (PANO) {
-          acc += (double)(z * fov);   // z is finite and >= 0: exact
-        } else {
-          Z[q] = z;
-        }
-        if constexpr (DBG) {
-          const size_t o = (size_t)h * Ns + q;
-          if (a.zbuf) a.zbuf[o] = z;
-          if (a.dbg_hit) a.dbg_hit[o] = e >= 2 && !far ? r.off : -1;
-          if (a.dbg_steps) a.dbg_steps[o] = r.it;
-        }
-        busy = false;
-      }
+      st = skip_iter(r, sm, off0);
     }
-    const unsigned long long idle = __ballot(!busy);
+    const unsigned long long idle = __ballot(st != 0);
     const int cnt = __popcll(idle);
     if (dry && cnt == 64) break;
     if (!dry && cnt >= REFILL) {
@@ -585,14 +590,19 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
       dry = base + cnt >= Ns;
       const int qn = base + (int)__builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-      if (!busy && qn < Ns) {
-        q = qn;
-        start(q);
-        if constexpr (PANO) fov = fov_of(q) ? 1.f : 0.f;
-        busy = true;
+      if (st != 0) {
+        if (st != 4) take(st);
+        st = 4;
+        if (qn < Ns) {
+          q = qn;
+          start(q);
+          if constexpr (PANO) fov = fov_of(q) ? 1.f : 0.f;
+          st = 0;
+        }
       }
     }
   }
+  if (st != 4) take(st);
 
   if constexpr (PANO) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
