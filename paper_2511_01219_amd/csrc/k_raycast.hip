@@ -144,7 +144,7 @@ struct SkipRay {
                        // (-256 a), of a corner (256 (b - a))
   uint32_t pbase;      // byte offset of the ray's walk plane
   float f, r;          // major crossings per cell of path (rounded down), b / a
-  float c;             // (1 - r) / 2: the landing estimate is na r + c
+  float c;             // (1 - r) / 2 - 2^-7: the landing estimate is na r + c
   float ninv;          // -1 / (256 b), -inf for b = 0
   float kmaj, kmin;    // metres per Q8 unit along the major / minor axis
   uint32_t v;          // walk word of the current cell
@@ -197,7 +197,7 @@ __device__ __forceinline__ void skip_start(SkipRay& r, int4 di, float4 df, const
   r.b8 = r.b << 8;
   r.na8 = -(r.a << 8);
   r.dab8 = (r.b - r.a) << 8;
-  r.c = 0.5f - 0.5f * r.r;
+  r.c = (0.5f - 0.5f * r.r) - 0x1p-7f;
   r.na = r.nb = r.it = 0;
   r.off = off0;
   r.v = sm.at(r.pbase, r.off);
@@ -227,9 +227,10 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 //  * Radius jump: J major crossings are safe when all cells within the
 //    free-space radius are free. The state just after the (na + J)-th major
 //    crossing has the unique minor count with 256 (b - a) <= Dm < 256 b. A
-//    float estimate of that count is within one of it; Dm is evaluated in
-//    wrapping 32-bit arithmetic (exact, the true value is within one step of
-//    the window) and one correction lands in the window.
+//    float estimate of that count, biased low, is the count or one below it;
+//    Dm is evaluated in wrapping 32-bit arithmetic (exact, the true value is
+//    within one step of the window) and at most one step up lands in the
+//    window.
 // Every product here has factors below 2^23 (counts below 2^12 for ranges
 // under 64 m at >= 1/32 m cells, |U| <= 2^20, strides <= 32768) and only its
 // low 32 bits are used, so the full-rate 24-bit multiplies are exact.
@@ -250,12 +251,13 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
   const int Jt = max(kr, J);
   if (Jt > 0) {
     const int na = r.na + Jt;
-    // nb = floor(x) with x = (na - 1/2) r + 1/2 >= 1/2, and the float x
-    // truncated is its floor up to rounding near an integer
+    // nb = floor(x) with x = (na - 1/2) r + 1/2 >= 1/2. The float value of
+    // x - 2^-7 is within 2^-10 of it (na < 2^13, r < 1), so it lies in
+    // (x - 1, x) and is positive: truncated it is nb or nb - 1, and one
+    // exact step up settles it
     int nb = (int)__builtin_fmaf((float)na, r.r, r.c);
     int Dm = (int)(__umul24(128 + 256 * na, r.b) - __umul24(128 + 256 * nb, r.a));
     if (Dm >= r.b8) { ++nb; Dm += r.na8; }
-    if (Dm < r.dab8) { --nb; Dm -= r.na8; }
     r.na = na;
     r.nb = nb;
     r.Dm = Dm;
