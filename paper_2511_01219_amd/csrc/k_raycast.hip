@@ -212,10 +212,10 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 
 // One iteration: at most one exact free-space jump, then one exact crossing
 // with an occupancy test of the entered cell(s). Returns 0 while the ray
-// goes on, 1 when it ends without a hit, 2 / 3 when it ends in the occupied
-// cell r.off entered across a major / minor boundary (skip_range gives the
-// range). Counts beyond la / lb mean the ray left the map or passed the
-// cut-off: a miss.
+// goes on, else 1-3: the ray has ended, and with r.v == 0 and code 2 / 3 in
+// the occupied cell r.off, entered across a major / minor boundary
+// (skip_hit, skip_range); otherwise without a hit. Counts beyond la / lb
+// mean the ray left the map or passed the cut-off: a miss.
 //
 // Two jumps are possible from the current cell, both landing just after a
 // major crossing on the exact crossing sequence; the one reaching further
@@ -238,12 +238,11 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
   // f < 1, so s <= 1 (s = -1 only for an occupied start cell) gives J = 0
   const int s = (int)(r.v & 255u) - 1;
   const int J = (int)((float)s * r.f);
-  int kr = 0;
-  if (r.Dm < 0) {
-    const float est = fminf((float)r.Dm * r.ninv, 256.f);
-    kr = min((int)(r.v >> 8), (int)ceilf(est));
-    if (kr > 0 && r.Dm + (int)__umul24((uint32_t)r.b, (uint32_t)(kr - 1) << 8) >= 0) --kr;
-  }
+  // no test of Dm < 0: for Dm >= 0 the minor step b is positive, the
+  // estimate is finite and at most 0, and kr <= 0 leaves the jump to J
+  const float est = fminf((float)r.Dm * r.ninv, 256.f);
+  int kr = min((int)(r.v >> 8), (int)ceilf(est));
+  if (kr > 0 && r.Dm + (int)__umul24((uint32_t)r.b, (uint32_t)(kr - 1) << 8) >= 0) --kr;
   // one update for both jumps: a run jump ends in the same window as the
   // radius jump (only major crossings on the way, nb unchanged), so the
   // state after the farther one is computed the same way for either, and
@@ -272,8 +271,7 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
     r.off += maj ? r.om : r.on;
     const bool out = r.na > r.la || r.nb > r.lb;
     r.v = out ? 1u : sm.at(r.pbase, r.off);
-    const bool occ = r.v == 0;
-    return occ ? (maj ? 2 : 3) : (out ? 1 : 0);
+    return out || r.v == 0 ? (maj ? 2 : 3) : 0;
   }
   // exact corner: both neighbours and the diagonal share the entry parameter
   const bool ina = r.na + 1 <= r.la, inb = r.nb + 1 <= r.lb;
@@ -293,10 +291,15 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
   if (best >= 0) {
     // the entry offset is measured along x at a corner
     r.off = best;
+    r.v = 0;
     return r.xmaj ? 2 : 3;
   }
   return ind ? 0 : 1;
 }
+
+// Whether the ray that skip_iter ended with code e stopped in an occupied
+// cell (r.off).
+__device__ __forceinline__ bool skip_hit(const SkipRay& r, int e) { return e >= 2 && r.v == 0; }
 
 // Range of a ray that skip_iter ended with code e: the entry offset along the
 // crossing's axis (n crossings of that axis done) times that axis' metres per
@@ -304,7 +307,7 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
 __device__ __forceinline__ float skip_range(const SkipRay& r, int e) {
   const bool mj = e == 2;
   const int n = mj ? r.na : r.nb;
-  return e >= 2 ? __fmul_rn((float)(128 + 256 * (n - 1)), mj ? r.kmaj : r.kmin) : 0.f;
+  return skip_hit(r, e) ? __fmul_rn((float)(128 + 256 * (n - 1)), mj ? r.kmaj : r.kmin) : 0.f;
 }
 
 __device__ __forceinline__ WalkMap make_walkmap(const RayArgs& a) {
@@ -365,7 +368,7 @@ __device__ __forceinline__ void raycast_skip_run(const RayArgs& a, int block) {
       const int e = skip_iter(r, sm, off0);
       if (e != 0) {
         float z = skip_range(r, e);
-        int hit = e >= 2 ? r.off : -1;
+        int hit = skip_hit(r, e) ? r.off : -1;
         if (z > a.rmax) {
           z = 0.f;
           hit = -1;
@@ -563,7 +566,7 @@ __device__ __forceinline__ void raycast_smad_run(const RayArgs& a, int pos, uint
     if constexpr (DBG) {
       const size_t o = (size_t)h * Ns + q;
       if (a.zbuf) a.zbuf[o] = z;
-      if (a.dbg_hit) a.dbg_hit[o] = e >= 2 && !far ? r.off : -1;
+      if (a.dbg_hit) a.dbg_hit[o] = skip_hit(r, e) && !far ? r.off : -1;
       if (a.dbg_steps) a.dbg_steps[o] = r.it;
     }
   };
