@@ -222,8 +222,9 @@ __device__ __forceinline__ void skip_init(SkipRay& r, int4 di, float4 df, int ix
 // is taken.
 //  * Run jump: while Dm < 0 the next ceil(-Dm / 256 b) crossings are all
 //    major, i.e. cells of the current minor row; the walk word says how
-//    many of those are free (run). A float estimate of the ceiling is at
-//    most one above it and is checked once in exact integers.
+//    many of those are free (run). A float estimate of the ceiling, biased
+//    low, is it or one below it: a run jump no longer than allowed, as exact
+//    as any other.
 //  * Radius jump: J major crossings are safe when all cells within the
 //    free-space radius are free. The state just after the (na + J)-th major
 //    crossing has the unique minor count with 256 (b - a) <= Dm < 256 b. A
@@ -238,11 +239,13 @@ __device__ __forceinline__ int skip_iter(SkipRay& r, const WalkMap& sm, int off0
   // f < 1, so s <= 1 (s = -1 only for an occupied start cell) gives J = 0
   const int s = (int)(r.v & 255u) - 1;
   const int J = (int)((float)s * r.f);
-  // no test of Dm < 0: for Dm >= 0 the minor step b is positive, the
-  // estimate is finite and at most 0, and kr <= 0 leaves the jump to J
-  const float est = fminf((float)r.Dm * r.ninv, 256.f);
-  int kr = min((int)(r.v >> 8), (int)ceilf(est));
-  if (kr > 0 && r.Dm + (int)__umul24((uint32_t)r.b, (uint32_t)(kr - 1) << 8) >= 0) --kr;
+  // t = -Dm / (256 b) less 2^-12, more than the float error of the product
+  // (below 2^-14 for t <= 256), so ceil(est) is ceil(t) or one less: never
+  // more major crossings than come before the next minor one. No test of
+  // Dm < 0: for Dm >= 0 the minor step b is positive, est < 0 and kr <= 0
+  // leaves the jump to J
+  const float est = fminf(__builtin_fmaf((float)r.Dm, r.ninv, -0x1p-12f), 256.f);
+  const int kr = min((int)(r.v >> 8), (int)ceilf(est));
   // one update for both jumps: a run jump ends in the same window as the
   // radius jump (only major crossings on the way, nb unchanged), so the
   // state after the farther one is computed the same way for either, and
